@@ -1,0 +1,137 @@
+/*
+ * libmessi: exact k-NN search over an HBM-resident collection of data series
+ * with an iSAX index (Peng, Fatourou, Palpanas, "Fast Data Series Indexing
+ * for In-Memory Data"), for one MI355X (gfx950).
+ *
+ * Problem (Section 2.1): given a collection of same-length series and a
+ * query of that length, find the series at the smallest distance, under
+ * Euclidean distance or DTW with a Sakoe-Chiba window (Section 3.4); the
+ * k-NN form keeps the k best (Section 5.6).  Series and queries are
+ * z-normalised by the library (mean 0, standard deviation 1, Section 2.1).
+ *
+ * Conventions for every call:
+ *   - Returns MESSI_OK (0) or a negative MESSI_E* code; on error the output
+ *     buffers' contents are unspecified and messi_last_error() describes
+ *     the cause.
+ *   - "device pointer" = memory on the current HIP device (hipMalloc'd or a
+ *     torch CUDA tensor); "host pointer" = ordinary process memory.
+ *     Passing a host pointer where a device pointer is required is rejected
+ *     with MESSI_EINVAL (checked with hipPointerGetAttributes).
+ *   - ids are 0-based row numbers of the collection passed to messi_build.
+ *   - Work is ordered on the index's stream (messi_set_stream; default the
+ *     null stream); every call returns after its outputs are complete.
+ *   - One index may be queried from one host thread at a time; calls that
+ *     overlap on one index return MESSI_EBUSY.
+ */
+#ifndef MESSI_H
+#define MESSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MESSI_OK = 0,
+  MESSI_EINVAL = -1, /* bad argument (sizes, pointer kind, unknown option) */
+  MESSI_ENOMEM = -2, /* device memory exhausted or over the option budget */
+  MESSI_EDEVICE = -3, /* a HIP call or kernel launch failed */
+  MESSI_EBUSY = -4   /* the index is in use by another call */
+};
+
+enum { MESSI_ED = 0, MESSI_DTW = 1 };
+
+typedef struct messi_index messi_index; /* opaque; owned by the library */
+
+/* Leaf record as exported by messi_get_leaves: the series at leaf-order
+ * positions [begin, end) share, in every segment s, the symbol prefix
+ * sym[s] of bits[s] bits (Section 2.2, variable cardinality). */
+typedef struct messi_leaf {
+  int64_t begin, end;
+  uint8_t sym[16];
+  uint8_t bits[16];
+} messi_leaf;
+
+/* Per-call work counters (Table 4 of the paper counts the same things). */
+typedef struct messi_stats {
+  int64_t queries;
+  int64_t leaves_total;     /* leaves in the index, times queries */
+  int64_t leaves_kept;      /* leaves whose bound passed the first k-best */
+  int64_t series_lb;        /* series-level lower bounds computed */
+  int64_t lb_keogh;         /* LB_Keogh bounds computed (DTW) */
+  int64_t refined;          /* real distances computed in FP32 */
+  int64_t rechecked_fp64;   /* near-tie candidates recomputed in FP64 */
+  int64_t log_overflows;    /* reruns forced by a full near-tie log */
+} messi_stats;
+
+/* Build an index (Section 3.2: iSAX summaries, then the leaves of the
+ * root subtrees).
+ *   series      device pointer, float32 [n][len] row-major, read only; the
+ *               caller keeps ownership (the library stores its own
+ *               z-normalised copy in leaf order).
+ *   n           number of series, 1 <= n < 2^31.
+ *   len         series length; len % segments == 0, len <= 4096.
+ *   segments    PAA segments w, 1..16 (the paper fixes 16, Section 3.1).
+ *   cardinality symbols per segment, a power of two in [2, 256] (the paper
+ *               uses 256, Section 2.2).
+ *   leaf_size   leaf capacity (the paper uses 2000, Section 5.2); a leaf
+ *               holds more only when no segment is left to refine.
+ *   out         receives the index; free it with messi_free. */
+int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
+                int32_t cardinality, int32_t leaf_size, messi_index** out);
+
+/* Exact k-NN (Algorithms 5-10; k-NN per Section 5.6).
+ *   queries    device pointer, float32 [nq][len] (raw; z-normalised here).
+ *   nq         number of queries, >= 0 (0 returns at once).
+ *   k          neighbours per query, 1 <= k <= 1024.
+ *   distance   MESSI_ED or MESSI_DTW.
+ *   window     DTW Sakoe-Chiba radius r in points (0 <= r; r >= len-1 is
+ *              unconstrained DTW; ignored for ED).
+ *   out_ids    device pointer, int64 [nq][k]; out_dists device pointer,
+ *              float32 [nq][k]; each row ascending by (distance, id); the
+ *              distance is the square root of the sum of squared
+ *              differences (ED) or of the squared-cost DTW; rows past n
+ *              neighbours hold id -1, distance +inf.
+ * Answers are exact: equal, id for id, to a brute-force scan that computes
+ * every distance in FP64 from the z-normalised FP32 values, ties broken by
+ * the lower id. */
+int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k,
+                int32_t distance, int32_t window, int64_t* out_ids, float* out_dists);
+
+/* Same as messi_query, also returning work counters (stats may be NULL). */
+int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int32_t k,
+                      int32_t distance, int32_t window, int64_t* out_ids, float* out_dists,
+                      messi_stats* stats);
+
+/* Order the index's work after / before the caller's on this HIP stream
+ * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */
+int messi_set_stream(messi_index* index, void* hip_stream);
+
+/* Shape of a built index (any pointer may be NULL). */
+int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t* segments,
+                     int32_t* card_bits, int64_t* n_leaves, int64_t* device_bytes);
+
+/* Copies out of a built index into HOST buffers, for inspection and tests:
+ *   words   uint8 [n][segments], series in id order (Section 2.2 symbols);
+ *   perm    int32 [n], the id at each leaf-order position;
+ *   leaves  messi_leaf [cap]; *count receives the number of leaves (if
+ *           cap is too small nothing is copied and MESSI_EINVAL returned). */
+int messi_get_words(const messi_index* index, uint8_t* words);
+int messi_get_perm(const messi_index* index, int32_t* perm);
+int messi_get_leaves(const messi_index* index, messi_leaf* leaves, int64_t cap, int64_t* count);
+
+/* The library's breakpoint table (Section 2.2): beta[k-1] = Phi^-1(k/2^b)
+ * for k = 1 .. 2^b - 1, as FP32, into a HOST buffer. */
+int messi_breakpoints(int32_t card_bits, float* beta);
+
+void messi_free(messi_index* index);
+
+/* Description of the last error on this thread; valid until the next call. */
+const char* messi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MESSI_H */

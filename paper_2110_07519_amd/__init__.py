@@ -1,0 +1,207 @@
+"""Python binding of libmessi (MESSI exact k-NN search on one MI355X).
+
+Argument marshalling only: every step of the build and of a query runs in
+the HIP kernels of libmessi.so behind the C ABI declared in
+include/messi.h.  Torch is used for device memory and streams.  If the
+library is not built, importing works but every call raises.
+
+Names follow the C ABI: messi_build, messi_query, messi_query_stats,
+messi_set_stream, messi_free, messi_breakpoints, messi_get_words,
+messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmessi.so")
+
+MESSI_OK = 0
+MESSI_EINVAL = -1
+MESSI_ENOMEM = -2
+MESSI_EDEVICE = -3
+MESSI_EBUSY = -4
+MESSI_ED = 0
+MESSI_DTW = 1
+
+EXPORTS = [
+    "messi_build", "messi_query", "messi_query_stats", "messi_set_stream", "messi_index_info",
+    "messi_get_words", "messi_get_perm", "messi_get_leaves", "messi_breakpoints", "messi_free",
+    "messi_last_error",
+]
+
+
+class MessiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libmessi error {code}: {msg}")
+        self.code = code
+
+
+class MessiLeaf(ctypes.Structure):
+    _fields_ = [("begin", ctypes.c_int64), ("end", ctypes.c_int64),
+                ("sym", ctypes.c_uint8 * 16), ("bits", ctypes.c_uint8 * 16)]
+
+
+class MessiStats(ctypes.Structure):
+    _fields_ = [("queries", ctypes.c_int64), ("leaves_total", ctypes.c_int64),
+                ("leaves_kept", ctypes.c_int64), ("series_lb", ctypes.c_int64),
+                ("lb_keogh", ctypes.c_int64), ("refined", ctypes.c_int64),
+                ("rechecked_fp64", ctypes.c_int64), ("log_overflows", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libmessi.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.messi_build.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(P)]
+        L.messi_query.argtypes = [P, P, i32, i32, i32, i32, P, P]
+        L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
+        L.messi_set_stream.argtypes = [P, P]
+        L.messi_index_info.argtypes = [P, P, P, P, P, P, P]
+        L.messi_get_words.argtypes = [P, P]
+        L.messi_get_perm.argtypes = [P, P]
+        L.messi_get_leaves.argtypes = [P, P, i64, P]
+        L.messi_breakpoints.argtypes = [i32, P]
+        L.messi_free.argtypes = [P]
+        L.messi_free.restype = None
+        L.messi_last_error.restype = ctypes.c_char_p
+        for name in ["messi_build", "messi_query", "messi_query_stats", "messi_set_stream",
+                     "messi_index_info", "messi_get_words", "messi_get_perm", "messi_get_leaves",
+                     "messi_breakpoints"]:
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != MESSI_OK:
+        raise MessiError(rc, lib().messi_last_error().decode())
+
+
+def _dev_ptr(t):
+    import torch
+
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError("expected a CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def messi_breakpoints(card_bits: int = 8) -> np.ndarray:
+    beta = np.empty((1 << card_bits) - 1, dtype=np.float32)
+    _check(lib().messi_breakpoints(card_bits, beta.ctypes.data_as(ctypes.c_void_p)))
+    return beta
+
+
+def messi_build(series, segments: int = 16, cardinality: int = 256, leaf_size: int = 2000):
+    """Build an index over a float32 CUDA tensor [n, len]; returns an Index."""
+    import torch
+
+    assert series.dtype == torch.float32 and series.dim() == 2
+    n, length = series.shape
+    h = ctypes.c_void_p()
+    _check(lib().messi_build(_dev_ptr(series), n, length, segments, cardinality, leaf_size,
+                             ctypes.byref(h)))
+    return Index(h, n, length, segments)
+
+
+def messi_query(index, queries, k: int = 1, distance: int = MESSI_ED, window: int = 0,
+                out_ids=None, out_dists=None, stats: bool = False):
+    """Exact k-NN of float32 CUDA queries [nq, len]: (ids int64 [nq,k], dists float32 [nq,k])."""
+    import torch
+
+    assert queries.dtype == torch.float32 and queries.dim() == 2
+    nq = queries.shape[0]
+    dev = queries.device
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    if out_dists is None:
+        out_dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    st = MessiStats()
+    _check(lib().messi_query_stats(index.handle, _dev_ptr(queries), nq, k, distance, window,
+                                   _dev_ptr(out_ids), _dev_ptr(out_dists),
+                                   ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)))
+    if stats:
+        return out_ids, out_dists, st.as_dict()
+    return out_ids, out_dists
+
+
+def messi_set_stream(index, stream) -> None:
+    _check(lib().messi_set_stream(index.handle, ctypes.c_void_p(stream)))
+
+
+def messi_free(index) -> None:
+    if index.handle:
+        lib().messi_free(index.handle)
+        index.handle = None
+
+
+def messi_index_info(index) -> dict:
+    n, ln, w, cb, nl, db = (ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(),
+                            ctypes.c_int64(), ctypes.c_int64())
+    _check(lib().messi_index_info(index.handle, ctypes.byref(n), ctypes.byref(ln), ctypes.byref(w),
+                                  ctypes.byref(cb), ctypes.byref(nl), ctypes.byref(db)))
+    return {"n": n.value, "len": ln.value, "segments": w.value, "card_bits": cb.value,
+            "n_leaves": nl.value, "device_bytes": db.value}
+
+
+def messi_get_words(index) -> np.ndarray:
+    out = np.empty((index.n, index.segments), dtype=np.uint8)
+    _check(lib().messi_get_words(index.handle, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def messi_get_perm(index) -> np.ndarray:
+    out = np.empty(index.n, dtype=np.int32)
+    _check(lib().messi_get_perm(index.handle, out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def messi_get_leaves(index) -> np.ndarray:
+    cnt = ctypes.c_int64()
+    info = messi_index_info(index)
+    cap = info["n_leaves"]
+    arr = (MessiLeaf * max(cap, 1))()
+    _check(lib().messi_get_leaves(index.handle, ctypes.cast(arr, ctypes.c_void_p), cap,
+                                  ctypes.byref(cnt)))
+    dt = np.dtype([("begin", np.int64), ("end", np.int64), ("sym", np.uint8, 16),
+                   ("bits", np.uint8, 16)])
+    raw = np.frombuffer(arr, dtype=np.uint8, count=cnt.value * ctypes.sizeof(MessiLeaf))
+    return raw.view(dt).copy()
+
+
+class Index:
+    """Owning handle of a built index."""
+
+    def __init__(self, handle, n, length, segments):
+        self.handle = handle
+        self.n, self.len, self.segments = n, length, segments
+
+    def query(self, queries, k=1, distance=MESSI_ED, window=0, stats=False):
+        return messi_query(self, queries, k, distance, window, stats=stats)
+
+    def info(self):
+        return messi_index_info(self)
+
+    def free(self):
+        messi_free(self)
+
+    def __del__(self):
+        try:
+            messi_free(self)
+        except Exception:
+            pass

@@ -1,0 +1,647 @@
+// libmessi C ABI: index build and exact k-NN queries on one gfx950 GPU.
+// Host side only orchestrates: it sizes buffers, launches the kernels of
+// build.hip and query.hip on the index's stream, and reads back the few
+// counters that decide how many split rounds or reruns are needed.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/messi.h"
+#include "build.h"
+#include "query.h"
+
+using namespace messi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+
+#define HIP_OR_THROW(x)                         \
+  do {                                          \
+    hipError_t _e = (x);                        \
+    if (_e != hipSuccess) throw HipError{_e, #x}; \
+  } while (0)
+
+struct OomError {
+  size_t bytes;
+};
+
+// Device allocation owned by a vector of frees.
+struct DevMem {
+  std::vector<void*> ptrs;
+  size_t bytes = 0;
+  template <typename T>
+  T* alloc(size_t count) {
+    void* p = nullptr;
+    const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw OomError{b};
+    }
+    ptrs.push_back(p);
+    bytes += b;
+    return static_cast<T*>(p);
+  }
+  void release(void* p) {
+    auto it = std::find(ptrs.begin(), ptrs.end(), p);
+    if (it != ptrs.end()) {
+      (void)hipFree(p);
+      ptrs.erase(it);
+    }
+  }
+  void clear() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+    bytes = 0;
+  }
+  ~DevMem() { clear(); }
+};
+
+bool is_device_ptr(const void* p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  std::memset(&a, 0, sizeof(a));
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+// --- Breakpoints: Phi^-1(k / 2^b).  Acklam's rational approximation of the
+// normal quantile, refined by two Halley steps on erfc, rounded to FP32; the
+// upper half from the lower by symmetry of N(0,1).
+double norm_quantile(double p) {
+  static const double a[] = {-3.969683028665376e+01, 2.209460984245205e+02, -2.759285104469687e+02,
+                             1.383577518672690e+02,  -3.066479806614716e+01, 2.506628277459239e+00};
+  static const double b[] = {-5.447609879822406e+01, 1.615858368580409e+02, -1.556989798598866e+02,
+                             6.680131188771972e+01,  -1.328068155288572e+01};
+  static const double c[] = {-7.784894002430293e-03, -3.223964580411365e-01, -2.400758277161838e+00,
+                             -2.549732539343734e+00, 4.374664141464968e+00,  2.938163982698783e+00};
+  static const double d[] = {7.784695709041462e-03, 3.224671290700398e-01, 2.445134137142996e+00,
+                             3.754408661907416e+00};
+  if (p > 0.5) return -norm_quantile(1.0 - p);
+  if (p == 0.5) return 0.0;
+  double x;
+  if (p < 0.02425) {
+    const double q = std::sqrt(-2.0 * std::log(p));
+    x = (((((c[0] * q + c[1]) * q + c[2]) * q + c[3]) * q + c[4]) * q + c[5]) /
+        ((((d[0] * q + d[1]) * q + d[2]) * q + d[3]) * q + 1.0);
+  } else {
+    const double q = p - 0.5, r = q * q;
+    x = (((((a[0] * r + a[1]) * r + a[2]) * r + a[3]) * r + a[4]) * r + a[5]) * q /
+        (((((b[0] * r + b[1]) * r + b[2]) * r + b[3]) * r + b[4]) * r + 1.0);
+  }
+  for (int it = 0; it < 2; ++it) {
+    const double e = 0.5 * std::erfc(-x / std::sqrt(2.0)) - p;
+    const double u = e * std::sqrt(2.0 * M_PI) * std::exp(0.5 * x * x);
+    x = x - u / (1.0 + 0.5 * x * u);
+  }
+  return x;
+}
+
+void breakpoints(int card_bits, float* beta) {
+  const int card = 1 << card_bits;
+  for (int k = 1; k < card; ++k) beta[k - 1] = (float)norm_quantile((double)k / (double)card);
+}
+
+int log2_exact(int v) {
+  int b = 0;
+  while ((1 << b) < v) ++b;
+  return (1 << b) == v ? b : -1;
+}
+
+// Per-call query buffers, grown on demand and reused.
+struct Workspace {
+  DevMem mem;
+  int nq = 0, k = 0, len = 0, w = 0, card = 0, log_cap = 0, L = 0;
+  QueryState qs{};
+  unsigned long long* cand_sorted = nullptr;
+};
+
+}  // namespace
+
+struct messi_index {
+  int64_t n = 0;
+  int len = 0, w = 0, card_bits = 0, leaf_size = 0;
+  int n_leaves = 0, n_nodes = 0;
+  int64_t max_leaf = 0;
+  hipStream_t stream = nullptr;
+  DevMem mem;
+  float* Z = nullptr;
+  uint4* words = nullptr;
+  int32_t* perm = nullptr;
+  int64_t* leaf_begin = nullptr;
+  int64_t* leaf_end = nullptr;
+  uint4* leaf_sym = nullptr;
+  uint4* leaf_bits = nullptr;
+  float* bp = nullptr;
+  NodeDev* nodes = nullptr;
+  int* root_node = nullptr;
+  Workspace ws;
+  int log_cap = 4096;
+  std::atomic<int> busy{0};
+
+  IndexDev view() const {
+    IndexDev v;
+    v.n = n;
+    v.len = len;
+    v.w = w;
+    v.m = len / w;
+    v.card_bits = card_bits;
+    v.n_leaves = n_leaves;
+    v.Z = Z;
+    v.words = words;
+    v.perm = perm;
+    v.leaf_begin = leaf_begin;
+    v.leaf_end = leaf_end;
+    v.leaf_sym = leaf_sym;
+    v.leaf_bits = leaf_bits;
+    v.bp = bp;
+    v.nodes = nodes;
+    v.root_node = root_node;
+    return v;
+  }
+};
+
+namespace {
+
+struct BusyGuard {
+  std::atomic<int>& f;
+  bool ok;
+  explicit BusyGuard(std::atomic<int>& flag) : f(flag) {
+    int z = 0;
+    ok = f.compare_exchange_strong(z, 1);
+  }
+  ~BusyGuard() {
+    if (ok) f.store(0);
+  }
+};
+
+template <typename T>
+void h2d(T* dst, const T* src, size_t count, hipStream_t st) {
+  HIP_OR_THROW(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyHostToDevice, st));
+}
+template <typename T>
+void d2h(T* dst, const T* src, size_t count, hipStream_t st) {
+  HIP_OR_THROW(hipMemcpyAsync(dst, src, count * sizeof(T), hipMemcpyDeviceToHost, st));
+  HIP_OR_THROW(hipStreamSynchronize(st));
+}
+
+void launch_check() { HIP_OR_THROW(hipGetLastError()); }
+
+// The build proper; throws HipError / OomError.  Returns false if the node
+// or leaf tables were too small (caller retries with larger ones).
+bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_cap) {
+  const int64_t n = ix->n;
+  const int len = ix->len, w = ix->w, cb = ix->card_bits, card = 1 << cb;
+  const int nkeys = 1 << w;
+  hipStream_t st = ix->stream;
+  DevMem tmp;
+
+  // breakpoints with open ends
+  std::vector<float> bph(card + 1);
+  bph[0] = -INFINITY;
+  breakpoints(cb, bph.data() + 1);
+  bph[card] = INFINITY;
+  ix->bp = ix->mem.alloc<float>(card + 1);
+  h2d(ix->bp, bph.data(), card + 1, st);
+
+  // (1) summaries
+  uint4* words_id = tmp.alloc<uint4>(n);
+  float2* musd = tmp.alloc<float2>(n);
+  unsigned int* hist = tmp.alloc<unsigned int>(nkeys);
+  HIP_OR_THROW(hipMemsetAsync(hist, 0, sizeof(unsigned int) * nkeys, st));
+  int spw = std::min(64, (16384 - 257) / len);
+  if (spw < 1) spw = 1;
+  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, st);
+  launch_check();
+
+  // (2) root grouping
+  int64_t* key_begin = tmp.alloc<int64_t>(nkeys + 1);
+  unsigned long long* key_cursor = tmp.alloc<unsigned long long>(nkeys);
+  launch_scan_hist(hist, nkeys, key_begin, key_cursor, st);
+  BuildDev d{};
+  d.W0 = tmp.alloc<uint4>(n);
+  d.W1 = tmp.alloc<uint4>(n);
+  d.I0 = tmp.alloc<int32_t>(n);
+  d.I1 = tmp.alloc<int32_t>(n);
+  launch_root_scatter(words_id, n, w, cb, key_cursor, d.W0, d.I0, st);
+  launch_check();
+
+  // node and leaf tables
+  d.nodes = ix->mem.alloc<NodeDev>(node_cap);
+  d.node_cap = node_cap;
+  d.leaves = tmp.alloc<int>(leaf_cap);
+  d.leaf_cap = leaf_cap;
+  d.root_node = ix->mem.alloc<int>(nkeys);
+  const int round_cap = (int)std::min<int64_t>(n / (ix->leaf_size + 1) + 1, (int64_t)node_cap);
+  d.cur_list = tmp.alloc<int>(round_cap);
+  d.next_list = tmp.alloc<int>(round_cap);
+  d.round_cap = round_cap;
+  int* counters = tmp.alloc<int>(8);  // node_count, leaf_count, next_count, overflow, chunk_count
+  HIP_OR_THROW(hipMemsetAsync(counters, 0, sizeof(int) * 8, st));
+  d.node_count = counters + 0;
+  d.leaf_count = counters + 1;
+  d.next_count = counters + 2;
+  d.overflow = counters + 3;
+  int* chunk_count = counters + 4;
+  d.c1 = tmp.alloc<int>((size_t)round_cap * kMaxSeg);
+  d.split_seg = tmp.alloc<int>(round_cap);
+  d.cursor = tmp.alloc<unsigned long long>((size_t)round_cap * 2);
+  const int chunk_cap = (int)std::min<int64_t>(n / kChunk + round_cap + 1, (int64_t)1 << 30);
+  Chunk* chunks = tmp.alloc<Chunk>(chunk_cap);
+
+  // the next_list of launch_roots becomes the first round's list
+  launch_roots(key_begin, nkeys, w, ix->leaf_size, d, st);
+  launch_check();
+
+  int hc[8];
+  d2h(hc, counters, 8, st);
+  if (hc[3]) return false;
+  int n_cur = hc[2];
+  // (3) split rounds
+  for (int round = 0; n_cur > 0; ++round) {
+    if (round > 16 * 8 + 8) throw HipError{hipErrorUnknown, "split rounds did not converge"};
+    std::swap(d.cur_list, d.next_list);
+    HIP_OR_THROW(hipMemsetAsync(d.next_count, 0, sizeof(int), st));
+    HIP_OR_THROW(hipMemsetAsync(d.c1, 0, sizeof(int) * (size_t)n_cur * kMaxSeg, st));
+    launch_make_chunks(d, n_cur, kChunk, chunks, chunk_cap, chunk_count, st);
+    launch_check();
+    int n_chunks = 0;
+    d2h(&n_chunks, chunk_count, 1, st);
+    if (n_chunks > chunk_cap) throw HipError{hipErrorUnknown, "chunk table overflow"};
+    launch_round_count(chunks, n_chunks, d, w, cb, st);
+    launch_round_decide(n_cur, w, cb, ix->leaf_size, d, st);
+    launch_round_scatter(chunks, n_chunks, d, cb, st);
+    launch_check();
+    d2h(hc, counters, 8, st);
+    if (hc[3]) return false;
+    n_cur = hc[2];
+  }
+  const int n_leaves = hc[1];
+  ix->n_nodes = hc[0];
+  ix->n_leaves = n_leaves;
+
+  // (4) leaf records, ids sorted inside each leaf
+  ix->leaf_begin = ix->mem.alloc<int64_t>(n_leaves);
+  ix->leaf_end = ix->mem.alloc<int64_t>(n_leaves);
+  ix->leaf_sym = ix->mem.alloc<uint4>(n_leaves);
+  ix->leaf_bits = ix->mem.alloc<uint4>(n_leaves);
+  int* leaf_buf = tmp.alloc<int>(n_leaves);
+  launch_leaf_records(d, n_leaves, ix->leaf_begin, ix->leaf_end, ix->leaf_sym, ix->leaf_bits,
+                      leaf_buf, st);
+  ix->perm = ix->mem.alloc<int32_t>(n);
+  launch_leaf_sort(n_leaves, ix->leaf_begin, ix->leaf_end, leaf_buf, d.I0, d.I1, ix->perm, st);
+  launch_check();
+  std::vector<int64_t> hb(n_leaves), he(n_leaves);
+  std::vector<int> hbuf(n_leaves);
+  d2h(hb.data(), ix->leaf_begin, n_leaves, st);
+  d2h(he.data(), ix->leaf_end, n_leaves, st);
+  d2h(hbuf.data(), leaf_buf, n_leaves, st);
+  int64_t maxl = 0;
+  int32_t* sort_scratch = nullptr;
+  for (int l = 0; l < n_leaves; ++l) {
+    const int64_t c = he[l] - hb[l];
+    maxl = std::max(maxl, c);
+    if (c > kLeafSortMax) {
+      int p2 = 1;
+      while (p2 < c) p2 <<= 1;
+      if (!sort_scratch) {
+        int64_t big = 1;
+        for (int j = 0; j < n_leaves; ++j) big = std::max<int64_t>(big, he[j] - hb[j]);
+        int64_t pb = 1;
+        while (pb < big) pb <<= 1;
+        sort_scratch = tmp.alloc<int32_t>(pb);
+      }
+      launch_leaf_sort_global(hb[l], (int)c, p2, hbuf[l] ? d.I1 : d.I0, sort_scratch, ix->perm, st);
+      launch_check();
+    }
+  }
+  ix->max_leaf = maxl;
+  // keep only what queries need
+  tmp.release(d.W0);
+  tmp.release(d.W1);
+
+  // (5) leaf-ordered words and z-normalised store
+  ix->words = ix->mem.alloc<uint4>(n);
+  ix->Z = ix->mem.alloc<float>((size_t)n * len);
+  launch_gather_store(series, n, len, ix->perm, musd, words_id, ix->Z, ix->words, st);
+  launch_check();
+  ix->nodes = d.nodes;
+  ix->root_node = d.root_node;
+  HIP_OR_THROW(hipStreamSynchronize(st));
+  return true;
+}
+
+// Grow the query workspace to hold (nq, k) with the current log capacity.
+void ensure_workspace(messi_index* ix, int nq, int k) {
+  Workspace& ws = ix->ws;
+  const int card = 1 << ix->card_bits;
+  if (ws.nq >= nq && ws.k >= k && ws.log_cap >= ix->log_cap && ws.L == ix->n_leaves &&
+      ws.len == ix->len)
+    return;
+  const int NQ = std::max(nq, ws.nq), K = std::max(k, ws.k), LC = ix->log_cap;
+  ws.mem.clear();
+  ws = Workspace{};
+  QueryState& s = ws.qs;
+  const int len = ix->len, L = ix->n_leaves;
+  s.zq = ws.mem.alloc<float>((size_t)NQ * len);
+  s.upper = ws.mem.alloc<float>((size_t)NQ * len);
+  s.lower = ws.mem.alloc<float>((size_t)NQ * len);
+  s.paa = ws.mem.alloc<float>((size_t)NQ * 3 * kMaxSeg);
+  s.table = ws.mem.alloc<float>((size_t)NQ * ix->w * card);
+  s.approx_range = ws.mem.alloc<int64_t>((size_t)NQ * 2);
+  s.approx_d2 = ws.mem.alloc<float>((size_t)NQ * kApproxCap);
+  s.slots = ws.mem.alloc<unsigned long long>((size_t)NQ * K);
+  s.log = ws.mem.alloc<unsigned long long>((size_t)NQ * LC);
+  s.log_count = ws.mem.alloc<int>(NQ);
+  s.cand = ws.mem.alloc<unsigned long long>((size_t)NQ * L);
+  s.cand_count = ws.mem.alloc<int>(NQ);
+  s.cand_thr = ws.mem.alloc<float>(NQ);
+  s.next = ws.mem.alloc<int>(NQ);
+  s.done = ws.mem.alloc<int>(NQ);
+  s.sel_done = ws.mem.alloc<int>(NQ);
+  s.stats = ws.mem.alloc<unsigned long long>((size_t)NQ * kStatCount);
+  s.status = ws.mem.alloc<int>(NQ);
+  ws.cand_sorted = ws.mem.alloc<unsigned long long>((size_t)NQ * L);
+  ws.nq = NQ;
+  ws.k = K;
+  ws.len = len;
+  ws.w = ix->w;
+  ws.card = card;
+  ws.log_cap = LC;
+  ws.L = L;
+}
+
+int run_query(messi_index* ix, const float* queries, int nq, int k, int distance, int window,
+              int64_t* out_ids, float* out_dists, messi_stats* stats) {
+  hipStream_t st = ix->stream;
+  const int len = ix->len;
+  const double u = std::ldexp(1.0, -24);
+  QueryParams p{};
+  p.nq = nq;
+  p.len = len;
+  p.w = ix->w;
+  p.m = len / ix->w;
+  p.card_bits = ix->card_bits;
+  p.k = k;
+  p.distance = distance;
+  p.window = distance == MESSI_DTW ? std::min(window, len - 1) : 0;
+  p.n_leaves = ix->n_leaves;
+  p.n = ix->n;
+  // FP32 error of a refined squared distance: at most rho relative, with
+  // rho = (4 len + 64) u covering ED's pairwise sums and DTW's paths of up
+  // to 2 len - 1 terms.
+  const double rho = (4.0 * len + 64.0) * u;
+  p.win = std::nextafter((float)((1.0 + rho) / (1.0 - rho) * (1.0 + std::ldexp(1.0, -20))), INFINITY);
+  p.lb_rel = std::nextafter((float)((1.0 + rho) * (1.0 + std::ldexp(1.0, -16))), INFINITY);
+  // PAA rounding: |PAA_fp32 - mean| <= 2 u sqrt(m len); the bound's error is
+  // at most 4 u len sqrt(m) (series side plus query side), 8x margin here.
+  p.eta = (float)(32.0 * u * len * std::sqrt((double)p.m));
+  int fin_waves = 0;
+  if (distance == MESSI_DTW) {
+    const size_t base = query_process_lds_for(p, 0);
+    fin_waves = 1;
+    for (int fw = 4; fw >= 1; --fw)
+      if (query_process_lds_for(p, fw) <= std::max<size_t>(base, 48 * 1024)) {
+        fin_waves = fw;
+        break;
+      }
+  }
+  p.fin_waves = fin_waves;
+  if (query_process_lds_for(p, fin_waves) > 64 * 1024)
+    return fail(MESSI_EINVAL, "series length %d too long for the query kernels", len);
+
+  int blocks = 1536 / std::max(1, nq);
+  blocks = std::max(4, std::min(blocks, 1536));
+  std::vector<int> status(nq);
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    ensure_workspace(ix, nq, k);
+    p.log_cap = ix->log_cap;
+    const IndexDev v = ix->view();
+    QueryState qs = ix->ws.qs;
+    launch_prep(v, queries, p, qs, st);
+    launch_approx(v, p, qs, st);
+    launch_select(v, p, qs, ix->ws.cand_sorted, st);
+    launch_process(v, p, qs, ix->ws.cand_sorted, blocks, out_ids, out_dists, st);
+    launch_check();
+    d2h(status.data(), qs.status, nq, st);
+    int worst = 0;
+    for (int s : status) worst |= s;
+    if (!(worst & 1)) {
+      if (stats) {
+        std::vector<unsigned long long> sv((size_t)nq * kStatCount);
+        d2h(sv.data(), qs.stats, sv.size(), st);
+        stats->queries += nq;
+        stats->leaves_total += (int64_t)nq * ix->n_leaves;
+        for (int q = 0; q < nq; ++q) {
+          const unsigned long long* r = &sv[(size_t)q * kStatCount];
+          stats->leaves_kept += (int64_t)r[kStatLeavesKept];
+          stats->series_lb += (int64_t)r[kStatSeriesLb];
+          stats->lb_keogh += (int64_t)r[kStatLbKeogh];
+          stats->refined += (int64_t)r[kStatRefined];
+          stats->rechecked_fp64 += (int64_t)r[kStatRecheck];
+        }
+      }
+      return MESSI_OK;
+    }
+    if (stats) stats->log_overflows += 1;
+    ix->log_cap *= 4;  // near-tie log overflowed: rerun with a larger one
+  }
+  return fail(MESSI_ENOMEM, "near-tie log kept overflowing");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* messi_last_error(void) { return g_err.c_str(); }
+
+int messi_breakpoints(int32_t card_bits, float* beta) {
+  if (card_bits < 1 || card_bits > 8 || !beta) return fail(MESSI_EINVAL, "card_bits must be 1..8");
+  breakpoints(card_bits, beta);
+  return MESSI_OK;
+}
+
+int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
+                int32_t cardinality, int32_t leaf_size, messi_index** out) {
+  g_err.clear();
+  if (!out) return fail(MESSI_EINVAL, "out is NULL");
+  if (n < 1 || n >= ((int64_t)1 << 31) - 1) return fail(MESSI_EINVAL, "n must be in [1, 2^31-2]");
+  if (segments < 1 || segments > kMaxSeg) return fail(MESSI_EINVAL, "segments must be in [1, 16]");
+  if (len < 1 || len > kMaxLen || len % segments)
+    return fail(MESSI_EINVAL, "len must be in [1, %d] and a multiple of segments", kMaxLen);
+  const int cb = log2_exact(cardinality);
+  if (cb < 1 || cb > 8) return fail(MESSI_EINVAL, "cardinality must be a power of two in [2, 256]");
+  if (leaf_size < 1) return fail(MESSI_EINVAL, "leaf_size must be >= 1");
+  if (!is_device_ptr(series)) return fail(MESSI_EINVAL, "series is not a device pointer");
+
+  messi_index* ix = new messi_index();
+  ix->n = n;
+  ix->len = len;
+  ix->w = segments;
+  ix->card_bits = cb;
+  ix->leaf_size = leaf_size;
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  const size_t need = (size_t)n * len * 4 + (size_t)n * (16 * 4 + 8 * 2 + 8 + 4 * 3);
+  if (need > free_b) {
+    delete ix;
+    return fail(MESSI_ENOMEM, "index needs about %zu bytes, %zu free", need, free_b);
+  }
+  int node_cap = (int)std::min<int64_t>(8 * (n / leaf_size) + 2 * ((int64_t)1 << segments) + 4096,
+                                        (int64_t)1 << 30);
+  int leaf_cap = (int)std::min<int64_t>(4 * (n / leaf_size) + ((int64_t)1 << segments) + 4096,
+                                        (int64_t)1 << 30);
+  try {
+    for (int attempt = 0;; ++attempt) {
+      if (build_index(ix, series, node_cap, leaf_cap)) break;
+      ix->mem.clear();
+      if (attempt >= 6) {
+        delete ix;
+        return fail(MESSI_ENOMEM, "node table kept overflowing");
+      }
+      node_cap = (int)std::min<int64_t>((int64_t)node_cap * 4, (int64_t)1 << 30);
+      leaf_cap = (int)std::min<int64_t>((int64_t)leaf_cap * 4, (int64_t)1 << 30);
+    }
+  } catch (const OomError& e) {
+    delete ix;
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    delete ix;
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  *out = ix;
+  return MESSI_OK;
+}
+
+int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int32_t k,
+                      int32_t distance, int32_t window, int64_t* out_ids, float* out_dists,
+                      messi_stats* stats) {
+  g_err.clear();
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
+  if (nq == 0) return MESSI_OK;
+  if (k < 1 || k > 1024) return fail(MESSI_EINVAL, "k must be in [1, 1024]");
+  if (distance != MESSI_ED && distance != MESSI_DTW) return fail(MESSI_EINVAL, "unknown distance");
+  if (window < 0) return fail(MESSI_EINVAL, "window must be >= 0");
+  if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
+    return fail(MESSI_EINVAL, "queries and outputs must be device pointers");
+  BusyGuard g(index->busy);
+  if (!g.ok) return fail(MESSI_EBUSY, "index is in use by another call");
+  try {
+    return run_query(index, queries, nq, k, distance, window, out_ids, out_dists, stats);
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+}
+
+int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t distance,
+                int32_t window, int64_t* out_ids, float* out_dists) {
+  return messi_query_stats(index, queries, nq, k, distance, window, out_ids, out_dists, nullptr);
+}
+
+int messi_set_stream(messi_index* index, void* hip_stream) {
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  index->stream = (hipStream_t)hip_stream;
+  return MESSI_OK;
+}
+
+int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t* segments,
+                     int32_t* card_bits, int64_t* n_leaves, int64_t* device_bytes) {
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (n) *n = index->n;
+  if (len) *len = index->len;
+  if (segments) *segments = index->w;
+  if (card_bits) *card_bits = index->card_bits;
+  if (n_leaves) *n_leaves = index->n_leaves;
+  if (device_bytes) *device_bytes = (int64_t)(index->mem.bytes + index->ws.mem.bytes);
+  return MESSI_OK;
+}
+
+int messi_get_perm(const messi_index* index, int32_t* perm) {
+  if (!index || !perm) return fail(MESSI_EINVAL, "NULL argument");
+  try {
+    d2h(perm, index->perm, (size_t)index->n, index->stream);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  return MESSI_OK;
+}
+
+int messi_get_words(const messi_index* index, uint8_t* words) {
+  if (!index || !words) return fail(MESSI_EINVAL, "NULL argument");
+  try {
+    std::vector<uint4> ws((size_t)index->n);
+    std::vector<int32_t> pm((size_t)index->n);
+    d2h(ws.data(), index->words, (size_t)index->n, index->stream);
+    d2h(pm.data(), index->perm, (size_t)index->n, index->stream);
+    for (int64_t p = 0; p < index->n; ++p) {
+      const uint8_t* b = reinterpret_cast<const uint8_t*>(&ws[(size_t)p]);
+      std::memcpy(words + (int64_t)pm[(size_t)p] * index->w, b, (size_t)index->w);
+    }
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  return MESSI_OK;
+}
+
+int messi_get_leaves(const messi_index* index, messi_leaf* leaves, int64_t cap, int64_t* count) {
+  if (!index || !count) return fail(MESSI_EINVAL, "NULL argument");
+  *count = index->n_leaves;
+  if (cap < index->n_leaves || !leaves) return fail(MESSI_EINVAL, "leaf buffer too small");
+  try {
+    const int L = index->n_leaves;
+    std::vector<int64_t> b(L), e(L);
+    std::vector<uint4> sy(L), bi(L);
+    d2h(b.data(), index->leaf_begin, L, index->stream);
+    d2h(e.data(), index->leaf_end, L, index->stream);
+    d2h(sy.data(), index->leaf_sym, L, index->stream);
+    d2h(bi.data(), index->leaf_bits, L, index->stream);
+    std::vector<int> order(L);
+    for (int l = 0; l < L; ++l) order[l] = l;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return b[x] < b[y]; });
+    for (int i = 0; i < L; ++i) {
+      const int l = order[i];
+      messi_leaf& o = leaves[i];
+      o.begin = b[l];
+      o.end = e[l];
+      std::memcpy(o.sym, &sy[l], 16);
+      std::memcpy(o.bits, &bi[l], 16);
+    }
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  return MESSI_OK;
+}
+
+void messi_free(messi_index* index) { delete index; }
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Build-side device structures and kernel launchers of libmessi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace messi {
+
+constexpr int kLeafSortMax = 4096;  // leaves up to this size are sorted in LDS
+constexpr int kChunk = 4096;        // entries per work chunk of a split round
+
+// A node of the index tree (root subtree node, inner node or leaf).
+struct NodeDev {
+  int64_t begin, end;       // range of entries (in buffer `buf`)
+  uint8_t sym[kMaxSeg];     // symbol prefix per segment
+  uint8_t bits[kMaxSeg];    // prefix length per segment
+  int32_t buf;              // which ping-pong buffer holds the range
+  int32_t seg;              // split segment (-1: not split)
+  int32_t child[2];         // children node ids (-1: empty)
+  int32_t leaf;             // leaf index (-1: not a leaf)
+  int32_t pad;
+};
+
+struct Chunk {
+  int32_t slot;  // index into the round's node list
+  int32_t pad;
+  int64_t begin, end;
+};
+
+// Device pointers shared by the build kernels.
+struct BuildDev {
+  NodeDev* nodes;
+  int* node_count;
+  int node_cap;
+  int* leaves;       // leaf index -> node id
+  int* leaf_count;
+  int leaf_cap;
+  int* root_node;    // root key -> node id (-1: empty)
+  int* cur_list;     // node ids of this round
+  int* next_list;    // node ids of the next round
+  int* next_count;
+  int round_cap;     // capacity of the round lists
+  int* c1;           // [round slot][16] ones per segment
+  int* split_seg;    // [round slot]
+  unsigned long long* cursor;  // [round slot][2]
+  int* overflow;
+  uint4* W0;
+  uint4* W1;
+  int32_t* I0;
+  int32_t* I1;
+};
+
+void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
+                      const float* bp, uint4* words, float2* musd, unsigned int* hist,
+                      hipStream_t st);
+void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
+                      unsigned long long* cursor, hipStream_t st);
+void launch_root_scatter(const uint4* words, int64_t n, int w, int card_bits,
+                         unsigned long long* cursor, uint4* W0, int32_t* I0, hipStream_t st);
+void launch_roots(const int64_t* begin, int nkeys, int w, int leaf_size, const BuildDev& d,
+                  hipStream_t st);
+void launch_round_count(const Chunk* chunks, int n_chunks, const BuildDev& d, int w,
+                        int card_bits, hipStream_t st);
+void launch_round_decide(int n_cur, int w, int card_bits, int leaf_size, const BuildDev& d,
+                         hipStream_t st);
+void launch_round_scatter(const Chunk* chunks, int n_chunks, const BuildDev& d, int card_bits,
+                          hipStream_t st);
+void launch_make_chunks(const BuildDev& d, int n_cur, int chunk, Chunk* out, int cap,
+                        int* out_count, hipStream_t st);
+void launch_leaf_records(const BuildDev& d, int n_leaves, int64_t* leaf_begin, int64_t* leaf_end,
+                         uint4* leaf_sym, uint4* leaf_bits, int* leaf_buf, hipStream_t st);
+void launch_leaf_sort(int n_leaves, const int64_t* leaf_begin, const int64_t* leaf_end,
+                      const int* leaf_buf, const int32_t* I0, const int32_t* I1, int32_t* perm,
+                      hipStream_t st);
+void launch_leaf_sort_global(int64_t b, int cnt, int p2, const int32_t* I, int32_t* scratch,
+                             int32_t* perm, hipStream_t st);
+void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* perm,
+                         const float2* musd, const uint4* words, float* Z, uint4* words_sorted,
+                         hipStream_t st);
+
+}  // namespace messi

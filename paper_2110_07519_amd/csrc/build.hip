@@ -1,0 +1,581 @@
+// Index build kernels (Section 3.2 of the paper: iSAX summaries of every
+// series, then the leaves of the root subtrees).
+//
+// GPU layout instead of the paper's per-thread iSAX buffers and pointer
+// tree: (1) one pass summarises every series into a packed 16-byte word and
+// counts its root key; (2) a counting scatter groups entries by root key;
+// (3) rounds of segmented two-way partitions split every over-full node on
+// its most balanced segment; (4) each leaf's ids are sorted so leaves are
+// contiguous, ascending-id ranges; (5) the z-normalised store and the words
+// are gathered into that leaf order.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "build.h"
+#include "common.h"
+
+namespace messi {
+
+// ---------------------------------------------------------------------------
+// (1) Summaries.  One lane per series: z-normalisation, PAA and symbols are
+// sequential FP32 sums in index order (the fixed order the words are defined
+// by), so the series sits in LDS, staged with one coalesced read of the
+// block's contiguous rows.  Element t of row l is stored at column
+// (t + l) mod len, so at any t the 64 lanes hit 64 distinct banks.
+
+__global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ raw, int64_t n, int len,
+                                                      int w, int card_bits, int spw,
+                                                      const float* __restrict__ bp_g,
+                                                      uint4* __restrict__ words,
+                                                      float2* __restrict__ musd,
+                                                      unsigned int* __restrict__ hist) {
+  extern __shared__ float smem[];
+  float* bp = smem;               // card + 1 entries (bp[0] = -inf, bp[card] = +inf)
+  float* tile = smem + 257;       // spw rows of len floats, rotated
+  const int card = 1 << card_bits;
+  const int lane = threadIdx.x;
+  for (int j = lane; j <= card; j += kWave) bp[j] = bp_g[j];
+
+  const int64_t first = (int64_t)blockIdx.x * spw;
+  const int rows = (int)((n - first) < spw ? (n - first) : spw);
+  const float* src = raw + first * (int64_t)len;
+  const int total = rows * len;
+  for (int e = lane; e < total; e += kWave) {
+    const int r = e / len;
+    const int t = e - r * len;
+    tile[r * len + (t + r) % len] = src[e];
+  }
+  __syncthreads();
+  if (lane >= rows) return;
+
+  const float* row = tile + lane * len;
+  const int rot = lane % len;
+  auto at = [&](int t) {
+    int c = t + rot;
+    c = c >= len ? c - len : c;
+    return row[c];
+  };
+  float s = 0.0f;
+  for (int t = 0; t < len; ++t) s = s + at(t);
+  const float flen = (float)len;
+  const float mu = __fdiv_rn(s, flen);
+  float v = 0.0f;
+  for (int t = 0; t < len; ++t) {
+    const float d = at(t) - mu;
+    v = v + d * d;
+  }
+  const float sd = __fsqrt_rn(__fdiv_rn(v, flen));
+  const bool flat = !(sd > 0.0f);
+  const int m = len / w;
+  const float fm = (float)m;
+  uint32_t packed[4] = {0u, 0u, 0u, 0u};
+  uint32_t key = 0;
+  for (int sg = 0; sg < w; ++sg) {
+    float a = 0.0f;
+    if (!flat) {
+      for (int t = sg * m; t < sg * m + m; ++t) a = a + __fdiv_rn(at(t) - mu, sd);
+    }
+    const float p = __fdiv_rn(a, fm);
+    const uint32_t sym = (uint32_t)symbol_of(p, bp, card);
+    packed[sg >> 2] |= sym << (8 * (sg & 3));
+    key = (key << 1) | (sym >> (card_bits - 1));
+  }
+  const int64_t id = first + lane;
+  words[id] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+  musd[id] = make_float2(mu, flat ? 0.0f : sd);
+  atomicAdd(&hist[key], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// (2) Root grouping: exclusive scan of the key histogram (one block), then a
+// scatter of (word, id) into the key's range.  Order inside a range is the
+// atomics' order; leaves are re-sorted by id at the end.
+
+__global__ __launch_bounds__(1024) void k_scan_hist(const unsigned int* __restrict__ hist, int nkeys,
+                                                     int64_t* __restrict__ begin,
+                                                     unsigned long long* __restrict__ cursor) {
+  __shared__ int64_t part[1024];
+  const int per = (nkeys + 1023) / 1024;
+  const int a = threadIdx.x * per;
+  const int b = min(a + per, nkeys);
+  int64_t s = 0;
+  for (int i = a; i < b; ++i) s += hist[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int64_t v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - s;
+  for (int i = a; i < b; ++i) {
+    begin[i] = run;
+    cursor[i] = (unsigned long long)run;
+    run += hist[i];
+  }
+  if (threadIdx.x == 1023) begin[nkeys] = part[1023];
+}
+
+__global__ void k_root_scatter(const uint4* __restrict__ words, int64_t n, int w, int card_bits,
+                               unsigned long long* __restrict__ cursor, uint4* __restrict__ W0,
+                               int32_t* __restrict__ I0) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint4 wd = words[i];
+  const uint32_t part[4] = {wd.x, wd.y, wd.z, wd.w};
+  uint32_t key = 0;
+  for (int s = 0; s < w; ++s) {
+    const uint32_t sym = (part[s >> 2] >> (8 * (s & 3))) & 0xffu;
+    key = (key << 1) | (sym >> (card_bits - 1));
+  }
+  const unsigned long long pos = atomicAdd(&cursor[key], 1ull);
+  W0[pos] = wd;
+  I0[pos] = (int32_t)i;
+}
+
+__device__ __forceinline__ int append(int* counter, int cap, int* overflow) {
+  const int i = atomicAdd(counter, 1);
+  if (i >= cap) {
+    atomicOr(overflow, 1);
+    return -1;
+  }
+  return i;
+}
+
+// A node over leaf_size goes to the round list, others become leaves.
+__device__ void place_node(int id, int64_t count, int leaf_size, BuildDev d) {
+  if (count > leaf_size) {
+    const int slot = append(d.next_count, d.round_cap, d.overflow);
+    if (slot >= 0) d.next_list[slot] = id;
+  } else {
+    const int leaf = append(d.leaf_count, d.leaf_cap, d.overflow);
+    if (leaf >= 0) {
+      d.leaves[leaf] = id;
+      d.nodes[id].leaf = leaf;
+    }
+  }
+}
+
+__global__ void k_roots(const int64_t* __restrict__ begin, int nkeys, int w, int leaf_size,
+                        BuildDev d) {
+  const int key = blockIdx.x * blockDim.x + threadIdx.x;
+  if (key >= nkeys) return;
+  const int64_t b = begin[key], e = begin[key + 1];
+  if (e == b) {
+    d.root_node[key] = -1;
+    return;
+  }
+  const int id = append(d.node_count, d.node_cap, d.overflow);
+  if (id < 0) return;
+  NodeDev nd;
+  nd.begin = b;
+  nd.end = e;
+  for (int s = 0; s < kMaxSeg; ++s) {
+    nd.sym[s] = s < w ? (uint8_t)((key >> (w - 1 - s)) & 1) : 0;
+    nd.bits[s] = s < w ? 1 : 0;
+  }
+  nd.buf = 0;
+  nd.seg = -1;
+  nd.child[0] = nd.child[1] = -1;
+  nd.leaf = -1;
+  d.nodes[id] = nd;
+  d.root_node[key] = id;
+  place_node(id, e - b, leaf_size, d);
+}
+
+// ---------------------------------------------------------------------------
+// (3) Split rounds.  Work is cut into chunks of one node each.
+
+__device__ __forceinline__ uint32_t word_byte(const uint4& wd, int s) {
+  const uint32_t v = s < 4 ? wd.x : (s < 8 ? wd.y : (s < 12 ? wd.z : wd.w));
+  return (v >> (8 * (s & 3))) & 0xffu;
+}
+
+__global__ __launch_bounds__(256) void k_round_count(const Chunk* __restrict__ chunks, BuildDev d,
+                                                      int w, int card_bits) {
+  const Chunk ch = chunks[blockIdx.x];
+  const int id = d.cur_list[ch.slot];
+  const NodeDev& nd = d.nodes[id];
+  const uint4* __restrict__ W = nd.buf ? d.W1 : d.W0;
+  int bits[kMaxSeg];
+  for (int s = 0; s < kMaxSeg; ++s) bits[s] = nd.bits[s];
+  int c[kMaxSeg];
+  for (int s = 0; s < kMaxSeg; ++s) c[s] = 0;
+  for (int64_t e = ch.begin + threadIdx.x; e < ch.end; e += 256) {
+    const uint4 wd = W[e];
+    for (int s = 0; s < kMaxSeg; ++s) {
+      if (s < w && bits[s] < card_bits) c[s] += (int)((word_byte(wd, s) >> (card_bits - 1 - bits[s])) & 1u);
+    }
+  }
+  __shared__ int acc[kMaxSeg];
+  if (threadIdx.x < kMaxSeg) acc[threadIdx.x] = 0;
+  __syncthreads();
+  for (int s = 0; s < kMaxSeg; ++s) {
+    int v = c[s];
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&acc[s], v);
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxSeg && acc[threadIdx.x])
+    atomicAdd(&d.c1[(int64_t)ch.slot * kMaxSeg + threadIdx.x], acc[threadIdx.x]);
+}
+
+// Most balanced split: the segment minimising |2 c1 - count| among those
+// with a bit left, lowest segment on ties (Section 2.2).
+__global__ void k_round_decide(int n_cur, int w, int card_bits, int leaf_size, BuildDev d) {
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  if (slot >= n_cur) return;
+  const int id = d.cur_list[slot];
+  NodeDev nd = d.nodes[id];
+  const int64_t count = nd.end - nd.begin;
+  int best = -1;
+  int64_t gap = 0;
+  for (int s = 0; s < w; ++s) {
+    if (nd.bits[s] >= card_bits) continue;
+    const int64_t c1 = d.c1[(int64_t)slot * kMaxSeg + s];
+    int64_t g = 2 * c1 - count;
+    g = g < 0 ? -g : g;
+    if (best < 0 || g < gap) {
+      best = s;
+      gap = g;
+    }
+  }
+  d.split_seg[slot] = best;
+  if (best < 0) {  // nothing left to refine: an over-full leaf
+    const int leaf = append(d.leaf_count, d.leaf_cap, d.overflow);
+    if (leaf >= 0) {
+      d.leaves[leaf] = id;
+      d.nodes[id].leaf = leaf;
+    }
+    return;
+  }
+  const int64_t n1 = d.c1[(int64_t)slot * kMaxSeg + best];
+  const int64_t n0 = count - n1;
+  d.cursor[2 * slot + 0] = (unsigned long long)nd.begin;
+  d.cursor[2 * slot + 1] = (unsigned long long)(nd.begin + n0);
+  int kids[2] = {-1, -1};
+  for (int b = 0; b < 2; ++b) {
+    const int64_t cb = b ? nd.begin + n0 : nd.begin;
+    const int64_t ce = b ? nd.end : nd.begin + n0;
+    if (ce == cb) continue;
+    const int cid = append(d.node_count, d.node_cap, d.overflow);
+    if (cid < 0) continue;
+    NodeDev ch = nd;
+    ch.begin = cb;
+    ch.end = ce;
+    ch.sym[best] = (uint8_t)((nd.sym[best] << 1) | b);
+    ch.bits[best] = (uint8_t)(nd.bits[best] + 1);
+    ch.buf = nd.buf ^ 1;
+    ch.seg = -1;
+    ch.child[0] = ch.child[1] = -1;
+    ch.leaf = -1;
+    d.nodes[cid] = ch;
+    kids[b] = cid;
+    place_node(cid, ce - cb, leaf_size, d);
+  }
+  d.nodes[id].seg = best;
+  d.nodes[id].child[0] = kids[0];
+  d.nodes[id].child[1] = kids[1];
+}
+
+// Two-way scatter into the other buffer; ranks inside a 256-entry tile by
+// ballot + prefix over the block's waves, tile bases by one atomic per side.
+__global__ __launch_bounds__(256) void k_round_scatter(const Chunk* __restrict__ chunks, BuildDev d,
+                                                        int card_bits) {
+  const Chunk ch = chunks[blockIdx.x];
+  const int seg = d.split_seg[ch.slot];
+  if (seg < 0) return;
+  const int id = d.cur_list[ch.slot];
+  const NodeDev& nd = d.nodes[id];
+  const uint4* __restrict__ Win = nd.buf ? d.W1 : d.W0;
+  const int32_t* __restrict__ Iin = nd.buf ? d.I1 : d.I0;
+  uint4* __restrict__ Wout = nd.buf ? d.W0 : d.W1;
+  int32_t* __restrict__ Iout = nd.buf ? d.I0 : d.I1;
+  const int shift = card_bits - 1 - nd.bits[seg];
+  __shared__ int wave_ones[4];
+  __shared__ int wave_vals[4];
+  __shared__ unsigned long long base[2];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x >> 6;
+  for (int64_t t0 = ch.begin; t0 < ch.end; t0 += 256) {
+    const int64_t e = t0 + threadIdx.x;
+    const bool valid = e < ch.end;
+    uint4 wd = make_uint4(0, 0, 0, 0);
+    int32_t idv = 0;
+    int bit = 0;
+    if (valid) {
+      wd = Win[e];
+      idv = Iin[e];
+      bit = (int)((word_byte(wd, seg) >> shift) & 1u);
+    }
+    const unsigned long long ones = __ballot(valid && bit);
+    const unsigned long long vals = __ballot(valid);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    const int ones_before = __popcll(ones & below);
+    const int zeros_before = __popcll(vals & ~ones & below);
+    if (lane == 0) {
+      wave_ones[wv] = __popcll(ones);
+      wave_vals[wv] = __popcll(vals);
+    }
+    __syncthreads();
+    int o_off = 0, z_off = 0, o_tot = 0, z_tot = 0;
+    for (int j = 0; j < 4; ++j) {
+      const int oj = wave_ones[j], zj = wave_vals[j] - wave_ones[j];
+      if (j < wv) {
+        o_off += oj;
+        z_off += zj;
+      }
+      o_tot += oj;
+      z_tot += zj;
+    }
+    if (threadIdx.x == 0) {
+      base[0] = z_tot ? atomicAdd(&d.cursor[2 * ch.slot + 0], (unsigned long long)z_tot) : 0ull;
+      base[1] = o_tot ? atomicAdd(&d.cursor[2 * ch.slot + 1], (unsigned long long)o_tot) : 0ull;
+    }
+    __syncthreads();
+    if (valid) {
+      const int64_t dst = bit ? (int64_t)base[1] + o_off + ones_before : (int64_t)base[0] + z_off + zeros_before;
+      Wout[dst] = wd;
+      Iout[dst] = idv;
+    }
+    __syncthreads();
+  }
+}
+
+// Chunk list of the next round (one block): exclusive scan of chunk counts.
+__global__ __launch_bounds__(1024) void k_make_chunks(BuildDev d, int n_cur, int chunk,
+                                                       Chunk* __restrict__ out, int cap,
+                                                       int* __restrict__ out_count) {
+  __shared__ int part[1024];
+  const int per = (n_cur + 1023) / 1024;
+  const int a = threadIdx.x * per;
+  const int b = min(a + per, n_cur);
+  int s = 0;
+  for (int i = a; i < b; ++i) {
+    const NodeDev& nd = d.nodes[d.cur_list[i]];
+    s += (int)((nd.end - nd.begin + chunk - 1) / chunk);
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    int v = threadIdx.x >= o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - s;
+  for (int i = a; i < b; ++i) {
+    const NodeDev& nd = d.nodes[d.cur_list[i]];
+    for (int64_t e = nd.begin; e < nd.end; e += chunk) {
+      if (run < cap) {
+        Chunk c;
+        c.slot = i;
+        c.pad = 0;
+        c.begin = e;
+        c.end = e + chunk < nd.end ? e + chunk : nd.end;
+        out[run] = c;
+      }
+      ++run;
+    }
+  }
+  if (threadIdx.x == 1023) *out_count = part[1023];
+}
+
+// ---------------------------------------------------------------------------
+// (4) Leaf records and id order inside each leaf.
+
+__global__ void k_leaf_records(BuildDev d, int n_leaves, int64_t* __restrict__ leaf_begin,
+                               int64_t* __restrict__ leaf_end, uint4* __restrict__ leaf_sym,
+                               uint4* __restrict__ leaf_bits, int* __restrict__ leaf_buf) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= n_leaves) return;
+  const NodeDev& nd = d.nodes[d.leaves[l]];
+  leaf_begin[l] = nd.begin;
+  leaf_end[l] = nd.end;
+  uint32_t s[4] = {0, 0, 0, 0}, b[4] = {0, 0, 0, 0};
+  for (int j = 0; j < kMaxSeg; ++j) {
+    s[j >> 2] |= (uint32_t)nd.sym[j] << (8 * (j & 3));
+    b[j >> 2] |= (uint32_t)nd.bits[j] << (8 * (j & 3));
+  }
+  leaf_sym[l] = make_uint4(s[0], s[1], s[2], s[3]);
+  leaf_bits[l] = make_uint4(b[0], b[1], b[2], b[3]);
+  leaf_buf[l] = nd.buf;
+}
+
+// Bitonic sort of one leaf's ids in LDS (size up to kLeafSortMax).
+__global__ __launch_bounds__(1024) void k_leaf_sort(const int64_t* __restrict__ leaf_begin,
+                                                     const int64_t* __restrict__ leaf_end,
+                                                     const int* __restrict__ leaf_buf,
+                                                     const int32_t* __restrict__ I0,
+                                                     const int32_t* __restrict__ I1,
+                                                     int32_t* __restrict__ perm) {
+  __shared__ int32_t v[kLeafSortMax];
+  const int l = blockIdx.x;
+  const int64_t b = leaf_begin[l], e = leaf_end[l];
+  const int cnt = (int)(e - b);
+  if (cnt > kLeafSortMax) return;  // sorted by k_leaf_sort_global
+  const int32_t* __restrict__ I = leaf_buf[l] ? I1 : I0;
+  int p2 = 1;
+  while (p2 < cnt) p2 <<= 1;
+  for (int i = threadIdx.x; i < p2; i += blockDim.x) v[i] = i < cnt ? I[b + i] : 0x7fffffff;
+  __syncthreads();
+  for (int size = 2; size <= p2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (p2 >> 1); i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int32_t a = v[lo], c = v[hi];
+        if ((a > c) == up) {
+          v[lo] = c;
+          v[hi] = a;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) perm[b + i] = v[i];
+}
+
+// Larger (over-full) leaves: the same network over a global scratch area.
+__global__ __launch_bounds__(1024) void k_leaf_sort_global(int64_t b, int cnt, int p2,
+                                                            const int32_t* __restrict__ I,
+                                                            int32_t* __restrict__ scratch,
+                                                            int32_t* __restrict__ perm) {
+  for (int i = threadIdx.x; i < p2; i += blockDim.x) scratch[i] = i < cnt ? I[b + i] : 0x7fffffff;
+  __syncthreads();
+  for (int size = 2; size <= p2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < (p2 >> 1); i += blockDim.x) {
+        const int lo = 2 * i - (i & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = (lo & size) == 0;
+        const int32_t a = scratch[lo], c = scratch[hi];
+        if ((a > c) == up) {
+          scratch[lo] = c;
+          scratch[hi] = a;
+        }
+      }
+      __threadfence();
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < cnt; i += blockDim.x) perm[b + i] = scratch[i];
+}
+
+// ---------------------------------------------------------------------------
+// (5) Leaf-ordered store: z = (x - mu) / sd per point (the same rounding as
+// in the summary pass), one wave per row, float4 per lane.
+
+__global__ __launch_bounds__(256) void k_gather_store(const float* __restrict__ raw, int64_t n, int len,
+                                                       const int32_t* __restrict__ perm,
+                                                       const float2* __restrict__ musd,
+                                                       const uint4* __restrict__ words,
+                                                       float* __restrict__ Z,
+                                                       uint4* __restrict__ words_sorted) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t p = wave; p < n; p += nwaves) {
+    const int32_t id = perm[p];
+    const float2 ms = musd[id];
+    const float* __restrict__ x = raw + (int64_t)id * len;
+    float* __restrict__ z = Z + p * (int64_t)len;
+    const bool flat = !(ms.y > 0.0f);
+    if ((len & 3) == 0) {
+      for (int t = 4 * lane; t < len; t += 4 * kWave) {
+        const float4 v = *reinterpret_cast<const float4*>(x + t);
+        float4 o;
+        o.x = flat ? 0.0f : __fdiv_rn(v.x - ms.x, ms.y);
+        o.y = flat ? 0.0f : __fdiv_rn(v.y - ms.x, ms.y);
+        o.z = flat ? 0.0f : __fdiv_rn(v.z - ms.x, ms.y);
+        o.w = flat ? 0.0f : __fdiv_rn(v.w - ms.x, ms.y);
+        *reinterpret_cast<float4*>(z + t) = o;
+      }
+    } else {
+      for (int t = lane; t < len; t += kWave) z[t] = flat ? 0.0f : __fdiv_rn(x[t] - ms.x, ms.y);
+    }
+    if (lane == 0) words_sorted[p] = words[id];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers.
+
+void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
+                      const float* bp, uint4* words, float2* musd, unsigned int* hist,
+                      hipStream_t st) {
+  const int64_t blocks = (n + spw - 1) / spw;
+  const size_t lds = (257 + (size_t)spw * len) * sizeof(float);
+  hipLaunchKernelGGL(k_summarize, dim3((unsigned)blocks), dim3(kWave), lds, st, raw, n, len, w,
+                     card_bits, spw, bp, words, musd, hist);
+}
+
+void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
+                      unsigned long long* cursor, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, st, hist, nkeys, begin, cursor);
+}
+
+void launch_root_scatter(const uint4* words, int64_t n, int w, int card_bits,
+                         unsigned long long* cursor, uint4* W0, int32_t* I0, hipStream_t st) {
+  hipLaunchKernelGGL(k_root_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, words, n,
+                     w, card_bits, cursor, W0, I0);
+}
+
+void launch_roots(const int64_t* begin, int nkeys, int w, int leaf_size, const BuildDev& d,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_roots, dim3((nkeys + 255) / 256), dim3(256), 0, st, begin, nkeys, w,
+                     leaf_size, d);
+}
+
+void launch_round_count(const Chunk* chunks, int n_chunks, const BuildDev& d, int w,
+                        int card_bits, hipStream_t st) {
+  hipLaunchKernelGGL(k_round_count, dim3(n_chunks), dim3(256), 0, st, chunks, d, w, card_bits);
+}
+
+void launch_round_decide(int n_cur, int w, int card_bits, int leaf_size, const BuildDev& d,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(k_round_decide, dim3((n_cur + 255) / 256), dim3(256), 0, st, n_cur, w,
+                     card_bits, leaf_size, d);
+}
+
+void launch_round_scatter(const Chunk* chunks, int n_chunks, const BuildDev& d, int card_bits,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_round_scatter, dim3(n_chunks), dim3(256), 0, st, chunks, d, card_bits);
+}
+
+void launch_make_chunks(const BuildDev& d, int n_cur, int chunk, Chunk* out, int cap,
+                        int* out_count, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_chunks, dim3(1), dim3(1024), 0, st, d, n_cur, chunk, out, cap,
+                     out_count);
+}
+
+void launch_leaf_records(const BuildDev& d, int n_leaves, int64_t* leaf_begin, int64_t* leaf_end,
+                         uint4* leaf_sym, uint4* leaf_bits, int* leaf_buf, hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_records, dim3((n_leaves + 255) / 256), dim3(256), 0, st, d, n_leaves,
+                     leaf_begin, leaf_end, leaf_sym, leaf_bits, leaf_buf);
+}
+
+void launch_leaf_sort(int n_leaves, const int64_t* leaf_begin, const int64_t* leaf_end,
+                      const int* leaf_buf, const int32_t* I0, const int32_t* I1, int32_t* perm,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_sort, dim3(n_leaves), dim3(1024), 0, st, leaf_begin, leaf_end,
+                     leaf_buf, I0, I1, perm);
+}
+
+void launch_leaf_sort_global(int64_t b, int cnt, int p2, const int32_t* I, int32_t* scratch,
+                             int32_t* perm, hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_sort_global, dim3(1), dim3(1024), 0, st, b, cnt, p2, I, scratch, perm);
+}
+
+void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* perm,
+                         const float2* musd, const uint4* words, float* Z, uint4* words_sorted,
+                         hipStream_t st) {
+  int64_t blocks = (n + 3) / 4;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_gather_store, dim3((unsigned)blocks), dim3(256), 0, st, raw, n, len, perm,
+                     musd, words, Z, words_sorted);
+}
+
+}  // namespace messi

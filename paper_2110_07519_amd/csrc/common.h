@@ -1,0 +1,119 @@
+// Shared device-side definitions of libmessi (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace messi {
+
+constexpr int kMaxSeg = 16;       // PAA segments per word (one byte each)
+constexpr int kMaxLen = 4096;     // longest series accepted
+constexpr int kWave = 64;         // CDNA wavefront width
+constexpr int kBuckets = 1024;    // LB buckets used to order candidate leaves
+constexpr int kApproxCap = 8192;  // most series refined by the approximate search
+constexpr int kTopCap = 2048;     // k best + near-tie candidates rechecked per FP64 pass
+
+// Packed (squared distance, id) key: positive FP32 bit patterns order like
+// the values, so one 64-bit integer min gives the lexicographic (d2, id)
+// min.  The empty slot is (+inf, 0xffffffff).
+constexpr unsigned long long kEmptyKey = (0x7f800000ull << 32) | 0xffffffffull;
+
+__device__ __forceinline__ unsigned long long pack_key(float d2, uint32_t id) {
+  return ((unsigned long long)__float_as_uint(d2) << 32) | (unsigned long long)id;
+}
+__device__ __forceinline__ float key_dist(unsigned long long k) {
+  return __uint_as_float((uint32_t)(k >> 32));
+}
+__device__ __forceinline__ uint32_t key_id(unsigned long long k) { return (uint32_t)k; }
+
+// Per-call query constants.
+struct QueryParams {
+  int nq, len, w, m, card_bits, k, distance;
+  int window;        // DTW radius, clipped to len - 1
+  int n_leaves;
+  int64_t n;
+  float win;         // near-tie window factor (1+rho)/(1-rho), rounded up
+  float lb_rel;      // (1+rho)(1+2^-16): relative slack on the k-th best
+  float eta;         // absolute slack (distance units) of PAA-based bounds
+  int log_cap;       // near-tie log entries per query
+  int fin_waves;     // waves used by the FP64 DTW recheck
+  int lds_words;     // floats of dynamic LDS of the process kernel
+};
+
+// Per-query device state, one entry per query (all arrays sized by nq).
+struct QueryState {
+  float* zq;                  // [nq][len]   z-normalised query
+  float* upper;               // [nq][len]   LB_Keogh envelope (DTW)
+  float* lower;               // [nq][len]
+  float* paa;                 // [nq][3][16] query PAA, envelope PAA upper, lower
+  float* table;               // [nq][16][card] series-bound table
+  int64_t* approx_range;      // [nq][2] positions refined by the approximate search
+  float* approx_d2;           // [nq][kApproxCap] their FP32 distances
+  unsigned long long* slots;  // [nq][k] running k best (packed keys)
+  unsigned long long* log;    // [nq][log_cap] near-tie candidates (d2, position)
+  int* log_count;             // [nq]
+  unsigned long long* cand;   // [nq][n_leaves] candidate leaves (lb bits, leaf)
+  int* cand_count;            // [nq]
+  float* cand_thr;            // [nq] k-th best when candidates were selected
+  int* next;                  // [nq] work counter of the process phase
+  int* done;                  // [nq] blocks finished (last one finalises)
+  int* sel_done;              // [nq] blocks finished in the selection phase
+  unsigned long long* stats;  // [nq][8] counters (see kStat*)
+  int* status;                // [nq] bit 0: near-tie log overflow
+};
+
+enum { kStatLeavesKept = 0, kStatSeriesLb, kStatLbKeogh, kStatRefined, kStatRecheck, kStatCount = 8 };
+
+// iSAX symbol of a PAA value: the number of breakpoints beta_1..beta_{card-1}
+// that are <= p, given bp[j] = beta_j (bp[0] = -inf).
+__device__ __forceinline__ int symbol_of(float p, const float* __restrict__ bp, int card) {
+  int lo = 0, hi = card - 1;  // answer in [lo, hi]
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (bp[mid] <= p)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Sum of a wavefront's values; every lane gets the total.
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    unsigned long long u = __shfl_xor(v, o, kWave);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+
+// Lock-free insertion into a sorted array of k packed keys held in global
+// memory.  Slot j keeps the minimum of everything offered to it and passes
+// the larger value on to slot j+1, so after all insertions slot j holds the
+// (j+1)-th smallest key ever offered.  Slots only decrease, which makes any
+// read of slot k-1 a safe (never too small) pruning threshold.
+__device__ __forceinline__ void topk_insert(unsigned long long* slots, int k,
+                                            unsigned long long key) {
+  for (int j = 0; j < k; ++j) {
+    unsigned long long cur = __atomic_load_n(&slots[j], __ATOMIC_RELAXED);
+    if (cur <= key) continue;  // slot j already at or below key: key moves on
+    unsigned long long old = atomicMin(&slots[j], key);
+    key = old > key ? old : key;
+    if (key == kEmptyKey) return;
+  }
+}
+
+}  // namespace messi
