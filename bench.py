@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark of the MESSI hot path on one MI355X.
+
+Workload (the paper's default collection, Section 5.1): 100,000,000 random
+walks of length 256 in FP32 (102.4 GB, generated in HBM by the seeded device
+generator), iSAX index with 16 segments, 8-bit symbols, leaves of 2000;
+random-walk queries from a separate seed answered one at a time (exact 1-NN,
+Euclidean distance).  A step is one query through the whole hot path
+(preparation, approximate search, leaf bounds, leaf processing with series
+bounds and refinement, FP64 near-tie recheck).  Also reported: index build
+time, DTW (10% window) 1-NN on the same index, per-phase device times, the
+roofline of the dominant kernel, and the CPU oracle timed on a sample.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def phase_bytes(st, length, n_leaves, queries):
+    """Algorithmic bytes per launch of each phase (per query), from the
+    work counters: a series word is 16 B, a series row 4*len B, a leaf
+    record (symbols, bits, range) 48 B."""
+    q = max(queries, 1)
+    row = 4 * length
+    return {
+        "select": 48.0 * n_leaves,
+        "process": (16.0 * st["series_lb"] + row * (st["refined"] + st["lb_keogh"])) / q,
+    }
+
+
+def run_queries(pm, idx, qt, k, distance, window, budget_s=None):
+    import torch
+
+    lat = []
+    tot = {}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for j in range(qt.shape[0]):
+        t0 = time.perf_counter()
+        _, _, st = pm.messi_query(idx, qt[j:j + 1], k, distance, window, stats=True)
+        lat.append(time.perf_counter() - t0)
+        for key, v in st.items():
+            tot[key] = tot.get(key, 0) + v
+        if budget_s is not None and time.perf_counter() - t_start > budget_s:
+            break
+    torch.cuda.synchronize()
+    return time.perf_counter() - t_start, np.array(lat), tot
+
+
+def cpu_baseline(n, length, queries, sample):
+    import oracle
+    import synth
+
+    log(f"cpu baseline: generating a {sample} x {length} sample on the host")
+    raw = synth.randomwalk(sample, length, seed=synth.SEED_DATA)
+    st = oracle.KnnState(queries, 1)
+    t0 = time.perf_counter()
+    st.scan(raw, 0)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    qps = queries.shape[0] / dt * (sample / n)
+    return {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle",
+            "sample": f"brute-force exact 1-NN ED of {queries.shape[0]} queries over the first "
+                      f"{sample} of the {n} series ({dt:.1f} s), scaled by {sample}/{n}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=100_000_000)
+    ap.add_argument("--len", type=int, default=256)
+    ap.add_argument("--leaf", type=int, default=2000)
+    ap.add_argument("--dtw-queries", type=int, default=20)
+    ap.add_argument("--window", type=int, default=25)
+    ap.add_argument("--cpu-sample", type=int, default=8_000_000)
+    ap.add_argument("--cpu-queries", type=int, default=8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the index is built and "
+              "queried on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2110_07519_amd as pm
+    import synth
+
+    n, length = args.n, args.len
+    torch.cuda.init()
+    log(f"generating {n} x {length} random walks in HBM")
+    data = torch.empty((n, length), dtype=torch.float32, device="cuda")
+    synth.randomwalk_device(data, seed=synth.SEED_DATA)
+    torch.cuda.synchronize()
+    log("building the index")
+    t0 = time.perf_counter()
+    idx = pm.messi_build(data, 16, 256, args.leaf)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = idx.info()
+    log(f"build {build_s:.3f} s, {info['n_leaves']} leaves")
+    del data
+    torch.cuda.empty_cache()
+
+    nq = args.warmup + args.steps
+    qs = synth.random_queries(nq, length)
+    qt = torch.from_numpy(qs).cuda()
+    log(f"warmup {args.warmup} queries")
+    run_queries(pm, idx, qt[:args.warmup], 1, pm.MESSI_ED, 0)
+    log(f"timing {args.steps} ED queries one at a time")
+    wall, lat, st = run_queries(pm, idx, qt[args.warmup:], 1, pm.MESSI_ED, 0)
+    k_done = len(lat)
+    value = k_done / wall
+    phases_us = {p: st[f"us_{p}"] / k_done for p in ["prep", "approx", "select", "process"]}
+    pb = phase_bytes(st, length, info["n_leaves"], k_done)
+    dom = max(phases_us, key=phases_us.get)
+    dom_bytes = pb.get(dom)
+    achieved = (dom_bytes / (phases_us[dom] * 1e-6) / 1e9) if dom_bytes else None
+    log(f"ED: {value:.1f} q/s, p50 {np.percentile(lat, 50) * 1e3:.3f} ms, phases {phases_us}")
+
+    dtw = None
+    if args.dtw_queries > 0:
+        dq = synth.random_queries(args.dtw_queries + 2, length, seed=synth.SEED_QUERY + 100)
+        dt = torch.from_numpy(dq).cuda()
+        run_queries(pm, idx, dt[:2], 1, pm.MESSI_DTW, args.window)
+        log(f"timing {args.dtw_queries} DTW queries (r={args.window})")
+        dwall, dlat, dst = run_queries(pm, idx, dt[2:], 1, pm.MESSI_DTW, args.window, budget_s=90)
+        dk = len(dlat)
+        dph = {p: dst[f"us_{p}"] / dk for p in ["prep", "approx", "select", "process"]}
+        dtw = {"metric": "exact 1-NN DTW queries/s", "value": dk / dwall, "unit": "queries/s",
+               "queries": dk, "window": args.window, "p50_ms": float(np.percentile(dlat, 50) * 1e3),
+               "p99_ms": float(np.percentile(dlat, 99) * 1e3), "phases_us": dph,
+               "refined_per_query": dst["refined"] / dk, "lb_keogh_per_query": dst["lb_keogh"] / dk}
+        log(f"DTW: {dtw['value']:.2f} q/s")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(n, length, qs[args.warmup:args.warmup + args.cpu_queries],
+                           min(args.cpu_sample, n))
+        log(f"cpu baseline {cpu['value']:.4f} q/s")
+
+    out = {
+        "metric": "exact 1-NN queries/s (ED, one query at a time)",
+        "value": value,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": k_done,
+        "warmup": args.warmup,
+        "ms_per_step": wall / k_done * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"random-walk collection {n} x {length} FP32 in HBM, 16 segments, "
+                               f"8-bit iSAX, leaf {args.leaf}; random-walk queries, exact 1-NN ED, "
+                               f"one at a time", "n": n, "len": length, "leaf_size": args.leaf,
+                   "k": 1},
+        "p50_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "build_s": build_s,
+        "n_leaves": info["n_leaves"],
+        "phases_us": phases_us,
+        "work_per_query": {"leaves_kept": st["leaves_kept"] / k_done,
+                           "series_lb": st["series_lb"] / k_done,
+                           "refined": st["refined"] / k_done,
+                           "rechecked_fp64": st["rechecked_fp64"] / k_done},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+                     "traffic": None, "bytes_per_launch": dom_bytes},
+        "dtw": dtw,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    idx.free()
+
+
+if __name__ == "__main__":
+    main()

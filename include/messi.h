@@ -63,6 +63,11 @@ typedef struct messi_stats {
   int64_t refined;          /* real distances computed in FP32 */
   int64_t rechecked_fp64;   /* near-tie candidates recomputed in FP64 */
   int64_t log_overflows;    /* reruns forced by a full near-tie log */
+  /* device time of each phase in microseconds (HIP events on the index's
+   * stream), summed over calls: query preparation, approximate search,
+   * leaf bounds and ordering, leaf processing with refinement and
+   * finalisation */
+  double us_prep, us_approx, us_select, us_process;
 } messi_stats;
 
 /* Build an index (Section 3.2: iSAX summaries, then the leaves of the

@@ -49,7 +49,9 @@ class MessiStats(ctypes.Structure):
     _fields_ = [("queries", ctypes.c_int64), ("leaves_total", ctypes.c_int64),
                 ("leaves_kept", ctypes.c_int64), ("series_lb", ctypes.c_int64),
                 ("lb_keogh", ctypes.c_int64), ("refined", ctypes.c_int64),
-                ("rechecked_fp64", ctypes.c_int64), ("log_overflows", ctypes.c_int64)]
+                ("rechecked_fp64", ctypes.c_int64), ("log_overflows", ctypes.c_int64),
+                ("us_prep", ctypes.c_double), ("us_approx", ctypes.c_double),
+                ("us_select", ctypes.c_double), ("us_process", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -131,13 +133,15 @@ def messi_query(index, queries, k: int = 1, distance: int = MESSI_ED, window: in
         out_ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
     if out_dists is None:
         out_dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    if not stats:
+        _check(lib().messi_query(index.handle, _dev_ptr(queries), nq, k, distance, window,
+                                 _dev_ptr(out_ids), _dev_ptr(out_dists)))
+        return out_ids, out_dists
     st = MessiStats()
     _check(lib().messi_query_stats(index.handle, _dev_ptr(queries), nq, k, distance, window,
                                    _dev_ptr(out_ids), _dev_ptr(out_dists),
                                    ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)))
-    if stats:
-        return out_ids, out_dists, st.as_dict()
-    return out_ids, out_dists
+    return out_ids, out_dists, st.as_dict()
 
 
 def messi_set_stream(index, stream) -> None:

@@ -165,6 +165,13 @@ struct messi_index {
   Workspace ws;
   int log_cap = 4096;
   std::atomic<int> busy{0};
+  hipEvent_t ev[5] = {};
+  bool events_ready = false;
+
+  ~messi_index() {
+    if (events_ready)
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
 
   IndexDev view() const {
     IndexDev v;
@@ -440,21 +447,41 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
   int blocks = 1536 / std::max(1, nq);
   blocks = std::max(4, std::min(blocks, 1536));
   std::vector<int> status(nq);
+  // phase timing (only when the caller asks for statistics)
+  hipEvent_t ev[5] = {};
+  if (stats) {
+    if (!ix->events_ready) {
+      for (int i = 0; i < 5; ++i) HIP_OR_THROW(hipEventCreate(&ix->ev[i]));
+      ix->events_ready = true;
+    }
+    for (int i = 0; i < 5; ++i) ev[i] = ix->ev[i];
+  }
   for (int attempt = 0; attempt < 8; ++attempt) {
     ensure_workspace(ix, nq, k);
     p.log_cap = ix->log_cap;
     const IndexDev v = ix->view();
     QueryState qs = ix->ws.qs;
+    if (stats) HIP_OR_THROW(hipEventRecord(ev[0], st));
     launch_prep(v, queries, p, qs, st);
+    if (stats) HIP_OR_THROW(hipEventRecord(ev[1], st));
     launch_approx(v, p, qs, st);
+    if (stats) HIP_OR_THROW(hipEventRecord(ev[2], st));
     launch_select(v, p, qs, ix->ws.cand_sorted, st);
+    if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
     launch_process(v, p, qs, ix->ws.cand_sorted, blocks, out_ids, out_dists, st);
+    if (stats) HIP_OR_THROW(hipEventRecord(ev[4], st));
     launch_check();
     d2h(status.data(), qs.status, nq, st);
     int worst = 0;
     for (int s : status) worst |= s;
     if (!(worst & 1)) {
       if (stats) {
+        float ms[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) HIP_OR_THROW(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+        stats->us_prep += 1e3 * ms[0];
+        stats->us_approx += 1e3 * ms[1];
+        stats->us_select += 1e3 * ms[2];
+        stats->us_process += 1e3 * ms[3];
         std::vector<unsigned long long> sv((size_t)nq * kStatCount);
         d2h(sv.data(), qs.stats, sv.size(), st);
         stats->queries += nq;
