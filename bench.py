@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PHASES = ["prep", "stage1", "stage2", "process", "finalize"]
 
 
 def log(msg):
@@ -38,7 +39,7 @@ def phase_bytes(st, length, n_leaves, queries):
     q = max(queries, 1)
     row = 4 * length
     return {
-        "select": 48.0 * n_leaves,
+        "stage2": 48.0 * n_leaves,
         "process": (16.0 * st["series_lb"] + row * (st["refined"] + st["lb_keogh"])) / q,
     }
 
@@ -92,6 +93,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=8_000_000)
     ap.add_argument("--cpu-queries", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the index is built and "
@@ -105,6 +108,14 @@ def main():
 
     n, length = args.n, args.len
     torch.cuda.init()
+    if args.copy_probe_mib > 0:
+        a = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        a.fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del a, b
     log(f"generating {n} x {length} random walks in HBM")
     data = torch.empty((n, length), dtype=torch.float32, device="cuda")
     synth.randomwalk_device(data, seed=synth.SEED_DATA)
@@ -128,7 +139,7 @@ def main():
     wall, lat, st = run_queries(pm, idx, qt[args.warmup:], 1, pm.MESSI_ED, 0)
     k_done = len(lat)
     value = k_done / wall
-    phases_us = {p: st[f"us_{p}"] / k_done for p in ["prep", "approx", "select", "process"]}
+    phases_us = {p: st[f"us_{p}"] / k_done for p in PHASES}
     pb = phase_bytes(st, length, info["n_leaves"], k_done)
     dom = max(phases_us, key=phases_us.get)
     dom_bytes = pb.get(dom)
@@ -143,7 +154,7 @@ def main():
         log(f"timing {args.dtw_queries} DTW queries (r={args.window})")
         dwall, dlat, dst = run_queries(pm, idx, dt[2:], 1, pm.MESSI_DTW, args.window, budget_s=90)
         dk = len(dlat)
-        dph = {p: dst[f"us_{p}"] / dk for p in ["prep", "approx", "select", "process"]}
+        dph = {p: dst[f"us_{p}"] / dk for p in PHASES}
         dtw = {"metric": "exact 1-NN DTW queries/s", "value": dk / dwall, "unit": "queries/s",
                "queries": dk, "window": args.window, "p50_ms": float(np.percentile(dlat, 50) * 1e3),
                "p99_ms": float(np.percentile(dlat, 99) * 1e3), "phases_us": dph,

@@ -57,17 +57,17 @@ typedef struct messi_leaf {
 typedef struct messi_stats {
   int64_t queries;
   int64_t leaves_total;     /* leaves in the index, times queries */
-  int64_t leaves_kept;      /* leaves whose bound passed the first k-best */
+  int64_t leaves_kept;      /* leaves processed (bound within the k-th best) */
   int64_t series_lb;        /* series-level lower bounds computed */
   int64_t lb_keogh;         /* LB_Keogh bounds computed (DTW) */
   int64_t refined;          /* real distances computed in FP32 */
   int64_t rechecked_fp64;   /* near-tie candidates recomputed in FP64 */
   int64_t log_overflows;    /* reruns forced by a full near-tie log */
   /* device time of each phase in microseconds (HIP events on the index's
-   * stream), summed over calls: query preparation, approximate search,
-   * leaf bounds and ordering, leaf processing with refinement and
-   * finalisation */
-  double us_prep, us_approx, us_select, us_process;
+   * stream), summed over calls: query preparation; approximate search with
+   * the leaf bounds; ordering of the leaves by bound; leaf processing with
+   * refinement; FP64 recheck and output */
+  double us_prep, us_stage1, us_stage2, us_process, us_finalize;
 } messi_stats;
 
 /* Build an index (Section 3.2: iSAX summaries, then the leaves of the

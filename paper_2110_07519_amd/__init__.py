@@ -50,8 +50,9 @@ class MessiStats(ctypes.Structure):
                 ("leaves_kept", ctypes.c_int64), ("series_lb", ctypes.c_int64),
                 ("lb_keogh", ctypes.c_int64), ("refined", ctypes.c_int64),
                 ("rechecked_fp64", ctypes.c_int64), ("log_overflows", ctypes.c_int64),
-                ("us_prep", ctypes.c_double), ("us_approx", ctypes.c_double),
-                ("us_select", ctypes.c_double), ("us_process", ctypes.c_double)]
+                ("us_prep", ctypes.c_double), ("us_stage1", ctypes.c_double),
+                ("us_stage2", ctypes.c_double), ("us_process", ctypes.c_double),
+                ("us_finalize", ctypes.c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -140,7 +140,6 @@ struct Workspace {
   DevMem mem;
   int nq = 0, k = 0, len = 0, w = 0, card = 0, log_cap = 0, L = 0;
   QueryState qs{};
-  unsigned long long* cand_sorted = nullptr;
 };
 
 }  // namespace
@@ -161,11 +160,14 @@ struct messi_index {
   uint4* leaf_bits = nullptr;
   float* bp = nullptr;
   NodeDev* nodes = nullptr;
+  int4* tree = nullptr;
   int* root_node = nullptr;
   Workspace ws;
+  int proc_blocks_cu[2] = {0, 0};  // per distance kind, cached occupancy
   int log_cap = 4096;
+  int n_cus = 0;
   std::atomic<int> busy{0};
-  hipEvent_t ev[5] = {};
+  hipEvent_t ev[6] = {};
   bool events_ready = false;
 
   ~messi_index() {
@@ -189,7 +191,7 @@ struct messi_index {
     v.leaf_sym = leaf_sym;
     v.leaf_bits = leaf_bits;
     v.bp = bp;
-    v.nodes = nodes;
+    v.tree = tree;
     v.root_node = root_node;
     return v;
   }
@@ -361,6 +363,9 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   launch_check();
   ix->nodes = d.nodes;
   ix->root_node = d.root_node;
+  ix->tree = ix->mem.alloc<int4>(ix->n_nodes);
+  launch_make_tree(d.nodes, ix->n_nodes, cb, ix->tree, st);
+  launch_check();
   HIP_OR_THROW(hipStreamSynchronize(st));
   return true;
 }
@@ -381,21 +386,22 @@ void ensure_workspace(messi_index* ix, int nq, int k) {
   s.upper = ws.mem.alloc<float>((size_t)NQ * len);
   s.lower = ws.mem.alloc<float>((size_t)NQ * len);
   s.paa = ws.mem.alloc<float>((size_t)NQ * 3 * kMaxSeg);
-  s.table = ws.mem.alloc<float>((size_t)NQ * ix->w * card);
+  s.table = ws.mem.alloc<float>((size_t)NQ * kMaxSeg * card);
   s.approx_range = ws.mem.alloc<int64_t>((size_t)NQ * 2);
   s.approx_d2 = ws.mem.alloc<float>((size_t)NQ * kApproxCap);
   s.slots = ws.mem.alloc<unsigned long long>((size_t)NQ * K);
   s.log = ws.mem.alloc<unsigned long long>((size_t)NQ * LC);
   s.log_count = ws.mem.alloc<int>(NQ);
-  s.cand = ws.mem.alloc<unsigned long long>((size_t)NQ * L);
-  s.cand_count = ws.mem.alloc<int>(NQ);
-  s.cand_thr = ws.mem.alloc<float>(NQ);
-  s.next = ws.mem.alloc<int>(NQ);
-  s.done = ws.mem.alloc<int>(NQ);
-  s.sel_done = ws.mem.alloc<int>(NQ);
+  s.leaf_lb = ws.mem.alloc<float>((size_t)NQ * L);
+  s.hist = ws.mem.alloc<int>((size_t)NQ * kLbBuckets);
+  s.fill = ws.mem.alloc<int>((size_t)NQ * kLbBuckets);
+  const int64_t item_cap = ix->n / kChunkSeries + L + 1;
+  s.items = ws.mem.alloc<unsigned long long>((size_t)NQ * item_cap);
+  s.ranges = ws.mem.alloc<int2>((size_t)NQ * item_cap);
+  s.n_items = ws.mem.alloc<int>(NQ);
+  s.next = ws.mem.alloc<int>((size_t)NQ * kCounterInts);
   s.stats = ws.mem.alloc<unsigned long long>((size_t)NQ * kStatCount);
   s.status = ws.mem.alloc<int>(NQ);
-  ws.cand_sorted = ws.mem.alloc<unsigned long long>((size_t)NQ * L);
   ws.nq = NQ;
   ws.k = K;
   ws.len = len;
@@ -421,6 +427,7 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
   p.window = distance == MESSI_DTW ? std::min(window, len - 1) : 0;
   p.n_leaves = ix->n_leaves;
   p.n = ix->n;
+  p.item_cap = (int)(ix->n / kChunkSeries + ix->n_leaves + 1);
   // FP32 error of a refined squared distance: at most rho relative, with
   // rho = (4 len + 64) u covering ED's pairwise sums and DTW's paths of up
   // to 2 len - 1 terms.
@@ -432,29 +439,38 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
   p.eta = (float)(32.0 * u * len * std::sqrt((double)p.m));
   int fin_waves = 0;
   if (distance == MESSI_DTW) {
-    const size_t base = query_process_lds_for(p, 0);
     fin_waves = 1;
-    for (int fw = 4; fw >= 1; --fw)
-      if (query_process_lds_for(p, fw) <= std::max<size_t>(base, 48 * 1024)) {
+    for (int fw = 4; fw >= 1; --fw) {
+      p.fin_waves = fw;
+      if (finalize_lds_bytes(p) <= 64 * 1024) {
         fin_waves = fw;
         break;
       }
+    }
   }
   p.fin_waves = fin_waves;
-  if (query_process_lds_for(p, fin_waves) > 64 * 1024)
+  if (process_lds_bytes(p) > 64 * 1024 || finalize_lds_bytes(p) > 64 * 1024)
     return fail(MESSI_EINVAL, "series length %d too long for the query kernels", len);
 
-  int blocks = 1536 / std::max(1, nq);
-  blocks = std::max(4, std::min(blocks, 1536));
+  int& per_cu = ix->proc_blocks_cu[distance == MESSI_DTW ? 1 : 0];
+  if (per_cu == 0 || distance == MESSI_DTW) per_cu = process_blocks_per_cu(p);
+  if (ix->n_cus == 0) {
+    int dev = 0;
+    HIP_OR_THROW(hipGetDevice(&dev));
+    HIP_OR_THROW(hipDeviceGetAttribute(&ix->n_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
+  const int resident = per_cu * ix->n_cus;
+  int blocks = resident / std::max(1, nq);
+  blocks = std::max(2, std::min(blocks, resident));
   std::vector<int> status(nq);
   // phase timing (only when the caller asks for statistics)
-  hipEvent_t ev[5] = {};
+  hipEvent_t ev[6] = {};
   if (stats) {
     if (!ix->events_ready) {
-      for (int i = 0; i < 5; ++i) HIP_OR_THROW(hipEventCreate(&ix->ev[i]));
+      for (int i = 0; i < 6; ++i) HIP_OR_THROW(hipEventCreate(&ix->ev[i]));
       ix->events_ready = true;
     }
-    for (int i = 0; i < 5; ++i) ev[i] = ix->ev[i];
+    for (int i = 0; i < 6; ++i) ev[i] = ix->ev[i];
   }
   for (int attempt = 0; attempt < 8; ++attempt) {
     ensure_workspace(ix, nq, k);
@@ -464,24 +480,27 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
     if (stats) HIP_OR_THROW(hipEventRecord(ev[0], st));
     launch_prep(v, queries, p, qs, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[1], st));
-    launch_approx(v, p, qs, st);
+    launch_stage1(v, p, qs, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[2], st));
-    launch_select(v, p, qs, ix->ws.cand_sorted, st);
+    launch_stage2(v, p, qs, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
-    launch_process(v, p, qs, ix->ws.cand_sorted, blocks, out_ids, out_dists, st);
+    launch_process(v, p, qs, blocks, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[4], st));
+    launch_finalize(v, p, qs, out_ids, out_dists, st);
+    if (stats) HIP_OR_THROW(hipEventRecord(ev[5], st));
     launch_check();
     d2h(status.data(), qs.status, nq, st);
     int worst = 0;
     for (int s : status) worst |= s;
     if (!(worst & 1)) {
       if (stats) {
-        float ms[4] = {0, 0, 0, 0};
-        for (int i = 0; i < 4; ++i) HIP_OR_THROW(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+        float ms[5] = {0, 0, 0, 0, 0};
+        for (int i = 0; i < 5; ++i) HIP_OR_THROW(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
         stats->us_prep += 1e3 * ms[0];
-        stats->us_approx += 1e3 * ms[1];
-        stats->us_select += 1e3 * ms[2];
+        stats->us_stage1 += 1e3 * ms[1];
+        stats->us_stage2 += 1e3 * ms[2];
         stats->us_process += 1e3 * ms[3];
+        stats->us_finalize += 1e3 * ms[4];
         std::vector<unsigned long long> sv((size_t)nq * kStatCount);
         d2h(sv.data(), qs.stats, sv.size(), st);
         stats->queries += nq;

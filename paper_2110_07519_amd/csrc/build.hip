@@ -39,17 +39,21 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
   const int64_t first = (int64_t)blockIdx.x * spw;
   const int rows = (int)((n - first) < spw ? (n - first) : spw);
   const float* src = raw + first * (int64_t)len;
-  const int total = rows * len;
-  for (int e = lane; e < total; e += kWave) {
-    const int r = e / len;
-    const int t = e - r * len;
-    tile[r * len + (t + r) % len] = src[e];
+  for (int r = 0; r < rows; ++r) {  // coalesced row reads, rotated LDS rows
+    const float* srow = src + (int64_t)r * len;
+    float* trow = tile + r * len;
+    const int rr = r < len ? r : r % len;
+    for (int t = lane; t < len; t += kWave) {
+      int c = t + rr;
+      c = c >= len ? c - len : c;
+      trow[c] = srow[t];
+    }
   }
   __syncthreads();
   if (lane >= rows) return;
 
   const float* row = tile + lane * len;
-  const int rot = lane % len;
+  const int rot = lane < len ? lane : lane % len;
   auto at = [&](int t) {
     int c = t + rot;
     c = c >= len ? c - len : c;
@@ -68,17 +72,41 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
   const bool flat = !(sd > 0.0f);
   const int m = len / w;
   const float fm = (float)m;
-  uint32_t packed[4] = {0u, 0u, 0u, 0u};
-  uint32_t key = 0;
-  for (int sg = 0; sg < w; ++sg) {
+  float pv[kMaxSeg];
+#pragma unroll
+  for (int sg = 0; sg < kMaxSeg; ++sg) {
     float a = 0.0f;
-    if (!flat) {
+    if (sg < w && !flat) {
       for (int t = sg * m; t < sg * m + m; ++t) a = a + __fdiv_rn(at(t) - mu, sd);
     }
-    const float p = __fdiv_rn(a, fm);
-    const uint32_t sym = (uint32_t)symbol_of(p, bp, card);
-    packed[sg >> 2] |= sym << (8 * (sg & 3));
-    key = (key << 1) | (sym >> (card_bits - 1));
+    pv[sg] = __fdiv_rn(a, fm);
+  }
+  // symbols: the w binary searches advance together, one level per step
+  int lo[kMaxSeg], hi[kMaxSeg];
+#pragma unroll
+  for (int sg = 0; sg < kMaxSeg; ++sg) {
+    lo[sg] = 0;
+    hi[sg] = card - 1;
+  }
+  for (int step = 0; step < card_bits; ++step) {
+#pragma unroll
+    for (int sg = 0; sg < kMaxSeg; ++sg) {
+      const int mid = (lo[sg] + hi[sg] + 1) >> 1;
+      if (bp[mid] <= pv[sg])
+        lo[sg] = mid;
+      else
+        hi[sg] = mid - 1;
+    }
+  }
+  uint32_t packed[4] = {0u, 0u, 0u, 0u};
+  uint32_t key = 0;
+#pragma unroll
+  for (int sg = 0; sg < kMaxSeg; ++sg) {
+    if (sg < w) {
+      const uint32_t sym = (uint32_t)lo[sg];
+      packed[sg >> 2] |= sym << (8 * (sg & 3));
+      key = (key << 1) | (sym >> (card_bits - 1));
+    }
   }
   const int64_t id = first + lane;
   words[id] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
@@ -500,6 +528,21 @@ __global__ __launch_bounds__(256) void k_gather_store(const float* __restrict__ 
   }
 }
 
+// Compact tree for the approximate-search descent: one 16-byte record per
+// node, so each level of the descent is a single load.
+__global__ void k_make_tree(const NodeDev* __restrict__ nodes, int n_nodes, int card_bits,
+                            int4* __restrict__ tree) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_nodes) return;
+  const NodeDev& nd = nodes[i];
+  if (nd.seg >= 0) {
+    const int shift = card_bits - 1 - nd.bits[nd.seg];
+    tree[i] = make_int4(nd.seg | (shift << 8), 0, nd.child[0], nd.child[1]);
+  } else {
+    tree[i] = make_int4(-1, (int)nd.begin, (int)nd.end, nd.leaf);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 
@@ -567,6 +610,12 @@ void launch_leaf_sort(int n_leaves, const int64_t* leaf_begin, const int64_t* le
 void launch_leaf_sort_global(int64_t b, int cnt, int p2, const int32_t* I, int32_t* scratch,
                              int32_t* perm, hipStream_t st) {
   hipLaunchKernelGGL(k_leaf_sort_global, dim3(1), dim3(1024), 0, st, b, cnt, p2, I, scratch, perm);
+}
+
+void launch_make_tree(const NodeDev* nodes, int n_nodes, int card_bits, int4* tree,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(k_make_tree, dim3((n_nodes + 255) / 256), dim3(256), 0, st, nodes, n_nodes,
+                     card_bits, tree);
 }
 
 void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* perm,

@@ -9,7 +9,12 @@ namespace messi {
 constexpr int kMaxSeg = 16;       // PAA segments per word (one byte each)
 constexpr int kMaxLen = 4096;     // longest series accepted
 constexpr int kWave = 64;         // CDNA wavefront width
-constexpr int kBuckets = 1024;    // LB buckets used to order candidate leaves
+constexpr int kLbBuckets = 2048;  // logarithmic bound buckets that order the leaves
+constexpr int kShards = 64;       // work counters per query (leaves dealt round robin)
+constexpr int kChunkSeries = 256; // series per work item of the process phase
+constexpr int kGrab = 8;          // work items taken per atomic grab
+constexpr int kCounterStride = 64;  // ints between two shard counters (own 256-byte line)
+constexpr int kCounterInts = kShards * kCounterStride + kCounterStride;
 constexpr int kApproxCap = 8192;  // most series refined by the approximate search
 constexpr int kTopCap = 2048;     // k best + near-tie candidates rechecked per FP64 pass
 
@@ -37,6 +42,7 @@ struct QueryParams {
   float eta;         // absolute slack (distance units) of PAA-based bounds
   int log_cap;       // near-tie log entries per query
   int fin_waves;     // waves used by the FP64 DTW recheck
+  int item_cap;      // leaf chunks per query: at most n / kChunkSeries + n_leaves
   int lds_words;     // floats of dynamic LDS of the process kernel
 };
 
@@ -52,12 +58,13 @@ struct QueryState {
   unsigned long long* slots;  // [nq][k] running k best (packed keys)
   unsigned long long* log;    // [nq][log_cap] near-tie candidates (d2, position)
   int* log_count;             // [nq]
-  unsigned long long* cand;   // [nq][n_leaves] candidate leaves (lb bits, leaf)
-  int* cand_count;            // [nq]
-  float* cand_thr;            // [nq] k-th best when candidates were selected
-  int* next;                  // [nq] work counter of the process phase
-  int* done;                  // [nq] blocks finished (last one finalises)
-  int* sel_done;              // [nq] blocks finished in the selection phase
+  float* leaf_lb;             // [nq][n_leaves] leaf bounds
+  int* hist;                  // [nq][kLbBuckets] leaves per bound bucket
+  int* fill;                  // [nq][kLbBuckets] scatter cursors
+  unsigned long long* items;  // [nq][item_cap] leaf chunks in bucket order (lb bits, leaf)
+  int2* ranges;               // [nq][item_cap] their position ranges
+  int* n_items;               // [nq] chunks in the order
+  int* next;                  // [nq][kCounterInts]: kShards counters kCounterStride apart, then a finished-shard mask
   unsigned long long* stats;  // [nq][8] counters (see kStat*)
   int* status;                // [nq] bit 0: near-tie log overflow
 };
@@ -78,17 +85,34 @@ __device__ __forceinline__ int symbol_of(float p, const float* __restrict__ bp, 
   return lo;
 }
 
-// Sum of a wavefront's values; every lane gets the total.
+// Wavefront reductions with DPP lane moves (quad permutes, row shifts and
+// row broadcasts) instead of LDS permutes; the result is read from the last
+// lane, so every lane gets the total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v, float old) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(v), CTRL,
+                                                    0xf, 0xf, false));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_f<0xb1>(v, 0.0f);   // quad_perm [1,0,3,2]
+  v += dpp_f<0x4e>(v, 0.0f);   // quad_perm [2,3,0,1]
+  v += dpp_f<0x114>(v, 0.0f);  // row_shr:4
+  v += dpp_f<0x118>(v, 0.0f);  // row_shr:8
+  v += dpp_f<0x142>(v, 0.0f);  // row_bcast:15
+  v += dpp_f<0x143>(v, 0.0f);  // row_bcast:31
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, kWave));
-  return v;
+  const float inf = __builtin_inff();
+  v = fminf(v, dpp_f<0xb1>(v, inf));
+  v = fminf(v, dpp_f<0x4e>(v, inf));
+  v = fminf(v, dpp_f<0x114>(v, inf));
+  v = fminf(v, dpp_f<0x118>(v, inf));
+  v = fminf(v, dpp_f<0x142>(v, inf));
+  v = fminf(v, dpp_f<0x143>(v, inf));
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v) {
@@ -100,6 +124,11 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
   return v;
 }
 
+// Relaxed load of a value other blocks update atomically (device scope).
+__device__ __forceinline__ unsigned long long load_relaxed(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Lock-free insertion into a sorted array of k packed keys held in global
 // memory.  Slot j keeps the minimum of everything offered to it and passes
 // the larger value on to slot j+1, so after all insertions slot j holds the
@@ -108,7 +137,7 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long v)
 __device__ __forceinline__ void topk_insert(unsigned long long* slots, int k,
                                             unsigned long long key) {
   for (int j = 0; j < k; ++j) {
-    unsigned long long cur = __atomic_load_n(&slots[j], __ATOMIC_RELAXED);
+    unsigned long long cur = load_relaxed(&slots[j]);
     if (cur <= key) continue;  // slot j already at or below key: key moves on
     unsigned long long old = atomicMin(&slots[j], key);
     key = old > key ? old : key;

@@ -11,7 +11,6 @@ namespace messi {
 
 constexpr int kSelectThreads = 1024;
 constexpr int kProcThreads = 256;
-constexpr int kTile = 1024;        // series of a leaf examined per pass of a block
 constexpr int kMaxBand = 64;       // largest DTW radius served by the register-band kernel
 
 // Read-only view of a built index.
@@ -26,20 +25,23 @@ struct IndexDev {
   const uint4* leaf_sym;     // [L]
   const uint4* leaf_bits;    // [L]
   const float* bp;           // [card + 1] breakpoints with -inf / +inf ends
-  const NodeDev* nodes;
+  const int4* tree;          // per node: inner {seg | shift << 8, -, child0, child1},
+                             //           leaf  {-1, begin, end, leaf index}
   const int* root_node;      // [2^w]
 };
 
 void launch_prep(const IndexDev& ix, const float* queries, const QueryParams& qp,
                  const QueryState& qs, hipStream_t st);
-void launch_approx(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
                    hipStream_t st);
-void launch_select(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   unsigned long long* cand_sorted, hipStream_t st);
-size_t query_process_lds(const QueryParams& qp);
-size_t query_process_lds_for(const QueryParams& qp, int fin_waves);
+void launch_stage2(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+                   hipStream_t st);
 void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                    const unsigned long long* cand_sorted, int blocks_per_query,
-                    int64_t* out_ids, float* out_dists, hipStream_t st);
+                    int blocks_per_query, hipStream_t st);
+void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+                     int64_t* out_ids, float* out_dists, hipStream_t st);
+size_t process_lds_bytes(const QueryParams& qp);
+size_t finalize_lds_bytes(const QueryParams& qp);
+int process_blocks_per_cu(const QueryParams& qp);
 
 }  // namespace messi

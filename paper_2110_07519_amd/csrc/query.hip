@@ -4,18 +4,21 @@
 // Phases, each one launch over all queries of a call (grid.y = query):
 //   prep     z-normalise the query, PAA (and LB_Keogh envelope + its PAA),
 //            the per-segment bound table, and the approximate-search leaf:
-//            the leaf reached by descending the query's own word.
-//   approx   real distances to that leaf's series -> the first k-best list.
-//   select   mindist of every leaf against the first k-th best; kept leaves
-//            are ordered by bound (counting sort over 1024 bound buckets)
-//            by the last block to finish -- the paper's priority queues.
-//   process  persistent blocks take leaves in bound order (one atomic
-//            counter replaces the queues' DeleteMin); per leaf: series
-//            bounds from the table in LDS, [LB_Keogh,] FP32 refinement, the
-//            k best kept by a lock-free atomicMin cascade.  A block stops
-//            when the next leaf's bound exceeds the current k-th best.  The
-//            last block to finish rechecks the near ties in FP64 and writes
-//            the answer.
+//            the leaf reached by descending the tree along the query's word.
+//   stage1   two kinds of blocks in one launch: some refine the series of
+//            the approximate leaf (the first k-best list, Algorithm 5), the
+//            others compute mindist of every leaf and a histogram of the
+//            bounds over 2048 logarithmic buckets.
+//   stage2   every leaf is placed in bucket order (counting scatter): the
+//            ascending-bound order the paper's priority queues give.
+//   process  waves take leaves in that order through one atomic counter
+//            (the queues' DeleteMin); per leaf: series bounds from the table
+//            in LDS, [LB_Keogh,] FP32 refinement, the k best kept by a
+//            lock-free atomicMin cascade.  A wave stops at the first leaf
+//            whose bucket starts above the current k-th best (every later
+//            leaf is at least that far).
+//   finalize FP64 recheck of the near ties and the exact (distance, id)
+//            order of the answer.
 //
 // Exactness: every prune compares a bound against the k-th best with slack
 // covering the FP32 rounding of both sides; every refined distance within
@@ -28,8 +31,12 @@
 
 namespace messi {
 
+__device__ __forceinline__ unsigned long long load_key(const unsigned long long* p) {
+  return load_relaxed(p);
+}
+
 __device__ __forceinline__ float kth_dist(const unsigned long long* slots, int k) {
-  return key_dist(__atomic_load_n(&slots[k - 1], __ATOMIC_RELAXED));
+  return key_dist(load_key(&slots[k - 1]));
 }
 
 // Bound threshold: a series whose bound exceeds it cannot be among the k
@@ -41,17 +48,24 @@ __device__ __forceinline__ float lb_threshold(float thr, const QueryParams& p) {
   return r * r * 1.0001f;
 }
 
-__device__ __forceinline__ int bucket_of(float lb, float thr0) {
-  if (!(thr0 < INFINITY) || !(thr0 > 0.0f)) return 0;
-  const float f = lb / thr0 * (float)kBuckets;
-  int b = (int)f;
-  b = b < 0 ? 0 : b;
-  return b >= kBuckets ? kBuckets - 1 : b;
+// Logarithmic bound buckets: exponent and top 6 mantissa bits of the FP32
+// bound, over [2^-16, 2^16); monotone in the bound.
+constexpr int kBucketBase = (127 - 16) << 6;
+__device__ __forceinline__ int lb_bucket(float lb) {
+  const int b = (int)(__float_as_uint(lb) >> 17) - kBucketBase;
+  return b < 0 ? 0 : (b >= kLbBuckets ? kLbBuckets - 1 : b);
+}
+__device__ __forceinline__ float bucket_floor(int b) {
+  return b <= 0 ? 0.0f : __uint_as_float((uint32_t)(b + kBucketBase) << 17);
 }
 
 __device__ __forceinline__ uint32_t byte_of(const uint4& v, int s) {
   const uint32_t x = s < 4 ? v.x : (s < 8 ? v.y : (s < 12 ? v.z : v.w));
   return (x >> (8 * (s & 3))) & 0xffu;
+}
+
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+  return a < b ? a : b;
 }
 
 // Squared ED between an LDS query and a global row, one wave.
@@ -77,18 +91,67 @@ __device__ __forceinline__ float ed_wave(const float* __restrict__ zq, const flo
   return wave_sum(acc);
 }
 
-// Squared LB_Keogh of a global row against an LDS envelope, one wave.
-__device__ __forceinline__ float lbk_wave(const float* __restrict__ U, const float* __restrict__ L,
-                                          const float* __restrict__ x, int len, int lane) {
-  float acc = 0.0f;
-  for (int t = lane; t < len; t += kWave) {
-    const float v = x[t];
-    const float a = fmaxf(v - U[t], 0.0f);
-    const float b = fmaxf(L[t] - v, 0.0f);
-    const float d = a + b;  // at most one is non-zero
-    acc = __builtin_fmaf(d, d, acc);
+// Squared ED (or LB_Keogh) of up to eight rows at once, their loads in
+// flight together.  Rows are given by wave-uniform positions and an active
+// mask; results for inactive rows are undefined.
+constexpr int kGroup = 8;
+
+__device__ __forceinline__ void ed_group(const float* __restrict__ zq, const float* __restrict__ Z,
+                                         int len, const int (&pos)[kGroup], unsigned act, int lane,
+                                         float (&out)[kGroup]) {
+  float acc[kGroup];
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) acc[c] = 0.0f;
+  if ((len & 3) == 0) {
+    for (int t = 4 * lane; t < len; t += 4 * kWave) {
+      const float4 b = *reinterpret_cast<const float4*>(zq + t);
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        if ((act >> c) & 1u) {
+          const float4 x = *reinterpret_cast<const float4*>(Z + (int64_t)pos[c] * len + t);
+          const float e0 = x.x - b.x, e1 = x.y - b.y, e2 = x.z - b.z, e3 = x.w - b.w;
+          acc[c] = __builtin_fmaf(e0, e0, acc[c]);
+          acc[c] = __builtin_fmaf(e1, e1, acc[c]);
+          acc[c] = __builtin_fmaf(e2, e2, acc[c]);
+          acc[c] = __builtin_fmaf(e3, e3, acc[c]);
+        }
+      }
+    }
+  } else {
+    for (int t = lane; t < len; t += kWave) {
+      const float b = zq[t];
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        if ((act >> c) & 1u) {
+          const float e = Z[(int64_t)pos[c] * len + t] - b;
+          acc[c] = __builtin_fmaf(e, e, acc[c]);
+        }
+      }
+    }
   }
-  return wave_sum(acc);
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) out[c] = ((act >> c) & 1u) ? wave_sum(acc[c]) : 0.0f;
+}
+
+__device__ __forceinline__ void lbk_group(const float* __restrict__ U, const float* __restrict__ L,
+                                          const float* __restrict__ Z, int len, const int (&pos)[kGroup],
+                                          unsigned act, int lane, float (&out)[kGroup]) {
+  float acc[kGroup];
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) acc[c] = 0.0f;
+  for (int t = lane; t < len; t += kWave) {
+    const float u = U[t], l = L[t];
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) {
+      if ((act >> c) & 1u) {
+        const float v = Z[(int64_t)pos[c] * len + t];
+        const float e = fmaxf(v - u, 0.0f) + fmaxf(l - v, 0.0f);  // one of the two is zero
+        acc[c] = __builtin_fmaf(e, e, acc[c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < kGroup; ++c) out[c] = ((act >> c) & 1u) ? wave_sum(acc[c]) : 0.0f;
 }
 
 // Banded DTW, squared costs, FP32, one pair per thread.  Rows run over the
@@ -98,28 +161,51 @@ __device__ __forceinline__ float lbk_wave(const float* __restrict__ U, const flo
 // the query in LDS with R +inf pads on each side (matrix edges cost +inf).
 // A path crosses every row, so a row minimum above `cutoff` ends the pair.
 template <int R, bool MASK>
+__device__ __forceinline__ void dtw_row(float (&D)[2 * R + 1], const float* __restrict__ qpad,
+                                        int j, float xj, int r) {
+  float left = INFINITY;
+#pragma unroll
+  for (int b = 0; b <= 2 * R; ++b) {
+    const float d = xj - qpad[j + b];
+    const float up = (b < 2 * R) ? D[b + 1] : INFINITY;
+    float c = __builtin_fmaf(d, d, fminf(fminf(D[b], up), left));
+    if (MASK && (b - R > r || R - b > r)) c = INFINITY;
+    D[b] = c;
+    left = c;
+  }
+}
+
+template <int R, bool MASK>
 __device__ float dtw_band(const float* __restrict__ qpad, const float* __restrict__ x, int len,
                           int r, float cutoff) {
   float D[2 * R + 1];
 #pragma unroll
   for (int b = 0; b <= 2 * R; ++b) D[b] = (b == R) ? 0.0f : INFINITY;
-  for (int j = 0; j < len; ++j) {
-    const float xj = x[j];
-    float left = INFINITY;
+  if ((len & 3) == 0) {
+#pragma unroll 1
+    for (int j = 0; j < len; j += 4) {
+      const float4 xa = *reinterpret_cast<const float4*>(x + j);
+      dtw_row<R, MASK>(D, qpad, j + 0, xa.x, r);
+      dtw_row<R, MASK>(D, qpad, j + 1, xa.y, r);
+      dtw_row<R, MASK>(D, qpad, j + 2, xa.z, r);
+      dtw_row<R, MASK>(D, qpad, j + 3, xa.w, r);
+      if ((j & 7) == 4) {
+        float mn = D[0];
 #pragma unroll
-    for (int b = 0; b <= 2 * R; ++b) {
-      const float d = xj - qpad[j + b];
-      const float up = (b < 2 * R) ? D[b + 1] : INFINITY;
-      float c = __builtin_fmaf(d, d, fminf(fminf(D[b], up), left));
-      if (MASK && (b - R > r || R - b > r)) c = INFINITY;
-      D[b] = c;
-      left = c;
+        for (int b = 1; b <= 2 * R; ++b) mn = fminf(mn, D[b]);
+        if (mn > cutoff) return INFINITY;
+      }
     }
-    if ((j & 7) == 7) {
-      float mn = D[0];
+  } else {
+#pragma unroll 1
+    for (int j = 0; j < len; ++j) {
+      dtw_row<R, MASK>(D, qpad, j, x[j], r);
+      if ((j & 7) == 7) {
+        float mn = D[0];
 #pragma unroll
-      for (int b = 1; b <= 2 * R; ++b) mn = fminf(mn, D[b]);
-      if (mn > cutoff) return INFINITY;
+        for (int b = 1; b <= 2 * R; ++b) mn = fminf(mn, D[b]);
+        if (mn > cutoff) return INFINITY;
+      }
     }
   }
   return D[R];
@@ -181,8 +267,7 @@ __device__ T dtw_wave(const float* __restrict__ q, const float* __restrict__ x, 
     }
   }
   // the final cell was written by the lane owning index len-1
-  const int owner = (len - 1) % kWave;
-  return __shfl(result, owner, kWave);
+  return __shfl(result, (len - 1) % kWave, kWave);
 }
 
 // ---------------------------------------------------------------------------
@@ -206,6 +291,10 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
   const float* src = queries + (int64_t)q * len;
   for (int t = tid; t < len; t += blockDim.x) x[t] = src[t];
   for (int j = tid; j <= card; j += blockDim.x) bp[j] = ix.bp[j];
+  for (int j = tid; j < kLbBuckets; j += blockDim.x) {
+    s.hist[(int64_t)q * kLbBuckets + j] = 0;
+    s.fill[(int64_t)q * kLbBuckets + j] = 0;
+  }
   __syncthreads();
   if (tid == 0) {  // same order and rounding as the build's summary pass
     float sum = 0.0f;
@@ -269,12 +358,16 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
   // bound table: T[s][sym] = m * gap(PAA, box of sym)^2 (mindist, Section
   // 2.2 / Property 1; DTW: the envelope PAA against the box, Section 3.4)
   const float fm = (float)m;
-  float* table = s.table + (int64_t)q * w * card;
-  for (int idx = tid; idx < w * card; idx += blockDim.x) {
+  float* table = s.table + (int64_t)q * kMaxSeg * card;
+  for (int idx = tid; idx < kMaxSeg * card; idx += blockDim.x) {
     const int sg = idx / card, j = idx - sg * card;
-    const float lo = bp[j], hi = bp[j + 1];
-    const float g = fmaxf(lo - paa[1][sg], 0.0f) + fmaxf(paa[2][sg] - hi, 0.0f);
-    table[idx] = fm * (g * g);
+    float v = 0.0f;  // segments past w contribute nothing (their symbols are 0)
+    if (sg < w) {
+      const float lo = bp[j], hi = bp[j + 1];
+      const float g = fmaxf(lo - paa[1][sg], 0.0f) + fmaxf(paa[2][sg] - hi, 0.0f);
+      v = fm * (g * g);
+    }
+    table[idx] = v;
   }
   // approximate search leaf: descend the tree along the query's word
   uint8_t word[kMaxSeg];
@@ -307,15 +400,14 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
     node = ix.root_node[(int)(s_best & 0xffffffffu)];
   }
   if (tid == 0) {
-    for (int guard = 0; guard < 4096 && ix.nodes[node].seg >= 0; ++guard) {
-      const NodeDev& nd = ix.nodes[node];
-      const int sg = nd.seg;
-      const int bit = (word[sg] >> (cb - 1 - nd.bits[sg])) & 1;
-      int ch = nd.child[bit];
-      if (ch < 0) ch = nd.child[bit ^ 1];
-      node = ch;
+    int4 t = ix.tree[node];
+    for (int guard = 0; guard < 4096 && t.x >= 0; ++guard) {
+      const int bit = (word[t.x & 0xff] >> (t.x >> 8)) & 1;
+      int ch = bit ? t.w : t.z;
+      if (ch < 0) ch = bit ? t.z : t.w;
+      t = ix.tree[ch];
     }
-    int64_t b = ix.nodes[node].begin, e = ix.nodes[node].end;
+    int64_t b = t.y, e = t.z;
     if (e - b > kApproxCap) e = b + kApproxCap;
     if (e - b < p.k) {
       e = b + p.k < ix.n ? b + p.k : ix.n;
@@ -324,220 +416,532 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
     s.approx_range[2 * q] = b;
     s.approx_range[2 * q + 1] = e;
     s.log_count[q] = 0;
-    s.cand_count[q] = 0;
-    s.next[q] = 0;
-    s.done[q] = 0;
-    s.sel_done[q] = 0;
     s.status[q] = 0;
   }
   for (int j = tid; j < p.k; j += blockDim.x) s.slots[(int64_t)q * p.k + j] = kEmptyKey;
   for (int j = tid; j < kStatCount; j += blockDim.x) s.stats[(int64_t)q * kStatCount + j] = 0;
+  for (int j = tid; j < kCounterInts; j += blockDim.x) s.next[(int64_t)q * kCounterInts + j] = 0;
 }
 
 // ---------------------------------------------------------------------------
-// Shared per-candidate step: offer a refined distance to the k best and log
-// it if it lies within the near-tie window of the k-th best.
+// Offer of refined distances (one lane per candidate): insert into the k
+// best if below the (cached) k-th best; log if within the near-tie window of
+// it.  `ckey` is this lane's view of slot k-1, never below the true one.
 
-__device__ __forceinline__ void offer(const QueryParams& p, const QueryState& s, int q, float d2,
-                                      int64_t pos, uint32_t id, bool log_it) {
+__device__ __forceinline__ bool offer(const IndexDev& ix, const QueryParams& p, const QueryState& s,
+                                      int q, float d2, int64_t pos, unsigned long long ckey,
+                                      bool log_it) {
+  if (!(d2 <= key_dist(ckey) * p.win)) return false;
   unsigned long long* slots = s.slots + (int64_t)q * p.k;
-  const float thr = kth_dist(slots, p.k);
-  const unsigned long long key = pack_key(d2, id);
-  if (key < __atomic_load_n(&slots[p.k - 1], __ATOMIC_RELAXED)) topk_insert(slots, p.k, key);
-  if (log_it && d2 <= thr * p.win) {
+  const unsigned long long key = pack_key(d2, (uint32_t)ix.perm[pos]);
+  if (log_it) {
     const int i = atomicAdd(&s.log_count[q], 1);
     if (i < p.log_cap) s.log[(int64_t)q * p.log_cap + i] = pack_key(d2, (uint32_t)pos);
   }
-}
-
-template <int R, bool MASK>
-__device__ float dtw_fp32(const float* __restrict__ qpad, const float* __restrict__ x, int len,
-                          int r, float cutoff) {
-  return dtw_band<R, MASK>(qpad, x, len, r, cutoff);
+  if (key < ckey) {
+    topk_insert(slots, p.k, key);
+    return true;
+  }
+  return false;
 }
 
 // ---------------------------------------------------------------------------
-// approx: refine the approximate-search range.  ED: one wave per series;
-// DTW: one thread per series.  Distances go to approx_d2 (logged later by
-// select, once the first k-th best is known).
+// stage1: blocks [0, A) refine the approximate range, blocks [A, ..) compute
+// the bound of every leaf and its bucket histogram.
 
 template <int R, bool MASK>
-__global__ __launch_bounds__(256) void k_approx(IndexDev ix, QueryParams p, QueryState s) {
+__global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, QueryState s,
+                                                int approx_blocks) {
   const int q = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1);
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int len = p.len;
   extern __shared__ float sm[];
+  const float* zq = s.zq + (int64_t)q * len;
+  if ((int)blockIdx.x >= approx_blocks) {
+    // leaf bounds (Algorithm 7's FindDist for every leaf)
+    const int w = p.w, cb = p.card_bits, card = 1 << cb;
+    float* bp = sm;
+    float* pa = bp + 257;
+    int* hist = reinterpret_cast<int*>(pa + 2 * kMaxSeg);
+    for (int j = tid; j <= card; j += blockDim.x) bp[j] = ix.bp[j];
+    if (tid < kMaxSeg) {
+      pa[tid] = s.paa[((int64_t)q * 3 + 1) * kMaxSeg + tid];
+      pa[kMaxSeg + tid] = s.paa[((int64_t)q * 3 + 2) * kMaxSeg + tid];
+    }
+    for (int j = tid; j < kLbBuckets; j += blockDim.x) hist[j] = 0;
+    __syncthreads();
+    const float fm = (float)p.m;
+    const int nb = gridDim.x - approx_blocks;
+    float* lbq = s.leaf_lb + (int64_t)q * p.n_leaves;
+    for (int l = (blockIdx.x - approx_blocks) * blockDim.x + tid; l < p.n_leaves; l += nb * blockDim.x) {
+      const uint4 sy = ix.leaf_sym[l], bi = ix.leaf_bits[l];
+      float lb = 0.0f;
+      for (int sg = 0; sg < w; ++sg) {
+        const int b = (int)byte_of(bi, sg), y = (int)byte_of(sy, sg);
+        const int sh = cb - b;
+        const float lo = bp[y << sh], hi = bp[(y + 1) << sh];
+        const float g = fmaxf(lo - pa[sg], 0.0f) + fmaxf(pa[kMaxSeg + sg] - hi, 0.0f);
+        lb += g * g;
+      }
+      lb *= fm;
+      lbq[l] = lb;
+      const int nchunk = (int)((ix.leaf_end[l] - ix.leaf_begin[l] + kChunkSeries - 1) / kChunkSeries);
+      atomicAdd(&hist[lb_bucket(lb)], nchunk);
+    }
+    __syncthreads();
+    int* gh = s.hist + (int64_t)q * kLbBuckets;
+    for (int j = tid; j < kLbBuckets; j += blockDim.x)
+      if (hist[j]) atomicAdd(&gh[j], hist[j]);
+    return;
+  }
+  // approximate search (Algorithm 5, approxSearch): real distances of the
+  // series of the leaf found by prep
   const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
   const int cnt = (int)(P1 - P0);
-  const float* zq = s.zq + (int64_t)q * len;
   float* approx_d2 = s.approx_d2 + (int64_t)q * kApproxCap;
-  if constexpr (R < 0) {  // ED
+  unsigned long long* slots = s.slots + (int64_t)q * p.k;
+  if constexpr (R == -1) {  // ED: one wave per series
     float* zl = sm;
     for (int t = tid; t < len; t += blockDim.x) zl[t] = zq[t];
     __syncthreads();
-    const int gw = blockIdx.x * (blockDim.x / kWave) + tid / kWave;
-    const int nw = gridDim.x * (blockDim.x / kWave);
+    const int gw = blockIdx.x * (blockDim.x / kWave) + wv;
+    const int nw = approx_blocks * (blockDim.x / kWave);
     for (int j = gw; j < cnt; j += nw) {
       const int64_t pos = P0 + j;
       const float d2 = ed_wave(zl, ix.Z + pos * len, len, lane);
       if (lane == 0) {
         approx_d2[j] = d2;
-        offer(p, s, q, d2, pos, (uint32_t)ix.perm[pos], false);
+        topk_insert(slots, p.k, pack_key(d2, (uint32_t)ix.perm[pos]));
       }
     }
-  } else {  // DTW, band of radius R
+  } else if constexpr (R == -2) {  // DTW, wide band: one wave per series
+    float* ql = sm;
+    float* xl = ql + len;          // [4][len]
+    float* buf = xl + 4 * len;     // [4][3 len]
+    for (int t = tid; t < len; t += blockDim.x) ql[t] = zq[t];
+    __syncthreads();
+    const int gw = blockIdx.x * 4 + wv, nw = approx_blocks * 4;
+    for (int j = gw; j < cnt; j += nw) {
+      const int64_t pos = P0 + j;
+      for (int t = lane; t < len; t += kWave) xl[wv * len + t] = ix.Z[pos * len + t];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      const float d2 = dtw_wave<float>(ql, xl + wv * len, len, p.window, buf + wv * 3 * len,
+                                       (float)INFINITY, lane);
+      if (lane == 0) {
+        approx_d2[j] = d2;
+        topk_insert(slots, p.k, pack_key(d2, (uint32_t)ix.perm[pos]));
+      }
+    }
+  } else {  // DTW, register band: one thread per series
     float* qpad = sm;
     for (int t = tid; t < len + 2 * R; t += blockDim.x)
       qpad[t] = (t >= R && t < R + len) ? zq[t - R] : INFINITY;
     __syncthreads();
-    for (int j = blockIdx.x * blockDim.x + tid; j < cnt; j += gridDim.x * blockDim.x) {
+    for (int j = blockIdx.x * blockDim.x + tid; j < cnt; j += approx_blocks * blockDim.x) {
       const int64_t pos = P0 + j;
-      const float d2 = dtw_fp32<R, MASK>(qpad, ix.Z + pos * len, len, p.window, INFINITY);
+      const float d2 = dtw_band<R, MASK>(qpad, ix.Z + pos * len, len, p.window, INFINITY);
       approx_d2[j] = d2;
-      offer(p, s, q, d2, pos, (uint32_t)ix.perm[pos], false);
+      topk_insert(slots, p.k, pack_key(d2, (uint32_t)ix.perm[pos]));
     }
   }
 }
 
-// Radii beyond the register band: one wave per series, anti-diagonals.
-__global__ __launch_bounds__(256) void k_approx_wave(IndexDev ix, QueryParams p, QueryState s) {
+// ---------------------------------------------------------------------------
+// stage2: counting scatter of the leaves into bucket order; block 0 also
+// logs the approximate-range distances inside the near-tie window of the
+// first k-th best.
+
+__global__ __launch_bounds__(1024) void k_stage2(IndexDev ix, QueryParams p, QueryState s) {
+  const int q = blockIdx.y;
+  const int tid = threadIdx.x;
+  __shared__ int base[kLbBuckets];  // bucket starts, then this block's slice starts
+  __shared__ int cnt[kLbBuckets];   // this block's leaves per bucket, then cursors
+  __shared__ int part[1024];
+  const int* gh = s.hist + (int64_t)q * kLbBuckets;
+  constexpr int per = kLbBuckets / 1024;
+  int loc[per];
+  int sum = 0;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    loc[j] = gh[tid * per + j];
+    sum += loc[j];
+    cnt[tid * per + j] = 0;
+  }
+  part[tid] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = tid >= o ? part[tid - o] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  int run = part[tid] - sum;
+#pragma unroll
+  for (int j = 0; j < per; ++j) {
+    base[tid * per + j] = run;
+    run += loc[j];
+  }
+  if (blockIdx.x == 0 && tid == 1023) s.n_items[q] = part[1023];
+  // this block's contiguous slice of leaves
+  const int L = p.n_leaves;
+  const int chunk = (L + gridDim.x - 1) / gridDim.x;
+  const int l0 = blockIdx.x * chunk;
+  const int l1 = l0 + chunk < L ? l0 + chunk : L;
+  const float* lbq = s.leaf_lb + (int64_t)q * L;
+  __syncthreads();
+  for (int l = l0 + tid; l < l1; l += blockDim.x) {
+    const int nc = (int)((ix.leaf_end[l] - ix.leaf_begin[l] + kChunkSeries - 1) / kChunkSeries);
+    atomicAdd(&cnt[lb_bucket(lbq[l])], nc);
+  }
+  __syncthreads();
+  // one global reservation per bucket present in the slice
+  int* fill = s.fill + (int64_t)q * kLbBuckets;
+  for (int b = tid; b < kLbBuckets; b += blockDim.x) {
+    const int c = cnt[b];
+    if (c) base[b] += atomicAdd(&fill[b], c);
+    cnt[b] = 0;
+  }
+  __syncthreads();
+  unsigned long long* items = s.items + (int64_t)q * p.item_cap;
+  int2* ranges = s.ranges + (int64_t)q * p.item_cap;
+  for (int l = l0 + tid; l < l1; l += blockDim.x) {
+    const float lb = lbq[l];
+    const int b = lb_bucket(lb);
+    const int lbeg = (int)ix.leaf_begin[l], lend = (int)ix.leaf_end[l];
+    const int nc = (lend - lbeg + kChunkSeries - 1) / kChunkSeries;
+    const int at = base[b] + atomicAdd(&cnt[b], nc);
+    const unsigned long long it = ((unsigned long long)__float_as_uint(lb) << 32) | (unsigned)l;
+    for (int c = 0; c < nc; ++c) {
+      const int cb = lbeg + c * kChunkSeries;
+      items[at + c] = it;
+      ranges[at + c] = make_int2(cb, cb + kChunkSeries < lend ? cb + kChunkSeries : lend);
+    }
+  }
+  if (blockIdx.x == 0) {
+    const unsigned long long* slots = s.slots + (int64_t)q * p.k;
+    const float win = kth_dist(slots, p.k) * p.win;
+    const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
+    const float* ad = s.approx_d2 + (int64_t)q * kApproxCap;
+    for (int j = tid; j < (int)(P1 - P0); j += blockDim.x) {
+      const float d2 = ad[j];
+      if (d2 <= win) {
+        const int i = atomicAdd(&s.log_count[q], 1);
+        if (i < p.log_cap) s.log[(int64_t)q * p.log_cap + i] = pack_key(d2, (uint32_t)(P0 + j));
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// process: persistent blocks over the ordered leaf chunks.
+// R = -1: ED; R >= 0: DTW with a register band of radius R; R = -2: DTW by
+// wave anti-diagonals (radius beyond the register band).
+//
+// A block takes kGrab consecutive chunks of one shard with one atomic (one
+// chunk per wave).  Each wave computes the series bounds of its chunk and
+// appends the survivors to the block's list in LDS; then all waves refine
+// the list together, eight rows per wave at a time.  For DTW the LB_Keogh
+// survivors wait in a block list until there is one pair per thread.
+
+constexpr int kUnroll = kChunkSeries / kWave;  // words per lane per chunk
+
+template <int R>
+struct ProcShape {
+  static constexpr int waves = (R == -2) ? 4 : kGrab;  // one chunk per wave
+  static constexpr int threads = waves * kWave;
+  static constexpr int surv_cap = waves * kChunkSeries;
+  static constexpr int pend_cap = (R >= 0) ? surv_cap + threads : 0;
+};
+
+template <int R, bool MASK>
+__global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, QueryParams p,
+                                                                   QueryState s) {
+  using Sh = ProcShape<R>;
+  constexpr int kW = Sh::waves;
   const int q = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int len = p.len;
+  const int len = p.len, card = 1 << p.card_bits, k = p.k;
+  constexpr bool dtw = R != -1;
   extern __shared__ float sm[];
-  float* ql = sm;
-  float* xl = ql + len;              // [4][len]
-  float* buf = xl + 4 * len;         // [4][3 len]
-  const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
-  const int cnt = (int)(P1 - P0);
+  float* table = sm;                          // [16][card]
+  float* ql = table + kMaxSeg * card;         // query (ED, wave DTW) / padded query (band DTW)
+  const int qlen = (R >= 0) ? len + 2 * R : len;
+  float* U = ql + qlen;                       // envelope (DTW)
+  float* Lw = U + (dtw ? len : 0);
+  int* surv = reinterpret_cast<int*>(Lw + (dtw ? len : 0));     // survivors of a grab
+  float* survlb = reinterpret_cast<float*>(surv + Sh::surv_cap);  // their bounds
+  int* pend = reinterpret_cast<int*>(survlb + Sh::surv_cap);    // DTW pairs waiting
+  float* wx = reinterpret_cast<float*>(pend + Sh::pend_cap);     // wave DTW rows [kW][len]
+  float* wbuf = wx + (R == -2 ? kW * len : 0);                   // wave DTW [kW][3 len]
+  __shared__ int s_batch, s_shard, s_stop, s_nsurv, s_npend;
+  __shared__ unsigned long long s_ckey;
+
+  const float* tq = s.table + (int64_t)q * kMaxSeg * card;
+  for (int i = tid; i < kMaxSeg * card; i += blockDim.x) table[i] = tq[i];
   const float* zq = s.zq + (int64_t)q * len;
-  for (int t = tid; t < len; t += blockDim.x) ql[t] = zq[t];
-  __syncthreads();
-  const int gw = blockIdx.x * 4 + wv, nw = gridDim.x * 4;
-  for (int j = gw; j < cnt; j += nw) {
-    const int64_t pos = P0 + j;
-    for (int t = lane; t < len; t += kWave) xl[wv * len + t] = ix.Z[pos * len + t];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const float d2 = dtw_wave<float>(ql, xl + wv * len, len, p.window, buf + wv * 3 * len,
-                                     (float)INFINITY, lane);
-    if (lane == 0) {
-      s.approx_d2[(int64_t)q * kApproxCap + j] = d2;
-      offer(p, s, q, d2, pos, (uint32_t)ix.perm[pos], false);
+  if (R >= 0) {
+    for (int t = tid; t < qlen; t += blockDim.x) ql[t] = (t >= R && t < R + len) ? zq[t - R] : INFINITY;
+  } else {
+    for (int t = tid; t < len; t += blockDim.x) ql[t] = zq[t];
+  }
+  if (dtw) {
+    for (int t = tid; t < len; t += blockDim.x) {
+      U[t] = s.upper[(int64_t)q * len + t];
+      Lw[t] = s.lower[(int64_t)q * len + t];
     }
   }
-}
-
-// ---------------------------------------------------------------------------
-// select: leaf bounds, kept leaves, and (last block) approx-range logging and
-// the bucket order of the kept leaves.
-
-__global__ __launch_bounds__(kSelectThreads) void k_select(IndexDev ix, QueryParams p, QueryState s,
-                                                           unsigned long long* __restrict__ cand_sorted) {
-  const int q = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1);
-  const int w = p.w, cb = p.card_bits, card = 1 << cb;
-  __shared__ float bp[257];
-  __shared__ float pa[2][kMaxSeg];
-  __shared__ int hist[kBuckets];
-  __shared__ int s_last;
-  for (int j = tid; j <= card; j += blockDim.x) bp[j] = ix.bp[j];
-  if (tid < kMaxSeg) {
-    pa[0][tid] = s.paa[((int64_t)q * 3 + 1) * kMaxSeg + tid];
-    pa[1][tid] = s.paa[((int64_t)q * 3 + 2) * kMaxSeg + tid];
-  }
-  __syncthreads();
-  unsigned long long* slots = s.slots + (int64_t)q * p.k;
-  const float thr = kth_dist(slots, p.k);
-  const float thr_adj = lb_threshold(thr, p);
-  const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
-  const int L = p.n_leaves;
-  unsigned long long* cand = s.cand + (int64_t)q * L;
-  const float fm = (float)p.m;
-  for (int l0 = blockIdx.x * blockDim.x; l0 < L; l0 += gridDim.x * blockDim.x) {
-    const int l = l0 + tid;
-    bool keep = false;
-    float lb = 0.0f;
-    if (l < L) {
-      const uint4 sy = ix.leaf_sym[l], bi = ix.leaf_bits[l];
-      for (int sg = 0; sg < w; ++sg) {
-        const int b = (int)byte_of(bi, sg), y = (int)byte_of(sy, sg);
-        const int sh = cb - b;
-        const float lo = bp[y << sh], hi = bp[(y + 1) << sh];
-        const float g = fmaxf(lo - pa[0][sg], 0.0f) + fmaxf(pa[1][sg] - hi, 0.0f);
-        lb += g * g;
-      }
-      lb *= fm;
-      const bool inside = ix.leaf_begin[l] >= P0 && ix.leaf_end[l] <= P1;
-      keep = lb <= thr_adj && !inside;
-    }
-    const unsigned long long mask = __ballot(keep);
-    if (mask) {
-      int base = 0;
-      const int leader = __ffsll((long long)mask) - 1;
-      if (lane == leader) base = atomicAdd(&s.cand_count[q], __popcll(mask));
-      base = __shfl(base, leader, kWave);
-      if (keep) {
-        const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-        cand[base + __popcll(mask & below)] = ((unsigned long long)__float_as_uint(lb) << 32) | (unsigned)l;
-      }
-    }
-  }
-  // the last block of this query finishes the phase
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&s.sel_done[q], 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  // approx-range distances inside the near-tie window of the first k-th best
-  const float win = thr * p.win;
-  const float* ad = s.approx_d2 + (int64_t)q * kApproxCap;
-  for (int j = tid; j < (int)(P1 - P0); j += blockDim.x) {
-    const float d2 = ad[j];
-    if (d2 <= win) {
-      const int i = atomicAdd(&s.log_count[q], 1);
-      if (i < p.log_cap) s.log[(int64_t)q * p.log_cap + i] = pack_key(d2, (uint32_t)(P0 + j));
-    }
-  }
-  // bucket order of the kept leaves
-  const int cnt = __atomic_load_n(&s.cand_count[q], __ATOMIC_RELAXED);
+  unsigned long long* slots = s.slots + (int64_t)q * k;
   if (tid == 0) {
-    s.cand_thr[q] = thr_adj;
-    s.stats[(int64_t)q * kStatCount + kStatLeavesKept] = (unsigned long long)cnt;
+    s_ckey = load_key(&slots[k - 1]);
+    s_nsurv = 0;
+    s_npend = 0;
+    s_shard = blockIdx.x % kShards;
   }
-  for (int b = tid; b < kBuckets; b += blockDim.x) hist[b] = 0;
   __syncthreads();
-  for (int i = tid; i < cnt; i += blockDim.x) atomicAdd(&hist[bucket_of(key_dist(cand[i]), thr_adj)], 1);
-  __syncthreads();
-  // exclusive scan over the buckets (kBuckets == blockDim)
-  const int mine = hist[tid];
-  for (int o = 1; o < kBuckets; o <<= 1) {
-    const int v = tid >= o ? hist[tid - o] : 0;
+
+  const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
+  const unsigned long long* items = s.items + (int64_t)q * p.item_cap;
+  const int2* ranges = s.ranges + (int64_t)q * p.item_cap;
+  const int n_items = s.n_items[q];
+  int* counters = s.next + (int64_t)q * kCounterInts;
+  unsigned long long* finished =
+      reinterpret_cast<unsigned long long*>(counters + kShards * kCounterStride);
+  unsigned long long c_lb = 0, c_lbk = 0, c_ref = 0, c_leaf = 0;
+
+  // DTW pairs in the pending list, one per thread, first `cnt` entries
+  auto run_pairs = [&](int cnt, unsigned long long ck) {
+    if constexpr (R >= 0) {
+      const float cut = key_dist(ck) * p.win * p.win;
+      bool ch = false;
+      unsigned long long mine = ck;
+      if (tid < cnt) {
+        const int pp = pend[tid];
+        const float e = dtw_band<(R >= 0 ? R : 0), MASK>(ql, ix.Z + (int64_t)pp * len, len, p.window, cut);
+        ++c_ref;
+        if (e < INFINITY) ch = offer(ix, p, s, q, e, pp, ck, true);
+      }
+      if (__ballot(ch) && lane == 0) {
+        mine = load_key(&slots[k - 1]);
+        atomicMin(&s_ckey, mine);
+      }
+    }
+  };
+
+  for (;;) {
+    if (tid == 0) {
+      s_stop = 0;
+      const unsigned long long fin = load_relaxed(finished);
+      if (fin == ~0ull) {
+        s_stop = 1;
+      } else {
+        int shard = s_shard;
+        if ((fin >> shard) & 1ull) {  // next unfinished shard after this one
+          const unsigned long long rot = ~((fin >> shard) | (fin << ((kShards - shard) & 63)));
+          shard = (shard + __ffsll((long long)rot) - 1) & (kShards - 1);
+        }
+        s_shard = shard;
+        s_batch = atomicAdd(&counters[shard * kCounterStride], 1);
+        s_ckey = umin64(s_ckey, load_key(&slots[k - 1]));
+      }
+    }
     __syncthreads();
-    hist[tid] += v;
+    if (s_stop) break;
+    const int shard = s_shard;
+    unsigned long long ckey = s_ckey;
+    const float tadj = lb_threshold(key_dist(ckey), p);
+    // one chunk per wave
+    const int i = (s_batch * kW + wv) * kShards + shard;
+    bool take = false;
+    int2 rg = make_int2(0, 0);
+    if (i < n_items) {
+      const unsigned long long item = items[i];
+      rg = ranges[i];
+      const float lb = key_dist(item);
+      take = lb <= tadj;
+      if (!take && bucket_floor(lb_bucket(lb)) > tadj && lane == 0)  // all later chunks above too
+        atomicOr(finished, 1ull << shard);
+    } else if (lane == 0) {
+      atomicOr(finished, 1ull << shard);
+    }
+    if (take) {
+      c_leaf += (lane == 0) ? 1 : 0;
+      // series bounds (Algorithm 9 / Algorithm 10, first test)
+      uint4 wd[kUnroll];
+      bool ok[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int pos = rg.x + lane + u * kWave;
+        ok[u] = pos < rg.y && !(pos >= P0 && pos < P1);
+        if (ok[u]) wd[u] = ix.words[pos];
+      }
+      float lbv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        lbv[u] = 0.0f;
+        if (ok[u]) {
+          // all sixteen lookups are independent; summed pairwise
+          float t[kMaxSeg];
+#pragma unroll
+          for (int sg = 0; sg < kMaxSeg; ++sg) t[sg] = table[sg * card + (int)byte_of(wd[u], sg)];
+#pragma unroll
+          for (int h = kMaxSeg / 2; h >= 1; h >>= 1)
+#pragma unroll
+            for (int sg = 0; sg < h; ++sg) t[sg] = t[sg] + t[sg + h];
+          ++c_lb;
+          lbv[u] = t[0];
+          ok[u] = lbv[u] <= tadj;
+        }
+      }
+      int nmine = 0;
+      unsigned long long msk[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        msk[u] = __ballot(ok[u]);
+        nmine += __popcll(msk[u]);
+      }
+      if (nmine) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_nsurv, nmine);
+        base = __shfl(base, 0, kWave);
+        const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (ok[u]) {
+            const int at = base + __popcll(msk[u] & below);
+            surv[at] = rg.x + lane + u * kWave;
+            survlb[at] = lbv[u];
+          }
+          base += __popcll(msk[u]);
+        }
+      }
+    }
+    __syncthreads();
+    // refine the grab's survivors, eight rows per wave; bounds re-checked
+    // against the latest k-th best this wave knows
+    const int ns = s_nsurv;
+    for (int g = wv * kGroup; g < ns; g += kW * kGroup) {
+      const float tcur = lb_threshold(key_dist(ckey), p);
+      int gp[kGroup];
+      unsigned act = 0;
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        const bool in = g + c < ns;
+        gp[c] = in ? surv[g + c] : 0;
+        act |= (in && survlb[g + c] <= tcur) ? (1u << c) : 0u;
+      }
+      if (!act) continue;
+      float dv[kGroup];
+      if constexpr (!dtw) {
+        ed_group(ql, ix.Z, len, gp, act, lane, dv);
+        c_ref += (lane == 0) ? __popc(act) : 0;
+        // distances are wave-uniform: the rare ones inside the window of
+        // the k-th best are offered by lane 0
+        bool ch = false;
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c)
+          if (((act >> c) & 1u) && dv[c] <= key_dist(ckey) * p.win && lane == 0)
+            ch |= offer(ix, p, s, q, dv[c], gp[c], ckey, true);
+        if (__ballot(ch)) ckey = umin64(ckey, load_key(&slots[k - 1]));
+      } else {
+        // LB_Keogh on the raw values (Algorithm 10, second test)
+        lbk_group(U, Lw, ix.Z, len, gp, act, lane, dv);
+        c_lbk += (lane == 0) ? __popc(act) : 0;
+        const float tk = key_dist(ckey) * p.win * p.win;
+        if constexpr (R >= 0) {
+          unsigned pass = 0;
+#pragma unroll
+          for (int c = 0; c < kGroup; ++c)
+            pass |= (((act >> c) & 1u) && dv[c] <= tk) ? (1u << c) : 0u;
+          if (pass) {
+            int at = 0;
+            if (lane == 0) at = atomicAdd(&s_npend, __popc(pass));
+            at = __shfl(at, 0, kWave);
+#pragma unroll
+            for (int c = 0; c < kGroup; ++c)
+              if ((pass >> c) & 1u) {
+                if (lane == 0) pend[at] = gp[c];
+                ++at;
+              }
+          }
+        } else {
+#pragma unroll 1
+          for (int c = 0; c < kGroup; ++c) {
+            if (!((act >> c) & 1u) || !(dv[c] <= tk)) continue;
+            const int pos = gp[c];
+            const float* x = ix.Z + (int64_t)pos * len;
+            for (int t = lane; t < len; t += kWave) wx[wv * len + t] = x[t];
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const float cut = key_dist(ckey) * p.win * p.win;
+            const float e = dtw_wave<float>(ql, wx + wv * len, len, p.window, wbuf + wv * 3 * len,
+                                            cut, lane);
+            bool ch = false;
+            if (lane == 0) {
+              ++c_ref;
+              ch = e < INFINITY && offer(ix, p, s, q, e, pos, ckey, true);
+            }
+            if (__ballot(ch)) ckey = umin64(ckey, load_key(&slots[k - 1]));
+          }
+        }
+      }
+    }
+    if (lane == 0) atomicMin(&s_ckey, ckey);
+    __syncthreads();
+    if constexpr (R >= 0) {
+      // full rounds of one DTW pair per thread; the rest waits for more
+      int np = s_npend;
+      while (np >= Sh::threads) {
+        run_pairs(Sh::threads, s_ckey);
+        __syncthreads();
+        const int rem = np - Sh::threads;  // move the rest to the front, block-uniform steps
+        for (int b0 = 0; b0 < rem; b0 += Sh::threads) {
+          const int t = b0 + tid;
+          const int v = t < rem ? pend[Sh::threads + t] : 0;
+          __syncthreads();
+          if (t < rem) pend[t] = v;
+          __syncthreads();
+        }
+        np = rem;
+      }
+      if (tid == 0) s_npend = np;
+    }
+    if (tid == 0) s_nsurv = 0;
     __syncthreads();
   }
-  hist[tid] -= mine;
-  __syncthreads();
-  unsigned long long* out = cand_sorted + (int64_t)q * L;
-  for (int i = tid; i < cnt; i += blockDim.x) {
-    const unsigned long long c = cand[i];
-    const int at = atomicAdd(&hist[bucket_of(key_dist(c), thr_adj)], 1);
-    out[at] = c;
+  if constexpr (R >= 0) {  // the block's last DTW pairs
+    const int np = s_npend;
+    if (np > 0) run_pairs(np, s_ckey);
+  }
+  // statistics
+  for (int o = 32; o >= 1; o >>= 1) {
+    c_lb += __shfl_xor(c_lb, o, kWave);
+    c_lbk += __shfl_xor(c_lbk, o, kWave);
+    c_ref += __shfl_xor(c_ref, o, kWave);
+    c_leaf += __shfl_xor(c_leaf, o, kWave);
+  }
+  if (lane == 0) {
+    unsigned long long* stq = s.stats + (int64_t)q * kStatCount;
+    if (c_leaf) atomicAdd(&stq[kStatLeavesKept], c_leaf);
+    if (c_lb) atomicAdd(&stq[kStatSeriesLb], c_lb);
+    if (c_lbk) atomicAdd(&stq[kStatLbKeogh], c_lbk);
+    if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
   }
 }
 
 // ---------------------------------------------------------------------------
-// Finalisation (last block of the process phase for a query): FP64 recheck
-// of the near ties, exact (distance, id) order, outputs.  The log is taken
-// in chunks; each chunk's candidates in the window are recomputed in FP64
-// and merged with the running k best by rank, so any number of ties fits.
+// finalize: one block per query.  FP64 recheck of the near ties, exact
+// (distance, id) order, outputs.  The log is taken in chunks; each chunk's
+// candidates in the window are recomputed in FP64 and merged with the
+// running k best by rank, so any number of ties fits.
 
-__device__ void finalize(const IndexDev& ix, const QueryParams& p, const QueryState& s, int q,
-                         float* sm, int64_t* out_ids, float* out_dists) {
+__global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryParams p, QueryState s,
+                                                           int64_t* __restrict__ out_ids,
+                                                           float* __restrict__ out_dists) {
+  const int q = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int len = p.len, k = p.k;
+  extern __shared__ float sm[];
   // layout: E[kTopCap] doubles | pos[kTopCap] | id[kTopCap] | q[len] |
   // x rows[fin_waves][len] | (8-byte aligned) DP buffers[fin_waves][3 len] doubles
   double* E = reinterpret_cast<double*>(sm);
@@ -551,7 +955,7 @@ __device__ void finalize(const IndexDev& ix, const QueryParams& p, const QuerySt
   const unsigned long long* slots = s.slots + (int64_t)q * k;
   const float T = kth_dist(slots, k);
   const float win = T * p.win;
-  const int lc = __atomic_load_n(&s.log_count[q], __ATOMIC_RELAXED);
+  const int lc = s.log_count[q];
   if (lc > p.log_cap) {
     if (tid == 0) s.status[q] |= 1;
     return;
@@ -650,183 +1054,9 @@ __device__ void finalize(const IndexDev& ix, const QueryParams& p, const QuerySt
 }
 
 // ---------------------------------------------------------------------------
-// process: persistent blocks over the ordered candidate leaves.
-// R = -1: ED; R >= 0: DTW with a register band of radius R; R = -2: DTW by
-// wave anti-diagonals (radius beyond the register band).
-
-template <int R, bool MASK>
-__global__ __launch_bounds__(kProcThreads) void k_process(IndexDev ix, QueryParams p, QueryState s,
-                                                          const unsigned long long* __restrict__ cand_sorted,
-                                                          int64_t* __restrict__ out_ids,
-                                                          float* __restrict__ out_dists) {
-  const int q = blockIdx.y;
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int len = p.len, w = p.w, card = 1 << p.card_bits, k = p.k;
-  const bool dtw = R != -1;
-  extern __shared__ float sm[];
-  float* table = sm;                          // [w][card]
-  float* ql = table + w * card;               // query (ED) / padded query (band DTW)
-  const int qlen = (R >= 0) ? len + 2 * R : len;
-  float* U = ql + qlen;                       // envelope (DTW)
-  float* Lw = U + (dtw ? len : 0);
-  int* list = reinterpret_cast<int*>(Lw + (dtw ? len : 0));   // [kTile] series survivors
-  int* list2 = list + kTile;                                  // [kTile] LB_Keogh survivors
-  float* wx = reinterpret_cast<float*>(list2 + kTile);        // wave DTW: [4][len] rows
-  float* wbuf = wx + 4 * len;                                 // wave DTW: [4][3 len]
-  __shared__ int s_item_leaf;
-  __shared__ int s_stop;
-  __shared__ int n1, n2;
-  __shared__ unsigned long long st_lb, st_lbk, st_ref;
-  __shared__ int s_last;
-
-  const float* tq = s.table + (int64_t)q * w * card;
-  for (int i = tid; i < w * card; i += blockDim.x) table[i] = tq[i];
-  const float* zq = s.zq + (int64_t)q * len;
-  if (R >= 0) {
-    for (int t = tid; t < qlen; t += blockDim.x) ql[t] = (t >= R && t < R + len) ? zq[t - R] : INFINITY;
-  } else {
-    for (int t = tid; t < len; t += blockDim.x) ql[t] = zq[t];
-  }
-  if (dtw) {
-    for (int t = tid; t < len; t += blockDim.x) {
-      U[t] = s.upper[(int64_t)q * len + t];
-      Lw[t] = s.lower[(int64_t)q * len + t];
-    }
-  }
-  if (tid == 0) {
-    st_lb = 0;
-    st_lbk = 0;
-    st_ref = 0;
-  }
-  __syncthreads();
-
-  unsigned long long* slots = s.slots + (int64_t)q * k;
-  const int cnt = __atomic_load_n(&s.cand_count[q], __ATOMIC_RELAXED);
-  const float thr0 = s.cand_thr[q];
-  const float bw = thr0 / (float)kBuckets;
-  const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
-  const unsigned long long* items = cand_sorted + (int64_t)q * p.n_leaves;
-  unsigned long long c_lb = 0, c_lbk = 0, c_ref = 0;
-
-  for (;;) {
-    if (tid == 0) {
-      s_stop = 0;
-      const int i = atomicAdd(&s.next[q], 1);
-      if (i >= cnt) {
-        s_stop = 1;
-      } else {
-        const unsigned long long it = items[i];
-        const float lb = key_dist(it);
-        const float tadj = lb_threshold(kth_dist(slots, k), p);
-        if (lb > tadj) {
-          // every later leaf is in a bucket at least this one's floor
-          const float floor_b = (float)bucket_of(lb, thr0) * bw;
-          s_stop = floor_b > tadj ? 1 : 2;
-        }
-        s_item_leaf = (int)(it & 0xffffffffu);
-      }
-    }
-    __syncthreads();
-    const int stop = s_stop;
-    if (stop == 1) break;
-    if (stop == 2) {
-      __syncthreads();
-      continue;
-    }
-    const int leaf = s_item_leaf;
-    const int64_t lb_ = ix.leaf_begin[leaf], le_ = ix.leaf_end[leaf];
-    for (int64_t t0 = lb_; t0 < le_; t0 += kTile) {
-      const int64_t t1 = t0 + kTile < le_ ? t0 + kTile : le_;
-      if (tid == 0) {
-        n1 = 0;
-        n2 = 0;
-      }
-      __syncthreads();
-      const float tadj = lb_threshold(kth_dist(slots, k), p);
-      // series-level bounds (Algorithm 9 / Algorithm 10, first test)
-      for (int64_t pos = t0 + tid; pos < t1; pos += blockDim.x) {
-        if (pos >= P0 && pos < P1) continue;  // refined by the approximate search
-        const uint4 wd = ix.words[pos];
-        float lb = 0.0f;
-        for (int sg = 0; sg < w; ++sg) lb += table[sg * card + (int)byte_of(wd, sg)];
-        ++c_lb;
-        if (lb <= tadj) list[atomicAdd(&n1, 1)] = (int)(pos - t0);
-      }
-      __syncthreads();
-      const int m1 = n1;
-      if (!dtw) {
-        for (int c = wv; c < m1; c += blockDim.x / kWave) {
-          const int64_t pos = t0 + list[c];
-          const float d2 = ed_wave(ql, ix.Z + pos * len, len, lane);
-          if (lane == 0) {
-            ++c_ref;
-            offer(p, s, q, d2, pos, (uint32_t)ix.perm[pos], true);
-          }
-        }
-      } else {
-        // LB_Keogh on the raw values (Algorithm 10, second test)
-        const float tk = kth_dist(slots, k) * p.win * p.win;
-        for (int c = wv; c < m1; c += blockDim.x / kWave) {
-          const int64_t pos = t0 + list[c];
-          const float lbk = lbk_wave(U, Lw, ix.Z + pos * len, len, lane);
-          if (lane == 0) {
-            ++c_lbk;
-            if (lbk <= tk) list2[atomicAdd(&n2, 1)] = list[c];
-          }
-        }
-        __syncthreads();
-        const int m2 = n2;
-        const float cut = kth_dist(slots, k) * p.win * p.win;
-        if constexpr (R >= 0) {
-          for (int c = tid; c < m2; c += blockDim.x) {
-            const int64_t pos = t0 + list2[c];
-            const float d2 = dtw_band<R, MASK>(ql, ix.Z + pos * len, len, p.window, cut);
-            ++c_ref;
-            if (d2 < INFINITY) offer(p, s, q, d2, pos, (uint32_t)ix.perm[pos], true);
-          }
-        } else {
-          for (int c = wv; c < m2; c += blockDim.x / kWave) {
-            const int64_t pos = t0 + list2[c];
-            const float* x = ix.Z + pos * len;
-            for (int t = lane; t < len; t += kWave) wx[wv * len + t] = x[t];
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            const float d2 = dtw_wave<float>(ql, wx + wv * len, len, p.window, wbuf + wv * 3 * len,
-                                             cut, lane);
-            if (lane == 0) {
-              ++c_ref;
-              if (d2 < INFINITY) offer(p, s, q, d2, pos, (uint32_t)ix.perm[pos], true);
-            }
-          }
-        }
-      }
-      __syncthreads();
-    }
-  }
-  atomicAdd(&st_lb, c_lb);
-  atomicAdd(&st_lbk, c_lbk);
-  atomicAdd(&st_ref, c_ref);
-  __syncthreads();
-  if (tid == 0) {
-    unsigned long long* stq = s.stats + (int64_t)q * kStatCount;
-    atomicAdd(&stq[kStatSeriesLb], st_lb);
-    atomicAdd(&stq[kStatLbKeogh], st_lbk);
-    atomicAdd(&stq[kStatRefined], st_ref);
-  }
-  // the last block of this query finalises it
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&s.done[q], 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (!s_last) return;
-  __threadfence();
-  finalize(ix, p, s, q, sm, out_ids, out_dists);
-}
-
-// ---------------------------------------------------------------------------
 // Launchers.  The DTW radius picks a register-band instance: exact radii of
 // the common windows, else the next larger band with a mask, else the wave
-// anti-diagonal kernel.
+// anti-diagonal kernels.
 
 #define MESSI_BANDS(X) X(0) X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(25) X(32) X(51) X(64)
 
@@ -847,16 +1077,47 @@ static int pick_band(int r, bool* mask) {
   return -2;
 }
 
-static size_t process_lds_bytes(const QueryParams& p, int R) {
+static int band_of(const QueryParams& p, bool* mask) {
+  *mask = false;
+  return p.distance == 0 ? -1 : pick_band(p.window, mask);
+}
+
+template <int R>
+static size_t process_lds_words(const QueryParams& p) {
+  using Sh = ProcShape<R>;
   const int card = 1 << p.card_bits;
-  const bool dtw = p.distance == 1;
+  const bool dtw = R != -1;
   const int qlen = R >= 0 ? p.len + 2 * R : p.len;
-  size_t words = (size_t)p.w * card + qlen + (dtw ? 2 * p.len : 0) + 2 * kTile;
-  if (R == -2) words += 4 * (size_t)p.len + 4 * 3 * (size_t)p.len;
-  // the finalisation reuses the same space (layout in finalize())
-  const size_t fin = ((((size_t)4 * kTopCap + p.len + (size_t)p.fin_waves * p.len) + 1) & ~(size_t)1) +
-                     (size_t)p.fin_waves * 3 * p.len * 2;
-  return (words > fin ? words : fin) * sizeof(float);
+  size_t words = (size_t)kMaxSeg * card + qlen + (dtw ? 2 * p.len : 0) + 2 * (size_t)Sh::surv_cap +
+                 Sh::pend_cap;
+  if (R == -2) words += (size_t)Sh::waves * 4 * p.len;
+  return words;
+}
+
+size_t process_lds_bytes(const QueryParams& p) {
+  bool mask;
+  const int R = band_of(p, &mask);
+  size_t w = 0;
+  if (R == -1) w = process_lds_words<-1>(p);
+  else if (R == -2) w = process_lds_words<-2>(p);
+  else w = process_lds_words<0>(p) + 2 * (size_t)R;  // the padded query grows with R
+  return w * sizeof(float);
+}
+
+static int process_threads(int R) {
+  return R == -2 ? ProcShape<-2>::threads : (R == -1 ? ProcShape<-1>::threads : ProcShape<0>::threads);
+}
+
+size_t finalize_lds_bytes(const QueryParams& p) {
+  const size_t words = ((((size_t)4 * kTopCap + p.len + (size_t)p.fin_waves * p.len) + 1) & ~(size_t)1) +
+                       (size_t)p.fin_waves * 3 * p.len * 2;
+  return words * sizeof(float);
+}
+
+static size_t stage1_lds_bytes(const QueryParams& p, int R) {
+  const size_t lb_words = 257 + 2 * kMaxSeg + kLbBuckets;
+  const size_t ap_words = R == -1 ? (size_t)p.len : (R == -2 ? 17 * (size_t)p.len : (size_t)p.len + 2 * R);
+  return (lb_words > ap_words ? lb_words : ap_words) * sizeof(float);
 }
 
 void launch_prep(const IndexDev& ix, const float* queries, const QueryParams& qp,
@@ -865,84 +1126,101 @@ void launch_prep(const IndexDev& ix, const float* queries, const QueryParams& qp
   hipLaunchKernelGGL(k_prep, dim3(qp.nq), dim3(256), lds, st, ix, queries, qp, qs);
 }
 
-void launch_approx(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
                    hipStream_t st) {
-  if (qp.distance == 0) {
-    hipLaunchKernelGGL((k_approx<-1, false>), dim3(64, qp.nq), dim3(256), qp.len * sizeof(float),
-                       st, ix, qp, qs);
+  bool mask;
+  const int R = band_of(qp, &mask);
+  const int approx_blocks = R == -1 ? 32 : (R == -2 ? 64 : (kApproxCap + 255) / 256);
+  int lb_blocks = (qp.n_leaves + 1023) / 1024;
+  lb_blocks = lb_blocks > 128 ? 128 : (lb_blocks < 1 ? 1 : lb_blocks);
+  const dim3 g(approx_blocks + lb_blocks, qp.nq);
+  const size_t lds = stage1_lds_bytes(qp, R);
+  if (R == -1) {
+    hipLaunchKernelGGL((k_stage1<-1, false>), g, dim3(256), lds, st, ix, qp, qs, approx_blocks);
     return;
   }
-  bool mask = false;
-  const int R = pick_band(qp.window, &mask);
   if (R == -2) {
-    const size_t lds = (size_t)(qp.len + 4 * qp.len + 12 * qp.len) * sizeof(float);
-    hipLaunchKernelGGL(k_approx_wave, dim3(64, qp.nq), dim3(256), lds, st, ix, qp, qs);
+    hipLaunchKernelGGL((k_stage1<-2, false>), g, dim3(256), lds, st, ix, qp, qs, approx_blocks);
     return;
   }
-  const size_t lds = (size_t)(qp.len + 2 * R) * sizeof(float);
-  const dim3 g((kApproxCap + 255) / 256, qp.nq);
-#define MESSI_APPROX_CASE(RR)                                                                 \
-  if (R == RR) {                                                                              \
-    if (mask)                                                                                 \
-      hipLaunchKernelGGL((k_approx<RR, true>), g, dim3(256), lds, st, ix, qp, qs);            \
-    else                                                                                      \
-      hipLaunchKernelGGL((k_approx<RR, false>), g, dim3(256), lds, st, ix, qp, qs);           \
-    return;                                                                                   \
+#define MESSI_S1_CASE(RR)                                                                          \
+  if (R == RR) {                                                                                   \
+    if (mask)                                                                                      \
+      hipLaunchKernelGGL((k_stage1<RR, true>), g, dim3(256), lds, st, ix, qp, qs, approx_blocks);  \
+    else                                                                                           \
+      hipLaunchKernelGGL((k_stage1<RR, false>), g, dim3(256), lds, st, ix, qp, qs, approx_blocks); \
+    return;                                                                                        \
   }
-  MESSI_BANDS(MESSI_APPROX_CASE)
-#undef MESSI_APPROX_CASE
+  MESSI_BANDS(MESSI_S1_CASE)
+#undef MESSI_S1_CASE
 }
 
-void launch_select(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   unsigned long long* cand_sorted, hipStream_t st) {
-  int blocks = (qp.n_leaves + kSelectThreads - 1) / kSelectThreads;
-  if (blocks > 256) blocks = 256;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_select, dim3(blocks, qp.nq), dim3(kSelectThreads), 0, st, ix, qp, qs,
-                     cand_sorted);
+void launch_stage2(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+                   hipStream_t st) {
+  int blocks = (qp.n_leaves + 4095) / 4096;
+  blocks = blocks > 64 ? 64 : (blocks < 1 ? 1 : blocks);
+  hipLaunchKernelGGL(k_stage2, dim3(blocks, qp.nq), dim3(1024), 0, st, ix, qp, qs);
 }
 
 void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                    const unsigned long long* cand_sorted, int blocks_per_query,
-                    int64_t* out_ids, float* out_dists, hipStream_t st) {
+                    int blocks_per_query, hipStream_t st) {
+  bool mask;
+  const int R = band_of(qp, &mask);
   const dim3 g(blocks_per_query, qp.nq);
-  if (qp.distance == 0) {
-    hipLaunchKernelGGL((k_process<-1, false>), g, dim3(kProcThreads), process_lds_bytes(qp, -1), st,
-                       ix, qp, qs, cand_sorted, out_ids, out_dists);
+  const dim3 b(process_threads(R));
+  const size_t lds = process_lds_bytes(qp);
+  if (R == -1) {
+    hipLaunchKernelGGL((k_process<-1, false>), g, b, lds, st, ix, qp, qs);
     return;
   }
-  bool mask = false;
-  const int R = pick_band(qp.window, &mask);
   if (R == -2) {
-    hipLaunchKernelGGL((k_process<-2, false>), g, dim3(kProcThreads), process_lds_bytes(qp, -2), st,
-                       ix, qp, qs, cand_sorted, out_ids, out_dists);
+    hipLaunchKernelGGL((k_process<-2, false>), g, b, lds, st, ix, qp, qs);
     return;
   }
-  const size_t lds = process_lds_bytes(qp, R);
-#define MESSI_PROC_CASE(RR)                                                                      \
-  if (R == RR) {                                                                                 \
-    if (mask)                                                                                    \
-      hipLaunchKernelGGL((k_process<RR, true>), g, dim3(kProcThreads), lds, st, ix, qp, qs,      \
-                         cand_sorted, out_ids, out_dists);                                       \
-    else                                                                                         \
-      hipLaunchKernelGGL((k_process<RR, false>), g, dim3(kProcThreads), lds, st, ix, qp, qs,     \
-                         cand_sorted, out_ids, out_dists);                                       \
-    return;                                                                                      \
+#define MESSI_PROC_CASE(RR)                                                   \
+  if (R == RR) {                                                              \
+    if (mask)                                                                 \
+      hipLaunchKernelGGL((k_process<RR, true>), g, b, lds, st, ix, qp, qs);   \
+    else                                                                      \
+      hipLaunchKernelGGL((k_process<RR, false>), g, b, lds, st, ix, qp, qs);  \
+    return;                                                                   \
   }
   MESSI_BANDS(MESSI_PROC_CASE)
 #undef MESSI_PROC_CASE
 }
 
-size_t query_process_lds(const QueryParams& qp) {
-  if (qp.distance == 0) return process_lds_bytes(qp, -1);
-  bool mask = false;
-  return process_lds_bytes(qp, pick_band(qp.window, &mask));
+void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+                     int64_t* out_ids, float* out_dists, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(qp.nq), dim3(kProcThreads), finalize_lds_bytes(qp), st, ix,
+                     qp, qs, out_ids, out_dists);
 }
 
-size_t query_process_lds_for(const QueryParams& qp, int fin_waves) {
-  QueryParams p = qp;
-  p.fin_waves = fin_waves;
-  return query_process_lds(p);
+int process_blocks_per_cu(const QueryParams& qp) {
+  bool mask;
+  const int R = band_of(qp, &mask);
+  const size_t lds = process_lds_bytes(qp);
+  const int th = process_threads(R);
+  int nb = 0;
+  hipError_t e = hipSuccess;
+  if (R == -1) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<-1, false>, th, lds);
+  } else if (R == -2) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<-2, false>, th, lds);
+  }
+#define MESSI_OCC_CASE(RR)                                                                  \
+  else if (R == RR) {                                                                       \
+    if (mask)                                                                               \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<RR, true>, th, lds);  \
+    else                                                                                    \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<RR, false>, th, lds); \
+  }
+  MESSI_BANDS(MESSI_OCC_CASE)
+#undef MESSI_OCC_CASE
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return nb > 0 ? nb : 1;
 }
 
 }  // namespace messi
