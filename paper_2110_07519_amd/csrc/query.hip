@@ -728,26 +728,45 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
     }
   };
 
+  // Thread 0 keeps one grab in flight: right after a grab is published to
+  // the block it already asks for the next batch of the same shard and for
+  // the current k-th best, so both round trips overlap the chunk work.  The
+  // finished-shard mask is consulted only when the shard has to change.
+  int next_batch = 0;
+  bool have_next = false;
+  unsigned long long next_key = ~0ull;
+  __shared__ int s_shard_done;
   for (;;) {
     if (tid == 0) {
       s_stop = 0;
-      const unsigned long long fin = load_relaxed(finished);
-      if (fin == ~0ull) {
-        s_stop = 1;
-      } else {
-        int shard = s_shard;
-        if ((fin >> shard) & 1ull) {  // next unfinished shard after this one
-          const unsigned long long rot = ~((fin >> shard) | (fin << ((kShards - shard) & 63)));
-          shard = (shard + __ffsll((long long)rot) - 1) & (kShards - 1);
+      s_shard_done = 0;
+      if (!have_next) {
+        const unsigned long long fin = load_relaxed(finished);
+        if (fin == ~0ull) {
+          s_stop = 1;
+        } else {
+          int shard = s_shard;
+          if ((fin >> shard) & 1ull) {  // next unfinished shard after this one
+            const unsigned long long rot = ~((fin >> shard) | (fin << ((kShards - shard) & 63)));
+            shard = (shard + __ffsll((long long)rot) - 1) & (kShards - 1);
+          }
+          s_shard = shard;
+          next_batch = atomicAdd(&counters[shard * kCounterStride], 1);
+          next_key = load_key(&slots[k - 1]);
         }
-        s_shard = shard;
-        s_batch = atomicAdd(&counters[shard * kCounterStride], 1);
-        s_ckey = umin64(s_ckey, load_key(&slots[k - 1]));
       }
+      s_batch = next_batch;
+      s_ckey = umin64(s_ckey, next_key);
+      have_next = false;
     }
     __syncthreads();
     if (s_stop) break;
     const int shard = s_shard;
+    if (tid == 0) {  // prefetch the next grab of this shard
+      next_batch = atomicAdd(&counters[shard * kCounterStride], 1);
+      next_key = load_key(&slots[k - 1]);
+      have_next = true;
+    }
     unsigned long long ckey = s_ckey;
     const float tadj = lb_threshold(key_dist(ckey), p);
     // one chunk per wave
@@ -759,10 +778,13 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
       rg = ranges[i];
       const float lb = key_dist(item);
       take = lb <= tadj;
-      if (!take && bucket_floor(lb_bucket(lb)) > tadj && lane == 0)  // all later chunks above too
+      if (!take && bucket_floor(lb_bucket(lb)) > tadj && lane == 0) {  // all later chunks above too
         atomicOr(finished, 1ull << shard);
+        s_shard_done = 1;
+      }
     } else if (lane == 0) {
       atomicOr(finished, 1ull << shard);
+      s_shard_done = 1;
     }
     if (take) {
       c_leaf += (lane == 0) ? 1 : 0;
@@ -906,7 +928,10 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
       }
       if (tid == 0) s_npend = np;
     }
-    if (tid == 0) s_nsurv = 0;
+    if (tid == 0) {
+      s_nsurv = 0;
+      if (s_shard_done) have_next = false;  // the prefetched batch lies past the shard's end
+    }
     __syncthreads();
   }
   if constexpr (R >= 0) {  // the block's last DTW pairs
