@@ -8,8 +8,10 @@ random-walk queries from a separate seed answered one at a time (exact 1-NN,
 Euclidean distance).  A step is one query through the whole hot path
 (preparation, approximate search, leaf bounds, leaf processing with series
 bounds and refinement, FP64 near-tie recheck).  Also reported: index build
-time, DTW (10% window) 1-NN on the same index, per-phase device times, the
-roofline of the dominant kernel, and the CPU oracle timed on a sample.
+time, per-phase device times, the roofline of the dominant kernel, the CPU
+oracle timed on a sample, and exact 1-NN DTW (radius 25 = 10% of 256) over
+the first 10,000,000 series with noisy dataset copies as queries (noise
+0.01, 0.1, 1.0 times the series' standard deviation, round robin).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -64,20 +66,26 @@ def run_queries(pm, idx, qt, k, distance, window, budget_s=None):
 
 
 def cpu_baseline(n, length, queries, sample):
+    """The oracle's brute-force scan on the host cores over the first
+    `sample` series (regenerated on the host in chunks; only the scans are
+    timed), scaled to the whole collection."""
     import oracle
     import synth
 
-    log(f"cpu baseline: generating a {sample} x {length} sample on the host")
-    raw = synth.randomwalk(sample, length, seed=synth.SEED_DATA)
+    log(f"cpu baseline: oracle scan of {queries.shape[0]} queries over {sample} x {length}")
     st = oracle.KnnState(queries, 1)
-    t0 = time.perf_counter()
-    st.scan(raw, 0)
-    dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    dt = 0.0
+    chunk = 2_000_000
+    for c in range(0, sample, chunk):
+        raw = synth.randomwalk(min(chunk, sample - c), length, seed=synth.SEED_DATA, id0=c)
+        t0 = time.perf_counter()
+        st.scan(raw, c)
+        dt += time.perf_counter() - t0
+    cores = oracle.threads()
     qps = queries.shape[0] / dt * (sample / n)
     return {"value": qps, "unit": "queries/s", "cores": cores, "kind": "oracle",
-            "sample": f"brute-force exact 1-NN ED of {queries.shape[0]} queries over the first "
-                      f"{sample} of the {n} series ({dt:.1f} s), scaled by {sample}/{n}"}
+            "sample": f"brute-force exact 1-NN ED (FP64) of {queries.shape[0]} queries over the first "
+                      f"{sample} of the {n} series: {dt:.1f} s of scanning, scaled by {sample}/{n}"}
 
 
 def main():
@@ -88,10 +96,11 @@ def main():
     ap.add_argument("--n", type=int, default=100_000_000)
     ap.add_argument("--len", type=int, default=256)
     ap.add_argument("--leaf", type=int, default=2000)
-    ap.add_argument("--dtw-queries", type=int, default=20)
+    ap.add_argument("--dtw-n", type=int, default=10_000_000)
+    ap.add_argument("--dtw-queries", type=int, default=100)
     ap.add_argument("--window", type=int, default=25)
-    ap.add_argument("--cpu-sample", type=int, default=8_000_000)
-    ap.add_argument("--cpu-queries", type=int, default=8)
+    ap.add_argument("--cpu-sample", type=int, default=16_000_000)
+    ap.add_argument("--cpu-queries", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
@@ -120,6 +129,12 @@ def main():
     data = torch.empty((n, length), dtype=torch.float32, device="cuda")
     synth.randomwalk_device(data, seed=synth.SEED_DATA)
     torch.cuda.synchronize()
+    dtw_n = min(args.dtw_n, n)
+    didx = None
+    if args.dtw_queries > 0:
+        log(f"building the DTW index over the first {dtw_n} series")
+        didx = pm.messi_build(data[:dtw_n], 16, 256, args.leaf)
+        torch.cuda.synchronize()
     log("building the index")
     t0 = time.perf_counter()
     idx = pm.messi_build(data, 16, 256, args.leaf)
@@ -147,19 +162,24 @@ def main():
     log(f"ED: {value:.1f} q/s, p50 {np.percentile(lat, 50) * 1e3:.3f} ms, phases {phases_us}")
 
     dtw = None
-    if args.dtw_queries > 0:
-        dq = synth.random_queries(args.dtw_queries + 2, length, seed=synth.SEED_QUERY + 100)
+    if didx is not None:
+        dq, _, dsig = synth.noisy_queries(args.dtw_queries + 3, dtw_n, length)
         dt = torch.from_numpy(dq).cuda()
-        run_queries(pm, idx, dt[:2], 1, pm.MESSI_DTW, args.window)
-        log(f"timing {args.dtw_queries} DTW queries (r={args.window})")
-        dwall, dlat, dst = run_queries(pm, idx, dt[2:], 1, pm.MESSI_DTW, args.window, budget_s=90)
+        run_queries(pm, didx, dt[:3], 1, pm.MESSI_DTW, args.window)
+        log(f"timing {args.dtw_queries} DTW queries (r={args.window}) over {dtw_n} series")
+        dwall, dlat, dst = run_queries(pm, didx, dt[3:], 1, pm.MESSI_DTW, args.window, budget_s=90)
         dk = len(dlat)
         dph = {p: dst[f"us_{p}"] / dk for p in PHASES}
-        dtw = {"metric": "exact 1-NN DTW queries/s", "value": dk / dwall, "unit": "queries/s",
-               "queries": dk, "window": args.window, "p50_ms": float(np.percentile(dlat, 50) * 1e3),
+        dtw = {"metric": "exact 1-NN DTW queries/s (one query at a time)", "value": dk / dwall,
+               "unit": "queries/s", "queries": dk, "window": args.window,
+               "workload": f"first {dtw_n} of the random walks, noisy dataset copies "
+                           "(noise 0.01/0.1/1.0 x series sd, round robin)",
+               "p50_ms": float(np.percentile(dlat, 50) * 1e3),
                "p99_ms": float(np.percentile(dlat, 99) * 1e3), "phases_us": dph,
-               "refined_per_query": dst["refined"] / dk, "lb_keogh_per_query": dst["lb_keogh"] / dk}
-        log(f"DTW: {dtw['value']:.2f} q/s")
+               "refined_per_query": dst["refined"] / dk, "lb_keogh_per_query": dst["lb_keogh"] / dk,
+               "series_lb_per_query": dst["series_lb"] / dk}
+        log(f"DTW: {dtw['value']:.2f} q/s, p50 {dtw['p50_ms']:.2f} ms, p99 {dtw['p99_ms']:.2f} ms")
+        didx.free()
 
     cpu = None
     if not args.no_cpu_baseline:

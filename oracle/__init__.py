@@ -79,6 +79,7 @@ def lib():
         L.oracle_paa.argtypes = [P, i32, i32, P]
         L.oracle_breakpoints.argtypes = [i32, P]
         L.oracle_symbol.argtypes = [ctypes.c_float, P, i32]
+        L.oracle_threads.restype = i32
         L.oracle_symbol.restype = i32
         L.oracle_words.argtypes = [P, i64, i32, i32, i32, P]
         L.oracle_leaf_partition.argtypes = [P, i64, i32, i32, i32, P, P, i64]
@@ -95,6 +96,7 @@ def lib():
         L.oracle_mindist2_dtw.argtypes = [P, P, P, P, P, i32, i32, i32]
         L.oracle_mindist2_dtw.restype = f64
         L.oracle_knn_scan.argtypes = [P, i64, i64, i32, P, i32, i32, i32, i32, P, P]
+        L.oracle_knn_scan_lbk.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P]
         L.oracle_index_search.argtypes = [P, i64, i32, i32, i32, P, P, P, i64, P, i32, i32, i32,
                                           P, P, P]
         _lib = L
@@ -107,6 +109,11 @@ def _f32(a):
 
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def threads():
+    """OpenMP threads the scans use."""
+    return int(lib().oracle_threads())
 
 
 def znorm(x):
@@ -210,7 +217,10 @@ def mindist2_dtw(upaa, lpaa, sym, bits, beta, length, card_bits=8):
 class KnnState:
     """Running brute-force k-NN over a collection fed in chunks."""
 
-    def __init__(self, raw_queries, k, distance=ED, r=0):
+    def __init__(self, raw_queries, k, distance=ED, r=0, lb_keogh=False):
+        """lb_keogh: for DTW, skip pairs by LB_Keogh against the running
+        k-th best (same lists, fewer DTW evaluations)."""
+        self.lb_keogh = bool(lb_keogh) and int(distance) == DTW
         self.q = _f32(raw_queries)
         self.nq, self.len = self.q.shape
         self.k, self.distance, self.r = int(k), int(distance), int(r)
@@ -219,6 +229,11 @@ class KnnState:
 
     def scan(self, raw_chunk, id0):
         raw_chunk = _f32(raw_chunk)
+        if self.lb_keogh:
+            lib().oracle_knn_scan_lbk(_p(raw_chunk), int(id0), raw_chunk.shape[0], self.len,
+                                      _p(self.q), self.nq, self.k, self.r, _p(self.ids),
+                                      _p(self.d2))
+            return self
         lib().oracle_knn_scan(_p(raw_chunk), int(id0), raw_chunk.shape[0], self.len, _p(self.q),
                               self.nq, self.k, self.distance, self.r, _p(self.ids), _p(self.d2))
         return self

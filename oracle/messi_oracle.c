@@ -10,11 +10,23 @@
 
 #include <float.h>
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdlib.h>
 #include <string.h>
 
 /* ------------------------------------------------------------------------ */
 /* Summarisation: Section 2.1 (z-normalised data), Section 2.2 (PAA, iSAX). */
+
+/* Threads the OpenMP scans use. */
+int32_t oracle_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 void oracle_znorm(const float* x, int32_t len, float* z) {
   float s = 0.0f;
@@ -400,6 +412,63 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
     free(ld);
     free(lid);
   }
+  free(zq);
+}
+
+/* Brute-force DTW k-NN with the LB_Keogh filter (Section 4.2): a pair is
+ * skipped only when its LB_Keogh exceeds the running k-th best by more than
+ * FP64 rounding of two length-len sums can explain (relative 1e-12), so the
+ * lists equal those of oracle_knn_scan.  Each thread filters against the
+ * smaller of its own k-th best and the k-th best before the chunk, both
+ * never below the final one. */
+void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
+                         const float* raw_queries, int32_t nq, int32_t k, int32_t r,
+                         int64_t* ids, double* d2) {
+  float* zq = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
+  float* up = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
+  float* lo = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
+  for (int32_t j = 0; j < nq; ++j) {
+    oracle_znorm(raw_queries + (int64_t)j * len, len, zq + (int64_t)j * len);
+    oracle_envelope(zq + (int64_t)j * len, len, r, up + (int64_t)j * len, lo + (int64_t)j * len);
+  }
+  double* bound = (double*)malloc(sizeof(double) * (size_t)nq);  /* k-th best before this chunk */
+  for (int32_t j = 0; j < nq; ++j) bound[j] = d2[(int64_t)j * k + k - 1];
+#pragma omp parallel
+  {
+    int64_t* lid = (int64_t*)malloc(sizeof(int64_t) * (size_t)nq * (size_t)k);
+    double* ld = (double*)malloc(sizeof(double) * (size_t)nq * (size_t)k);
+    float* z = (float*)malloc(sizeof(float) * (size_t)len);
+    for (int64_t t = 0; t < (int64_t)nq * k; ++t) {
+      lid[t] = -1;
+      ld[t] = INFINITY;
+    }
+#pragma omp for schedule(dynamic, 256)
+    for (int64_t i = 0; i < count; ++i) {
+      oracle_znorm(raw_chunk + i * len, len, z);
+      for (int32_t j = 0; j < nq; ++j) {
+        const double own = ld[(int64_t)j * k + k - 1];
+        const double kth = own < bound[j] ? own : bound[j];
+        const double lb = oracle_lb_keogh2(up + (int64_t)j * len, lo + (int64_t)j * len, z, len);
+        if (lb > kth * (1.0 + 1e-12)) continue;
+        const double d = oracle_dtw2(zq + (int64_t)j * len, z, len, r);
+        knn_insert(lid + (int64_t)j * k, ld + (int64_t)j * k, k, d, id0 + i);
+      }
+    }
+#pragma omp critical
+    {
+      for (int32_t j = 0; j < nq; ++j)
+        for (int32_t t = 0; t < k; ++t)
+          if (lid[(int64_t)j * k + t] >= 0)
+            knn_insert(ids + (int64_t)j * k, d2 + (int64_t)j * k, k, ld[(int64_t)j * k + t],
+                       lid[(int64_t)j * k + t]);
+    }
+    free(z);
+    free(ld);
+    free(lid);
+  }
+  free(bound);
+  free(lo);
+  free(up);
   free(zq);
 }
 

@@ -49,6 +49,9 @@ typedef struct oracle_search_stats {
 
 /* Z-normalisation (Section 2.1): mean 0, population standard deviation 1,
  * FP32, sums taken in index order.  A constant series maps to zeros. */
+/* Number of threads the OpenMP scans use. */
+int32_t oracle_threads(void);
+
 void oracle_znorm(const float* x, int32_t len, float* z);
 
 /* PAA (Section 2.2): w equal segments, each the FP32 mean of its points,
@@ -99,6 +102,12 @@ double oracle_mindist2_dtw(const float* upaa, const float* lpaa, const uint8_t* 
 void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
                      const float* raw_queries, int32_t nq, int32_t k, int32_t distance,
                      int32_t r, int64_t* ids, double* d2);
+
+/* The same lists for DTW, with LB_Keogh (Section 4.2) skipping pairs whose
+ * bound exceeds the running k-th best beyond FP64 rounding. */
+void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
+                         const float* raw_queries, int32_t nq, int32_t k, int32_t r,
+                         int64_t* ids, double* d2);
 
 /* Serial index search with the method's semantics (Algorithms 5-10 with
  * one priority order): approximate search for the first k-best list, leaf

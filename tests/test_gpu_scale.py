@@ -1,0 +1,117 @@
+"""GPU parity at the benchmark sizes, in the benchmark's launch configuration.
+
+* Exact 1-NN ED over 100,000,000 random walks of length 256 (16 segments,
+  8-bit symbols, leaves of 2000), queries answered one at a time, and a
+  10-NN call over the same queries.  The oracle scans the whole collection,
+  regenerated on the host in chunks by the seeded generator.
+* Exact 1-NN DTW (radius 25) over 10,000,000 random walks of length 256 with
+  noisy dataset copies as queries.  For noise 0.01 and 0.1 the oracle's
+  LB_Keogh-filtered brute force (equal to the plain scan, pinned on the CPU)
+  gives the exact answer; for noise 1.0 that scan is too slow on the host, so
+  the answer is checked by properties that hold at any size: its distance is
+  the oracle's DTW of the returned series, and no larger than the oracle's
+  DTW of the query's source series nor of its ED nearest neighbour.
+
+The device collection comes from the seeded device generator, which is
+bitwise equal to the host generator (test_device_generator_matches_host).
+"""
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+CHUNK = 2_000_000
+
+
+def _say(msg):
+    print(f"[scale] {msg}", file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import paper_2110_07519_amd as pm
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    pm.lib()
+    return pm
+
+
+def _device_index(pm, n, length, leaf):
+    data = torch.empty((n, length), dtype=torch.float32, device="cuda")
+    synth.randomwalk_device(data, seed=synth.SEED_DATA)
+    idx = pm.messi_build(data, 16, 256, leaf)
+    torch.cuda.synchronize()
+    del data
+    torch.cuda.empty_cache()
+    return idx
+
+
+def _host_scan(states, n, length):
+    t0 = time.perf_counter()
+    for c in range(0, n, CHUNK):
+        raw = synth.randomwalk(min(CHUNK, n - c), length, seed=synth.SEED_DATA, id0=c)
+        for st in states:
+            st.scan(raw, c)
+        if (c // CHUNK) % 10 == 9:
+            _say(f"oracle scanned {c + len(raw)} / {n} series ({time.perf_counter() - t0:.0f} s)")
+
+
+def _check(ids, d, oids, od2):
+    assert np.array_equal(ids, oids), (ids, oids)
+    od = np.sqrt(od2)
+    assert np.all(np.abs(d - od) <= 1e-4 * np.maximum(od, 1e-3)), (d, od)
+
+
+def test_ed_100m_one_query_at_a_time(pm):
+    n, length = 100_000_000, 256
+    _say(f"ED: building the index over {n} x {length}")
+    idx = _device_index(pm, n, length, 2000)
+    qn, _, _ = synth.noisy_queries(3, n, length)  # noise 0.01, 0.1, 1.0
+    qs = np.concatenate([synth.random_queries(3, length), qn[[0, 2]]])
+    qt = torch.from_numpy(qs).cuda()
+    one = [pm.messi_query(idx, qt[j:j + 1], 1) for j in range(len(qs))]
+    ids1 = np.concatenate([o[0].cpu().numpy() for o in one])
+    d1 = np.concatenate([o[1].cpu().numpy() for o in one])
+    ids10, d10 = (t.cpu().numpy() for t in pm.messi_query(idx, qt, 10))
+    idx.free()
+    _say("ED: GPU answers ready; oracle scan of the whole collection")
+    st = oracle.KnnState(qs, 10)
+    _host_scan([st], n, length)
+    _check(ids1, d1, st.ids[:, :1], st.d2[:, :1])
+    _check(ids10, d10, st.ids, st.d2)
+
+
+def test_dtw_10m_noisy_queries(pm):
+    n, length, r = 10_000_000, 256, 25
+    _say(f"DTW: building the index over {n} x {length}")
+    idx = _device_index(pm, n, length, 2000)
+    qs, src, sig = synth.noisy_queries(9, n, length)  # noise 0.01, 0.1, 1.0 round robin
+    qt = torch.from_numpy(qs).cuda()
+    one = [pm.messi_query(idx, qt[j:j + 1], 1, pm.MESSI_DTW, r) for j in range(len(qs))]
+    ids = np.concatenate([o[0].cpu().numpy() for o in one])[:, 0]
+    d = np.concatenate([o[1].cpu().numpy() for o in one])[:, 0]
+    idx.free()
+    easy = np.nonzero(sig < 0.5)[0]
+    hard = np.nonzero(sig >= 0.5)[0]
+    _say("DTW: GPU answers ready; oracle scans")
+    st_dtw = oracle.KnnState(qs[easy], 1, oracle.DTW, r, lb_keogh=True)
+    st_ed = oracle.KnnState(qs[hard], 1)
+    _host_scan([st_dtw, st_ed], n, length)
+    _check(ids[easy][:, None], d[easy][:, None], st_dtw.ids, st_dtw.d2)
+    # noise 1.0: properties of the returned answer
+    zq = oracle.znorm(qs[hard])
+    for t, j in enumerate(hard):
+        x_ans = oracle.znorm(synth.randomwalk(1, length, seed=synth.SEED_DATA, id0=int(ids[j])))[0]
+        d_ans = oracle.dtw2(zq[t], x_ans, r)
+        assert abs(d[j] - np.sqrt(d_ans)) <= 1e-4 * max(np.sqrt(d_ans), 1e-3)
+        for other in (int(src[j]), int(st_ed.ids[t, 0])):
+            x_o = oracle.znorm(synth.randomwalk(1, length, seed=synth.SEED_DATA, id0=other))[0]
+            assert d_ans <= oracle.dtw2(zq[t], x_o, r)

@@ -440,3 +440,21 @@ def test_index_search_prunes():
     for j in range(4):
         ids, d2, st = oracle.index_search(raw, W, perm, leaves, q[j], 1)
         assert st["real_dist"] < 0.1 * raw.shape[0]
+
+
+def test_lb_keogh_filtered_scan_equals_plain_scan():
+    """Skipping pairs by LB_Keogh <= DTW (Section 4.2) changes no list: same
+    ids and bitwise the same FP64 distances as the unfiltered scan, over
+    chunks, with exact duplicates (ties) and noisy and random queries."""
+    x = synth.randomwalk(6000, 96, seed=1)
+    x = np.concatenate([x, x[:40]])
+    q = np.concatenate([synth.noisy_queries(6, 6000, 96, data_seed=1)[0],
+                        synth.random_queries(2, 96)])
+    for r in (0, 4, 20):
+        for k in (1, 5):
+            a = oracle.KnnState(q, k, oracle.DTW, r)
+            b = oracle.KnnState(q, k, oracle.DTW, r, lb_keogh=True)
+            for c in range(0, len(x), 1700):
+                a.scan(x[c:c + 1700], c)
+                b.scan(x[c:c + 1700], c)
+            assert np.array_equal(a.ids, b.ids) and np.array_equal(a.d2, b.d2)
