@@ -247,7 +247,10 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   HIP_OR_THROW(hipMemsetAsync(hist, 0, sizeof(unsigned int) * nkeys, st));
   int spw = std::min(64, (16384 - 257) / len);
   if (spw < 1) spw = 1;
-  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, st);
+  int dev = 0, n_cus = 0;
+  HIP_OR_THROW(hipGetDevice(&dev));
+  HIP_OR_THROW(hipDeviceGetAttribute(&n_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, st, n_cus);
   launch_check();
 
   // (2) root grouping

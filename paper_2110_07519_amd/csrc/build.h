@@ -54,7 +54,7 @@ struct BuildDev {
 
 void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
                       const float* bp, uint4* words, float2* musd, unsigned int* hist,
-                      hipStream_t st);
+                      hipStream_t st, int n_cus);
 void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
                       unsigned long long* cursor, hipStream_t st);
 void launch_root_scatter(const uint4* words, int64_t n, int w, int card_bits,

@@ -9,6 +9,7 @@
 // contiguous, ascending-id ranges; (5) the z-normalised store and the words
 // are gathered into that leaf order.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include "build.h"
@@ -112,6 +113,100 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
   words[id] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
   musd[id] = make_float2(mu, flat ? 0.0f : sd);
   atomicAdd(&hist[key], 1u);
+}
+
+// Summaries for 16 segments and len a multiple of 64 up to 256 (the usual
+// shapes): 16 lanes per series, lane g holding the len/16 points of segment
+// g in registers, four series per wave, no LDS staging.  The two sequential
+// sums of the z-normalisation keep their index order by passing the running
+// sum from lane g to lane g+1 (a DPP row shift) after lane g has added its
+// points; the point-wise work (squares, z, segment sums) runs on all lanes.
+
+template <int C>
+__device__ __forceinline__ float chain_sum16(const float (&v)[C], int g) {
+  float acc = 0.0f;
+#pragma unroll
+  for (int stage = 0; stage < 16; ++stage) {
+    if (g == stage) {
+#pragma unroll
+      for (int i = 0; i < C; ++i) acc = acc + v[i];
+    }
+    if (stage < 15)  // row_shr:1 - lane g receives lane g-1's sum
+      acc = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(acc), __float_as_int(acc),
+                                                       0x111, 0xf, 0xf, false));
+  }
+  return __shfl(acc, (int)(threadIdx.x & 48) | 15);  // lane 15 of the row holds the total
+}
+
+template <int C>
+__global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ raw, int64_t n,
+                                                     int card_bits, const float* __restrict__ bp_g,
+                                                     uint8_t* __restrict__ words,
+                                                     float2* __restrict__ musd,
+                                                     unsigned int* __restrict__ hist) {
+  __shared__ float bp[257];
+  const int card = 1 << card_bits;
+  for (int j = threadIdx.x; j <= card; j += blockDim.x) bp[j] = bp_g[j];
+  __syncthreads();
+  constexpr int len = 16 * C;
+  const int lane = threadIdx.x & 63;
+  const int g = lane & 15;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const float flen = (float)len;
+  const float fm = (float)C;
+  for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); grp * 4 < n;
+       grp += waves) {
+    const int64_t id = grp * 4 + (lane >> 4);
+    const bool valid = id < n;
+    float v[C];
+    if (valid) {
+      const float4* src = reinterpret_cast<const float4*>(raw + id * len + g * C);
+#pragma unroll
+      for (int i = 0; i < C / 4; ++i) {
+        const float4 t = src[i];
+        v[4 * i] = t.x;
+        v[4 * i + 1] = t.y;
+        v[4 * i + 2] = t.z;
+        v[4 * i + 3] = t.w;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < C; ++i) v[i] = 0.0f;
+    }
+    const float mu = __fdiv_rn(chain_sum16<C>(v, g), flen);
+    float sq[C];
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+      const float d = v[i] - mu;
+      sq[i] = d * d;
+    }
+    const float sd = __fsqrt_rn(__fdiv_rn(chain_sum16<C>(sq, g), flen));
+    const bool flat = !(sd > 0.0f);
+    float a = 0.0f;
+    if (!flat) {
+#pragma unroll
+      for (int i = 0; i < C; ++i) a = a + __fdiv_rn(v[i] - mu, sd);
+    }
+    const float p = __fdiv_rn(a, fm);
+    int lo = 0, hi = card - 1;
+    for (int step = 0; step < card_bits; ++step) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (bp[mid] <= p)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const unsigned long long msb = __ballot((lo >> (card_bits - 1)) & 1);
+    if (valid) {
+      words[id * 16 + g] = (uint8_t)lo;
+      if (g == 0) {
+        const uint32_t bits16 = (uint32_t)(msb >> (lane & 48)) & 0xffffu;  // bit g = segment g
+        const uint32_t key = __brev(bits16) >> 16;                         // segment 0 -> bit 15
+        musd[id] = make_float2(mu, flat ? 0.0f : sd);
+        atomicAdd(&hist[key], 1u);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -548,7 +643,21 @@ __global__ void k_make_tree(const NodeDev* __restrict__ nodes, int n_nodes, int 
 
 void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
                       const float* bp, uint4* words, float2* musd, unsigned int* hist,
-                      hipStream_t st) {
+                      hipStream_t st, int n_cus) {
+  // the register path reads float4s: the rows must start 16-byte aligned
+  if (w == 16 && len % 64 == 0 && len <= 256 && (reinterpret_cast<uintptr_t>(raw) & 15) == 0) {
+    const int64_t groups = (n + 3) / 4;  // 4 series per wave, 4 waves per block
+    const int64_t want = (groups + 3) / 4;
+    const unsigned blocks = (unsigned)std::min<int64_t>(want, (int64_t)n_cus * 32);
+    uint8_t* wb = reinterpret_cast<uint8_t*>(words);
+    switch (len / 16) {
+      case 4: hipLaunchKernelGGL(k_summarize16<4>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
+      case 8: hipLaunchKernelGGL(k_summarize16<8>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
+      case 12: hipLaunchKernelGGL(k_summarize16<12>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
+      default: hipLaunchKernelGGL(k_summarize16<16>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
+    }
+    return;
+  }
   const int64_t blocks = (n + spw - 1) / spw;
   const size_t lds = (257 + (size_t)spw * len) * sizeof(float);
   hipLaunchKernelGGL(k_summarize, dim3((unsigned)blocks), dim3(kWave), lds, st, raw, n, len, w,

@@ -58,6 +58,8 @@ def test_device_generator_matches_host():
 @pytest.mark.parametrize("n,length,w,card,leaf", [
     (100_000, 256, 16, 256, 2000),   # the tiny configuration
     (3001, 128, 16, 256, 50),        # ragged tail, deep splits
+    (1003, 64, 16, 256, 30),         # 4 points per segment
+    (517, 192, 16, 16, 25),          # 12 points per segment, 4-bit symbols
     (777, 96, 8, 16, 20),            # fewer segments, 4-bit symbols
     (500, 100, 4, 4, 7),             # length not a multiple of 4
     (300, 16, 16, 2, 5),             # one point per segment, 1-bit symbols (over-full leaves)
