@@ -27,7 +27,26 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+# HBM bytes per launch of the leaf-processing kernel over this benchmark's
+# timed queries, from two rocprofv3 --pmc runs of this script (FETCH_SIZE x
+# 2.0 + WRITE_SIZE x 1.0 KiB; factors from a 1 GiB device copy and fill).
+# Valid only for the query kernel sources they were taken on.
+MEASURED_TRAFFIC = {"sources_sha256": "e5af832daec95bfab0d5a223ac8e392d3ac682631bbb3c938cd33086b10470df",
+                    "bytes_per_launch": 318928101}
+QUERY_SOURCES = ["paper_2110_07519_amd/csrc/query.hip", "paper_2110_07519_amd/csrc/query.h",
+                 "paper_2110_07519_amd/csrc/common.h"]
 PHASES = ["prep", "stage1", "stage2", "process", "finalize"]
+
+
+def query_sources_digest():
+    import hashlib
+
+    h = hashlib.sha256()
+    for rel in QUERY_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def log(msg):
@@ -187,6 +206,9 @@ def main():
                            min(args.cpu_sample, n))
         log(f"cpu baseline {cpu['value']:.4f} q/s")
 
+    traffic = None
+    if dom == "process" and MEASURED_TRAFFIC["sources_sha256"] == query_sources_digest():
+        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
     out = {
         "metric": "exact 1-NN queries/s (ED, one query at a time)",
         "value": value,
@@ -215,7 +237,7 @@ def main():
                            "rechecked_fp64": st["rechecked_fp64"] / k_done},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": None, "bytes_per_launch": dom_bytes},
+                     "traffic": traffic, "bytes_per_launch": dom_bytes},
         "dtw": dtw,
         "cpu_baseline": cpu,
     }

@@ -6,7 +6,7 @@
  * Problem (Section 2.1): given a collection of same-length series and a
  * query of that length, find the series at the smallest distance, under
  * Euclidean distance or DTW with a Sakoe-Chiba window (Section 3.4); the
- * k-NN form keeps the k best (Section 5.6).  Series and queries are
+ * k-NN form keeps the k best (Section 5.4).  Series and queries are
  * z-normalised by the library (mean 0, standard deviation 1, Section 2.1).
  *
  * Conventions for every call:
@@ -86,7 +86,7 @@ typedef struct messi_stats {
 int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
                 int32_t cardinality, int32_t leaf_size, messi_index** out);
 
-/* Exact k-NN (Algorithms 5-10; k-NN per Section 5.6).
+/* Exact k-NN (Algorithms 5-10; k-NN per Section 5.4).
  *   queries    device pointer, float32 [nq][len] (raw; z-normalised here).
  *   nq         number of queries, >= 0 (0 returns at once).
  *   k          neighbours per query, 1 <= k <= 1024.

@@ -350,7 +350,7 @@ double oracle_mindist2_dtw(const float* upaa, const float* lpaa, const uint8_t* 
 }
 
 /* ------------------------------------------------------------------------ */
-/* k-best lists ordered by (d2, id): the BSF array of Section 5.6. */
+/* k-best lists ordered by (d2, id): the BSF array of Section 5.4. */
 
 static int knn_less(double da, int64_t ia, double db, int64_t ib) {
   if (da < db) return 1;
@@ -415,7 +415,7 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
   free(zq);
 }
 
-/* Brute-force DTW k-NN with the LB_Keogh filter (Section 4.2): a pair is
+/* Brute-force DTW k-NN with the LB_Keogh filter (Section 3.4): a pair is
  * skipped only when its LB_Keogh exceeds the running k-th best by more than
  * FP64 rounding of two length-len sums can explain (relative 1e-12), so the
  * lists equal those of oracle_knn_scan.  Each thread filters against the
@@ -474,7 +474,7 @@ void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int
 
 /* ------------------------------------------------------------------------ */
 /* Serial index search (Algorithms 5-10, one priority order over all
- * leaves; k-best list per Section 5.6).
+ * leaves; k-best list per Section 5.4).
  *
  * Lower bounds are computed in FP64 from FP32 PAA values; the FP32 PAA of a
  * series differs from the exact mean of its FP32 points by rounding, so a

@@ -103,7 +103,7 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
                      const float* raw_queries, int32_t nq, int32_t k, int32_t distance,
                      int32_t r, int64_t* ids, double* d2);
 
-/* The same lists for DTW, with LB_Keogh (Section 4.2) skipping pairs whose
+/* The same lists for DTW, with LB_Keogh (Section 3.4) skipping pairs whose
  * bound exceeds the running k-th best beyond FP64 rounding. */
 void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
                          const float* raw_queries, int32_t nq, int32_t k, int32_t r,

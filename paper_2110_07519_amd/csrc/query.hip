@@ -1,5 +1,5 @@
 // Exact k-NN query kernels (Algorithms 5-10 of the paper, k-NN per Section
-// 5.6), for ED and for DTW with a Sakoe-Chiba band (Section 3.4).
+// 5.4), for ED and for DTW with a Sakoe-Chiba band (Section 3.4).
 //
 // Phases, each one launch over all queries of a call (grid.y = query):
 //   prep     z-normalise the query, PAA (and LB_Keogh envelope + its PAA),

@@ -6,7 +6,7 @@ definition lives in ``randomwalk.h``; ``libsynth_host.so`` (gcc, OpenMP)
 and ``libsynth_dev.so`` (hipcc, gfx950) are two builds of that one header
 and produce the same bits.
 
-Workload recipes (Section 5.1 and Section 5.4 of the paper):
+Workload recipes (Sections 5.1 and 5.3 of the paper):
   * collection: random walks, x_0 ~ N(0,1), x_t = x_{t-1} + N(0,1), FP64
     cumulative sum rounded to FP32; series i of the collection is keyed by
     (seed 1, i);

@@ -2,7 +2,7 @@
  * Seeded synthetic inputs for the index: random-walk series and the query
  * workloads built from them (Section 5.1: a first value drawn from N(0,1),
  * then a fresh N(0,1) step added at every time point; noisy-copy queries of
- * Section 5.4: a collection series plus Gaussian noise).
+ * Section 5.3: a collection series plus Gaussian noise).
  *
  * This header holds no arithmetic of the indexing method itself: no
  * z-normalisation, summarisation or distance.  It is compiled both by a C

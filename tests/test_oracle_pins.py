@@ -443,7 +443,7 @@ def test_index_search_prunes():
 
 
 def test_lb_keogh_filtered_scan_equals_plain_scan():
-    """Skipping pairs by LB_Keogh <= DTW (Section 4.2) changes no list: same
+    """Skipping pairs by LB_Keogh <= DTW (Section 3.4) changes no list: same
     ids and bitwise the same FP64 distances as the unfiltered scan, over
     chunks, with exact duplicates (ties) and noisy and random queries."""
     x = synth.randomwalk(6000, 96, seed=1)

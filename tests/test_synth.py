@@ -1,6 +1,6 @@
 """The seeded input generator: reproducible, chunk-addressable, and drawing
 the distributions the paper's workloads name (Section 5.1: N(0,1) steps of a
-random walk; Section 5.4: Gaussian noise on collection series)."""
+random walk; Section 5.3: Gaussian noise on collection series)."""
 import math
 
 import numpy as np
