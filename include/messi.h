@@ -42,6 +42,9 @@ enum {
 
 enum { MESSI_ED = 0, MESSI_DTW = 1 };
 
+/* Flags of messi_query_batch. */
+enum { MESSI_SCREEN_BF16 = 1 };
+
 typedef struct messi_index messi_index; /* opaque; owned by the library */
 
 /* Leaf record as exported by messi_get_leaves: the series at leaf-order
@@ -68,6 +71,7 @@ typedef struct messi_stats {
    * the leaf bounds; ordering of the leaves by bound; leaf processing with
    * refinement; FP64 recheck and output */
   double us_prep, us_stage1, us_stage2, us_process, us_finalize;
+  int64_t screened;         /* (query, series) pairs through the BF16 screen */
 } messi_stats;
 
 /* Build an index (Section 3.2: iSAX summaries, then the leaves of the
@@ -108,6 +112,34 @@ int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k,
 int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int32_t k,
                       int32_t distance, int32_t window, int64_t* out_ids, float* out_dists,
                       messi_stats* stats);
+
+/* Batch of exact k-NN queries with per-query k, distance and window
+ * (Section 5.4's k-best array per query; Sections 3.3 and 3.4).  Queries
+ * that share a distance and an effective window run together, one launch
+ * per phase for the whole group.
+ *   queries    device pointer, float32 [nq][len] (raw).
+ *   k, distance, window   HOST arrays of nq entries (as in messi_query);
+ *              1 <= k[i] <= kmax.
+ *   kmax       row length of the outputs, 1..1024.
+ *   flags      MESSI_SCREEN_BF16: ED queries go through a BF16 MFMA screen
+ *              (q.x with FP32 accumulation and a rigorous error bound) in
+ *              front of the FP32 refinement; needs len 64, 128, 256 or 512
+ *              (otherwise ignored) and 2 len bytes per series of
+ *              device memory for a BF16 copy of the store, made on first
+ *              use (or ahead of time by messi_prepare_screen).  Answers are
+ *              identical with and without the flag.
+ *   out_ids    device pointer, int64 [nq][kmax]; out_dists device pointer,
+ *              float32 [nq][kmax]: row i holds query i's k[i] neighbours
+ *              ascending by (distance, id), then (-1, +inf) up to kmax.
+ *   stats      may be NULL; counters and phase times summed over groups. */
+int messi_query_batch(messi_index* index, const float* queries, int32_t nq, const int32_t* k,
+                      const int32_t* distance, const int32_t* window, int32_t kmax, int32_t flags,
+                      int64_t* out_ids, float* out_dists, messi_stats* stats);
+
+/* Make the BF16 copy of the store and its row norms used by
+ * MESSI_SCREEN_BF16 now rather than on the first screened batch.  The
+ * copy lives until messi_free. */
+int messi_prepare_screen(messi_index* index);
 
 /* Order the index's work after / before the caller's on this HIP stream
  * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */

@@ -6,7 +6,7 @@ include/messi.h.  Torch is used for device memory and streams.  If the
 library is not built, importing works but every call raises.
 
 Names follow the C ABI: messi_build, messi_query, messi_query_stats,
-messi_set_stream, messi_free, messi_breakpoints, messi_get_words,
+messi_query_batch, messi_prepare_screen, messi_set_stream, messi_free, messi_breakpoints, messi_get_words,
 messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
 """
 from __future__ import annotations
@@ -26,11 +26,12 @@ MESSI_EDEVICE = -3
 MESSI_EBUSY = -4
 MESSI_ED = 0
 MESSI_DTW = 1
+MESSI_SCREEN_BF16 = 1
 
 EXPORTS = [
     "messi_build", "messi_query", "messi_query_stats", "messi_set_stream", "messi_index_info",
     "messi_get_words", "messi_get_perm", "messi_get_leaves", "messi_breakpoints", "messi_free",
-    "messi_last_error",
+    "messi_last_error", "messi_query_batch", "messi_prepare_screen",
 ]
 
 
@@ -52,7 +53,7 @@ class MessiStats(ctypes.Structure):
                 ("rechecked_fp64", ctypes.c_int64), ("log_overflows", ctypes.c_int64),
                 ("us_prep", ctypes.c_double), ("us_stage1", ctypes.c_double),
                 ("us_stage2", ctypes.c_double), ("us_process", ctypes.c_double),
-                ("us_finalize", ctypes.c_double)]
+                ("us_finalize", ctypes.c_double), ("screened", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -72,6 +73,8 @@ def lib():
         L.messi_build.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(P)]
         L.messi_query.argtypes = [P, P, i32, i32, i32, i32, P, P]
         L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
+        L.messi_query_batch.argtypes = [P, P, i32, P, P, P, i32, i32, P, P, P]
+        L.messi_prepare_screen.argtypes = [P]
         L.messi_set_stream.argtypes = [P, P]
         L.messi_index_info.argtypes = [P, P, P, P, P, P, P]
         L.messi_get_words.argtypes = [P, P]
@@ -81,7 +84,8 @@ def lib():
         L.messi_free.argtypes = [P]
         L.messi_free.restype = None
         L.messi_last_error.restype = ctypes.c_char_p
-        for name in ["messi_build", "messi_query", "messi_query_stats", "messi_set_stream",
+        for name in ["messi_build", "messi_query", "messi_query_stats", "messi_query_batch",
+                     "messi_prepare_screen", "messi_set_stream",
                      "messi_index_info", "messi_get_words", "messi_get_perm", "messi_get_leaves",
                      "messi_breakpoints"]:
             getattr(L, name).restype = ctypes.c_int
@@ -143,6 +147,40 @@ def messi_query(index, queries, k: int = 1, distance: int = MESSI_ED, window: in
                                    _dev_ptr(out_ids), _dev_ptr(out_dists),
                                    ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)))
     return out_ids, out_dists, st.as_dict()
+
+
+def messi_query_batch(index, queries, k, distance, window, kmax=None, flags=0, out_ids=None,
+                      out_dists=None, stats: bool = False):
+    """Batch with per-query k / distance / window (sequences of nq ints):
+    (ids int64 [nq,kmax], dists float32 [nq,kmax][, stats])."""
+    import torch
+
+    assert queries.dtype == torch.float32 and queries.dim() == 2
+    nq = queries.shape[0]
+    kk = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (nq,)))
+    dd = np.ascontiguousarray(np.broadcast_to(np.asarray(distance, dtype=np.int32), (nq,)))
+    ww = np.ascontiguousarray(np.broadcast_to(np.asarray(window, dtype=np.int32), (nq,)))
+    if kmax is None:
+        kmax = int(kk.max()) if nq else 1
+    dev = queries.device
+    if out_ids is None:
+        out_ids = torch.empty((nq, kmax), dtype=torch.int64, device=dev)
+    if out_dists is None:
+        out_dists = torch.empty((nq, kmax), dtype=torch.float32, device=dev)
+    st = MessiStats() if stats else None
+    sp = ctypes.cast(ctypes.pointer(st), ctypes.c_void_p) if stats else None
+    _check(lib().messi_query_batch(index.handle, _dev_ptr(queries), nq,
+                                   kk.ctypes.data_as(ctypes.c_void_p),
+                                   dd.ctypes.data_as(ctypes.c_void_p),
+                                   ww.ctypes.data_as(ctypes.c_void_p), int(kmax), int(flags),
+                                   _dev_ptr(out_ids), _dev_ptr(out_dists), sp))
+    if stats:
+        return out_ids, out_dists, st.as_dict()
+    return out_ids, out_dists
+
+
+def messi_prepare_screen(index) -> None:
+    _check(lib().messi_prepare_screen(index.handle))
 
 
 def messi_set_stream(index, stream) -> None:

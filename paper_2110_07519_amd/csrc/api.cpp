@@ -163,6 +163,22 @@ struct messi_index {
   int4* tree = nullptr;
   int* root_node = nullptr;
   Workspace ws;
+  // BF16 screen: shadow of Z and squared row norms, built on first use
+  DevMem screen_mem;
+  uint16_t* Zb = nullptr;
+  float* xn = nullptr;
+  // batch maps and screen buffers, grown on demand
+  DevMem batch_mem;
+  int batch_nq = 0;
+  int* bmap = nullptr;
+  int* bk = nullptr;
+  uint16_t* qb = nullptr;
+  float* qn = nullptr;
+  int* cnt = nullptr;
+  int64_t* off = nullptr;
+  int* lists = nullptr;
+  int* counter = nullptr;
+  unsigned long long* tally = nullptr;
   int proc_blocks_cu[2] = {0, 0};  // per distance kind, cached occupancy
   int log_cap = 4096;
   int n_cus = 0;
@@ -414,8 +430,40 @@ void ensure_workspace(messi_index* ix, int nq, int k) {
   ws.L = L;
 }
 
-int run_query(messi_index* ix, const float* queries, int nq, int k, int distance, int window,
-              int64_t* out_ids, float* out_dists, messi_stats* stats) {
+// BF16 shadow of the store (screen operand) and the squared row norms.
+void ensure_screen(messi_index* ix) {
+  if (ix->Zb) return;
+  ix->Zb = ix->screen_mem.alloc<uint16_t>((size_t)ix->n * ix->len);
+  ix->xn = ix->screen_mem.alloc<float>((size_t)ix->n);
+  launch_bf16_rows(ix->Z, ix->n, ix->len, ix->Zb, ix->xn, ix->stream);
+  launch_check();
+  HIP_OR_THROW(hipStreamSynchronize(ix->stream));
+}
+
+// Batch maps (row and k of each query) and screen buffers for nq queries.
+void ensure_batch(messi_index* ix, int nq) {
+  if (ix->batch_nq >= nq) return;
+  ix->batch_mem.clear();
+  const int L = ix->n_leaves;
+  ix->bmap = ix->batch_mem.alloc<int>(nq);
+  ix->bk = ix->batch_mem.alloc<int>(nq);
+  ix->qb = ix->batch_mem.alloc<uint16_t>((size_t)nq * ix->len);
+  ix->qn = ix->batch_mem.alloc<float>(nq);
+  ix->cnt = ix->batch_mem.alloc<int>(L);
+  ix->off = ix->batch_mem.alloc<int64_t>((size_t)L + 1);
+  ix->lists = ix->batch_mem.alloc<int>((size_t)nq * L);
+  ix->counter = ix->batch_mem.alloc<int>(1);
+  ix->tally = ix->batch_mem.alloc<unsigned long long>(2);
+  ix->batch_nq = nq;
+}
+
+// One group of queries sharing a distance and window: nq queries whose rows
+// (input and output) are d_qmap[i] and whose k are d_kq[i] (both null for a
+// plain call: rows 0..nq-1, every k = kmax).  Slots are kmax apart and
+// output rows out_stride = kmax entries long.
+int run_group(messi_index* ix, const float* queries, int nq, int kmax, int distance, int window,
+              const int* d_kq, const int* d_qmap, bool screen, int64_t* out_ids,
+              float* out_dists, messi_stats* stats) {
   hipStream_t st = ix->stream;
   const int len = ix->len;
   const double u = std::ldexp(1.0, -24);
@@ -425,7 +473,8 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
   p.w = ix->w;
   p.m = len / ix->w;
   p.card_bits = ix->card_bits;
-  p.k = k;
+  p.k = kmax;
+  p.out_stride = kmax;
   p.distance = distance;
   p.window = distance == MESSI_DTW ? std::min(window, len - 1) : 0;
   p.n_leaves = ix->n_leaves;
@@ -465,6 +514,25 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
   const int resident = per_cu * ix->n_cus;
   int blocks = resident / std::max(1, nq);
   blocks = std::max(2, std::min(blocks, resident));
+  ScreenDev sc{};
+  if (screen) {
+    sc.Zb = ix->Zb;
+    sc.xn = ix->xn;
+    sc.qb = ix->qb;
+    sc.qn = ix->qn;
+    sc.cnt = ix->cnt;
+    sc.off = ix->off;
+    sc.lists = ix->lists;
+    sc.counter = ix->counter;
+    sc.tally = ix->tally;
+    // bound constants (see the screen kernel): u_b = 2^-8, gamma at 2^-23
+    const double ub = std::ldexp(1.0, -8);
+    const double g = len * std::ldexp(1.0, -23) / (1.0 - len * std::ldexp(1.0, -23));
+    const double cdot = 2.0 * ((2.0 * ub + ub * ub) + g * (1.0 + ub) * (1.0 + ub)) * (1.0 + std::ldexp(1.0, -10));
+    sc.c_dot = std::nextafter((float)cdot, INFINITY);
+    sc.c_abs = (float)std::ldexp(1.0, -19);
+  }
+  const int screen_blocks = 4 * ix->n_cus;
   std::vector<int> status(nq);
   // phase timing (only when the caller asks for statistics)
   hipEvent_t ev[6] = {};
@@ -476,18 +544,26 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
     for (int i = 0; i < 6; ++i) ev[i] = ix->ev[i];
   }
   for (int attempt = 0; attempt < 8; ++attempt) {
-    ensure_workspace(ix, nq, k);
+    ensure_workspace(ix, nq, kmax);
     p.log_cap = ix->log_cap;
     const IndexDev v = ix->view();
     QueryState qs = ix->ws.qs;
+    qs.kq = d_kq;
+    qs.qmap = d_qmap;
     if (stats) HIP_OR_THROW(hipEventRecord(ev[0], st));
     launch_prep(v, queries, p, qs, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[1], st));
     launch_stage1(v, p, qs, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[2], st));
-    launch_stage2(v, p, qs, st);
-    if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
-    launch_process(v, p, qs, blocks, st);
+    if (screen) {
+      launch_bf16_rows(qs.zq, nq, len, sc.qb, sc.qn, st);
+      if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
+      launch_screen(v, p, qs, sc, screen_blocks, st);
+    } else {
+      launch_stage2(v, p, qs, st);
+      if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
+      launch_process(v, p, qs, blocks, st);
+    }
     if (stats) HIP_OR_THROW(hipEventRecord(ev[4], st));
     launch_finalize(v, p, qs, out_ids, out_dists, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[5], st));
@@ -516,6 +592,14 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
           stats->refined += (int64_t)r[kStatRefined];
           stats->rechecked_fp64 += (int64_t)r[kStatRecheck];
         }
+        if (screen) {
+          unsigned long long t[2];
+          int64_t pairs = 0;
+          d2h(t, sc.tally, 2, st);
+          d2h(&pairs, sc.off + ix->n_leaves, 1, st);
+          stats->screened += (int64_t)t[0];
+          stats->leaves_kept += pairs;
+        }
       }
       return MESSI_OK;
     }
@@ -523,6 +607,12 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
     ix->log_cap *= 4;  // near-tie log overflowed: rerun with a larger one
   }
   return fail(MESSI_ENOMEM, "near-tie log kept overflowing");
+}
+
+int run_query(messi_index* ix, const float* queries, int nq, int k, int distance, int window,
+              int64_t* out_ids, float* out_dists, messi_stats* stats) {
+  return run_group(ix, queries, nq, k, distance, window, nullptr, nullptr, false, out_ids,
+                   out_dists, stats);
 }
 
 }  // namespace
@@ -617,6 +707,88 @@ int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k,
   return messi_query_stats(index, queries, nq, k, distance, window, out_ids, out_dists, nullptr);
 }
 
+int messi_prepare_screen(messi_index* index) {
+  g_err.clear();
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (!screen_supported(index->len))
+    return fail(MESSI_EINVAL, "the BF16 screen needs len 64, 128, 256 or 512");
+  BusyGuard g(index->busy);
+  if (!g.ok) return fail(MESSI_EBUSY, "index is in use by another call");
+  try {
+    ensure_screen(index);
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  return MESSI_OK;
+}
+
+int messi_query_batch(messi_index* index, const float* queries, int32_t nq, const int32_t* k,
+                      const int32_t* distance, const int32_t* window, int32_t kmax, int32_t flags,
+                      int64_t* out_ids, float* out_dists, messi_stats* stats) {
+  g_err.clear();
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
+  if (nq == 0) return MESSI_OK;
+  if (kmax < 1 || kmax > 1024) return fail(MESSI_EINVAL, "kmax must be in [1, 1024]");
+  if (!k || !distance || !window) return fail(MESSI_EINVAL, "k, distance and window are required");
+  if (is_device_ptr(k) || is_device_ptr(distance) || is_device_ptr(window))
+    return fail(MESSI_EINVAL, "k, distance and window must be host arrays");
+  if (flags & ~MESSI_SCREEN_BF16) return fail(MESSI_EINVAL, "unknown flags");
+  if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
+    return fail(MESSI_EINVAL, "queries and outputs must be device pointers");
+  const int len = index->len;
+  // groups of queries sharing (distance, effective window), in first-seen order
+  std::vector<std::pair<int, int>> keys;
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < nq; ++i) {
+    if (k[i] < 1 || k[i] > kmax) return fail(MESSI_EINVAL, "k[%d] must be in [1, kmax]", i);
+    if (distance[i] != MESSI_ED && distance[i] != MESSI_DTW)
+      return fail(MESSI_EINVAL, "unknown distance[%d]", i);
+    if (window[i] < 0) return fail(MESSI_EINVAL, "window[%d] must be >= 0", i);
+    const std::pair<int, int> key(distance[i], distance[i] == MESSI_DTW ? std::min(window[i], len - 1) : 0);
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != key) ++g;
+    if (g == keys.size()) {
+      keys.push_back(key);
+      members.emplace_back();
+    }
+    members[g].push_back(i);
+  }
+  BusyGuard guard(index->busy);
+  if (!guard.ok) return fail(MESSI_EBUSY, "index is in use by another call");
+  try {
+    const bool want_screen = (flags & MESSI_SCREEN_BF16) && screen_supported(len);
+    ensure_batch(index, nq);
+    std::vector<int> hmap, hk;
+    hmap.reserve(nq);
+    hk.reserve(nq);
+    for (const auto& m : members)
+      for (int i : m) {
+        hmap.push_back(i);
+        hk.push_back(k[i]);
+      }
+    h2d(index->bmap, hmap.data(), (size_t)nq, index->stream);
+    h2d(index->bk, hk.data(), (size_t)nq, index->stream);
+    int at = 0;
+    for (size_t g = 0; g < keys.size(); ++g) {
+      const int cnt = (int)members[g].size();
+      const bool screen = want_screen && keys[g].first == MESSI_ED;
+      if (screen) ensure_screen(index);
+      const int rc = run_group(index, queries, cnt, kmax, keys[g].first, keys[g].second,
+                               index->bk + at, index->bmap + at, screen, out_ids, out_dists, stats);
+      if (rc != MESSI_OK) return rc;
+      at += cnt;
+    }
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  return MESSI_OK;
+}
+
 int messi_set_stream(messi_index* index, void* hip_stream) {
   if (!index) return fail(MESSI_EINVAL, "index is NULL");
   index->stream = (hipStream_t)hip_stream;
@@ -631,7 +803,9 @@ int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t
   if (segments) *segments = index->w;
   if (card_bits) *card_bits = index->card_bits;
   if (n_leaves) *n_leaves = index->n_leaves;
-  if (device_bytes) *device_bytes = (int64_t)(index->mem.bytes + index->ws.mem.bytes);
+  if (device_bytes)
+    *device_bytes = (int64_t)(index->mem.bytes + index->ws.mem.bytes + index->screen_mem.bytes +
+                              index->batch_mem.bytes);
   return MESSI_OK;
 }
 

@@ -44,6 +44,7 @@ struct QueryParams {
   int fin_waves;     // waves used by the FP64 DTW recheck
   int item_cap;      // leaf chunks per query: at most n / kChunkSeries + n_leaves
   int lds_words;     // floats of dynamic LDS of the process kernel
+  int out_stride;    // output row stride (k of the call, or kmax of a batch)
 };
 
 // Per-query device state, one entry per query (all arrays sized by nq).
@@ -67,7 +68,15 @@ struct QueryState {
   int* next;                  // [nq][kCounterInts]: kShards counters kCounterStride apart, then a finished-shard mask
   unsigned long long* stats;  // [nq][8] counters (see kStat*)
   int* status;                // [nq] bit 0: near-tie log overflow
+  const int* kq;              // [nq] k of each query (batches), or null: every query uses p.k
+  const int* qmap;            // [nq] input / output row of each query (batches), or null: row q
 };
+
+// k of query q: its own in a batch, else the call's; slots are always p.k apart.
+__device__ __forceinline__ int k_of(const QueryParams& p, const QueryState& s, int q) {
+  return s.kq ? s.kq[q] : p.k;
+}
+__device__ __forceinline__ int row_of(const QueryState& s, int q) { return s.qmap ? s.qmap[q] : q; }
 
 enum { kStatLeavesKept = 0, kStatSeriesLb, kStatLbKeogh, kStatRefined, kStatRecheck, kStatCount = 8 };
 

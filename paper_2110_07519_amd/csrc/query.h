@@ -30,6 +30,29 @@ struct IndexDev {
   const int* root_node;      // [2^w]
 };
 
+// BF16 screen of batched ED queries: a BF16 shadow of the store with the
+// squared norm of every row, the queries' BF16 rows and norms, the leaves'
+// query lists, and the bound constants.
+struct ScreenDev {
+  const uint16_t* Zb;     // [n][len] BF16 (round to nearest even) of Z
+  const float* xn;        // [n] squared norm of each row of Z (FP64 sum, rounded)
+  uint16_t* qb;           // [nq][len] BF16 of the normalised queries
+  float* qn;              // [nq] their squared norms
+  int* cnt;               // [L] queries that keep each leaf
+  int64_t* off;           // [L + 1] start of each leaf's query list
+  int* lists;             // [sum of cnt] query indices, leaf by leaf
+  int* counter;           // leaf work counter
+  unsigned long long* tally;  // [2] pairs screened, pairs passed to refinement
+  float c_dot;            // bound: c_dot |q||x| + c_abs (|q|^2 + |x|^2 + 2 |s|)
+  float c_abs;
+};
+
+bool screen_supported(int len);
+void launch_bf16_rows(const float* src, int64_t rows, int len, uint16_t* dst, float* norms,
+                      hipStream_t st);
+void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+                   const ScreenDev& sc, int blocks, hipStream_t st);
+
 void launch_prep(const IndexDev& ix, const float* queries, const QueryParams& qp,
                  const QueryState& qs, hipStream_t st);
 void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,

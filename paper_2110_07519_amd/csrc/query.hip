@@ -25,6 +25,7 @@
 // the FP32 error window of the running k-th best is logged, and the final
 // order is decided on FP64 distances of the logged candidates.
 #include <hip/hip_runtime.h>
+#include <algorithm>
 #include <stdint.h>
 
 #include "query.h"
@@ -288,7 +289,7 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
   __shared__ float s_mu, s_sd;
   __shared__ unsigned long long s_best;
 
-  const float* src = queries + (int64_t)q * len;
+  const float* src = queries + (int64_t)row_of(s, q) * len;
   for (int t = tid; t < len; t += blockDim.x) x[t] = src[t];
   for (int j = tid; j <= card; j += blockDim.x) bp[j] = ix.bp[j];
   for (int j = tid; j < kLbBuckets; j += blockDim.x) {
@@ -408,10 +409,11 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
       t = ix.tree[ch];
     }
     int64_t b = t.y, e = t.z;
+    const int kk = k_of(p, s, q);
     if (e - b > kApproxCap) e = b + kApproxCap;
-    if (e - b < p.k) {
-      e = b + p.k < ix.n ? b + p.k : ix.n;
-      if (e - b < p.k) b = e - p.k > 0 ? e - p.k : 0;
+    if (e - b < kk) {
+      e = b + kk < ix.n ? b + kk : ix.n;
+      if (e - b < kk) b = e - kk > 0 ? e - kk : 0;
     }
     s.approx_range[2 * q] = b;
     s.approx_range[2 * q + 1] = e;
@@ -433,13 +435,14 @@ __device__ __forceinline__ bool offer(const IndexDev& ix, const QueryParams& p, 
                                       bool log_it) {
   if (!(d2 <= key_dist(ckey) * p.win)) return false;
   unsigned long long* slots = s.slots + (int64_t)q * p.k;
+  const int kk = k_of(p, s, q);
   const unsigned long long key = pack_key(d2, (uint32_t)ix.perm[pos]);
   if (log_it) {
     const int i = atomicAdd(&s.log_count[q], 1);
     if (i < p.log_cap) s.log[(int64_t)q * p.log_cap + i] = pack_key(d2, (uint32_t)pos);
   }
   if (key < ckey) {
-    topk_insert(slots, p.k, key);
+    topk_insert(slots, kk, key);
     return true;
   }
   return false;
@@ -500,6 +503,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
   const int cnt = (int)(P1 - P0);
   float* approx_d2 = s.approx_d2 + (int64_t)q * kApproxCap;
   unsigned long long* slots = s.slots + (int64_t)q * p.k;
+  const int kk = k_of(p, s, q);
   if constexpr (R == -1) {  // ED: one wave per series
     float* zl = sm;
     for (int t = tid; t < len; t += blockDim.x) zl[t] = zq[t];
@@ -511,7 +515,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
       const float d2 = ed_wave(zl, ix.Z + pos * len, len, lane);
       if (lane == 0) {
         approx_d2[j] = d2;
-        topk_insert(slots, p.k, pack_key(d2, (uint32_t)ix.perm[pos]));
+        topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
       }
     }
   } else if constexpr (R == -2) {  // DTW, wide band: one wave per series
@@ -530,7 +534,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
                                        (float)INFINITY, lane);
       if (lane == 0) {
         approx_d2[j] = d2;
-        topk_insert(slots, p.k, pack_key(d2, (uint32_t)ix.perm[pos]));
+        topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
       }
     }
   } else {  // DTW, register band: one thread per series
@@ -542,7 +546,25 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
       const int64_t pos = P0 + j;
       const float d2 = dtw_band<R, MASK>(qpad, ix.Z + pos * len, len, p.window, INFINITY);
       approx_d2[j] = d2;
-      topk_insert(slots, p.k, pack_key(d2, (uint32_t)ix.perm[pos]));
+      topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
+    }
+  }
+}
+
+// Near-tie log entries of the approximate search: its distances within the
+// window of the first k-th best (the k-th best only decreases afterwards,
+// so this covers the window of the final one).
+__device__ __forceinline__ void log_approx(const QueryParams& p, const QueryState& s, int q,
+                                           int tid, int nthreads) {
+  const unsigned long long* slots = s.slots + (int64_t)q * p.k;
+  const float win = kth_dist(slots, k_of(p, s, q)) * p.win;
+  const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
+  const float* ad = s.approx_d2 + (int64_t)q * kApproxCap;
+  for (int j = tid; j < (int)(P1 - P0); j += nthreads) {
+    const float d2 = ad[j];
+    if (d2 <= win) {
+      const int i = atomicAdd(&s.log_count[q], 1);
+      if (i < p.log_cap) s.log[(int64_t)q * p.log_cap + i] = pack_key(d2, (uint32_t)(P0 + j));
     }
   }
 }
@@ -618,19 +640,7 @@ __global__ __launch_bounds__(1024) void k_stage2(IndexDev ix, QueryParams p, Que
       ranges[at + c] = make_int2(cb, cb + kChunkSeries < lend ? cb + kChunkSeries : lend);
     }
   }
-  if (blockIdx.x == 0) {
-    const unsigned long long* slots = s.slots + (int64_t)q * p.k;
-    const float win = kth_dist(slots, p.k) * p.win;
-    const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
-    const float* ad = s.approx_d2 + (int64_t)q * kApproxCap;
-    for (int j = tid; j < (int)(P1 - P0); j += blockDim.x) {
-      const float d2 = ad[j];
-      if (d2 <= win) {
-        const int i = atomicAdd(&s.log_count[q], 1);
-        if (i < p.log_cap) s.log[(int64_t)q * p.log_cap + i] = pack_key(d2, (uint32_t)(P0 + j));
-      }
-    }
-  }
+  if (blockIdx.x == 0) log_approx(p, s, q, tid, blockDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -661,7 +671,7 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
   constexpr int kW = Sh::waves;
   const int q = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int len = p.len, card = 1 << p.card_bits, k = p.k;
+  const int len = p.len, card = 1 << p.card_bits, k = k_of(p, s, q);
   constexpr bool dtw = R != -1;
   extern __shared__ float sm[];
   float* table = sm;                          // [16][card]
@@ -691,7 +701,7 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
       Lw[t] = s.lower[(int64_t)q * len + t];
     }
   }
-  unsigned long long* slots = s.slots + (int64_t)q * k;
+  unsigned long long* slots = s.slots + (int64_t)q * p.k;
   if (tid == 0) {
     s_ckey = load_key(&slots[k - 1]);
     s_nsurv = 0;
@@ -965,7 +975,7 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
                                                            float* __restrict__ out_dists) {
   const int q = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int len = p.len, k = p.k;
+  const int len = p.len, k = k_of(p, s, q);
   extern __shared__ float sm[];
   // layout: E[kTopCap] doubles | pos[kTopCap] | id[kTopCap] | q[len] |
   // x rows[fin_waves][len] | (8-byte aligned) DP buffers[fin_waves][3 len] doubles
@@ -977,7 +987,7 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
   const size_t dbuf_off = (((size_t)4 * kTopCap + len + (size_t)p.fin_waves * len) + 1) & ~(size_t)1;
   double* dbuf = reinterpret_cast<double*>(sm + dbuf_off);
   __shared__ int s_cnt;
-  const unsigned long long* slots = s.slots + (int64_t)q * k;
+  const unsigned long long* slots = s.slots + (int64_t)q * p.k;
   const float T = kth_dist(slots, k);
   const float win = T * p.win;
   const int lc = s.log_count[q];
@@ -1066,16 +1076,220 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
     __syncthreads();
     topn = cnt < k ? cnt : k;
   }
-  for (int j = tid; j < k; j += blockDim.x) {
+  const int64_t orow = (int64_t)row_of(s, q) * p.out_stride;
+  for (int j = tid; j < p.out_stride; j += blockDim.x) {
     if (j < topn) {
-      out_ids[(int64_t)q * k + j] = (int64_t)id_l[j];
-      out_dists[(int64_t)q * k + j] = (float)sqrt(E[j]);
+      out_ids[orow + j] = (int64_t)id_l[j];
+      out_dists[orow + j] = (float)sqrt(E[j]);
     } else {
-      out_ids[(int64_t)q * k + j] = -1;
-      out_dists[(int64_t)q * k + j] = INFINITY;
+      out_ids[orow + j] = -1;
+      out_dists[orow + j] = INFINITY;
     }
   }
   if (tid == 0) s.stats[(int64_t)q * kStatCount + kStatRecheck] = rechecked;
+}
+
+// ---------------------------------------------------------------------------
+// BF16 screen of batched ED queries (a lower-bound filter in front of the
+// FP32 refinement; not part of the paper's method, the answers stay exact).
+//
+// The leaves are taken leaf-major: each leaf is read once for every query
+// whose leaf bound passed its first k-th best, and q.x of every (query,
+// series) pair comes from BF16 MFMA (16x16x32, FP32 accumulation).  With
+// s~ that dot product, d~^2 = |q|^2 + |x|^2 - 2 s~ is within
+//   E = c_dot |q| |x| + c_abs (|q|^2 + |x|^2 + 2 |s~|)
+// of the exact squared distance of the FP32 rows: c_dot covers the BF16
+// rounding of both operands, 2 (2 u_b + u_b^2), u_b = 2^-8, and the FP32
+// accumulation of len products, 2 gamma_len (1 + u_b)^2 with gamma taken
+// at unit 2^-23; c_abs covers the FP32 norms and the FP32 evaluation of
+// d~^2.  A pair is dropped only if d~^2 - E exceeds the k-th best times the
+// near-tie window, so every pair that could be logged or accepted is
+// refined in FP32 as in the unscreened path.  The series the approximate
+// search already refined are skipped (their keys are in the k best; they
+// are logged from the approximate distances).
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t bf16_bits(float f) {  // finite f, round to nearest even
+  const uint32_t u = __float_as_uint(f);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+// One wave per row: BF16 copy and FP64 squared norm (len % 4 == 0).
+__global__ __launch_bounds__(256) void k_bf16_rows(const float* __restrict__ src, int64_t rows,
+                                                   int len, uint16_t* __restrict__ dst,
+                                                   float* __restrict__ norms) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < rows;
+       r += waves) {
+    const float* x = src + r * len;
+    uint2* y = reinterpret_cast<uint2*>(dst + r * len);
+    double acc = 0.0;
+    for (int t = 4 * lane; t < len; t += 4 * kWave) {
+      const float4 v = *reinterpret_cast<const float4*>(x + t);
+      acc += (double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z + (double)v.w * v.w;
+      y[t >> 2] = make_uint2(bf16_bits(v.x) | (bf16_bits(v.y) << 16),
+                             bf16_bits(v.z) | (bf16_bits(v.w) << 16));
+    }
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, kWave);
+    if (lane == 0) norms[r] = (float)acc;
+  }
+}
+
+// Leaf query lists: a query keeps a leaf whose bound passes its first k-th
+// best (from the approximate search).  Thread per leaf, queries in LDS
+// chunks; `fill` = false counts, true writes the lists.
+__global__ __launch_bounds__(256) void k_leaf_lists(QueryParams p, QueryState s, ScreenDev sc,
+                                                    bool fill) {
+  __shared__ float thr[256];
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  int c = 0;
+  int64_t at = (fill && l < p.n_leaves) ? sc.off[l] : 0;
+  for (int q0 = 0; q0 < p.nq; q0 += 256) {
+    __syncthreads();
+    const int q = q0 + (int)threadIdx.x;
+    if (q < p.nq) thr[threadIdx.x] = lb_threshold(kth_dist(s.slots + (int64_t)q * p.k, k_of(p, s, q)), p);
+    __syncthreads();
+    const int nn = min(256, p.nq - q0);
+    if (l < p.n_leaves) {
+      for (int j = 0; j < nn; ++j) {
+        if (s.leaf_lb[(int64_t)(q0 + j) * p.n_leaves + l] <= thr[j]) {
+          if (fill) sc.lists[at++] = q0 + j;
+          ++c;
+        }
+      }
+    }
+  }
+  if (!fill && l < p.n_leaves) sc.cnt[l] = c;
+}
+
+__global__ __launch_bounds__(256) void k_log_approx(QueryParams p, QueryState s) {
+  log_approx(p, s, blockIdx.x, threadIdx.x, blockDim.x);
+}
+
+// Exclusive scan of the list lengths (one block); also resets the work
+// counter and the tallies.
+__global__ __launch_bounds__(1024) void k_list_scan(QueryParams p, ScreenDev sc) {
+  __shared__ int64_t part[1024];
+  const int L = p.n_leaves;
+  const int per = (L + 1023) / 1024;
+  const int a = threadIdx.x * per, b = min(a + per, L);
+  int64_t sum = 0;
+  for (int i = a; i < b; ++i) sum += sc.cnt[i];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int64_t run = part[threadIdx.x] - sum;
+  for (int i = a; i < b; ++i) {
+    sc.off[i] = run;
+    run += sc.cnt[i];
+  }
+  if (threadIdx.x == 1023) sc.off[L] = part[1023];
+  if (threadIdx.x == 0) {
+    *sc.counter = 0;
+    sc.tally[0] = 0;
+    sc.tally[1] = 0;
+  }
+}
+
+// Screen and refinement, leaf-major.  A block takes one leaf at a time;
+// its four waves take 16-series column tiles of the leaf (the BF16 rows
+// held in registers as the MFMA B operand) and run over the leaf's query
+// list in 16-query row tiles (A operand).  Lane l holds output rows
+// 4 (l / 16) .. + 3 of column l % 16.  Pairs passing the bound are refined
+// by the whole wave in FP32 and offered to their query's k best.
+template <int KS>  // len = 32 KS
+__global__ __launch_bounds__(256) void k_screen(IndexDev ix, QueryParams p, QueryState s,
+                                                ScreenDev sc) {
+  constexpr int len = 32 * KS;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int col = lane & 15, kb = 8 * (lane >> 4);
+  __shared__ int s_leaf;
+  unsigned long long screened = 0, passed = 0;
+  for (;;) {
+    if (tid == 0) s_leaf = atomicAdd(sc.counter, 1);
+    __syncthreads();
+    const int leaf = s_leaf;
+    __syncthreads();
+    if (leaf >= p.n_leaves) break;
+    const int64_t l0 = sc.off[leaf], l1 = sc.off[leaf + 1];
+    if (l0 == l1) continue;
+    const int64_t b = ix.leaf_begin[leaf], e = ix.leaf_end[leaf];
+    for (int64_t t0 = b + 16 * wv; t0 < e; t0 += 64) {
+      const int64_t j = t0 + col;
+      const bool jv = j < e;
+      bf16x8 B[KS];
+      if (jv) {
+        const uint4* src = reinterpret_cast<const uint4*>(sc.Zb + j * len + kb);
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) B[ks] = __builtin_bit_cast(bf16x8, src[4 * ks]);
+      } else {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) B[ks] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+      }
+      const float xn = jv ? sc.xn[j] : 0.0f;
+      const int64_t cnt_cols = (e - t0) < 16 ? (e - t0) : 16;
+      for (int64_t qt = l0; qt < l1; qt += 16) {
+        const int64_t ai = qt + col;
+        const int qa = ai < l1 ? sc.lists[ai] : -1;
+        bf16x8 A[KS];
+        if (qa >= 0) {
+          const uint4* src = reinterpret_cast<const uint4*>(sc.qb + (int64_t)qa * len + kb);
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) A[ks] = __builtin_bit_cast(bf16x8, src[4 * ks]);
+        } else {
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) A[ks] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+        }
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks], B[ks], acc, 0, 0, 0);
+        const int64_t rows = (l1 - qt) < 16 ? (l1 - qt) : 16;
+        screened += (unsigned long long)(rows * cnt_cols);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t ri = qt + 4 * (lane >> 4) + r;
+          const int qr = ri < l1 ? sc.lists[ri] : -1;
+          bool keep = false;
+          if (qr >= 0 && jv && !(j >= s.approx_range[2 * qr] && j < s.approx_range[2 * qr + 1])) {
+            const float qn = sc.qn[qr];
+            const float thr = kth_dist(s.slots + (int64_t)qr * p.k, k_of(p, s, qr)) * p.win;
+            const float dt = qn + xn - 2.0f * acc[r];
+            const float E = sc.c_dot * __fsqrt_rn(qn * xn) + sc.c_abs * (qn + xn + 2.0f * fabsf(acc[r]));
+            keep = !(dt - E > thr);
+          }
+          unsigned long long m = __ballot(keep);
+          while (m) {
+            const int src_lane = __ffsll((long long)m) - 1;
+            m &= m - 1;
+            const int qsel = __shfl(qr, src_lane, kWave);
+            const int64_t jsel = __shfl(j, src_lane, kWave);
+            const float d2 = ed_wave(s.zq + (int64_t)qsel * len, ix.Z + jsel * len, len, lane);
+            if (lane == 0) {
+              const int kk = k_of(p, s, qsel);
+              const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
+              offer(ix, p, s, qsel, d2, jsel, ck, true);
+              atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
+            }
+            ++passed;
+          }
+        }
+      }
+    }
+  }
+  // lanes of a wave counted the same tiles: one add per wave
+  if (lane == 0) {
+    atomicAdd(&sc.tally[0], screened);
+    atomicAdd(&sc.tally[1], passed);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1218,6 +1432,30 @@ void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState
                      int64_t* out_ids, float* out_dists, hipStream_t st) {
   hipLaunchKernelGGL(k_finalize, dim3(qp.nq), dim3(kProcThreads), finalize_lds_bytes(qp), st, ix,
                      qp, qs, out_ids, out_dists);
+}
+
+bool screen_supported(int len) { return len == 64 || len == 128 || len == 256 || len == 512; }
+
+void launch_bf16_rows(const float* src, int64_t rows, int len, uint16_t* dst, float* norms,
+                      hipStream_t st) {
+  if (rows <= 0) return;
+  const int64_t blocks = std::min<int64_t>((rows + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_bf16_rows, dim3((unsigned)blocks), dim3(256), 0, st, src, rows, len, dst, norms);
+}
+
+void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
+                   const ScreenDev& sc, int blocks, hipStream_t st) {
+  const unsigned lb = (unsigned)((qp.n_leaves + 255) / 256);
+  hipLaunchKernelGGL(k_log_approx, dim3(qp.nq), dim3(256), 0, st, qp, qs);
+  hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, false);
+  hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, qp, sc);
+  hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, true);
+  switch (qp.len / 32) {
+    case 2: hipLaunchKernelGGL(k_screen<2>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
+    case 4: hipLaunchKernelGGL(k_screen<4>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
+    case 8: hipLaunchKernelGGL(k_screen<8>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
+    case 16: hipLaunchKernelGGL(k_screen<16>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
+  }
 }
 
 int process_blocks_per_cu(const QueryParams& qp) {
