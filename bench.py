@@ -84,6 +84,49 @@ def run_queries(pm, idx, qt, k, distance, window, budget_s=None):
     return time.perf_counter() - t_start, np.array(lat), tot
 
 
+def run_batched(pm, idx, n, length, nq, reps):
+    """One call per batch of nq noisy-copy queries (noise 0.01/0.1/1.0 round
+    robin), ED, k alternating 1 and 10: plain FP32 path vs the BF16 screen.
+    Returns queries/s of each and whether their answers are identical."""
+    import torch
+    import synth
+
+    bq, _, _ = synth.noisy_queries(nq, n, length, j0=100_000)
+    ks = [1 if i % 2 == 0 else 10 for i in range(nq)]
+    bt = torch.from_numpy(bq).cuda()
+    t0 = time.perf_counter()
+    pm.messi_prepare_screen(idx)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t0
+    out = {"workload": f"{nq} noisy dataset copies per call, ED, k alternating 1 and 10",
+           "screen_prepare_s": prep_s}
+    answers = {}
+    for name, flags in (("plain", 0), ("screen", pm.MESSI_SCREEN_BF16)):
+        pm.messi_query_batch(idx, bt[:32], ks[:32], 0, 0, kmax=10, flags=flags)  # warm up
+        best = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ids, d, st = pm.messi_query_batch(idx, bt, ks, 0, 0, kmax=10, flags=flags, stats=True)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if best is None or dt < best[0]:
+                best = (dt, st)
+        dt, st = best
+        answers[name] = (ids.cpu().numpy(), d.cpu().numpy())
+        out[name] = {"queries_per_s": nq / dt, "ms_per_batch": dt * 1e3,
+                     "phases_us": {p: st[f"us_{p}"] for p in PHASES},
+                     "refined_per_query": st["refined"] / nq,
+                     "series_lb_per_query": st["series_lb"] / nq,
+                     "screened_pairs_per_query": st["screened"] / nq}
+        log(f"batched {name}: {nq / dt:.0f} q/s ({dt * 1e3:.1f} ms per {nq}), phases "
+            f"{ {p: round(st[f'us_{p}']) for p in PHASES} }, refined/q {st['refined'] / nq:.0f}")
+    out["identical_answers"] = bool(np.array_equal(answers["plain"][0], answers["screen"][0]) and
+                                    np.array_equal(answers["plain"][1], answers["screen"][1]))
+    out["screen_speedup"] = out["screen"]["queries_per_s"] / out["plain"]["queries_per_s"]
+    return out
+
+
 def cpu_baseline(n, length, queries, sample):
     """The oracle's brute-force scan on the host cores over the first
     `sample` series (regenerated on the host in chunks; only the scans are
@@ -118,6 +161,9 @@ def main():
     ap.add_argument("--dtw-n", type=int, default=10_000_000)
     ap.add_argument("--dtw-queries", type=int, default=100)
     ap.add_argument("--window", type=int, default=25)
+    ap.add_argument("--batch", type=int, default=1024,
+                    help="queries of the batched run (noisy copies, k alternating 1 and 10)")
+    ap.add_argument("--batch-reps", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
     ap.add_argument("--cpu-queries", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -200,6 +246,10 @@ def main():
         log(f"DTW: {dtw['value']:.2f} q/s, p50 {dtw['p50_ms']:.2f} ms, p99 {dtw['p99_ms']:.2f} ms")
         didx.free()
 
+    batched = None
+    if args.batch > 0:
+        batched = run_batched(pm, idx, n, length, args.batch, args.batch_reps)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(n, length, qs[args.warmup:args.warmup + args.cpu_queries],
@@ -239,6 +289,7 @@ def main():
                      "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
                      "traffic": traffic, "bytes_per_launch": dom_bytes},
         "dtw": dtw,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -530,9 +530,9 @@ int run_group(messi_index* ix, const float* queries, int nq, int kmax, int dista
     const double g = len * std::ldexp(1.0, -23) / (1.0 - len * std::ldexp(1.0, -23));
     const double cdot = 2.0 * ((2.0 * ub + ub * ub) + g * (1.0 + ub) * (1.0 + ub)) * (1.0 + std::ldexp(1.0, -10));
     sc.c_dot = std::nextafter((float)cdot, INFINITY);
-    sc.c_abs = (float)std::ldexp(1.0, -19);
+    sc.c_abs = (float)std::ldexp(1.0, -17);
   }
-  const int screen_blocks = 4 * ix->n_cus;
+  const int screen_blocks = screen ? screen_blocks_per_cu(len) * ix->n_cus : 0;
   std::vector<int> status(nq);
   // phase timing (only when the caller asks for statistics)
   hipEvent_t ev[6] = {};

@@ -43,11 +43,12 @@ struct ScreenDev {
   int* lists;             // [sum of cnt] query indices, leaf by leaf
   int* counter;           // leaf work counter
   unsigned long long* tally;  // [2] pairs screened, pairs passed to refinement
-  float c_dot;            // bound: c_dot |q||x| + c_abs (|q|^2 + |x|^2 + 2 |s|)
+  float c_dot;            // bound: c_dot |q||x| + c_abs (|q|^2 + |x|^2)
   float c_abs;
 };
 
 bool screen_supported(int len);
+int screen_blocks_per_cu(int len);
 void launch_bf16_rows(const float* src, int64_t rows, int len, uint16_t* dst, float* norms,
                       hipStream_t st);
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,

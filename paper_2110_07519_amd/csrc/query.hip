@@ -1200,19 +1200,53 @@ __global__ __launch_bounds__(1024) void k_list_scan(QueryParams p, ScreenDev sc)
   }
 }
 
-// Screen and refinement, leaf-major.  A block takes one leaf at a time;
-// its four waves take 16-series column tiles of the leaf (the BF16 rows
-// held in registers as the MFMA B operand) and run over the leaf's query
-// list in 16-query row tiles (A operand).  Lane l holds output rows
-// 4 (l / 16) .. + 3 of column l % 16.  Pairs passing the bound are refined
-// by the whole wave in FP32 and offered to their query's k best.
-template <int KS>  // len = 32 KS
-__global__ __launch_bounds__(256) void k_screen(IndexDev ix, QueryParams p, QueryState s,
-                                                ScreenDev sc) {
-  constexpr int len = 32 * KS;
+// Screen and refinement, leaf-major, as a tiled BF16 GEMM per leaf: the
+// block's eight waves hold 64 series each (16 at len 512) of a column pass
+// in registers (MFMA B operand); the leaf's query list streams through LDS
+// in chunks of 64 queries (A operand), double buffered.  Lane l holds
+// output rows 4 (l / 16) .. + 3 of column l % 16 of each 16 x 16 tile.
+//
+// The test of a pair is folded into per-row and per-column terms.  With
+// |s~| <= (|q|^2 + |x|^2) / 2 the bound is at most
+//   c_dot |q| |x| + c_abs (|q|^2 + |x|^2),   c_abs = 2^-17,
+// which also covers the FP32 rounding of the folded expression, so a pair
+// is dropped iff
+//   R_q + C_x - a_q s_x - 2 s~ > 0,
+//   R_q = |q|^2 (1 - c_abs) - thr_q,  C_x = |x|^2 (1 - c_abs),
+//   a_q = c_dot |q|,  s_x = |x|.
+// Rows past the list and columns past the leaf get R_q / C_x = +inf.  Pairs
+// kept are refined by the whole wave in FP32 and offered to their query's
+// k best, except the query's own approximate-search range (already in its
+// k best and logged).
+constexpr int kScreenWaves = 8;
+constexpr int kScreenChunk = 64;
+
+template <int KS>
+struct ScreenShape {
+  static constexpr int len = 32 * KS;
+  static constexpr int row_bytes = 2 * len + 16;  // padded: rows start 4 banks apart
+  static constexpr int a_bytes = kScreenChunk * row_bytes;
+  static constexpr int per_thread = kScreenChunk * (len / 8) / (kScreenWaves * kWave);  // uint4 loads
+  static constexpr size_t lds = 2 * (size_t)a_bytes;
+  static constexpr int tiles = KS >= 16 ? 1 : 4;  // 16-series column tiles per wave
+  static constexpr int pass = 16 * tiles * kScreenWaves;
+};
+
+template <int KS>
+__global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, QueryParams p,
+                                                                 QueryState s, ScreenDev sc) {
+  using Sh = ScreenShape<KS>;
+  constexpr int len = Sh::len;
+  constexpr int NT = Sh::tiles;
+  constexpr int kThreads = kScreenWaves * kWave;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int col = lane & 15, kb = 8 * (lane >> 4);
+  extern __shared__ uint4 smem_v[];
+  char* abuf = reinterpret_cast<char*>(smem_v);
+  __shared__ float s_R[2][kScreenChunk], s_a[2][kScreenChunk];
+  __shared__ int s_q[2][kScreenChunk];
   __shared__ int s_leaf;
+  const float one_m = 1.0f - sc.c_abs;
   unsigned long long screened = 0, passed = 0;
   for (;;) {
     if (tid == 0) s_leaf = atomicAdd(sc.counter, 1);
@@ -1222,66 +1256,132 @@ __global__ __launch_bounds__(256) void k_screen(IndexDev ix, QueryParams p, Quer
     if (leaf >= p.n_leaves) break;
     const int64_t l0 = sc.off[leaf], l1 = sc.off[leaf + 1];
     if (l0 == l1) continue;
+    const int nlist = (int)(l1 - l0);
+    const int nch = (nlist + kScreenChunk - 1) / kScreenChunk;
     const int64_t b = ix.leaf_begin[leaf], e = ix.leaf_end[leaf];
-    for (int64_t t0 = b + 16 * wv; t0 < e; t0 += 64) {
-      const int64_t j = t0 + col;
-      const bool jv = j < e;
-      bf16x8 B[KS];
-      if (jv) {
+    // chunk c of the list into registers: A rows and the row terms
+    uint4 pa[Sh::per_thread];
+    int pq = -1;
+    float pR = INFINITY, pA = 0.0f;
+    auto fetch = [&](int c) {
+#pragma unroll
+      for (int u = 0; u < Sh::per_thread; ++u) {
+        const int v = tid + u * kThreads;  // uint4 index in the chunk
+        const int row = v / (len / 8), c16 = v % (len / 8);
+        const int li = c * kScreenChunk + row;
+        pa[u] = make_uint4(0, 0, 0, 0);
+        if (li < nlist) {
+          const int q = sc.lists[l0 + li];
+          pa[u] = reinterpret_cast<const uint4*>(sc.qb + (int64_t)q * len)[c16];
+        }
+      }
+      if (tid < kScreenChunk) {
+        const int li = c * kScreenChunk + tid;
+        pq = -1;
+        pR = INFINITY;
+        pA = 0.0f;
+        if (li < nlist) {
+          pq = sc.lists[l0 + li];
+          const float qn = sc.qn[pq];
+          const float thr = kth_dist(s.slots + (int64_t)pq * p.k, k_of(p, s, pq)) * p.win;
+          pR = qn * one_m - thr;
+          pA = sc.c_dot * __fsqrt_rn(qn);
+        }
+      }
+    };
+    auto stash = [&](int buf) {
+      char* dst = abuf + buf * Sh::a_bytes;
+#pragma unroll
+      for (int u = 0; u < Sh::per_thread; ++u) {
+        const int v = tid + u * kThreads;
+        const int row = v / (len / 8), c16 = v % (len / 8);
+        *reinterpret_cast<uint4*>(dst + row * Sh::row_bytes + 16 * c16) = pa[u];
+      }
+      if (tid < kScreenChunk) {
+        s_q[buf][tid] = pq;
+        s_R[buf][tid] = pR;
+        s_a[buf][tid] = pA;
+      }
+    };
+    for (int64_t base = b; base < e; base += Sh::pass) {
+      const int64_t wbase = base + 16 * NT * wv;
+      float cx[NT], sx[NT];
+      bf16x8 B[NT][KS];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int64_t j = wbase + 16 * t + col;
+        const bool v = j < e;
+        const float xn = v ? sc.xn[j] : 0.0f;
+        cx[t] = v ? xn * one_m : INFINITY;
+        sx[t] = __fsqrt_rn(xn);
         const uint4* src = reinterpret_cast<const uint4*>(sc.Zb + j * len + kb);
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) B[ks] = __builtin_bit_cast(bf16x8, src[4 * ks]);
-      } else {
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) B[ks] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+        for (int ks = 0; ks < KS; ++ks)
+          B[t][ks] = __builtin_bit_cast(bf16x8, v ? src[4 * ks] : make_uint4(0, 0, 0, 0));
       }
-      const float xn = jv ? sc.xn[j] : 0.0f;
-      const int64_t cnt_cols = (e - t0) < 16 ? (e - t0) : 16;
-      for (int64_t qt = l0; qt < l1; qt += 16) {
-        const int64_t ai = qt + col;
-        const int qa = ai < l1 ? sc.lists[ai] : -1;
-        bf16x8 A[KS];
-        if (qa >= 0) {
-          const uint4* src = reinterpret_cast<const uint4*>(sc.qb + (int64_t)qa * len + kb);
+      const int ncols = (int)((e - wbase) < 16 * NT ? ((e - wbase) > 0 ? (e - wbase) : 0) : 16 * NT);
+      fetch(0);
+      stash(0);
+      __syncthreads();
+      for (int c = 0; c < nch; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nch) fetch(c + 1);
+        const char* A = abuf + buf * Sh::a_bytes;
+        const int rows_valid = min(kScreenChunk, nlist - c * kScreenChunk);
+#pragma unroll 1
+        for (int qt = 0; qt < kScreenChunk / 16 && 16 * qt < rows_valid; ++qt) {
+          f32x4 acc[NT];
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks) A[ks] = __builtin_bit_cast(bf16x8, src[4 * ks]);
-        } else {
+          for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+          const char* arow = A + (16 * qt + col) * Sh::row_bytes + 2 * kb;
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks) A[ks] = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-        }
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+          for (int ks = 0; ks < KS; ++ks) {
+            const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(arow + 64 * ks));
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ks], B[ks], acc, 0, 0, 0);
-        const int64_t rows = (l1 - qt) < 16 ? (l1 - qt) : 16;
-        screened += (unsigned long long)(rows * cnt_cols);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t ri = qt + 4 * (lane >> 4) + r;
-          const int qr = ri < l1 ? sc.lists[ri] : -1;
-          bool keep = false;
-          if (qr >= 0 && jv && !(j >= s.approx_range[2 * qr] && j < s.approx_range[2 * qr + 1])) {
-            const float qn = sc.qn[qr];
-            const float thr = kth_dist(s.slots + (int64_t)qr * p.k, k_of(p, s, qr)) * p.win;
-            const float dt = qn + xn - 2.0f * acc[r];
-            const float E = sc.c_dot * __fsqrt_rn(qn * xn) + sc.c_abs * (qn + xn + 2.0f * fabsf(acc[r]));
-            keep = !(dt - E > thr);
+            for (int t = 0; t < NT; ++t)
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[t][ks], acc[t], 0, 0, 0);
           }
-          unsigned long long m = __ballot(keep);
-          while (m) {
-            const int src_lane = __ffsll((long long)m) - 1;
-            m &= m - 1;
-            const int qsel = __shfl(qr, src_lane, kWave);
-            const int64_t jsel = __shfl(j, src_lane, kWave);
-            const float d2 = ed_wave(s.zq + (int64_t)qsel * len, ix.Z + jsel * len, len, lane);
-            if (lane == 0) {
-              const int kk = k_of(p, s, qsel);
-              const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
-              offer(ix, p, s, qsel, d2, jsel, ck, true);
-              atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
+          screened += (unsigned long long)(min(16, rows_valid - 16 * qt) * ncols);
+          uint32_t keep = 0;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * qt + 4 * (lane >> 4) + r;
+            const float R = s_R[buf][row], a = s_a[buf][row];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              const float x = __builtin_fmaf(-2.0f, acc[t][r], __builtin_fmaf(-a, sx[t], R + cx[t]));
+              keep |= (x > 0.0f ? 0u : 1u) << (r * NT + t);
             }
-            ++passed;
+          }
+          if (__ballot(keep != 0)) {  // rare: refine the kept pairs one at a time
+            unsigned long long m = __ballot(keep != 0);
+            while (m) {
+              const int src_lane = __ffsll((long long)m) - 1;
+              m &= m - 1;
+              uint32_t bits = __shfl(keep, src_lane, kWave);
+              while (bits) {
+                const int bit = __ffs(bits) - 1;
+                bits &= bits - 1;
+                const int r = bit / NT, t = bit % NT;
+                const int row = 16 * qt + 4 * (src_lane >> 4) + r;
+                const int qsel = s_q[buf][row];
+                const int64_t jsel = wbase + 16 * t + (src_lane & 15);
+                if (qsel < 0 || jsel >= e) continue;
+                if (jsel >= s.approx_range[2 * qsel] && jsel < s.approx_range[2 * qsel + 1]) continue;
+                const float d2 = ed_wave(s.zq + (int64_t)qsel * len, ix.Z + jsel * len, len, lane);
+                if (lane == 0) {
+                  const int kk = k_of(p, s, qsel);
+                  const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
+                  offer(ix, p, s, qsel, d2, jsel, ck, true);
+                  atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
+                }
+                ++passed;
+              }
+            }
           }
         }
+        if (c + 1 < nch) stash(buf ^ 1);
+        __syncthreads();
       }
     }
   }
@@ -1436,6 +1536,23 @@ void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState
 
 bool screen_supported(int len) { return len == 64 || len == 128 || len == 256 || len == 512; }
 
+int screen_blocks_per_cu(int len) {
+  int per = 0;
+  hipError_t e = hipSuccess;
+  const int th = kScreenWaves * kWave;
+  switch (len / 32) {
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<2>, th, ScreenShape<2>::lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<4>, th, ScreenShape<4>::lds); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<8>, th, ScreenShape<8>::lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<16>, th, ScreenShape<16>::lds); break;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 1;
+  }
+  return per < 1 ? 1 : per;
+}
+
 void launch_bf16_rows(const float* src, int64_t rows, int len, uint16_t* dst, float* norms,
                       hipStream_t st) {
   if (rows <= 0) return;
@@ -1450,11 +1567,12 @@ void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& 
   hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, false);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, qp, sc);
   hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, true);
+  const dim3 th(kScreenWaves * kWave);
   switch (qp.len / 32) {
-    case 2: hipLaunchKernelGGL(k_screen<2>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
-    case 4: hipLaunchKernelGGL(k_screen<4>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
-    case 8: hipLaunchKernelGGL(k_screen<8>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
-    case 16: hipLaunchKernelGGL(k_screen<16>, dim3(blocks), dim3(256), 0, st, ix, qp, qs, sc); break;
+    case 2: hipLaunchKernelGGL(k_screen<2>, dim3(blocks), th, ScreenShape<2>::lds, st, ix, qp, qs, sc); break;
+    case 4: hipLaunchKernelGGL(k_screen<4>, dim3(blocks), th, ScreenShape<4>::lds, st, ix, qp, qs, sc); break;
+    case 8: hipLaunchKernelGGL(k_screen<8>, dim3(blocks), th, ScreenShape<8>::lds, st, ix, qp, qs, sc); break;
+    case 16: hipLaunchKernelGGL(k_screen<16>, dim3(blocks), th, ScreenShape<16>::lds, st, ix, qp, qs, sc); break;
   }
 }
 

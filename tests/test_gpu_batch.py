@@ -134,3 +134,18 @@ def test_batch_edge_cases_and_errors(pm):
     with pytest.raises(pm.MessiError):
         pm.messi_query_batch(idx, qt, [1, 1, 1], [0, 0, 0], [0, 0, 0], flags=4)
     idx.free()
+
+
+def test_screen_length_512(pm):
+    raw = synth.randomwalk(5000, 512, seed=12)
+    t = torch.from_numpy(raw).cuda()
+    idx = pm.messi_build(t, 16, 256, 100)
+    qs = np.concatenate([synth.noisy_queries(9, 5000, 512, data_seed=12)[0],
+                         synth.random_queries(3, 512)])
+    qt = torch.from_numpy(qs).cuda()
+    ks = [1, 10] * 6
+    oids, od = _oracle_rows(raw, qs, ks, [0] * 12, [0] * 12)
+    for flags in (0, pm.MESSI_SCREEN_BF16):
+        ids, d, _ = _run(pm, idx, qt, ks, [0] * 12, [0] * 12, flags)
+        _check(ids, d, oids, od)
+    idx.free()
