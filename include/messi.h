@@ -141,6 +141,50 @@ int messi_query_batch(messi_index* index, const float* queries, int32_t nq, cons
  * copy lives until messi_free. */
 int messi_prepare_screen(messi_index* index);
 
+/* Serving loop over a built index.  Requests carry one raw query (HOST
+ * memory, len floats, copied at submit) with its k, distance and window.
+ * Worker threads, each with its own HIP stream and buffers, repeatedly take
+ * the pending requests that fit - at most the batch capacity, and only while
+ * the device bytes held by admitted, unfinished requests stay within
+ * mem_budget_bytes (a request alone is always admitted) - and run them as
+ * one messi_query_batch-style batch; requests arriving meanwhile go to the
+ * next free worker, so batches overlap on the GPU.  Answers equal those of
+ * messi_query for the same query, k, distance and window.
+ * The index must outlive the server and must not be freed while it runs. */
+typedef struct messi_server messi_server;
+
+typedef struct messi_server_options { /* zero-initialised = defaults */
+  int32_t workers;          /* concurrent batches, 1..8 (0: 2) */
+  int32_t max_batch;        /* most requests per batch (0: 1024) */
+  int64_t mem_budget_bytes; /* device bytes in-flight requests may hold (0: no limit) */
+  int32_t flags;            /* MESSI_SCREEN_BF16: screen ED requests */
+  int32_t kmax;             /* largest k a request may ask (0: 64) */
+} messi_server_options;
+
+typedef struct messi_server_stats {
+  int64_t submitted, completed, batches, max_batch_seen;
+  int64_t inflight_bytes, peak_inflight_bytes, mem_budget_bytes;
+  int64_t request_bytes;    /* device bytes accounted per admitted request */
+  int64_t batch_capacity;   /* requests a worker can take at once */
+  double busy_us;           /* summed worker time with a batch on the GPU */
+} messi_server_stats;
+
+int messi_server_start(messi_index* index, const messi_server_options* opts, messi_server** out);
+/* Queue one request; *id receives its number (0, 1, 2, ... in submit order). */
+int messi_server_submit(messi_server* server, const float* query, int32_t k, int32_t distance,
+                        int32_t window, uint64_t* id);
+/* Up to max finished requests into HOST arrays: req_ids[max], status[max]
+ * (MESSI_OK or the batch's error), ids[max][kmax], dists[max][kmax] (k
+ * entries then -1 / +inf), latency_us[max] (submit to result); any array
+ * may be NULL.  Waits up to timeout_ms for the first one (-1: no limit,
+ * 0: no wait).  *count receives the number returned. */
+int messi_server_poll(messi_server* server, int32_t max, int32_t timeout_ms, uint64_t* req_ids,
+                      int32_t* status, int64_t* ids, float* dists, double* latency_us,
+                      int32_t* count);
+int messi_server_get_stats(messi_server* server, messi_server_stats* stats);
+/* Finish every queued request, stop the workers and free the server. */
+void messi_server_stop(messi_server* server);
+
 /* Order the index's work after / before the caller's on this HIP stream
  * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */
 int messi_set_stream(messi_index* index, void* hip_stream);

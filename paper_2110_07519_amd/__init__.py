@@ -32,6 +32,8 @@ EXPORTS = [
     "messi_build", "messi_query", "messi_query_stats", "messi_set_stream", "messi_index_info",
     "messi_get_words", "messi_get_perm", "messi_get_leaves", "messi_breakpoints", "messi_free",
     "messi_last_error", "messi_query_batch", "messi_prepare_screen",
+    "messi_server_start", "messi_server_submit", "messi_server_poll", "messi_server_get_stats",
+    "messi_server_stop",
 ]
 
 
@@ -59,6 +61,23 @@ class MessiStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class MessiServerOptions(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("mem_budget_bytes", ctypes.c_int64), ("flags", ctypes.c_int32),
+                ("kmax", ctypes.c_int32)]
+
+
+class MessiServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("batches", ctypes.c_int64), ("max_batch_seen", ctypes.c_int64),
+                ("inflight_bytes", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64),
+                ("mem_budget_bytes", ctypes.c_int64), ("request_bytes", ctypes.c_int64),
+                ("batch_capacity", ctypes.c_int64), ("busy_us", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -75,6 +94,12 @@ def lib():
         L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
         L.messi_query_batch.argtypes = [P, P, i32, P, P, P, i32, i32, P, P, P]
         L.messi_prepare_screen.argtypes = [P]
+        L.messi_server_start.argtypes = [P, P, P]
+        L.messi_server_submit.argtypes = [P, P, i32, i32, i32, P]
+        L.messi_server_poll.argtypes = [P, i32, i32, P, P, P, P, P, P]
+        L.messi_server_get_stats.argtypes = [P, P]
+        L.messi_server_stop.argtypes = [P]
+        L.messi_server_stop.restype = None
         L.messi_set_stream.argtypes = [P, P]
         L.messi_index_info.argtypes = [P, P, P, P, P, P, P]
         L.messi_get_words.argtypes = [P, P]
@@ -85,7 +110,8 @@ def lib():
         L.messi_free.restype = None
         L.messi_last_error.restype = ctypes.c_char_p
         for name in ["messi_build", "messi_query", "messi_query_stats", "messi_query_batch",
-                     "messi_prepare_screen", "messi_set_stream",
+                     "messi_prepare_screen", "messi_server_start", "messi_server_submit",
+                     "messi_server_poll", "messi_server_get_stats", "messi_set_stream",
                      "messi_index_info", "messi_get_words", "messi_get_perm", "messi_get_leaves",
                      "messi_breakpoints"]:
             getattr(L, name).restype = ctypes.c_int
@@ -225,6 +251,57 @@ def messi_get_leaves(index) -> np.ndarray:
                    ("bits", np.uint8, 16)])
     raw = np.frombuffer(arr, dtype=np.uint8, count=cnt.value * ctypes.sizeof(MessiLeaf))
     return raw.view(dt).copy()
+
+
+class Server:
+    """Serving loop over a built index (messi_server_*): submit() queues a
+    host query, poll() returns finished requests as
+    (request id, status, ids[k], dists[k], latency in microseconds)."""
+
+    def __init__(self, index, workers=2, max_batch=1024, mem_budget_bytes=0, flags=0, kmax=64):
+        o = MessiServerOptions(workers, max_batch, mem_budget_bytes, flags, kmax)
+        h = ctypes.c_void_p()
+        _check(lib().messi_server_start(index.handle, ctypes.byref(o), ctypes.byref(h)))
+        self.handle, self.index, self.kmax, self.len = h, index, kmax, index.len
+
+    def submit(self, query, k=1, distance=MESSI_ED, window=0) -> int:
+        q = np.ascontiguousarray(query, dtype=np.float32).reshape(-1)
+        assert q.shape[0] == self.len
+        rid = ctypes.c_uint64()
+        _check(lib().messi_server_submit(self.handle, q.ctypes.data_as(ctypes.c_void_p), int(k),
+                                         int(distance), int(window), ctypes.byref(rid)))
+        return rid.value
+
+    def poll(self, max_results=256, timeout_ms=0):
+        rid = np.empty(max_results, dtype=np.uint64)
+        stt = np.empty(max_results, dtype=np.int32)
+        ids = np.empty((max_results, self.kmax), dtype=np.int64)
+        dd = np.empty((max_results, self.kmax), dtype=np.float32)
+        lat = np.empty(max_results, dtype=np.float64)
+        cnt = ctypes.c_int32()
+        P = ctypes.c_void_p
+        _check(lib().messi_server_poll(self.handle, max_results, int(timeout_ms),
+                                       rid.ctypes.data_as(P), stt.ctypes.data_as(P),
+                                       ids.ctypes.data_as(P), dd.ctypes.data_as(P),
+                                       lat.ctypes.data_as(P), ctypes.byref(cnt)))
+        return [(int(rid[i]), int(stt[i]), ids[i].copy(), dd[i].copy(), float(lat[i]))
+                for i in range(cnt.value)]
+
+    def stats(self):
+        st = MessiServerStats()
+        _check(lib().messi_server_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()
+
+    def stop(self):
+        if self.handle:
+            lib().messi_server_stop(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
 
 
 class Index:

@@ -6,7 +6,13 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <thread>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -142,6 +148,38 @@ struct Workspace {
   QueryState qs{};
 };
 
+// Everything one in-flight call needs besides the index: its stream, the
+// query workspace, the batch maps and screen buffers, timing events and the
+// near-tie log capacity.  An index owns one for its own calls; a server
+// owns one per worker, so batches on different workers run concurrently.
+struct QueryCtx {
+  hipStream_t stream = nullptr;
+  Workspace ws;
+  DevMem batch_mem;
+  int batch_nq = 0;
+  int* bmap = nullptr;
+  int* bk = nullptr;
+  uint16_t* qb = nullptr;
+  float* qn = nullptr;
+  int* cnt = nullptr;
+  int64_t* off = nullptr;
+  int* lists = nullptr;
+  int* counter = nullptr;
+  unsigned long long* tally = nullptr;
+  int log_cap = 4096;
+  int proc_blocks_ed = 0;  // cached occupancy of the ED process kernel
+  hipEvent_t ev[6] = {};
+  bool events_ready = false;
+
+  QueryCtx() = default;
+  QueryCtx(const QueryCtx&) = delete;
+  QueryCtx& operator=(const QueryCtx&) = delete;
+  ~QueryCtx() {
+    if (events_ready)
+      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 }  // namespace
 
 struct messi_index {
@@ -149,7 +187,6 @@ struct messi_index {
   int len = 0, w = 0, card_bits = 0, leaf_size = 0;
   int n_leaves = 0, n_nodes = 0;
   int64_t max_leaf = 0;
-  hipStream_t stream = nullptr;
   DevMem mem;
   float* Z = nullptr;
   uint4* words = nullptr;
@@ -162,34 +199,14 @@ struct messi_index {
   NodeDev* nodes = nullptr;
   int4* tree = nullptr;
   int* root_node = nullptr;
-  Workspace ws;
   // BF16 screen: shadow of Z and squared row norms, built on first use
   DevMem screen_mem;
   uint16_t* Zb = nullptr;
   float* xn = nullptr;
-  // batch maps and screen buffers, grown on demand
-  DevMem batch_mem;
-  int batch_nq = 0;
-  int* bmap = nullptr;
-  int* bk = nullptr;
-  uint16_t* qb = nullptr;
-  float* qn = nullptr;
-  int* cnt = nullptr;
-  int64_t* off = nullptr;
-  int* lists = nullptr;
-  int* counter = nullptr;
-  unsigned long long* tally = nullptr;
-  int proc_blocks_cu[2] = {0, 0};  // per distance kind, cached occupancy
-  int log_cap = 4096;
   int n_cus = 0;
+  std::mutex screen_mu;  // first-use construction of the BF16 copy
+  QueryCtx ctx;  // the index's own calls (messi_query, messi_query_batch)
   std::atomic<int> busy{0};
-  hipEvent_t ev[6] = {};
-  bool events_ready = false;
-
-  ~messi_index() {
-    if (events_ready)
-      for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-  }
 
   IndexDev view() const {
     IndexDev v;
@@ -245,7 +262,7 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   const int64_t n = ix->n;
   const int len = ix->len, w = ix->w, cb = ix->card_bits, card = 1 << cb;
   const int nkeys = 1 << w;
-  hipStream_t st = ix->stream;
+  hipStream_t st = ix->ctx.stream;
   DevMem tmp;
 
   // breakpoints with open ends
@@ -263,10 +280,10 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   HIP_OR_THROW(hipMemsetAsync(hist, 0, sizeof(unsigned int) * nkeys, st));
   int spw = std::min(64, (16384 - 257) / len);
   if (spw < 1) spw = 1;
-  int dev = 0, n_cus = 0;
+  int dev = 0;
   HIP_OR_THROW(hipGetDevice(&dev));
-  HIP_OR_THROW(hipDeviceGetAttribute(&n_cus, hipDeviceAttributeMultiprocessorCount, dev));
-  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, st, n_cus);
+  HIP_OR_THROW(hipDeviceGetAttribute(&ix->n_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, st, ix->n_cus);
   launch_check();
 
   // (2) root grouping
@@ -390,13 +407,13 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
 }
 
 // Grow the query workspace to hold (nq, k) with the current log capacity.
-void ensure_workspace(messi_index* ix, int nq, int k) {
-  Workspace& ws = ix->ws;
+void ensure_workspace(messi_index* ix, QueryCtx& c, int nq, int k) {
+  Workspace& ws = c.ws;
   const int card = 1 << ix->card_bits;
-  if (ws.nq >= nq && ws.k >= k && ws.log_cap >= ix->log_cap && ws.L == ix->n_leaves &&
+  if (ws.nq >= nq && ws.k >= k && ws.log_cap >= c.log_cap && ws.L == ix->n_leaves &&
       ws.len == ix->len)
     return;
-  const int NQ = std::max(nq, ws.nq), K = std::max(k, ws.k), LC = ix->log_cap;
+  const int NQ = std::max(nq, ws.nq), K = std::max(k, ws.k), LC = c.log_cap;
   ws.mem.clear();
   ws = Workspace{};
   QueryState& s = ws.qs;
@@ -432,39 +449,40 @@ void ensure_workspace(messi_index* ix, int nq, int k) {
 
 // BF16 shadow of the store (screen operand) and the squared row norms.
 void ensure_screen(messi_index* ix) {
+  std::lock_guard<std::mutex> lk(ix->screen_mu);
   if (ix->Zb) return;
   ix->Zb = ix->screen_mem.alloc<uint16_t>((size_t)ix->n * ix->len);
   ix->xn = ix->screen_mem.alloc<float>((size_t)ix->n);
-  launch_bf16_rows(ix->Z, ix->n, ix->len, ix->Zb, ix->xn, ix->stream);
+  launch_bf16_rows(ix->Z, ix->n, ix->len, ix->Zb, ix->xn, ix->ctx.stream);
   launch_check();
-  HIP_OR_THROW(hipStreamSynchronize(ix->stream));
+  HIP_OR_THROW(hipStreamSynchronize(ix->ctx.stream));
 }
 
 // Batch maps (row and k of each query) and screen buffers for nq queries.
-void ensure_batch(messi_index* ix, int nq) {
-  if (ix->batch_nq >= nq) return;
-  ix->batch_mem.clear();
+void ensure_batch(messi_index* ix, QueryCtx& c, int nq) {
+  if (c.batch_nq >= nq) return;
+  c.batch_mem.clear();
   const int L = ix->n_leaves;
-  ix->bmap = ix->batch_mem.alloc<int>(nq);
-  ix->bk = ix->batch_mem.alloc<int>(nq);
-  ix->qb = ix->batch_mem.alloc<uint16_t>((size_t)nq * ix->len);
-  ix->qn = ix->batch_mem.alloc<float>(nq);
-  ix->cnt = ix->batch_mem.alloc<int>(L);
-  ix->off = ix->batch_mem.alloc<int64_t>((size_t)L + 1);
-  ix->lists = ix->batch_mem.alloc<int>((size_t)nq * L);
-  ix->counter = ix->batch_mem.alloc<int>(1);
-  ix->tally = ix->batch_mem.alloc<unsigned long long>(2);
-  ix->batch_nq = nq;
+  c.bmap = c.batch_mem.alloc<int>(nq);
+  c.bk = c.batch_mem.alloc<int>(nq);
+  c.qb = c.batch_mem.alloc<uint16_t>((size_t)nq * ix->len);
+  c.qn = c.batch_mem.alloc<float>(nq);
+  c.cnt = c.batch_mem.alloc<int>(L);
+  c.off = c.batch_mem.alloc<int64_t>((size_t)L + 1);
+  c.lists = c.batch_mem.alloc<int>((size_t)nq * L);
+  c.counter = c.batch_mem.alloc<int>(1);
+  c.tally = c.batch_mem.alloc<unsigned long long>(2);
+  c.batch_nq = nq;
 }
 
 // One group of queries sharing a distance and window: nq queries whose rows
 // (input and output) are d_qmap[i] and whose k are d_kq[i] (both null for a
 // plain call: rows 0..nq-1, every k = kmax).  Slots are kmax apart and
 // output rows out_stride = kmax entries long.
-int run_group(messi_index* ix, const float* queries, int nq, int kmax, int distance, int window,
-              const int* d_kq, const int* d_qmap, bool screen, int64_t* out_ids,
+int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int kmax, int distance,
+              int window, const int* d_kq, const int* d_qmap, bool screen, int64_t* out_ids,
               float* out_dists, messi_stats* stats) {
-  hipStream_t st = ix->stream;
+  hipStream_t st = c.stream;
   const int len = ix->len;
   const double u = std::ldexp(1.0, -24);
   QueryParams p{};
@@ -504,12 +522,12 @@ int run_group(messi_index* ix, const float* queries, int nq, int kmax, int dista
   if (process_lds_bytes(p) > 64 * 1024 || finalize_lds_bytes(p) > 64 * 1024)
     return fail(MESSI_EINVAL, "series length %d too long for the query kernels", len);
 
-  int& per_cu = ix->proc_blocks_cu[distance == MESSI_DTW ? 1 : 0];
-  if (per_cu == 0 || distance == MESSI_DTW) per_cu = process_blocks_per_cu(p);
-  if (ix->n_cus == 0) {
-    int dev = 0;
-    HIP_OR_THROW(hipGetDevice(&dev));
-    HIP_OR_THROW(hipDeviceGetAttribute(&ix->n_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  int per_cu = 0;
+  if (distance == MESSI_DTW) {
+    per_cu = process_blocks_per_cu(p);
+  } else {
+    if (c.proc_blocks_ed == 0) c.proc_blocks_ed = process_blocks_per_cu(p);
+    per_cu = c.proc_blocks_ed;
   }
   const int resident = per_cu * ix->n_cus;
   int blocks = resident / std::max(1, nq);
@@ -518,13 +536,13 @@ int run_group(messi_index* ix, const float* queries, int nq, int kmax, int dista
   if (screen) {
     sc.Zb = ix->Zb;
     sc.xn = ix->xn;
-    sc.qb = ix->qb;
-    sc.qn = ix->qn;
-    sc.cnt = ix->cnt;
-    sc.off = ix->off;
-    sc.lists = ix->lists;
-    sc.counter = ix->counter;
-    sc.tally = ix->tally;
+    sc.qb = c.qb;
+    sc.qn = c.qn;
+    sc.cnt = c.cnt;
+    sc.off = c.off;
+    sc.lists = c.lists;
+    sc.counter = c.counter;
+    sc.tally = c.tally;
     // bound constants (see the screen kernel): u_b = 2^-8, gamma at 2^-23
     const double ub = std::ldexp(1.0, -8);
     const double g = len * std::ldexp(1.0, -23) / (1.0 - len * std::ldexp(1.0, -23));
@@ -537,17 +555,17 @@ int run_group(messi_index* ix, const float* queries, int nq, int kmax, int dista
   // phase timing (only when the caller asks for statistics)
   hipEvent_t ev[6] = {};
   if (stats) {
-    if (!ix->events_ready) {
-      for (int i = 0; i < 6; ++i) HIP_OR_THROW(hipEventCreate(&ix->ev[i]));
-      ix->events_ready = true;
+    if (!c.events_ready) {
+      for (int i = 0; i < 6; ++i) HIP_OR_THROW(hipEventCreate(&c.ev[i]));
+      c.events_ready = true;
     }
-    for (int i = 0; i < 6; ++i) ev[i] = ix->ev[i];
+    for (int i = 0; i < 6; ++i) ev[i] = c.ev[i];
   }
   for (int attempt = 0; attempt < 8; ++attempt) {
-    ensure_workspace(ix, nq, kmax);
-    p.log_cap = ix->log_cap;
+    ensure_workspace(ix, c, nq, kmax);
+    p.log_cap = c.log_cap;
     const IndexDev v = ix->view();
-    QueryState qs = ix->ws.qs;
+    QueryState qs = c.ws.qs;
     qs.kq = d_kq;
     qs.qmap = d_qmap;
     if (stats) HIP_OR_THROW(hipEventRecord(ev[0], st));
@@ -604,17 +622,241 @@ int run_group(messi_index* ix, const float* queries, int nq, int kmax, int dista
       return MESSI_OK;
     }
     if (stats) stats->log_overflows += 1;
-    ix->log_cap *= 4;  // near-tie log overflowed: rerun with a larger one
+    c.log_cap *= 4;  // near-tie log overflowed: rerun with a larger one
   }
   return fail(MESSI_ENOMEM, "near-tie log kept overflowing");
 }
 
 int run_query(messi_index* ix, const float* queries, int nq, int k, int distance, int window,
               int64_t* out_ids, float* out_dists, messi_stats* stats) {
-  return run_group(ix, queries, nq, k, distance, window, nullptr, nullptr, false, out_ids,
+  return run_group(ix, ix->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, out_ids,
                    out_dists, stats);
 }
 
+// Validated batch on one query context: groups of queries sharing
+// (distance, effective window), in first-seen order, one run_group each.
+int run_batch(messi_index* index, QueryCtx& ctx, const float* queries, int nq, const int32_t* k,
+              const int32_t* distance, const int32_t* window, int kmax, int flags,
+              int64_t* out_ids, float* out_dists, messi_stats* stats) {
+  const int len = index->len;
+  std::vector<std::pair<int, int>> keys;
+  std::vector<std::vector<int>> members;
+  for (int i = 0; i < nq; ++i) {
+    const std::pair<int, int> key(distance[i], distance[i] == MESSI_DTW ? std::min(window[i], len - 1) : 0);
+    size_t g = 0;
+    while (g < keys.size() && keys[g] != key) ++g;
+    if (g == keys.size()) {
+      keys.push_back(key);
+      members.emplace_back();
+    }
+    members[g].push_back(i);
+  }
+  try {
+    const bool want_screen = (flags & MESSI_SCREEN_BF16) && screen_supported(len);
+    ensure_batch(index, ctx, nq);
+    std::vector<int> hmap, hk;
+    hmap.reserve(nq);
+    hk.reserve(nq);
+    for (const auto& m : members)
+      for (int i : m) {
+        hmap.push_back(i);
+        hk.push_back(k[i]);
+      }
+    h2d(ctx.bmap, hmap.data(), (size_t)nq, ctx.stream);
+    h2d(ctx.bk, hk.data(), (size_t)nq, ctx.stream);
+    int at = 0;
+    for (size_t g = 0; g < keys.size(); ++g) {
+      const int cnt = (int)members[g].size();
+      const bool screen = want_screen && keys[g].first == MESSI_ED;
+      if (screen && !index->Zb) return fail(MESSI_EINVAL, "the BF16 screen copy is not prepared");
+      const int rc = run_group(index, ctx, queries, cnt, kmax, keys[g].first, keys[g].second,
+                               ctx.bk + at, ctx.bmap + at, screen, out_ids, out_dists, stats);
+      if (rc != MESSI_OK) return rc;
+      at += cnt;
+    }
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  return MESSI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Serving loop.  Requests (one raw query each, its k, distance and window)
+// are queued on the host; every worker owns a query context (stream,
+// workspace, device I/O buffers, pinned staging) and repeatedly takes the
+// pending requests that fit - at most its batch capacity, and only while
+// the device bytes held by admitted, unfinished requests stay within the
+// budget - runs them as one batch, and posts the results.  Requests that
+// arrive while a batch is on the GPU are taken by the next free worker, so
+// batches overlap on the device and a batch is formed from whatever has
+// arrived (continuous batching).
+
+using Clock = std::chrono::steady_clock;
+
+struct SrvRequest {
+  uint64_t id;
+  int k, distance, window;
+  std::vector<float> q;
+  Clock::time_point t_submit;
+  int64_t bytes;
+};
+
+struct SrvResult {
+  uint64_t id;
+  int status;
+  std::vector<int64_t> ids;
+  std::vector<float> dists;
+  double latency_us;
+};
+
+struct SrvWorker {
+  QueryCtx ctx;
+  int cap = 0;
+  float* d_q = nullptr;
+  int64_t* d_ids = nullptr;
+  float* d_d = nullptr;
+  float* h_q = nullptr;
+  int64_t* h_ids = nullptr;
+  float* h_d = nullptr;
+  DevMem io;
+  std::thread th;
+  ~SrvWorker() {
+    if (h_q) (void)hipHostFree(h_q);
+    if (h_ids) (void)hipHostFree(h_ids);
+    if (h_d) (void)hipHostFree(h_d);
+    if (ctx.stream) (void)hipStreamDestroy(ctx.stream);
+  }
+};
+
+// Device bytes one query holds while in flight: its share of the query
+// workspace (normalised query, envelope, bound table, approximate-search
+// distances, k best, near-tie log, leaf bounds and order, work counters),
+// of the batch buffers (maps, BF16 row, leaf lists) and of the I/O buffers.
+int64_t request_bytes(const messi_index* ix, int kmax, int log_cap) {
+  const int64_t len = ix->len, L = ix->n_leaves, card = (int64_t)1 << ix->card_bits;
+  const int64_t item_cap = ix->n / kChunkSeries + L + 1;
+  int64_t b = 0;
+  b += 3 * len * 4 + 3 * kMaxSeg * 4 + kMaxSeg * card * 4 + 16 + (int64_t)kApproxCap * 4;
+  b += (int64_t)kmax * 8 + (int64_t)log_cap * 8 + 4 + L * 4 + 2 * (int64_t)kLbBuckets * 4;
+  b += item_cap * 16 + 4 + (int64_t)kCounterInts * 4 + kStatCount * 8 + 4;
+  b += 8 + len * 2 + 4 + L * 4;
+  b += len * 4 + (int64_t)kmax * 12;
+  return b;
+}
+
+}  // namespace
+
+struct messi_server {
+  messi_index* ix = nullptr;
+  int device = 0;
+  int kmax = 64, flags = 0, workers_n = 2, max_batch = 1024;
+  int64_t budget = 0, req_bytes = 0;
+  std::mutex mu;
+  std::condition_variable cv_work;   // new requests, freed memory, stop
+  std::condition_variable cv_done;   // new results
+  std::deque<SrvRequest> pending;
+  std::deque<SrvResult> done;
+  int64_t inflight = 0, peak_inflight = 0;
+  int64_t submitted = 0, completed = 0, batches = 0, max_batch_seen = 0;
+  double busy_us = 0.0;
+  uint64_t next_id = 0;
+  bool stopping = false;
+  std::vector<std::unique_ptr<SrvWorker>> workers;
+
+  void run(SrvWorker* w);
+};
+
+namespace {
+
+void server_worker_main(messi_server* S, SrvWorker* w) { S->run(w); }
+
+}  // namespace
+
+void messi_server::run(SrvWorker* w) {
+  (void)hipSetDevice(device);
+  const int len = ix->len;
+  std::vector<SrvRequest> batch;
+  std::vector<int32_t> ks, ds, ws;
+  for (;;) {
+    batch.clear();
+    int64_t taken = 0;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      for (;;) {
+        if (stopping && pending.empty()) return;
+        while (!pending.empty() && (int)batch.size() < w->cap &&
+               (budget <= 0 || inflight + taken + pending.front().bytes <= budget ||
+                (inflight + taken == 0))) {
+          taken += pending.front().bytes;
+          batch.push_back(std::move(pending.front()));
+          pending.pop_front();
+        }
+        if (!batch.empty()) break;
+        cv_work.wait(lk);
+      }
+      inflight += taken;
+      peak_inflight = std::max(peak_inflight, inflight);
+      max_batch_seen = std::max<int64_t>(max_batch_seen, (int64_t)batch.size());
+      ++batches;
+    }
+    const int nb = (int)batch.size();
+    ks.resize(nb);
+    ds.resize(nb);
+    ws.resize(nb);
+    for (int i = 0; i < nb; ++i) {
+      std::memcpy(w->h_q + (size_t)i * len, batch[i].q.data(), sizeof(float) * len);
+      ks[i] = batch[i].k;
+      ds[i] = batch[i].distance;
+      ws[i] = batch[i].window;
+    }
+    const auto t0 = Clock::now();
+    int rc = MESSI_OK;
+    std::string err;
+    try {
+      HIP_OR_THROW(hipMemcpyAsync(w->d_q, w->h_q, sizeof(float) * len * nb, hipMemcpyHostToDevice,
+                                  w->ctx.stream));
+      rc = run_batch(ix, w->ctx, w->d_q, nb, ks.data(), ds.data(), ws.data(), kmax, flags,
+                     w->d_ids, w->d_d, nullptr);
+      if (rc == MESSI_OK) {
+        HIP_OR_THROW(hipMemcpyAsync(w->h_ids, w->d_ids, sizeof(int64_t) * kmax * nb,
+                                    hipMemcpyDeviceToHost, w->ctx.stream));
+        HIP_OR_THROW(hipMemcpyAsync(w->h_d, w->d_d, sizeof(float) * kmax * nb,
+                                    hipMemcpyDeviceToHost, w->ctx.stream));
+        HIP_OR_THROW(hipStreamSynchronize(w->ctx.stream));
+      } else {
+        err = g_err;
+      }
+    } catch (const HipError& e) {
+      rc = MESSI_EDEVICE;
+    } catch (const OomError& e) {
+      rc = MESSI_ENOMEM;
+    }
+    const auto t1 = Clock::now();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int i = 0; i < nb; ++i) {
+        SrvResult r;
+        r.id = batch[i].id;
+        r.status = rc;
+        if (rc == MESSI_OK) {
+          r.ids.assign(w->h_ids + (size_t)i * kmax, w->h_ids + (size_t)i * kmax + batch[i].k);
+          r.dists.assign(w->h_d + (size_t)i * kmax, w->h_d + (size_t)i * kmax + batch[i].k);
+        }
+        r.latency_us = std::chrono::duration<double, std::micro>(t1 - batch[i].t_submit).count();
+        done.push_back(std::move(r));
+      }
+      completed += nb;
+      inflight -= taken;
+      busy_us += std::chrono::duration<double, std::micro>(t1 - t0).count();
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();
+  }
+}
+
+namespace {
 }  // namespace
 
 extern "C" {
@@ -738,60 +980,30 @@ int messi_query_batch(messi_index* index, const float* queries, int32_t nq, cons
   if (flags & ~MESSI_SCREEN_BF16) return fail(MESSI_EINVAL, "unknown flags");
   if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
     return fail(MESSI_EINVAL, "queries and outputs must be device pointers");
-  const int len = index->len;
-  // groups of queries sharing (distance, effective window), in first-seen order
-  std::vector<std::pair<int, int>> keys;
-  std::vector<std::vector<int>> members;
   for (int i = 0; i < nq; ++i) {
     if (k[i] < 1 || k[i] > kmax) return fail(MESSI_EINVAL, "k[%d] must be in [1, kmax]", i);
     if (distance[i] != MESSI_ED && distance[i] != MESSI_DTW)
       return fail(MESSI_EINVAL, "unknown distance[%d]", i);
     if (window[i] < 0) return fail(MESSI_EINVAL, "window[%d] must be >= 0", i);
-    const std::pair<int, int> key(distance[i], distance[i] == MESSI_DTW ? std::min(window[i], len - 1) : 0);
-    size_t g = 0;
-    while (g < keys.size() && keys[g] != key) ++g;
-    if (g == keys.size()) {
-      keys.push_back(key);
-      members.emplace_back();
-    }
-    members[g].push_back(i);
   }
   BusyGuard guard(index->busy);
   if (!guard.ok) return fail(MESSI_EBUSY, "index is in use by another call");
-  try {
-    const bool want_screen = (flags & MESSI_SCREEN_BF16) && screen_supported(len);
-    ensure_batch(index, nq);
-    std::vector<int> hmap, hk;
-    hmap.reserve(nq);
-    hk.reserve(nq);
-    for (const auto& m : members)
-      for (int i : m) {
-        hmap.push_back(i);
-        hk.push_back(k[i]);
-      }
-    h2d(index->bmap, hmap.data(), (size_t)nq, index->stream);
-    h2d(index->bk, hk.data(), (size_t)nq, index->stream);
-    int at = 0;
-    for (size_t g = 0; g < keys.size(); ++g) {
-      const int cnt = (int)members[g].size();
-      const bool screen = want_screen && keys[g].first == MESSI_ED;
-      if (screen) ensure_screen(index);
-      const int rc = run_group(index, queries, cnt, kmax, keys[g].first, keys[g].second,
-                               index->bk + at, index->bmap + at, screen, out_ids, out_dists, stats);
-      if (rc != MESSI_OK) return rc;
-      at += cnt;
+  if ((flags & MESSI_SCREEN_BF16) && screen_supported(index->len)) {
+    try {
+      ensure_screen(index);
+    } catch (const OomError& e) {
+      return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+    } catch (const HipError& e) {
+      return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
     }
-  } catch (const OomError& e) {
-    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-  } catch (const HipError& e) {
-    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
   }
-  return MESSI_OK;
+  return run_batch(index, index->ctx, queries, nq, k, distance, window, kmax, flags, out_ids,
+                   out_dists, stats);
 }
 
 int messi_set_stream(messi_index* index, void* hip_stream) {
   if (!index) return fail(MESSI_EINVAL, "index is NULL");
-  index->stream = (hipStream_t)hip_stream;
+  index->ctx.stream = (hipStream_t)hip_stream;
   return MESSI_OK;
 }
 
@@ -804,15 +1016,15 @@ int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t
   if (card_bits) *card_bits = index->card_bits;
   if (n_leaves) *n_leaves = index->n_leaves;
   if (device_bytes)
-    *device_bytes = (int64_t)(index->mem.bytes + index->ws.mem.bytes + index->screen_mem.bytes +
-                              index->batch_mem.bytes);
+    *device_bytes = (int64_t)(index->mem.bytes + index->ctx.ws.mem.bytes +
+                              index->screen_mem.bytes + index->ctx.batch_mem.bytes);
   return MESSI_OK;
 }
 
 int messi_get_perm(const messi_index* index, int32_t* perm) {
   if (!index || !perm) return fail(MESSI_EINVAL, "NULL argument");
   try {
-    d2h(perm, index->perm, (size_t)index->n, index->stream);
+    d2h(perm, index->perm, (size_t)index->n, index->ctx.stream);
   } catch (const HipError& e) {
     return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
   }
@@ -824,8 +1036,8 @@ int messi_get_words(const messi_index* index, uint8_t* words) {
   try {
     std::vector<uint4> ws((size_t)index->n);
     std::vector<int32_t> pm((size_t)index->n);
-    d2h(ws.data(), index->words, (size_t)index->n, index->stream);
-    d2h(pm.data(), index->perm, (size_t)index->n, index->stream);
+    d2h(ws.data(), index->words, (size_t)index->n, index->ctx.stream);
+    d2h(pm.data(), index->perm, (size_t)index->n, index->ctx.stream);
     for (int64_t p = 0; p < index->n; ++p) {
       const uint8_t* b = reinterpret_cast<const uint8_t*>(&ws[(size_t)p]);
       std::memcpy(words + (int64_t)pm[(size_t)p] * index->w, b, (size_t)index->w);
@@ -844,10 +1056,10 @@ int messi_get_leaves(const messi_index* index, messi_leaf* leaves, int64_t cap, 
     const int L = index->n_leaves;
     std::vector<int64_t> b(L), e(L);
     std::vector<uint4> sy(L), bi(L);
-    d2h(b.data(), index->leaf_begin, L, index->stream);
-    d2h(e.data(), index->leaf_end, L, index->stream);
-    d2h(sy.data(), index->leaf_sym, L, index->stream);
-    d2h(bi.data(), index->leaf_bits, L, index->stream);
+    d2h(b.data(), index->leaf_begin, L, index->ctx.stream);
+    d2h(e.data(), index->leaf_end, L, index->ctx.stream);
+    d2h(sy.data(), index->leaf_sym, L, index->ctx.stream);
+    d2h(bi.data(), index->leaf_bits, L, index->ctx.stream);
     std::vector<int> order(L);
     for (int l = 0; l < L; ++l) order[l] = l;
     std::sort(order.begin(), order.end(), [&](int x, int y) { return b[x] < b[y]; });
@@ -863,6 +1075,143 @@ int messi_get_leaves(const messi_index* index, messi_leaf* leaves, int64_t cap, 
     return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
   }
   return MESSI_OK;
+}
+
+
+int messi_server_start(messi_index* index, const messi_server_options* opts, messi_server** out) {
+  g_err.clear();
+  if (!index || !out) return fail(MESSI_EINVAL, "NULL argument");
+  messi_server_options o{};
+  if (opts) o = *opts;
+  const int workers = o.workers == 0 ? 2 : o.workers;
+  const int max_batch = o.max_batch == 0 ? 1024 : o.max_batch;
+  const int kmax = o.kmax == 0 ? 64 : o.kmax;
+  if (workers < 1 || workers > 8) return fail(MESSI_EINVAL, "workers must be in [1, 8]");
+  if (max_batch < 1 || max_batch > 65536) return fail(MESSI_EINVAL, "max_batch must be in [1, 65536]");
+  if (kmax < 1 || kmax > 1024) return fail(MESSI_EINVAL, "kmax must be in [1, 1024]");
+  if (o.mem_budget_bytes < 0) return fail(MESSI_EINVAL, "mem_budget_bytes must be >= 0");
+  if (o.flags & ~MESSI_SCREEN_BF16) return fail(MESSI_EINVAL, "unknown flags");
+  std::unique_ptr<messi_server> S(new messi_server());
+  S->ix = index;
+  S->kmax = kmax;
+  S->flags = o.flags;
+  S->workers_n = workers;
+  S->max_batch = max_batch;
+  S->budget = o.mem_budget_bytes;
+  S->req_bytes = request_bytes(index, kmax, 4096);
+  if (hipGetDevice(&S->device) != hipSuccess) return fail(MESSI_EDEVICE, "no current HIP device");
+  int cap = max_batch;
+  if (S->budget > 0) cap = (int)std::max<int64_t>(1, std::min<int64_t>(cap, S->budget / S->req_bytes));
+  try {
+    if ((o.flags & MESSI_SCREEN_BF16) && screen_supported(index->len)) ensure_screen(index);
+    for (int i = 0; i < workers; ++i) {
+      std::unique_ptr<SrvWorker> w(new SrvWorker());
+      HIP_OR_THROW(hipStreamCreateWithFlags(&w->ctx.stream, hipStreamNonBlocking));
+      w->cap = cap;
+      w->d_q = w->io.alloc<float>((size_t)cap * index->len);
+      w->d_ids = w->io.alloc<int64_t>((size_t)cap * kmax);
+      w->d_d = w->io.alloc<float>((size_t)cap * kmax);
+      HIP_OR_THROW(hipHostMalloc((void**)&w->h_q, sizeof(float) * cap * index->len, hipHostMallocDefault));
+      HIP_OR_THROW(hipHostMalloc((void**)&w->h_ids, sizeof(int64_t) * cap * kmax, hipHostMallocDefault));
+      HIP_OR_THROW(hipHostMalloc((void**)&w->h_d, sizeof(float) * cap * kmax, hipHostMallocDefault));
+      S->workers.push_back(std::move(w));
+    }
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  for (auto& w : S->workers) w->th = std::thread(server_worker_main, S.get(), w.get());
+  *out = S.release();
+  return MESSI_OK;
+}
+
+int messi_server_submit(messi_server* server, const float* query, int32_t k, int32_t distance,
+                        int32_t window, uint64_t* id) {
+  g_err.clear();
+  if (!server || !query || !id) return fail(MESSI_EINVAL, "NULL argument");
+  if (is_device_ptr(query)) return fail(MESSI_EINVAL, "query must be a host pointer");
+  if (k < 1 || k > server->kmax) return fail(MESSI_EINVAL, "k must be in [1, kmax]");
+  if (distance != MESSI_ED && distance != MESSI_DTW) return fail(MESSI_EINVAL, "unknown distance");
+  if (window < 0) return fail(MESSI_EINVAL, "window must be >= 0");
+  SrvRequest r;
+  r.k = k;
+  r.distance = distance;
+  r.window = window;
+  r.q.assign(query, query + server->ix->len);
+  r.bytes = server->req_bytes;
+  {
+    std::lock_guard<std::mutex> lk(server->mu);
+    if (server->stopping) return fail(MESSI_EBUSY, "server is stopping");
+    r.id = server->next_id++;
+    r.t_submit = Clock::now();
+    *id = r.id;
+    server->pending.push_back(std::move(r));
+    ++server->submitted;
+  }
+  server->cv_work.notify_one();
+  return MESSI_OK;
+}
+
+int messi_server_poll(messi_server* server, int32_t max, int32_t timeout_ms, uint64_t* req_ids,
+                      int32_t* status, int64_t* ids, float* dists, double* latency_us,
+                      int32_t* count) {
+  g_err.clear();
+  if (!server || !count || max < 0) return fail(MESSI_EINVAL, "bad argument");
+  *count = 0;
+  std::unique_lock<std::mutex> lk(server->mu);
+  if (server->done.empty() && timeout_ms != 0) {
+    if (timeout_ms < 0)
+      server->cv_done.wait(lk, [&] { return !server->done.empty(); });
+    else
+      server->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms),
+                               [&] { return !server->done.empty(); });
+  }
+  const int kmax = server->kmax;
+  int n = 0;
+  while (n < max && !server->done.empty()) {
+    SrvResult& r = server->done.front();
+    if (req_ids) req_ids[n] = r.id;
+    if (status) status[n] = r.status;
+    if (latency_us) latency_us[n] = r.latency_us;
+    for (int j = 0; j < kmax; ++j) {
+      const bool have = j < (int)r.ids.size();
+      if (ids) ids[(size_t)n * kmax + j] = have ? r.ids[j] : -1;
+      if (dists) dists[(size_t)n * kmax + j] = have ? r.dists[j] : INFINITY;
+    }
+    server->done.pop_front();
+    ++n;
+  }
+  *count = n;
+  return MESSI_OK;
+}
+
+int messi_server_get_stats(messi_server* server, messi_server_stats* st) {
+  if (!server || !st) return fail(MESSI_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(server->mu);
+  st->submitted = server->submitted;
+  st->completed = server->completed;
+  st->batches = server->batches;
+  st->max_batch_seen = server->max_batch_seen;
+  st->inflight_bytes = server->inflight;
+  st->peak_inflight_bytes = server->peak_inflight;
+  st->mem_budget_bytes = server->budget;
+  st->request_bytes = server->req_bytes;
+  st->batch_capacity = server->workers.empty() ? 0 : server->workers[0]->cap;
+  st->busy_us = server->busy_us;
+  return MESSI_OK;
+}
+
+void messi_server_stop(messi_server* server) {
+  if (!server) return;
+  {
+    std::lock_guard<std::mutex> lk(server->mu);
+    server->stopping = true;
+  }
+  server->cv_work.notify_all();
+  for (auto& w : server->workers)
+    if (w->th.joinable()) w->th.join();
+  delete server;
 }
 
 void messi_free(messi_index* index) { delete index; }
