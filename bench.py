@@ -127,6 +127,102 @@ def run_batched(pm, idx, n, length, nq, reps):
     return out
 
 
+def serving_mix(count, n, length, j0):
+    """Request mix: ED / DTW 50/50, DTW window 5/10/20% of the length, k 1 or
+    10, noisy dataset copies (noise 0.01/0.1/1.0 round robin); seed 4."""
+    import synth
+
+    qs, _, _ = synth.noisy_queries(count, n, length, j0=j0)
+    rng = np.random.default_rng(synth.SEED_MIX + j0)
+    dist = rng.integers(0, 2, count)
+    wins = [int(length * f) for f in (0.05, 0.10, 0.20)]
+    win = np.where(dist == 1, rng.choice(wins, count), 0)
+    ks = rng.choice([1, 10], count)
+    return qs, [int(x) for x in ks], [int(x) for x in dist], [int(x) for x in win]
+
+
+def run_serving(pm, idx, n, length, seconds, cap_requests):
+    """Poisson arrivals of the request mix at 0.25, 0.5, 1 and 2 times the
+    capacity of the unbatched plain path (one messi_query per request),
+    served by the continuous-batching server; latency is arrival to result."""
+    import threading
+
+    import torch
+    import synth
+
+    qs, ks, dist, win = serving_mix(cap_requests, n, length, 200_000)
+    qt = torch.from_numpy(qs).cuda()
+    pm.messi_query(idx, qt[:1], 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(cap_requests):
+        pm.messi_query(idx, qt[i:i + 1], ks[i], dist[i], win[i])
+    torch.cuda.synchronize()
+    plain_s = (time.perf_counter() - t0) / cap_requests
+    capacity = 1.0 / plain_s
+    log(f"serving: plain path {capacity:.1f} requests/s on the mix (one at a time)")
+    out = {"workload": "Poisson arrivals; ED/DTW 50/50, DTW window 5/10/20%, k 1/10, noise "
+                       "0.01/0.1/1.0; 2 workers, continuous batching, BF16 screen for ED",
+           "plain_unbatched_requests_per_s": capacity, "capacity_sample": cap_requests,
+           "rates": []}
+    last = None
+    srv = pm.Server(idx, workers=2, max_batch=1024, mem_budget_bytes=16 << 30,
+                    flags=pm.MESSI_SCREEN_BF16, kmax=10)
+    j0 = 300_000
+    for f in (0.25, 0.5, 1.0, 2.0):
+        lam = f * capacity
+        cnt = max(20, int(lam * seconds))
+        rq, rk, rd, rw = serving_mix(cnt, n, length, j0)
+        last = (rq, rk, rd, rw)
+        j0 += cnt
+        gaps = np.random.default_rng(synth.SEED_ARRIVAL).exponential(1.0 / lam, cnt)
+        lat = []
+
+        def producer():
+            t_next = time.perf_counter()
+            for i in range(cnt):
+                t_next += gaps[i]
+                dt = t_next - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+                srv.submit(rq[i], rk[i], rd[i], rw[i])
+
+        t_start = time.perf_counter()
+        th = threading.Thread(target=producer)
+        th.start()
+        t_limit = t_start + seconds * 4 + 60
+        while len(lat) < cnt and time.perf_counter() < t_limit:
+            for r in srv.poll(256, timeout_ms=20):
+                assert r[1] == 0, "serving request failed"
+                lat.append(r[4])
+        th.join()
+        wall = time.perf_counter() - t_start
+        lat = np.array(lat) / 1e3
+        row = {"rate_factor": f, "offered_requests_per_s": lam, "requests": cnt,
+               "completed": int(len(lat)), "achieved_requests_per_s": len(lat) / wall,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99))}
+        out["rates"].append(row)
+        log(f"serving at {f} x capacity ({lam:.1f}/s): {row['achieved_requests_per_s']:.1f}/s, "
+            f"p50 {row['p50_ms']:.1f} ms, p99 {row['p99_ms']:.1f} ms")
+    st = srv.stats()
+    srv.stop()
+    out["batches"] = st["batches"]
+    out["max_batch_seen"] = st["max_batch_seen"]
+    # the plain path on exactly the requests of the heaviest stream, one at a time
+    rq, rk, rd, rw = last
+    rt = torch.from_numpy(rq).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(len(rk)):
+        pm.messi_query(idx, rt[i:i + 1], rk[i], rd[i], rw[i])
+    torch.cuda.synchronize()
+    same = len(rk) / (time.perf_counter() - t0)
+    out["plain_unbatched_same_requests_per_s"] = same
+    out["served_vs_plain_at_2x"] = out["rates"][-1]["achieved_requests_per_s"] / same
+    log(f"serving: plain path on the 2x stream's {len(rk)} requests: {same:.1f}/s")
+    return out
+
+
 def cpu_baseline(n, length, queries, sample):
     """The oracle's brute-force scan on the host cores over the first
     `sample` series (regenerated on the host in chunks; only the scans are
@@ -164,6 +260,9 @@ def main():
     ap.add_argument("--batch", type=int, default=1024,
                     help="queries of the batched run (noisy copies, k alternating 1 and 10)")
     ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--serve-seconds", type=float, default=6.0,
+                    help="length of each Poisson arrival stream of the serving run (0: skip)")
+    ap.add_argument("--serve-capacity-requests", type=int, default=40)
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
     ap.add_argument("--cpu-queries", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -250,6 +349,10 @@ def main():
     if args.batch > 0:
         batched = run_batched(pm, idx, n, length, args.batch, args.batch_reps)
 
+    serving = None
+    if args.serve_seconds > 0:
+        serving = run_serving(pm, idx, n, length, args.serve_seconds, args.serve_capacity_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(n, length, qs[args.warmup:args.warmup + args.cpu_queries],
@@ -290,6 +393,7 @@ def main():
                      "traffic": traffic, "bytes_per_launch": dom_bytes},
         "dtw": dtw,
         "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

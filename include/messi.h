@@ -121,9 +121,9 @@ int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int3
  *   k, distance, window   HOST arrays of nq entries (as in messi_query);
  *              1 <= k[i] <= kmax.
  *   kmax       row length of the outputs, 1..1024.
- *   flags      MESSI_SCREEN_BF16: ED queries go through a BF16 MFMA screen
- *              (q.x with FP32 accumulation and a rigorous error bound) in
- *              front of the FP32 refinement; needs len 64, 128, 256 or 512
+ *   flags      MESSI_SCREEN_BF16: ED queries, in groups of at least 32,
+ *              go through a BF16 MFMA screen (q.x with FP32 accumulation
+ *              and a rigorous error bound) in front of the FP32 refinement; needs len 64, 128, 256 or 512
  *              (otherwise ignored) and 2 len bytes per series of
  *              device memory for a BF16 copy of the store, made on first
  *              use (or ahead of time by messi_prepare_screen).  Answers are

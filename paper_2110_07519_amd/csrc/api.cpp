@@ -633,6 +633,8 @@ int run_query(messi_index* ix, const float* queries, int nq, int k, int distance
                    out_dists, stats);
 }
 
+constexpr int kScreenMinGroup = 32;  // fewer ED queries go the unscreened way
+
 // Validated batch on one query context: groups of queries sharing
 // (distance, effective window), in first-seen order, one run_group each.
 int run_batch(messi_index* index, QueryCtx& ctx, const float* queries, int nq, const int32_t* k,
@@ -667,7 +669,9 @@ int run_batch(messi_index* index, QueryCtx& ctx, const float* queries, int nq, c
     int at = 0;
     for (size_t g = 0; g < keys.size(); ++g) {
       const int cnt = (int)members[g].size();
-      const bool screen = want_screen && keys[g].first == MESSI_ED;
+      // the screen streams every leaf some query of the group keeps, so it
+      // pays off only when many queries share that pass
+      const bool screen = want_screen && keys[g].first == MESSI_ED && cnt >= kScreenMinGroup;
       if (screen && !index->Zb) return fail(MESSI_EINVAL, "the BF16 screen copy is not prepared");
       const int rc = run_group(index, ctx, queries, cnt, kmax, keys[g].first, keys[g].second,
                                ctx.bk + at, ctx.bmap + at, screen, out_ids, out_dists, stats);

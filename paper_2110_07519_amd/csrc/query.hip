@@ -669,9 +669,8 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
                                                                    QueryState s) {
   using Sh = ProcShape<R>;
   constexpr int kW = Sh::waves;
-  const int q = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
-  const int len = p.len, card = 1 << p.card_bits, k = k_of(p, s, q);
+  const int len = p.len, card = 1 << p.card_bits;
   constexpr bool dtw = R != -1;
   extern __shared__ float sm[];
   float* table = sm;                          // [16][card]
@@ -684,8 +683,25 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
   int* pend = reinterpret_cast<int*>(survlb + Sh::surv_cap);    // DTW pairs waiting
   float* wx = reinterpret_cast<float*>(pend + Sh::pend_cap);     // wave DTW rows [kW][len]
   float* wbuf = wx + (R == -2 ? kW * len : 0);                   // wave DTW [kW][3 len]
-  __shared__ int s_batch, s_shard, s_stop, s_nsurv, s_npend;
+  __shared__ int s_batch, s_shard, s_stop, s_nsurv, s_npend, s_skip;
   __shared__ unsigned long long s_ckey;
+  __shared__ int s_shard_done;
+
+  // A block starts on query blockIdx.x % nq and, once every shard of that
+  // query is finished, moves on to the next query, so the blocks of queries
+  // that end early help the ones still running.
+  for (int visit = 0; visit < p.nq; ++visit) {
+  const int q = (int)((blockIdx.x + (unsigned)visit) % (unsigned)p.nq);
+  const int k = k_of(p, s, q);
+  {
+    int* cq = s.next + (int64_t)q * kCounterInts;
+    if (tid == 0)
+      s_skip = load_relaxed(reinterpret_cast<unsigned long long*>(cq + kShards * kCounterStride)) == ~0ull;
+    __syncthreads();
+    const bool skip = s_skip;
+    __syncthreads();
+    if (skip) continue;
+  }
 
   const float* tq = s.table + (int64_t)q * kMaxSeg * card;
   for (int i = tid; i < kMaxSeg * card; i += blockDim.x) table[i] = tq[i];
@@ -706,7 +722,7 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
     s_ckey = load_key(&slots[k - 1]);
     s_nsurv = 0;
     s_npend = 0;
-    s_shard = blockIdx.x % kShards;
+    s_shard = (int)((blockIdx.x / (unsigned)p.nq) % kShards);
   }
   __syncthreads();
 
@@ -745,7 +761,6 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
   int next_batch = 0;
   bool have_next = false;
   unsigned long long next_key = ~0ull;
-  __shared__ int s_shard_done;
   for (;;) {
     if (tid == 0) {
       s_stop = 0;
@@ -961,6 +976,8 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
     if (c_lb) atomicAdd(&stq[kStatSeriesLb], c_lb);
     if (c_lbk) atomicAdd(&stq[kStatLbKeogh], c_lbk);
     if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
+  }
+  __syncthreads();  // LDS is reloaded for the next query
   }
 }
 
@@ -1505,7 +1522,7 @@ void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState&
                     int blocks_per_query, hipStream_t st) {
   bool mask;
   const int R = band_of(qp, &mask);
-  const dim3 g(blocks_per_query, qp.nq);
+  const dim3 g((unsigned)blocks_per_query * (unsigned)qp.nq);  // block b starts on query b % nq
   const dim3 b(process_threads(R));
   const size_t lds = process_lds_bytes(qp);
   if (R == -1) {

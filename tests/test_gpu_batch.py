@@ -54,7 +54,7 @@ def test_mixed_batch_matches_oracle_and_single_calls(pm, length):
     n = 30_000
     raw = synth.randomwalk(n, length, seed=31)
     raw = np.concatenate([raw, raw[:200]])  # exact duplicates: ties
-    qn, _, _ = synth.noisy_queries(30, n, length, data_seed=31)
+    qn, _, _ = synth.noisy_queries(60, n, length, data_seed=31)
     qs = np.concatenate([qn, synth.random_queries(6, length), raw[[3, 150]]])
     nq = len(qs)
     rng = np.random.default_rng(4)
@@ -72,7 +72,7 @@ def test_mixed_batch_matches_oracle_and_single_calls(pm, length):
     assert np.array_equal(plain[0], scr[0]) and np.array_equal(plain[1], scr[1])
     assert scr[2]["screened"] > 0
     # one call per query gives the same rows
-    for i in range(0, nq, 5):
+    for i in range(0, nq, 7):
         ids1, d1 = pm.messi_query(idx, qt[i:i + 1], ks[i], dist[i], wins[i])
         assert np.array_equal(ids1.cpu().numpy()[0], plain[0][i, :ks[i]])
         assert np.array_equal(d1.cpu().numpy()[0], plain[1][i, :ks[i]])
@@ -84,9 +84,9 @@ def test_screen_with_many_ties_and_large_k(pm):
     raw = np.concatenate([base, np.repeat(base[7:8], 2500, axis=0)])
     t = torch.from_numpy(raw).cuda()
     idx = pm.messi_build(t, 16, 256, 100)
-    qs = np.concatenate([raw[[7, 11, 2999]], synth.noisy_queries(5, 3000, 128, data_seed=5)[0]])
+    qs = np.concatenate([raw[[7, 11, 2999]], synth.noisy_queries(29, 3000, 128, data_seed=5)[0]])
     qt = torch.from_numpy(qs).cuda()
-    ks = [3, 50, 1, 64, 2, 7, 1, 20]
+    ks = ([3, 50, 1, 64, 2, 7, 1, 20] * 4)[:len(qs)]
     oids, od = _oracle_rows(raw, qs, ks, [0] * len(qs), [0] * len(qs))
     for flags in (0, pm.MESSI_SCREEN_BF16):
         ids, d, _ = _run(pm, idx, qt, ks, [0] * len(qs), [0] * len(qs), flags)
@@ -101,11 +101,12 @@ def test_screen_ignored_for_unsupported_length(pm):
         length = data.shape[1]
         t = torch.from_numpy(data).cuda()
         idx = pm.messi_build(t, 4 if length == 100 else 16, 256, 50)
-        qs = synth.noisy_queries(7, 4000, length, data_seed=9)[0]
+        qs = synth.noisy_queries(40, 4000, length, data_seed=9)[0]
         qt = torch.from_numpy(qs).cuda()
-        ks = [1, 5, 2, 1, 3, 1, 4]
-        oids, od = _oracle_rows(data, qs, ks, [0] * 7, [0] * 7)
-        ids, d, _ = _run(pm, idx, qt, ks, [0] * 7, [0] * 7, pm.MESSI_SCREEN_BF16)
+        ks = [1, 5, 2, 1, 3, 1, 4, 2] * 5
+        oids, od = _oracle_rows(data, qs, ks, [0] * 40, [0] * 40)
+        ids, d, st = _run(pm, idx, qt, ks, [0] * 40, [0] * 40, pm.MESSI_SCREEN_BF16)
+        assert st["screened"] == 0
         _check(ids, d, oids, od)
         idx.free()
 
@@ -140,12 +141,13 @@ def test_screen_length_512(pm):
     raw = synth.randomwalk(5000, 512, seed=12)
     t = torch.from_numpy(raw).cuda()
     idx = pm.messi_build(t, 16, 256, 100)
-    qs = np.concatenate([synth.noisy_queries(9, 5000, 512, data_seed=12)[0],
+    qs = np.concatenate([synth.noisy_queries(33, 5000, 512, data_seed=12)[0],
                          synth.random_queries(3, 512)])
     qt = torch.from_numpy(qs).cuda()
-    ks = [1, 10] * 6
-    oids, od = _oracle_rows(raw, qs, ks, [0] * 12, [0] * 12)
+    ks = [1, 10] * 18
+    oids, od = _oracle_rows(raw, qs, ks, [0] * 36, [0] * 36)
     for flags in (0, pm.MESSI_SCREEN_BF16):
-        ids, d, _ = _run(pm, idx, qt, ks, [0] * 12, [0] * 12, flags)
+        ids, d, st = _run(pm, idx, qt, ks, [0] * 36, [0] * 36, flags)
         _check(ids, d, oids, od)
+    assert st["screened"] > 0
     idx.free()
