@@ -66,22 +66,32 @@ def phase_bytes(st, length, n_leaves, queries):
 
 
 def run_queries(pm, idx, qt, k, distance, window, budget_s=None):
+    """One messi_query per query (the production call, no statistics);
+    returns wall seconds and per-query latencies."""
     import torch
 
     lat = []
-    tot = {}
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for j in range(qt.shape[0]):
         t0 = time.perf_counter()
-        _, _, st = pm.messi_query(idx, qt[j:j + 1], k, distance, window, stats=True)
+        pm.messi_query(idx, qt[j:j + 1], k, distance, window)
         lat.append(time.perf_counter() - t0)
-        for key, v in st.items():
-            tot[key] = tot.get(key, 0) + v
         if budget_s is not None and time.perf_counter() - t_start > budget_s:
             break
     torch.cuda.synchronize()
-    return time.perf_counter() - t_start, np.array(lat), tot
+    return time.perf_counter() - t_start, np.array(lat)
+
+
+def query_stats(pm, idx, qt, k, distance, window):
+    """The same queries again through messi_query_stats (untimed): work
+    counters and per-phase device times (HIP events on the index's stream)."""
+    tot = {}
+    for j in range(qt.shape[0]):
+        _, _, st = pm.messi_query(idx, qt[j:j + 1], k, distance, window, stats=True)
+        for key, v in st.items():
+            tot[key] = tot.get(key, 0) + v
+    return tot
 
 
 def run_batched(pm, idx, n, length, nq, reps):
@@ -315,8 +325,9 @@ def main():
     log(f"warmup {args.warmup} queries")
     run_queries(pm, idx, qt[:args.warmup], 1, pm.MESSI_ED, 0)
     log(f"timing {args.steps} ED queries one at a time")
-    wall, lat, st = run_queries(pm, idx, qt[args.warmup:], 1, pm.MESSI_ED, 0)
+    wall, lat = run_queries(pm, idx, qt[args.warmup:], 1, pm.MESSI_ED, 0)
     k_done = len(lat)
+    st = query_stats(pm, idx, qt[args.warmup:args.warmup + k_done], 1, pm.MESSI_ED, 0)
     value = k_done / wall
     phases_us = {p: st[f"us_{p}"] / k_done for p in PHASES}
     pb = phase_bytes(st, length, info["n_leaves"], k_done)
@@ -331,8 +342,9 @@ def main():
         dt = torch.from_numpy(dq).cuda()
         run_queries(pm, didx, dt[:3], 1, pm.MESSI_DTW, args.window)
         log(f"timing {args.dtw_queries} DTW queries (r={args.window}) over {dtw_n} series")
-        dwall, dlat, dst = run_queries(pm, didx, dt[3:], 1, pm.MESSI_DTW, args.window, budget_s=90)
+        dwall, dlat = run_queries(pm, didx, dt[3:], 1, pm.MESSI_DTW, args.window, budget_s=90)
         dk = len(dlat)
+        dst = query_stats(pm, didx, dt[3:3 + dk], 1, pm.MESSI_DTW, args.window)
         dph = {p: dst[f"us_{p}"] / dk for p in PHASES}
         dtw = {"metric": "exact 1-NN DTW queries/s (one query at a time)", "value": dk / dwall,
                "unit": "queries/s", "queries": dk, "window": args.window,

@@ -199,6 +199,12 @@ struct messi_index {
   NodeDev* nodes = nullptr;
   int4* tree = nullptr;
   int* root_node = nullptr;
+  int* shard_off = nullptr;  // [kShards + 1] first chunk of each shard
+  int64_t n_chunks = 0;
+  uint4* sh_sym = nullptr;   // leaf table in shard-major order
+  uint4* sh_bits = nullptr;
+  int2* sh_rng = nullptr;
+  int* leaf_sh_off = nullptr;  // [kShards + 1] first shard-major leaf of each shard
   // BF16 screen: shadow of Z and squared row norms, built on first use
   DevMem screen_mem;
   uint16_t* Zb = nullptr;
@@ -226,6 +232,11 @@ struct messi_index {
     v.bp = bp;
     v.tree = tree;
     v.root_node = root_node;
+    v.shard_off = shard_off;
+    v.sh_sym = sh_sym;
+    v.sh_bits = sh_bits;
+    v.sh_rng = sh_rng;
+    v.leaf_sh_off = leaf_sh_off;
     return v;
   }
 };
@@ -402,7 +413,44 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   ix->tree = ix->mem.alloc<int4>(ix->n_nodes);
   launch_make_tree(d.nodes, ix->n_nodes, cb, ix->tree, st);
   launch_check();
-  HIP_OR_THROW(hipStreamSynchronize(st));
+  // chunk layout of the query's leaf order: leaf l in shard l % kShards,
+  // each shard's chunks contiguous
+  {
+    const int L = ix->n_leaves;
+    std::vector<int64_t> lb(L), le(L);
+    d2h(lb.data(), ix->leaf_begin, L, st);
+    d2h(le.data(), ix->leaf_end, L, st);
+    std::vector<int> off(kShards + 1, 0);
+    for (int l = 0; l < L; ++l)
+      off[l % kShards + 1] += (int)((le[l] - lb[l] + kChunkSeries - 1) / kChunkSeries);
+    for (int sh = 0; sh < kShards; ++sh) off[sh + 1] += off[sh];
+    ix->n_chunks = off[kShards];
+    ix->shard_off = ix->mem.alloc<int>(kShards + 1);
+    h2d(ix->shard_off, off.data(), kShards + 1, st);
+    // the leaf table again in shard-major order (shard s: leaves s, s + 64,
+    // ...), read contiguously by the per-shard bound blocks
+    std::vector<uint4> sy(L), bi(L), shs(L), shb(L);
+    std::vector<int2> shr(L);
+    std::vector<int> loff(kShards + 1, 0);
+    d2h(sy.data(), ix->leaf_sym, L, st);
+    d2h(bi.data(), ix->leaf_bits, L, st);
+    for (int sh = 0; sh < kShards; ++sh) loff[sh + 1] = loff[sh] + (sh < L ? (L - sh + kShards - 1) / kShards : 0);
+    for (int l = 0; l < L; ++l) {
+      const int j = loff[l % kShards] + l / kShards;
+      shs[j] = sy[l];
+      shb[j] = bi[l];
+      shr[j] = make_int2((int)lb[l], (int)le[l]);
+    }
+    ix->sh_sym = ix->mem.alloc<uint4>(L);
+    ix->sh_bits = ix->mem.alloc<uint4>(L);
+    ix->sh_rng = ix->mem.alloc<int2>(L);
+    ix->leaf_sh_off = ix->mem.alloc<int>(kShards + 1);
+    h2d(ix->sh_sym, shs.data(), L, st);
+    h2d(ix->sh_bits, shb.data(), L, st);
+    h2d(ix->sh_rng, shr.data(), L, st);
+    h2d(ix->leaf_sh_off, loff.data(), kShards + 1, st);
+    HIP_OR_THROW(hipStreamSynchronize(st));  // the host vectors are pageable memory
+  }
   return true;
 }
 
@@ -429,12 +477,9 @@ void ensure_workspace(messi_index* ix, QueryCtx& c, int nq, int k) {
   s.log = ws.mem.alloc<unsigned long long>((size_t)NQ * LC);
   s.log_count = ws.mem.alloc<int>(NQ);
   s.leaf_lb = ws.mem.alloc<float>((size_t)NQ * L);
-  s.hist = ws.mem.alloc<int>((size_t)NQ * kLbBuckets);
-  s.fill = ws.mem.alloc<int>((size_t)NQ * kLbBuckets);
-  const int64_t item_cap = ix->n / kChunkSeries + L + 1;
+  const int64_t item_cap = ix->n_chunks;
   s.items = ws.mem.alloc<unsigned long long>((size_t)NQ * item_cap);
   s.ranges = ws.mem.alloc<int2>((size_t)NQ * item_cap);
-  s.n_items = ws.mem.alloc<int>(NQ);
   s.next = ws.mem.alloc<int>((size_t)NQ * kCounterInts);
   s.stats = ws.mem.alloc<unsigned long long>((size_t)NQ * kStatCount);
   s.status = ws.mem.alloc<int>(NQ);
@@ -497,7 +542,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   p.window = distance == MESSI_DTW ? std::min(window, len - 1) : 0;
   p.n_leaves = ix->n_leaves;
   p.n = ix->n;
-  p.item_cap = (int)(ix->n / kChunkSeries + ix->n_leaves + 1);
+  p.item_cap = (int)ix->n_chunks;
   // FP32 error of a refined squared distance: at most rho relative, with
   // rho = (4 len + 64) u covering ED's pairwise sums and DTW's paths of up
   // to 2 len - 1 terms.
@@ -578,7 +623,6 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
       if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
       launch_screen(v, p, qs, sc, screen_blocks, st);
     } else {
-      launch_stage2(v, p, qs, st);
       if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
       launch_process(v, p, qs, blocks, st);
     }
@@ -740,11 +784,11 @@ struct SrvWorker {
 // of the batch buffers (maps, BF16 row, leaf lists) and of the I/O buffers.
 int64_t request_bytes(const messi_index* ix, int kmax, int log_cap) {
   const int64_t len = ix->len, L = ix->n_leaves, card = (int64_t)1 << ix->card_bits;
-  const int64_t item_cap = ix->n / kChunkSeries + L + 1;
+  const int64_t item_cap = ix->n_chunks;
   int64_t b = 0;
   b += 3 * len * 4 + 3 * kMaxSeg * 4 + kMaxSeg * card * 4 + 16 + (int64_t)kApproxCap * 4;
-  b += (int64_t)kmax * 8 + (int64_t)log_cap * 8 + 4 + L * 4 + 2 * (int64_t)kLbBuckets * 4;
-  b += item_cap * 16 + 4 + (int64_t)kCounterInts * 4 + kStatCount * 8 + 4;
+  b += (int64_t)kmax * 8 + (int64_t)log_cap * 8 + 4 + L * 4;
+  b += item_cap * 16 + (int64_t)kCounterInts * 4 + kStatCount * 8 + 4;
   b += 8 + len * 2 + 4 + L * 4;
   b += len * 4 + (int64_t)kmax * 12;
   return b;

@@ -42,7 +42,7 @@ struct QueryParams {
   float eta;         // absolute slack (distance units) of PAA-based bounds
   int log_cap;       // near-tie log entries per query
   int fin_waves;     // waves used by the FP64 DTW recheck
-  int item_cap;      // leaf chunks per query: at most n / kChunkSeries + n_leaves
+  int item_cap;      // leaf chunks per query (all shards)
   int lds_words;     // floats of dynamic LDS of the process kernel
   int out_stride;    // output row stride (k of the call, or kmax of a batch)
 };
@@ -60,11 +60,8 @@ struct QueryState {
   unsigned long long* log;    // [nq][log_cap] near-tie candidates (d2, position)
   int* log_count;             // [nq]
   float* leaf_lb;             // [nq][n_leaves] leaf bounds
-  int* hist;                  // [nq][kLbBuckets] leaves per bound bucket
-  int* fill;                  // [nq][kLbBuckets] scatter cursors
-  unsigned long long* items;  // [nq][item_cap] leaf chunks in bucket order (lb bits, leaf)
+  unsigned long long* items;  // [nq][item_cap] leaf chunks, shard by shard in bucket order (lb bits, leaf)
   int2* ranges;               // [nq][item_cap] their position ranges
-  int* n_items;               // [nq] chunks in the order
   int* next;                  // [nq][kCounterInts]: kShards counters kCounterStride apart, then a finished-shard mask
   unsigned long long* stats;  // [nq][8] counters (see kStat*)
   int* status;                // [nq] bit 0: near-tie log overflow

@@ -28,6 +28,11 @@ struct IndexDev {
   const int4* tree;          // per node: inner {seg | shift << 8, -, child0, child1},
                              //           leaf  {-1, begin, end, leaf index}
   const int* root_node;      // [2^w]
+  const int* shard_off;      // [kShards + 1] first chunk of each shard (leaf l in shard l % kShards)
+  const uint4* sh_sym;       // leaf symbols, bits and position ranges in shard-major order:
+  const uint4* sh_bits;      //   entry leaf_sh_off[s] + i is leaf s + kShards i
+  const int2* sh_rng;
+  const int* leaf_sh_off;    // [kShards + 1]
 };
 
 // BF16 screen of batched ED queries: a BF16 shadow of the store with the
@@ -57,8 +62,6 @@ void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& 
 void launch_prep(const IndexDev& ix, const float* queries, const QueryParams& qp,
                  const QueryState& qs, hipStream_t st);
 void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   hipStream_t st);
-void launch_stage2(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
                    hipStream_t st);
 void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
                     int blocks_per_query, hipStream_t st);

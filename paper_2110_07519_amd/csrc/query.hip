@@ -7,12 +7,13 @@
 //            the leaf reached by descending the tree along the query's word.
 //   stage1   two kinds of blocks in one launch: some refine the series of
 //            the approximate leaf (the first k-best list, Algorithm 5), the
-//            others compute mindist of every leaf and a histogram of the
-//            bounds over 2048 logarithmic buckets.
-//   stage2   every leaf is placed in bucket order (counting scatter): the
-//            ascending-bound order the paper's priority queues give.
-//   process  waves take leaves in that order through one atomic counter
-//            (the queues' DeleteMin); per leaf: series bounds from the table
+//            others compute mindist of every leaf; leaves are dealt to 64
+//            shards (leaf l to shard l mod 64) and each shard's block
+//            writes its leaves' 256-series chunks in ascending order of
+//            2048 logarithmic bound buckets: the ascending-bound order the
+//            paper's priority queues give, kept per shard.
+//   process  waves take chunks in that order through the shards' atomic
+//            counters (the queues' DeleteMin); per chunk: series bounds from the table
 //            in LDS, [LB_Keogh,] FP32 refinement, the k best kept by a
 //            lock-free atomicMin cascade.  A wave stops at the first leaf
 //            whose bucket starts above the current k-th best (every later
@@ -286,28 +287,44 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
   float* L = U + len;
   float* bp = L + len;
   __shared__ float paa[3][kMaxSeg];
+  __shared__ int s_sym[kMaxSeg];
   __shared__ float s_mu, s_sd;
   __shared__ unsigned long long s_best;
 
   const float* src = queries + (int64_t)row_of(s, q) * len;
   for (int t = tid; t < len; t += blockDim.x) x[t] = src[t];
   for (int j = tid; j <= card; j += blockDim.x) bp[j] = ix.bp[j];
-  for (int j = tid; j < kLbBuckets; j += blockDim.x) {
-    s.hist[(int64_t)q * kLbBuckets + j] = 0;
-    s.fill[(int64_t)q * kLbBuckets + j] = 0;
-  }
   __syncthreads();
   if (tid == 0) {  // same order and rounding as the build's summary pass
+    // (values read 16 at a time so the LDS reads overlap the add chain)
     float sum = 0.0f;
-    for (int t = 0; t < len; ++t) sum = sum + x[t];
+    int t = 0;
+    for (; t + 16 <= len; t += 16) {
+      float v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = x[t + i];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) sum = sum + v[i];
+    }
+    for (; t < len; ++t) sum = sum + x[t];
     const float mu = __fdiv_rn(sum, (float)len);
-    float v = 0.0f;
-    for (int t = 0; t < len; ++t) {
+    float var = 0.0f;
+    for (t = 0; t + 16 <= len; t += 16) {
+      float v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float d = x[t + i] - mu;
+        v[i] = d * d;
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) var = var + v[i];
+    }
+    for (; t < len; ++t) {
       const float d = x[t] - mu;
-      v = v + d * d;
+      var = var + d * d;
     }
     s_mu = mu;
-    s_sd = __fsqrt_rn(__fdiv_rn(v, (float)len));
+    s_sd = __fsqrt_rn(__fdiv_rn(var, (float)len));
   }
   __syncthreads();
   const float mu = s_mu, sd = s_sd;
@@ -354,6 +371,7 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
       paa[2][tid] = paa[0][tid];
     }
     for (int j = 0; j < 3; ++j) s.paa[((int64_t)q * 3 + j) * kMaxSeg + tid] = paa[j][tid];
+    s_sym[tid] = symbol_of(paa[0][tid], bp, card);
   }
   __syncthreads();
   // bound table: T[s][sym] = m * gap(PAA, box of sym)^2 (mindist, Section
@@ -374,7 +392,7 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
   uint8_t word[kMaxSeg];
   uint32_t key = 0;
   for (int sg = 0; sg < w; ++sg) {
-    word[sg] = (uint8_t)symbol_of(paa[0][sg], bp, card);
+    word[sg] = (uint8_t)s_sym[sg];
     key = (key << 1) | (word[sg] >> (cb - 1));
   }
   int node = ix.root_node[key];
@@ -461,40 +479,120 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
   extern __shared__ float sm[];
   const float* zq = s.zq + (int64_t)q * len;
   if ((int)blockIdx.x >= approx_blocks) {
-    // leaf bounds (Algorithm 7's FindDist for every leaf)
+    // leaf bounds (Algorithm 7's FindDist for every leaf).  Block `shard`
+    // takes leaves shard, shard + kShards, ... and writes their chunks into
+    // the shard's fixed item range in ascending bound-bucket order: a
+    // counting sort over the logarithmic buckets, in LDS.
+    const int shard = (int)blockIdx.x - approx_blocks;
     const int w = p.w, cb = p.card_bits, card = 1 << cb;
-    float* bp = sm;
-    float* pa = bp + 257;
-    int* hist = reinterpret_cast<int*>(pa + 2 * kMaxSeg);
-    for (int j = tid; j <= card; j += blockDim.x) bp[j] = ix.bp[j];
-    if (tid < kMaxSeg) {
-      pa[tid] = s.paa[((int64_t)q * 3 + 1) * kMaxSeg + tid];
-      pa[kMaxSeg + tid] = s.paa[((int64_t)q * 3 + 2) * kMaxSeg + tid];
+    // Per segment, a min-tree over the series table: node (b, y) = the
+    // smallest entry among symbols y 2^(cb-b) .. (y+1) 2^(cb-b) - 1, which
+    // is the table value of the box of the b-bit prefix y (the gap to a
+    // union of adjacent boxes is attained at its first or last box).
+    const int tw = 2 * card - 1;
+    float* tree = sm;                                          // [16][2 card - 1]
+    int* cnt = reinterpret_cast<int*>(tree + kMaxSeg * tw);    // [kLbBuckets] chunks, then cursors
+    __shared__ int part[256];
+    const float* T = s.table + (int64_t)q * kMaxSeg * card;
+    for (int i = tid; i < kMaxSeg * card; i += blockDim.x) {
+      const int sg = i >> cb, j = i & (card - 1);
+      tree[sg * tw + card - 1 + j] = T[i];
     }
-    for (int j = tid; j < kLbBuckets; j += blockDim.x) hist[j] = 0;
+    for (int j = tid; j < kLbBuckets; j += blockDim.x) cnt[j] = 0;
     __syncthreads();
-    const float fm = (float)p.m;
-    const int nb = gridDim.x - approx_blocks;
-    float* lbq = s.leaf_lb + (int64_t)q * p.n_leaves;
-    for (int l = (blockIdx.x - approx_blocks) * blockDim.x + tid; l < p.n_leaves; l += nb * blockDim.x) {
-      const uint4 sy = ix.leaf_sym[l], bi = ix.leaf_bits[l];
-      float lb = 0.0f;
-      for (int sg = 0; sg < w; ++sg) {
-        const int b = (int)byte_of(bi, sg), y = (int)byte_of(sy, sg);
-        const int sh = cb - b;
-        const float lo = bp[y << sh], hi = bp[(y + 1) << sh];
-        const float g = fmaxf(lo - pa[sg], 0.0f) + fmaxf(pa[kMaxSeg + sg] - hi, 0.0f);
-        lb += g * g;
+    for (int b = cb - 1; b >= 0; --b) {
+      for (int i = tid; i < (kMaxSeg << b); i += blockDim.x) {
+        const int sg = i >> b, y = i & ((1 << b) - 1);
+        const float* c = tree + sg * tw + (2 << b) - 1 + 2 * y;
+        tree[sg * tw + (1 << b) - 1 + y] = fminf(c[0], c[1]);
       }
-      lb *= fm;
-      lbq[l] = lb;
-      const int nchunk = (int)((ix.leaf_end[l] - ix.leaf_begin[l] + kChunkSeries - 1) / kChunkSeries);
-      atomicAdd(&hist[lb_bucket(lb)], nchunk);
+      __syncthreads();
+    }
+    float* lbq = s.leaf_lb + (int64_t)q * p.n_leaves;
+    const int j0 = ix.leaf_sh_off[shard], nl = ix.leaf_sh_off[shard + 1] - j0;
+    // bound of a leaf: sixteen min-tree lookups, summed pairwise
+    auto leaf_bound = [&](const uint4& sy, const uint4& bi) {
+      float t[kMaxSeg];  // segments past w read level 0 of an all-zero row
+#pragma unroll
+      for (int sg = 0; sg < kMaxSeg; ++sg)
+        t[sg] = tree[sg * tw + (1 << byte_of(bi, sg)) - 1 + (int)byte_of(sy, sg)];
+#pragma unroll
+      for (int h = kMaxSeg / 2; h >= 1; h >>= 1)
+#pragma unroll
+        for (int sg = 0; sg < h; ++sg) t[sg] = t[sg] + t[sg + h];
+      return t[0];
+    };
+    constexpr int kLB = 4;  // leaves per thread whose loads are in flight together
+    const int bs = (int)blockDim.x;
+    for (int jb = tid; jb < nl; jb += kLB * bs) {
+      uint4 sy[kLB], bi[kLB];
+      int2 rg[kLB];
+#pragma unroll
+      for (int u = 0; u < kLB; ++u)
+        if (jb + u * bs < nl) {
+          sy[u] = ix.sh_sym[j0 + jb + u * bs];
+          bi[u] = ix.sh_bits[j0 + jb + u * bs];
+          rg[u] = ix.sh_rng[j0 + jb + u * bs];
+        }
+#pragma unroll
+      for (int u = 0; u < kLB; ++u)
+        if (jb + u * bs < nl) {
+          const float lb = leaf_bound(sy[u], bi[u]);
+          lbq[shard + (jb + u * bs) * kShards] = lb;
+          atomicAdd(&cnt[lb_bucket(lb)], (rg[u].y - rg[u].x + kChunkSeries - 1) / kChunkSeries);
+        }
     }
     __syncthreads();
-    int* gh = s.hist + (int64_t)q * kLbBuckets;
-    for (int j = tid; j < kLbBuckets; j += blockDim.x)
-      if (hist[j]) atomicAdd(&gh[j], hist[j]);
+    // exclusive scan of the bucket counts (8 per thread)
+    constexpr int per = kLbBuckets / 256;
+    int loc[per], sum = 0;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+      loc[j] = cnt[tid * per + j];
+      sum += loc[j];
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const int v = tid >= o ? part[tid - o] : 0;
+      __syncthreads();
+      part[tid] += v;
+      __syncthreads();
+    }
+    int run = ix.shard_off[shard] + part[tid] - sum;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+      cnt[tid * per + j] = run;
+      run += loc[j];
+    }
+    __syncthreads();
+    unsigned long long* items = s.items + (int64_t)q * p.item_cap;
+    int2* ranges = s.ranges + (int64_t)q * p.item_cap;
+    for (int jb = tid; jb < nl; jb += kLB * bs) {
+      uint4 sy[kLB], bi[kLB];
+      int2 rg[kLB];
+#pragma unroll
+      for (int u = 0; u < kLB; ++u)
+        if (jb + u * bs < nl) {
+          sy[u] = ix.sh_sym[j0 + jb + u * bs];
+          bi[u] = ix.sh_bits[j0 + jb + u * bs];
+          rg[u] = ix.sh_rng[j0 + jb + u * bs];
+        }
+#pragma unroll
+      for (int u = 0; u < kLB; ++u) {
+        if (jb + u * bs >= nl) continue;
+        const float lb = leaf_bound(sy[u], bi[u]);  // the same value as in the count pass
+        const int nc = (rg[u].y - rg[u].x + kChunkSeries - 1) / kChunkSeries;
+        const int at = atomicAdd(&cnt[lb_bucket(lb)], nc);
+        const unsigned long long it = ((unsigned long long)__float_as_uint(lb) << 32) |
+                                      (unsigned)(shard + (jb + u * bs) * kShards);
+        for (int c = 0; c < nc; ++c) {
+          const int cb0 = rg[u].x + c * kChunkSeries;
+          items[at + c] = it;
+          ranges[at + c] = make_int2(cb0, cb0 + kChunkSeries < rg[u].y ? cb0 + kChunkSeries : rg[u].y);
+        }
+      }
+    }
     return;
   }
   // approximate search (Algorithm 5, approxSearch): real distances of the
@@ -570,80 +668,6 @@ __device__ __forceinline__ void log_approx(const QueryParams& p, const QueryStat
 }
 
 // ---------------------------------------------------------------------------
-// stage2: counting scatter of the leaves into bucket order; block 0 also
-// logs the approximate-range distances inside the near-tie window of the
-// first k-th best.
-
-__global__ __launch_bounds__(1024) void k_stage2(IndexDev ix, QueryParams p, QueryState s) {
-  const int q = blockIdx.y;
-  const int tid = threadIdx.x;
-  __shared__ int base[kLbBuckets];  // bucket starts, then this block's slice starts
-  __shared__ int cnt[kLbBuckets];   // this block's leaves per bucket, then cursors
-  __shared__ int part[1024];
-  const int* gh = s.hist + (int64_t)q * kLbBuckets;
-  constexpr int per = kLbBuckets / 1024;
-  int loc[per];
-  int sum = 0;
-#pragma unroll
-  for (int j = 0; j < per; ++j) {
-    loc[j] = gh[tid * per + j];
-    sum += loc[j];
-    cnt[tid * per + j] = 0;
-  }
-  part[tid] = sum;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = tid >= o ? part[tid - o] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  int run = part[tid] - sum;
-#pragma unroll
-  for (int j = 0; j < per; ++j) {
-    base[tid * per + j] = run;
-    run += loc[j];
-  }
-  if (blockIdx.x == 0 && tid == 1023) s.n_items[q] = part[1023];
-  // this block's contiguous slice of leaves
-  const int L = p.n_leaves;
-  const int chunk = (L + gridDim.x - 1) / gridDim.x;
-  const int l0 = blockIdx.x * chunk;
-  const int l1 = l0 + chunk < L ? l0 + chunk : L;
-  const float* lbq = s.leaf_lb + (int64_t)q * L;
-  __syncthreads();
-  for (int l = l0 + tid; l < l1; l += blockDim.x) {
-    const int nc = (int)((ix.leaf_end[l] - ix.leaf_begin[l] + kChunkSeries - 1) / kChunkSeries);
-    atomicAdd(&cnt[lb_bucket(lbq[l])], nc);
-  }
-  __syncthreads();
-  // one global reservation per bucket present in the slice
-  int* fill = s.fill + (int64_t)q * kLbBuckets;
-  for (int b = tid; b < kLbBuckets; b += blockDim.x) {
-    const int c = cnt[b];
-    if (c) base[b] += atomicAdd(&fill[b], c);
-    cnt[b] = 0;
-  }
-  __syncthreads();
-  unsigned long long* items = s.items + (int64_t)q * p.item_cap;
-  int2* ranges = s.ranges + (int64_t)q * p.item_cap;
-  for (int l = l0 + tid; l < l1; l += blockDim.x) {
-    const float lb = lbq[l];
-    const int b = lb_bucket(lb);
-    const int lbeg = (int)ix.leaf_begin[l], lend = (int)ix.leaf_end[l];
-    const int nc = (lend - lbeg + kChunkSeries - 1) / kChunkSeries;
-    const int at = base[b] + atomicAdd(&cnt[b], nc);
-    const unsigned long long it = ((unsigned long long)__float_as_uint(lb) << 32) | (unsigned)l;
-    for (int c = 0; c < nc; ++c) {
-      const int cb = lbeg + c * kChunkSeries;
-      items[at + c] = it;
-      ranges[at + c] = make_int2(cb, cb + kChunkSeries < lend ? cb + kChunkSeries : lend);
-    }
-  }
-  if (blockIdx.x == 0) log_approx(p, s, q, tid, blockDim.x);
-}
-
-// ---------------------------------------------------------------------------
 // process: persistent blocks over the ordered leaf chunks.
 // R = -1: ED; R >= 0: DTW with a register band of radius R; R = -2: DTW by
 // wave anti-diagonals (radius beyond the register band).
@@ -693,6 +717,9 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
   for (int visit = 0; visit < p.nq; ++visit) {
   const int q = (int)((blockIdx.x + (unsigned)visit) % (unsigned)p.nq);
   const int k = k_of(p, s, q);
+  // the near-tie log entries of the approximate search, once per query
+  // (block q's first visit; it runs even if the query is already done)
+  if (visit == 0 && (int)blockIdx.x == q) log_approx(p, s, q, tid, blockDim.x);
   {
     int* cq = s.next + (int64_t)q * kCounterInts;
     if (tid == 0)
@@ -729,7 +756,7 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
   const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
   const unsigned long long* items = s.items + (int64_t)q * p.item_cap;
   const int2* ranges = s.ranges + (int64_t)q * p.item_cap;
-  const int n_items = s.n_items[q];
+
   int* counters = s.next + (int64_t)q * kCounterInts;
   unsigned long long* finished =
       reinterpret_cast<unsigned long long*>(counters + kShards * kCounterStride);
@@ -794,11 +821,11 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
     }
     unsigned long long ckey = s_ckey;
     const float tadj = lb_threshold(key_dist(ckey), p);
-    // one chunk per wave
-    const int i = (s_batch * kW + wv) * kShards + shard;
+    // one chunk per wave, consecutive in the shard's bound order
+    const int i = ix.shard_off[shard] + s_batch * kW + wv;
     bool take = false;
     int2 rg = make_int2(0, 0);
-    if (i < n_items) {
+    if (i < ix.shard_off[shard + 1]) {
       const unsigned long long item = items[i];
       rg = ranges[i];
       const float lb = key_dist(item);
@@ -1031,15 +1058,34 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
     rechecked += (unsigned long long)(cnt - topn);
     // exact distances of the new entries, FP64, index order, unfused
     if (p.distance == 0) {
-      for (int c = topn + tid; c < cnt; c += blockDim.x) {
-        const float* x = ix.Z + (int64_t)pos_l[c] * len;
-        double acc = 0.0;
-        for (int t = 0; t < len; ++t) {
-          const double d = (double)ql[t] - (double)x[t];
-          acc = __dadd_rn(acc, __dmul_rn(d, d));
+      // one wave per candidate: lanes load and square 64 points at a time,
+      // the sum runs in index order, unfused, through the lanes in turn
+      const int nw = blockDim.x / kWave;
+      for (int c0 = topn; c0 < cnt; c0 += nw) {
+        const int c = c0 + wv;
+        if (c < cnt) {
+          const float* x = ix.Z + (int64_t)pos_l[c] * len;
+          double acc = 0.0;
+          for (int t0 = 0; t0 < len; t0 += kWave) {
+            double sq = 0.0;
+            if (t0 + lane < len) {
+              const double d = (double)ql[t0 + lane] - (double)x[t0 + lane];
+              sq = __dmul_rn(d, d);
+            }
+            const long long bits = __double_as_longlong(sq);
+            const int lo = (int)bits, hi = (int)(bits >> 32);
+            const int nn = len - t0 < kWave ? len - t0 : kWave;
+            for (int i = 0; i < nn; ++i) {
+              const long long b2 = ((long long)__builtin_amdgcn_readlane(hi, i) << 32) |
+                                   (unsigned)__builtin_amdgcn_readlane(lo, i);
+              acc = __dadd_rn(acc, __longlong_as_double(b2));
+            }
+          }
+          if (lane == 0) {
+            E[c] = acc;
+            id_l[c] = ix.perm[pos_l[c]];
+          }
         }
-        E[c] = acc;
-        id_l[c] = ix.perm[pos_l[c]];
       }
     } else {
       for (int c0 = topn; c0 < cnt; c0 += p.fin_waves) {
@@ -1471,7 +1517,7 @@ size_t finalize_lds_bytes(const QueryParams& p) {
 }
 
 static size_t stage1_lds_bytes(const QueryParams& p, int R) {
-  const size_t lb_words = 257 + 2 * kMaxSeg + kLbBuckets;
+  const size_t lb_words = (size_t)kMaxSeg * (2 * ((size_t)1 << p.card_bits) - 1) + kLbBuckets;
   const size_t ap_words = R == -1 ? (size_t)p.len : (R == -2 ? 17 * (size_t)p.len : (size_t)p.len + 2 * R);
   return (lb_words > ap_words ? lb_words : ap_words) * sizeof(float);
 }
@@ -1487,9 +1533,7 @@ void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& 
   bool mask;
   const int R = band_of(qp, &mask);
   const int approx_blocks = R == -1 ? 32 : (R == -2 ? 64 : (kApproxCap + 255) / 256);
-  int lb_blocks = (qp.n_leaves + 1023) / 1024;
-  lb_blocks = lb_blocks > 128 ? 128 : (lb_blocks < 1 ? 1 : lb_blocks);
-  const dim3 g(approx_blocks + lb_blocks, qp.nq);
+  const dim3 g(approx_blocks + kShards, qp.nq);  // one bound block per shard
   const size_t lds = stage1_lds_bytes(qp, R);
   if (R == -1) {
     hipLaunchKernelGGL((k_stage1<-1, false>), g, dim3(256), lds, st, ix, qp, qs, approx_blocks);
@@ -1509,13 +1553,6 @@ void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& 
   }
   MESSI_BANDS(MESSI_S1_CASE)
 #undef MESSI_S1_CASE
-}
-
-void launch_stage2(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   hipStream_t st) {
-  int blocks = (qp.n_leaves + 4095) / 4096;
-  blocks = blocks > 64 ? 64 : (blocks < 1 ? 1 : blocks);
-  hipLaunchKernelGGL(k_stage2, dim3(blocks, qp.nq), dim3(1024), 0, st, ix, qp, qs);
 }
 
 void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
