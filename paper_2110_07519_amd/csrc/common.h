@@ -11,7 +11,7 @@ constexpr int kMaxLen = 4096;     // longest series accepted
 constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kLbBuckets = 2048;  // logarithmic bound buckets that order the leaves
 constexpr int kShards = 64;       // work counters per query (leaves dealt round robin)
-constexpr int kChunkSeries = 256; // series per work item of the process phase
+constexpr int kChunkSeries = 512; // series per work item of the process phase
 constexpr int kGrab = 8;          // work items taken per atomic grab
 constexpr int kCounterStride = 64;  // ints between two shard counters (own 256-byte line)
 constexpr int kCounterInts = kShards * kCounterStride + kCounterStride;

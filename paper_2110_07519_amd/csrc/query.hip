@@ -9,7 +9,7 @@
 //            the approximate leaf (the first k-best list, Algorithm 5), the
 //            others compute mindist of every leaf; leaves are dealt to 64
 //            shards (leaf l to shard l mod 64) and each shard's block
-//            writes its leaves' 256-series chunks in ascending order of
+//            writes its leaves' 512-series chunks in ascending order of
 //            2048 logarithmic bound buckets: the ascending-bound order the
 //            paper's priority queues give, kept per shard.
 //   process  waves take chunks in that order through the shards' atomic
@@ -682,15 +682,15 @@ constexpr int kUnroll = kChunkSeries / kWave;  // words per lane per chunk
 
 template <int R>
 struct ProcShape {
-  static constexpr int waves = (R == -2) ? 4 : kGrab;  // one chunk per wave
+  static constexpr int waves = (R == -1) ? kGrab : 4;  // one chunk per wave (DTW: LDS for its lists)
   static constexpr int threads = waves * kWave;
   static constexpr int surv_cap = waves * kChunkSeries;
   static constexpr int pend_cap = (R >= 0) ? surv_cap + threads : 0;
 };
 
 template <int R, bool MASK>
-__global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, QueryParams p,
-                                                                   QueryState s) {
+__device__ __forceinline__ void process_body(const IndexDev& ix, const QueryParams& p,
+                                             const QueryState& s) {
   using Sh = ProcShape<R>;
   constexpr int kW = Sh::waves;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
@@ -1006,6 +1006,17 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
   }
   __syncthreads();  // LDS is reloaded for the next query
   }
+}
+
+template <int R, bool MASK>
+__global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, QueryParams p,
+                                                                   QueryState s) {
+  process_body<R, MASK>(ix, p, s);
+}
+
+__global__ __launch_bounds__(ProcShape<-1>::threads) void k_process_ed(IndexDev ix, QueryParams p,
+                                                                       QueryState s) {
+  process_body<-1, false>(ix, p, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1563,7 +1574,7 @@ void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState&
   const dim3 b(process_threads(R));
   const size_t lds = process_lds_bytes(qp);
   if (R == -1) {
-    hipLaunchKernelGGL((k_process<-1, false>), g, b, lds, st, ix, qp, qs);
+    hipLaunchKernelGGL(k_process_ed, g, b, lds, st, ix, qp, qs);
     return;
   }
   if (R == -2) {
@@ -1638,7 +1649,7 @@ int process_blocks_per_cu(const QueryParams& qp) {
   int nb = 0;
   hipError_t e = hipSuccess;
   if (R == -1) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<-1, false>, th, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process_ed, th, lds);
   } else if (R == -2) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<-2, false>, th, lds);
   }
