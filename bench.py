@@ -32,8 +32,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # timed queries, from two rocprofv3 --pmc runs of this script (FETCH_SIZE x
 # 2.0 + WRITE_SIZE x 1.0 KiB; factors from a 1 GiB device copy and fill).
 # Valid only for the query kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256": "e5af832daec95bfab0d5a223ac8e392d3ac682631bbb3c938cd33086b10470df",
-                    "bytes_per_launch": 318928101}
+MEASURED_TRAFFIC = {"sources_sha256": "7bd4911f98d2849c94e08a05eba2c46efb5d4aa07f01f626d3fcc4ba7b27a7f7",
+                    "bytes_per_launch": 300990299}
 QUERY_SOURCES = ["paper_2110_07519_amd/csrc/query.hip", "paper_2110_07519_amd/csrc/query.h",
                  "paper_2110_07519_amd/csrc/common.h"]
 PHASES = ["prep", "stage1", "stage2", "process", "finalize"]
