@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA, published
 
 # HBM bytes per launch of the leaf-processing kernel over this benchmark's
 # timed queries, from two rocprofv3 --pmc runs of this script (FETCH_SIZE x
@@ -131,6 +132,15 @@ def run_batched(pm, idx, n, length, nq, reps):
                      "screened_pairs_per_query": st["screened"] / nq}
         log(f"batched {name}: {nq / dt:.0f} q/s ({dt * 1e3:.1f} ms per {nq}), phases "
             f"{ {p: round(st[f'us_{p}']) for p in PHASES} }, refined/q {st['refined'] / nq:.0f}")
+    sc = out["screen"]
+    flops = sc["screened_pairs_per_query"] * nq * 2.0 * length
+    us = sc["phases_us"]["process"]
+    sc["mfma_roofline"] = {"bound": "mfma", "achieved": flops / (us * 1e-6) / 1e12,
+                           "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": flops / (us * 1e-6) / 1e12 / BF16_PEAK_TFLOPS,
+                           "flops_per_launch": flops,
+                           "note": "algorithmic q.x flops (2 len per screened pair) over the screen "
+                                   "phase (leaf lists + screen kernel)"}
     out["identical_answers"] = bool(np.array_equal(answers["plain"][0], answers["screen"][0]) and
                                     np.array_equal(answers["plain"][1], answers["screen"][1]))
     out["screen_speedup"] = out["screen"]["queries_per_s"] / out["plain"]["queries_per_s"]

@@ -538,6 +538,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   p.card_bits = ix->card_bits;
   p.k = kmax;
   p.out_stride = kmax;
+  p.order_leaves = screen ? 0 : 1;
   p.distance = distance;
   p.window = distance == MESSI_DTW ? std::min(window, len - 1) : 0;
   p.n_leaves = ix->n_leaves;

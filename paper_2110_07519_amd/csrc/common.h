@@ -45,6 +45,7 @@ struct QueryParams {
   int item_cap;      // leaf chunks per query (all shards)
   int lds_words;     // floats of dynamic LDS of the process kernel
   int out_stride;    // output row stride (k of the call, or kmax of a batch)
+  int order_leaves;  // 1: stage1 also writes the chunk order of the process kernel
 };
 
 // Per-query device state, one entry per query (all arrays sized by nq).

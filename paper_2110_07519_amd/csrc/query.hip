@@ -509,7 +509,10 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
       __syncthreads();
     }
     float* lbq = s.leaf_lb + (int64_t)q * p.n_leaves;
-    const int j0 = ix.leaf_sh_off[shard], nl = ix.leaf_sh_off[shard + 1] - j0;
+    // with the chunk order, one shard per block; without it (the screen
+    // needs the bounds only) a few blocks per query take every shard
+    const int nlb = (int)gridDim.x - approx_blocks;
+    int j0 = 0, nl = 0;
     // bound of a leaf: sixteen min-tree lookups, summed pairwise
     auto leaf_bound = [&](const uint4& sy, const uint4& bi) {
       float t[kMaxSeg];  // segments past w read level 0 of an all-zero row
@@ -524,25 +527,31 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     };
     constexpr int kLB = 4;  // leaves per thread whose loads are in flight together
     const int bs = (int)blockDim.x;
-    for (int jb = tid; jb < nl; jb += kLB * bs) {
-      uint4 sy[kLB], bi[kLB];
-      int2 rg[kLB];
+    for (int sh = shard; sh < kShards; sh += nlb) {
+      j0 = ix.leaf_sh_off[sh];
+      nl = ix.leaf_sh_off[sh + 1] - j0;
+      for (int jb = tid; jb < nl; jb += kLB * bs) {
+        uint4 sy[kLB], bi[kLB];
+        int2 rg[kLB];
 #pragma unroll
-      for (int u = 0; u < kLB; ++u)
-        if (jb + u * bs < nl) {
-          sy[u] = ix.sh_sym[j0 + jb + u * bs];
-          bi[u] = ix.sh_bits[j0 + jb + u * bs];
-          rg[u] = ix.sh_rng[j0 + jb + u * bs];
-        }
+        for (int u = 0; u < kLB; ++u)
+          if (jb + u * bs < nl) {
+            sy[u] = ix.sh_sym[j0 + jb + u * bs];
+            bi[u] = ix.sh_bits[j0 + jb + u * bs];
+            rg[u] = ix.sh_rng[j0 + jb + u * bs];
+          }
 #pragma unroll
-      for (int u = 0; u < kLB; ++u)
-        if (jb + u * bs < nl) {
-          const float lb = leaf_bound(sy[u], bi[u]);
-          lbq[shard + (jb + u * bs) * kShards] = lb;
-          atomicAdd(&cnt[lb_bucket(lb)], (rg[u].y - rg[u].x + kChunkSeries - 1) / kChunkSeries);
-        }
+        for (int u = 0; u < kLB; ++u)
+          if (jb + u * bs < nl) {
+            const float lb = leaf_bound(sy[u], bi[u]);
+            lbq[sh + (jb + u * bs) * kShards] = lb;
+            if (p.order_leaves)
+              atomicAdd(&cnt[lb_bucket(lb)], (rg[u].y - rg[u].x + kChunkSeries - 1) / kChunkSeries);
+          }
+      }
     }
     __syncthreads();
+    if (!p.order_leaves) return;  // the screen reads the bounds only
     // exclusive scan of the bucket counts (8 per thread)
     constexpr int per = kLbBuckets / 256;
     int loc[per], sum = 0;
@@ -1544,7 +1553,8 @@ void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& 
   bool mask;
   const int R = band_of(qp, &mask);
   const int approx_blocks = R == -1 ? 32 : (R == -2 ? 64 : (kApproxCap + 255) / 256);
-  const dim3 g(approx_blocks + kShards, qp.nq);  // one bound block per shard
+  // one bound block per shard when the chunk order is written, else eight
+  const dim3 g(approx_blocks + (qp.order_leaves ? kShards : 8), qp.nq);
   const size_t lds = stage1_lds_bytes(qp, R);
   if (R == -1) {
     hipLaunchKernelGGL((k_stage1<-1, false>), g, dim3(256), lds, st, ix, qp, qs, approx_blocks);
