@@ -147,6 +147,32 @@ def run_batched(pm, idx, n, length, nq, reps):
     return out
 
 
+def run_classification(pm, idx, labels, n, length, nq):
+    """k-NN classification (Section 5.4) of nq noisy dataset copies, ED,
+    BF16 screen, k in {1, 10, 50}: queries/s per k, and agreement of the
+    vote with the trend class of each query's source series."""
+    import torch
+    import synth
+
+    qs, src, _ = synth.noisy_queries(nq, n, length, j0=400_000)
+    qt = torch.from_numpy(qs).cuda()
+    truth = labels[torch.from_numpy(src).cuda()].cpu().numpy()
+    out = {"workload": f"{nq} noisy dataset copies per call, ED, BF16 screen; classes = trend "
+                       "shape of the generated series (4 classes)", "k": []}
+    for k in (1, 10, 50):
+        pm.messi_classify(idx, labels, 4, qt[:32], k, flags=pm.MESSI_SCREEN_BF16)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cls, _, _ = pm.messi_classify(idx, labels, 4, qt, k, flags=pm.MESSI_SCREEN_BF16)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        acc = float((cls.cpu().numpy() == truth).mean())
+        out["k"].append({"k": k, "queries_per_s": nq / dt, "ms_per_call": dt * 1e3,
+                         "agreement_with_source_class": acc})
+        log(f"classification k={k}: {nq / dt:.0f} q/s, agreement {acc:.3f}")
+    return out
+
+
 def serving_mix(count, n, length, j0):
     """Request mix: ED / DTW 50/50, DTW window 5/10/20% of the length, k 1 or
     10, noisy dataset copies (noise 0.01/0.1/1.0 round robin); seed 4."""
@@ -280,6 +306,8 @@ def main():
     ap.add_argument("--batch", type=int, default=1024,
                     help="queries of the batched run (noisy copies, k alternating 1 and 10)")
     ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--classify", type=int, default=1024,
+                    help="queries per k-NN classification call (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of each Poisson arrival stream of the serving run (0: skip)")
     ap.add_argument("--serve-capacity-requests", type=int, default=40)
@@ -319,6 +347,10 @@ def main():
         log(f"building the DTW index over the first {dtw_n} series")
         didx = pm.messi_build(data[:dtw_n], 16, 256, args.leaf)
         torch.cuda.synchronize()
+    labels = None
+    if args.classify > 0:
+        labels = torch.empty(n, dtype=torch.int32, device="cuda")
+        synth.trend_labels_device(data, labels)
     log("building the index")
     t0 = time.perf_counter()
     idx = pm.messi_build(data, 16, 256, args.leaf)
@@ -371,6 +403,11 @@ def main():
     if args.batch > 0:
         batched = run_batched(pm, idx, n, length, args.batch, args.batch_reps)
 
+    classification = None
+    if labels is not None:
+        classification = run_classification(pm, idx, labels, n, length, args.classify)
+        del labels
+
     serving = None
     if args.serve_seconds > 0:
         serving = run_serving(pm, idx, n, length, args.serve_seconds, args.serve_capacity_requests)
@@ -415,6 +452,7 @@ def main():
                      "traffic": traffic, "bytes_per_launch": dom_bytes},
         "dtw": dtw,
         "batched": batched,
+        "classification": classification,
         "serving": serving,
         "cpu_baseline": cpu,
     }

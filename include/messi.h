@@ -136,6 +136,19 @@ int messi_query_batch(messi_index* index, const float* queries, int32_t nq, cons
                       const int32_t* distance, const int32_t* window, int32_t kmax, int32_t flags,
                       int64_t* out_ids, float* out_dists, messi_stats* stats);
 
+/* k-NN classifier (Section 5.4): each query takes the class held by most of
+ * its k nearest neighbours (as messi_query_batch computes them, flags
+ * alike); a tie goes to the tied class whose first member is nearest in
+ * the (distance, id) order.
+ *   labels     device pointer, int32 [n], the class of each series by id;
+ *              values outside [0, n_classes) are not counted.
+ *   n_classes  1..4096.
+ *   out_class  device pointer, int32 [nq]: the class, or -1 if no series.
+ *   out_ids, out_dists   device pointers [nq][k]: the neighbours voted on. */
+int messi_classify(messi_index* index, const int32_t* labels, int32_t n_classes,
+                   const float* queries, int32_t nq, int32_t k, int32_t distance, int32_t window,
+                   int32_t flags, int32_t* out_class, int64_t* out_ids, float* out_dists);
+
 /* Make the BF16 copy of the store and its row norms used by
  * MESSI_SCREEN_BF16 now rather than on the first screened batch.  The
  * copy lives until messi_free. */

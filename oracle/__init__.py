@@ -97,6 +97,7 @@ def lib():
         L.oracle_mindist2_dtw.restype = f64
         L.oracle_knn_scan.argtypes = [P, i64, i64, i32, P, i32, i32, i32, i32, P, P]
         L.oracle_knn_scan_lbk.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P]
+        L.oracle_knn_vote.argtypes = [P, i32, i32, P, i32, P]
         L.oracle_index_search.argtypes = [P, i64, i32, i32, i32, P, P, P, i64, P, i32, i32, i32,
                                           P, P, P]
         _lib = L
@@ -243,6 +244,15 @@ def knn(raw, raw_queries, k, distance=ED, r=0):
     """Brute-force k-NN by definition: (ids int64[nq,k], d2 float64[nq,k])."""
     st = KnnState(raw_queries, k, distance, r).scan(raw, 0)
     return st.ids, st.d2
+
+
+def knn_vote(ids, labels, n_classes):
+    """Majority class of each k-NN list (ties: the class met first)."""
+    ids = np.ascontiguousarray(ids, dtype=np.int64)
+    labels = np.ascontiguousarray(labels, dtype=np.int32)
+    out = np.empty(ids.shape[0], dtype=np.int32)
+    lib().oracle_knn_vote(_p(ids), ids.shape[0], ids.shape[1], _p(labels), int(n_classes), _p(out))
+    return out
 
 
 def index_search(raw, wds, perm, leaves, raw_query, k, distance=ED, r=0, card_bits=8):

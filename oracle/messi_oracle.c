@@ -592,3 +592,36 @@ void oracle_index_search(const float* raw, int64_t n, int32_t len, int32_t w, in
   free(z);
   free(q);
 }
+
+/* k-NN classifier (Section 5.4): each query takes the class held by most of
+ * its k nearest neighbours; entries with id -1 (fewer than k series) and
+ * labels outside [0, n_classes) are skipped; a tie goes to the tied class whose first member comes earliest
+ * in the (distance, id) order; no neighbour at all gives -1. */
+void oracle_knn_vote(const int64_t* ids, int32_t nq, int32_t k, const int32_t* labels,
+                     int32_t n_classes, int32_t* out) {
+  int32_t* count = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_classes);
+  int32_t* first = (int32_t*)malloc(sizeof(int32_t) * (size_t)n_classes);
+  for (int32_t q = 0; q < nq; ++q) {
+    for (int32_t c = 0; c < n_classes; ++c) {
+      count[c] = 0;
+      first[c] = k;
+    }
+    for (int32_t j = 0; j < k; ++j) {
+      const int64_t id = ids[(int64_t)q * k + j];
+      if (id < 0) continue;
+      const int32_t c = labels[id];
+      if (c < 0 || c >= n_classes) continue;  /* not a class: not counted */
+      count[c] = count[c] + 1;
+      if (first[c] == k) first[c] = j;
+    }
+    int32_t best = -1;
+    for (int32_t c = 0; c < n_classes; ++c) {
+      if (count[c] == 0) continue;
+      if (best < 0 || count[c] > count[best] || (count[c] == count[best] && first[c] < first[best]))
+        best = c;
+    }
+    out[q] = best;
+  }
+  free(first);
+  free(count);
+}

@@ -109,6 +109,12 @@ void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int
                          const float* raw_queries, int32_t nq, int32_t k, int32_t r,
                          int64_t* ids, double* d2);
 
+/* k-NN classifier vote (Section 5.4) over k-NN lists ids [nq][k] (-1 =
+ * none): the majority class; a tie goes to the tied class whose first
+ * member is nearest; -1 if a list is empty. */
+void oracle_knn_vote(const int64_t* ids, int32_t nq, int32_t k, const int32_t* labels,
+                     int32_t n_classes, int32_t* out);
+
 /* Serial index search with the method's semantics (Algorithms 5-10 with
  * one priority order): approximate search for the first k-best list, leaf
  * lower bounds, leaves in ascending bound until the bound passes the k-th

@@ -6,7 +6,8 @@ include/messi.h.  Torch is used for device memory and streams.  If the
 library is not built, importing works but every call raises.
 
 Names follow the C ABI: messi_build, messi_query, messi_query_stats,
-messi_query_batch, messi_prepare_screen, messi_set_stream, messi_free, messi_breakpoints, messi_get_words,
+messi_query_batch, messi_prepare_screen, messi_classify, messi_set_stream,
+messi_free, messi_breakpoints, messi_get_words,
 messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
 """
 from __future__ import annotations
@@ -33,7 +34,7 @@ EXPORTS = [
     "messi_get_words", "messi_get_perm", "messi_get_leaves", "messi_breakpoints", "messi_free",
     "messi_last_error", "messi_query_batch", "messi_prepare_screen",
     "messi_server_start", "messi_server_submit", "messi_server_poll", "messi_server_get_stats",
-    "messi_server_stop",
+    "messi_server_stop", "messi_classify",
 ]
 
 
@@ -94,6 +95,7 @@ def lib():
         L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
         L.messi_query_batch.argtypes = [P, P, i32, P, P, P, i32, i32, P, P, P]
         L.messi_prepare_screen.argtypes = [P]
+        L.messi_classify.argtypes = [P, P, i32, P, i32, i32, i32, i32, i32, P, P, P]
         L.messi_server_start.argtypes = [P, P, P]
         L.messi_server_submit.argtypes = [P, P, i32, i32, i32, P]
         L.messi_server_poll.argtypes = [P, i32, i32, P, P, P, P, P, P]
@@ -110,7 +112,8 @@ def lib():
         L.messi_free.restype = None
         L.messi_last_error.restype = ctypes.c_char_p
         for name in ["messi_build", "messi_query", "messi_query_stats", "messi_query_batch",
-                     "messi_prepare_screen", "messi_server_start", "messi_server_submit",
+                     "messi_prepare_screen", "messi_classify", "messi_server_start",
+                     "messi_server_submit",
                      "messi_server_poll", "messi_server_get_stats", "messi_set_stream",
                      "messi_index_info", "messi_get_words", "messi_get_perm", "messi_get_leaves",
                      "messi_breakpoints"]:
@@ -203,6 +206,23 @@ def messi_query_batch(index, queries, k, distance, window, kmax=None, flags=0, o
     if stats:
         return out_ids, out_dists, st.as_dict()
     return out_ids, out_dists
+
+
+def messi_classify(index, labels, n_classes, queries, k=1, distance=MESSI_ED, window=0, flags=0):
+    """k-NN classification of float32 CUDA queries [nq, len] with int32 CUDA
+    labels [n]: (classes int32 [nq], ids int64 [nq, k], dists float32 [nq, k])."""
+    import torch
+
+    assert queries.dtype == torch.float32 and queries.dim() == 2 and labels.dtype == torch.int32
+    nq = queries.shape[0]
+    dev = queries.device
+    cls = torch.empty(nq, dtype=torch.int32, device=dev)
+    ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    d = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    _check(lib().messi_classify(index.handle, _dev_ptr(labels), int(n_classes), _dev_ptr(queries), nq,
+                                int(k), int(distance), int(window), int(flags), _dev_ptr(cls),
+                                _dev_ptr(ids), _dev_ptr(d)))
+    return cls, ids, d
 
 
 def messi_prepare_screen(index) -> None:

@@ -1050,6 +1050,40 @@ int messi_query_batch(messi_index* index, const float* queries, int32_t nq, cons
                    out_dists, stats);
 }
 
+int messi_classify(messi_index* index, const int32_t* labels, int32_t n_classes,
+                   const float* queries, int32_t nq, int32_t k, int32_t distance, int32_t window,
+                   int32_t flags, int32_t* out_class, int64_t* out_ids, float* out_dists) {
+  g_err.clear();
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
+  if (nq == 0) return MESSI_OK;
+  if (n_classes < 1 || n_classes > 4096) return fail(MESSI_EINVAL, "n_classes must be in [1, 4096]");
+  if (k < 1 || k > 1024) return fail(MESSI_EINVAL, "k must be in [1, 1024]");
+  if (distance != MESSI_ED && distance != MESSI_DTW) return fail(MESSI_EINVAL, "unknown distance");
+  if (window < 0) return fail(MESSI_EINVAL, "window must be >= 0");
+  if (flags & ~MESSI_SCREEN_BF16) return fail(MESSI_EINVAL, "unknown flags");
+  if (!is_device_ptr(labels) || !is_device_ptr(queries) || !is_device_ptr(out_class) ||
+      !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
+    return fail(MESSI_EINVAL, "labels, queries and outputs must be device pointers");
+  BusyGuard guard(index->busy);
+  if (!guard.ok) return fail(MESSI_EBUSY, "index is in use by another call");
+  try {
+    if ((flags & MESSI_SCREEN_BF16) && screen_supported(index->len)) ensure_screen(index);
+    const std::vector<int32_t> ks(nq, k), ds(nq, distance), ws(nq, window);
+    const int rc = run_batch(index, index->ctx, queries, nq, ks.data(), ds.data(), ws.data(), k,
+                             flags, out_ids, out_dists, nullptr);
+    if (rc != MESSI_OK) return rc;
+    launch_vote(out_ids, k, nq, k, labels, n_classes, out_class, index->ctx.stream);
+    launch_check();
+    HIP_OR_THROW(hipStreamSynchronize(index->ctx.stream));
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  return MESSI_OK;
+}
+
 int messi_set_stream(messi_index* index, void* hip_stream) {
   if (!index) return fail(MESSI_EINVAL, "index is NULL");
   index->ctx.stream = (hipStream_t)hip_stream;

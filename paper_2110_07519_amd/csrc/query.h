@@ -59,6 +59,8 @@ void launch_bf16_rows(const float* src, int64_t rows, int len, uint16_t* dst, fl
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
                    const ScreenDev& sc, int blocks, hipStream_t st);
 
+void launch_vote(const int64_t* ids, int64_t stride, int nq, int k, const int* labels, int n_classes,
+                 int* out, hipStream_t st);
 void launch_prep(const IndexDev& ix, const float* queries, const QueryParams& qp,
                  const QueryState& qs, hipStream_t st);
 void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,

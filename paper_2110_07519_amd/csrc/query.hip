@@ -1476,6 +1476,58 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
 }
 
 // ---------------------------------------------------------------------------
+// k-NN classifier vote (Section 5.4): one block per query; the class held
+// by most of its k neighbours, ties to the class met first in the (distance,
+// id) order.  The key (count << 32 | (2047 - first rank) << 12 | class) is
+// maximised over classes; labels outside [0, n_classes) are not counted.
+
+__global__ __launch_bounds__(256) void k_vote(const int64_t* __restrict__ ids, int64_t stride, int k,
+                                              const int* __restrict__ labels, int n_classes,
+                                              int* __restrict__ out) {
+  extern __shared__ int vsm[];
+  int* cnt = vsm;                 // [n_classes]
+  int* first = vsm + n_classes;   // [n_classes]
+  __shared__ unsigned long long s_best;
+  const int q = blockIdx.x;
+  for (int c = threadIdx.x; c < n_classes; c += blockDim.x) {
+    cnt[c] = 0;
+    first[c] = k;
+  }
+  if (threadIdx.x == 0) s_best = 0;
+  __syncthreads();
+  for (int j = threadIdx.x; j < k; j += blockDim.x) {
+    const int64_t id = ids[(int64_t)q * stride + j];
+    if (id < 0) continue;
+    const int c = labels[id];
+    if (c < 0 || c >= n_classes) continue;
+    atomicAdd(&cnt[c], 1);
+    atomicMin(&first[c], j);
+  }
+  __syncthreads();
+  unsigned long long best = 0;
+  for (int c = threadIdx.x; c < n_classes; c += blockDim.x) {
+    if (cnt[c] == 0) continue;
+    const unsigned long long key = ((unsigned long long)cnt[c] << 32) |
+                                   ((unsigned long long)(2047 - first[c]) << 12) | (unsigned)c;
+    best = key > best ? key : best;
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const unsigned long long u = __shfl_xor(best, o, kWave);
+    best = u > best ? u : best;
+  }
+  if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(&s_best, best);
+  __syncthreads();
+  if (threadIdx.x == 0) out[q] = s_best ? (int)(s_best & 4095u) : -1;
+}
+
+void launch_vote(const int64_t* ids, int64_t stride, int nq, int k, const int* labels, int n_classes,
+                 int* out, hipStream_t st) {
+  if (nq <= 0) return;
+  hipLaunchKernelGGL(k_vote, dim3(nq), dim3(256), 2 * sizeof(int) * (size_t)n_classes, st, ids,
+                     stride, k, labels, n_classes, out);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers.  The DTW radius picks a register-band instance: exact radii of
 // the common windows, else the next larger band with a mask, else the wave
 // anti-diagonal kernels.

@@ -67,6 +67,7 @@ def host():
         L.synth_host_noisy_queries.argtypes = [u64, u64, i32, u64, i64, P, P, P]
         L.synth_host_normals.argtypes = [u64, u64, i64, P]
         L.synth_host_uniforms.argtypes = [u64, u64, i64, P]
+        L.synth_host_trend_labels.argtypes = [P, i64, i32, P]
         L.synth_host_log.argtypes = [ctypes.c_double]
         L.synth_host_log.restype = ctypes.c_double
         L.synth_host_sqrt.argtypes = [ctypes.c_double]
@@ -84,6 +85,9 @@ def device():
         L.synth_dev_randomwalk.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
         L.synth_dev_randomwalk.restype = ctypes.c_int
+        L.synth_dev_trend_labels.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p]
+        L.synth_dev_trend_labels.restype = ctypes.c_int
         _dev = L
     return _dev
 
@@ -115,6 +119,29 @@ def noisy_queries(nq, n, length=256, data_seed=SEED_DATA, j0=0):
     sig = np.empty(nq, dtype=np.float64)
     host().synth_host_noisy_queries(data_seed, n, length, j0, nq, _p(out), _p(src), _p(sig))
     return out, src, sig
+
+
+def trend_labels(raw):
+    """Trend class (0..3) of each raw series: 2 [x_end > x_0] + [x_mid > x_0]."""
+    raw = np.ascontiguousarray(raw, dtype=np.float32)
+    out = np.empty(raw.shape[0], dtype=np.int32)
+    host().synth_host_trend_labels(_p(raw), raw.shape[0], raw.shape[1], _p(out))
+    return out
+
+
+def trend_labels_device(tensor, out, stream=None):
+    """Trend classes of a contiguous float32 CUDA tensor [n, len] into an
+    int32 CUDA tensor [n]."""
+    import torch
+
+    assert tensor.is_cuda and tensor.is_contiguous() and tensor.dtype == torch.float32
+    assert out.is_cuda and out.dtype == torch.int32 and out.numel() == tensor.shape[0]
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    rc = device().synth_dev_trend_labels(ctypes.c_void_p(tensor.data_ptr()), tensor.shape[0],
+                                         tensor.shape[1], ctypes.c_void_p(out.data_ptr()),
+                                         ctypes.c_void_p(s))
+    if rc != 0:
+        raise RuntimeError(f"synth_dev_trend_labels failed ({rc})")
 
 
 def normals(count, seed=7, stream=0):

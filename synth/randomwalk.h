@@ -191,4 +191,11 @@ SYNTH_FN void synth_noisy_query(const float* src, int len, double sigma, uint64_
   for (int t = 0; t < len; ++t) out[t] = (float)((double)src[t] + sigma * sd * synth_normal(&s));
 }
 
+/* Class of a series for the k-NN classification workload (the paper's
+ * collections carry no classes): its trend shape, 2 [x_end > x_0] +
+ * [x_mid > x_0], four classes, read off the raw generated values. */
+SYNTH_FN int synth_trend_class(const float* x, int len) {
+  return 2 * (x[len - 1] > x[0] ? 1 : 0) + (x[len / 2] > x[0] ? 1 : 0);
+}
+
 #endif /* SYNTH_RANDOMWALK_H */

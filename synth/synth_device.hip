@@ -44,3 +44,19 @@ extern "C" int synth_dev_randomwalk(uint64_t seed, uint64_t id0, int64_t count, 
                      (hipStream_t)stream, seed, id0, count, (int)len, dev_out);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
+
+__global__ void synth_trend_labels_kernel(const float* __restrict__ raw, int64_t n, int len,
+                                          int* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = synth_trend_class(raw + i * len, len);
+}
+
+/* Trend classes of raw device series into a device int32 array [n]. */
+extern "C" int synth_dev_trend_labels(const float* dev_raw, int64_t n, int32_t len, int32_t* dev_out,
+                                      void* stream) {
+  if (n < 0 || len < 1 || (n > 0 && (dev_raw == nullptr || dev_out == nullptr))) return -1;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(synth_trend_labels_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, dev_raw, n, (int)len, dev_out);
+  return hipGetLastError() == hipSuccess ? 0 : -3;
+}

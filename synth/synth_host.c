@@ -49,3 +49,8 @@ void synth_host_uniforms(uint64_t seed, uint64_t id, int64_t count, double* out)
 
 double synth_host_log(double x) { return synth_log(x); }
 double synth_host_sqrt(double x) { return synth_sqrt(x); }
+
+/* Trend classes of raw series (synth_trend_class), one per row. */
+void synth_host_trend_labels(const float* raw, int64_t n, int32_t len, int32_t* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = synth_trend_class(raw + i * len, len);
+}

@@ -458,3 +458,37 @@ def test_lb_keogh_filtered_scan_equals_plain_scan():
                 a.scan(x[c:c + 1700], c)
                 b.scan(x[c:c + 1700], c)
             assert np.array_equal(a.ids, b.ids) and np.array_equal(a.d2, b.d2)
+
+
+def test_knn_vote_hand_cases():
+    """Majority class of the k nearest neighbours (Section 5.4), worked by
+    hand: plain majority, a two-way tie going to the class met first,
+    a three-way count tie, k = 1, and lists shorter than k (id -1)."""
+    labels = np.array([0, 1, 2, 1, 0, 2, 2, 1, 0, 1], dtype=np.int32)
+    ids = np.array([
+        [5, 3, 9, -1, -1],   # classes 2, 1, 1 -> 1 (two votes)
+        [3, 6, -1, -1, -1],  # 1, 2 tie -> 1 (met first)
+        [6, 3, 4, 1, 8],     # 2, 1, 0, 1, 0: 1 and 0 tie at two, 1 met first -> 1
+        [4, 2, 5, 0, 7],     # 0, 2, 2, 0, 1: 0 and 2 tie, 0 met first -> 0
+        [2, -1, -1, -1, -1],  # k effectively 1 -> 2
+        [-1, -1, -1, -1, -1],  # empty -> -1
+    ], dtype=np.int64)
+    assert oracle.knn_vote(ids, labels, 3).tolist() == [1, 1, 1, 0, 2, -1]
+    # labels outside [0, n_classes) are not votes
+    bad = labels.copy()
+    bad[3] = 7
+    bad[9] = -1
+    assert oracle.knn_vote(ids[:1], bad, 3).tolist() == [2]
+
+
+def test_knn_vote_properties():
+    """k = 1 gives the nearest neighbour's class; a unanimous list gives
+    that class; renaming classes renames the vote."""
+    rng = np.random.default_rng(3)
+    labels = rng.integers(0, 5, 200).astype(np.int32)
+    ids = rng.integers(0, 200, (50, 9)).astype(np.int64)
+    assert np.array_equal(oracle.knn_vote(ids[:, :1], labels, 5), labels[ids[:, 0]])
+    same = np.repeat(ids[:, :1], 9, axis=1)
+    assert np.array_equal(oracle.knn_vote(same, labels, 5), labels[ids[:, 0]])
+    perm = rng.permutation(5).astype(np.int32)
+    assert np.array_equal(perm[oracle.knn_vote(ids, labels, 5)], oracle.knn_vote(ids, perm[labels], 5))
