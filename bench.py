@@ -147,6 +147,68 @@ def run_batched(pm, idx, n, length, nq, reps):
     return out
 
 
+SWEEP_SHAPES = [  # (series, length): about 100 GB at every length, then sizes at 256
+    (200_000_000, 128), (100_000_000, 256), (50_000_000, 512), (25_000_000, 1024),
+    (12_500_000, 2048), (50_000_000, 256),
+]
+
+
+def sweep_one(pm, args):
+    """One sweep shape: build time and exact 1-NN ED queries/s, one query at
+    a time, over random walks (the same generator and seeds as the default
+    run)."""
+    import torch
+    import synth
+
+    parts = [int(x) for x in args.sweep_one.split(",")]
+    n, length = parts[0], parts[1]
+    data = torch.empty((n, length), dtype=torch.float32, device="cuda")
+    synth.randomwalk_device(data, seed=synth.SEED_DATA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx = pm.messi_build(data, 16, 256, args.leaf)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    del data
+    torch.cuda.empty_cache()
+    qt = torch.from_numpy(synth.random_queries(args.warmup + 50, length)).cuda()
+    run_queries(pm, idx, qt[:args.warmup], 1, pm.MESSI_ED, 0)
+    wall, lat = run_queries(pm, idx, qt[args.warmup:], 1, pm.MESSI_ED, 0)
+    st = query_stats(pm, idx, qt[args.warmup:], 1, pm.MESSI_ED, 0)
+    nqs = len(lat)
+    idx.free()
+    return {"n": n, "len": length, "gb": n * length * 4 / 1e9, "build_s": build_s,
+            "queries_per_s": nqs / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "series_lb_per_query": st["series_lb"] / nqs, "refined_per_query": st["refined"] / nqs}
+
+
+def run_sweep(args):
+    """Size and length sweep (the paper's Section 5.3 sweeps), one child
+    process per shape."""
+    import subprocess
+
+    rows = []
+    for n, length in SWEEP_SHAPES:
+        cmd = [sys.executable, os.path.abspath(__file__), "--sweep-one", f"{n},{length}",
+               "--leaf", str(args.leaf), "--warmup", str(args.warmup)]
+        res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
+        if res.returncode != 0:
+            raise RuntimeError(f"sweep shape {n} x {length} failed ({res.returncode})")
+        row = json.loads(res.stdout.strip().splitlines()[-1])
+        rows.append(row)
+        log(f"sweep {n} x {length}: build {row['build_s']:.3f} s, {row['queries_per_s']:.0f} q/s, "
+            f"p50 {row['p50_ms']:.3f} ms")
+    ref = [r for r in rows if r["n"] == 100_000_000 and r["len"] == 256][0]
+    return {"metric": "exact 1-NN queries/s (ED, one query at a time), size and length sweep",
+            "value": ref["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": 50,
+            "warmup": args.warmup, "ms_per_step": 1e3 / ref["queries_per_s"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "random-walk collections, 16 segments, 8-bit "
+                                                        "iSAX, leaf 2000; 50 random-walk queries per shape"},
+            "sweep": rows}
+
+
 def run_classification(pm, idx, labels, n, length, nq):
     """k-NN classification (Section 5.4) of nq noisy dataset copies, ED,
     BF16 screen, k in {1, 10, 50}: queries/s per k, and agreement of the
@@ -314,6 +376,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
     ap.add_argument("--cpu-queries", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="size and length sweep instead of the default run (one JSON line)")
+    ap.add_argument("--sweep-one", type=str, default="",
+                    help="internal: one sweep shape 'n,len[,inplace]' in this process")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -322,6 +388,10 @@ def main():
               "queried on a single MI355X", file=sys.stderr)
         sys.exit(2)
 
+    if args.sweep:  # each shape in a child process, so every build starts from a clean allocator
+        print(json.dumps(run_sweep(args)), flush=True)
+        return
+
     import torch
 
     import paper_2110_07519_amd as pm
@@ -329,6 +399,9 @@ def main():
 
     n, length = args.n, args.len
     torch.cuda.init()
+    if args.sweep_one:
+        print(json.dumps(sweep_one(pm, args)), flush=True)
+        return
     if args.copy_probe_mib > 0:
         a = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         a.fill_(1.0)

@@ -90,6 +90,23 @@ typedef struct messi_stats {
 int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
                 int32_t cardinality, int32_t leaf_size, messi_index** out);
 
+/* Build options (zero-initialised = the defaults of messi_build). */
+typedef struct messi_options {
+  int32_t inplace;     /* 1: z-normalise `series` in place and use it as the
+                          store (rows stay in id order, reached through the
+                          leaf permutation); the index keeps no copy, so a
+                          collection may take most of the device memory.
+                          The caller keeps ownership: the buffer must stay
+                          allocated and unmodified until messi_free.  It
+                          must be 16-byte aligned. */
+  int32_t bf16_screen; /* 1: also make the BF16 copy used by MESSI_SCREEN_BF16 */
+} messi_options;
+
+/* messi_build with options (NULL = defaults).  With inplace, `series` is
+ * overwritten with its z-normalised rows; otherwise it is only read. */
+int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int32_t cardinality,
+                   int32_t leaf_size, const messi_options* opts, messi_index** out);
+
 /* Exact k-NN (Algorithms 5-10; k-NN per Section 5.4).
  *   queries    device pointer, float32 [nq][len] (raw; z-normalised here).
  *   nq         number of queries, >= 0 (0 returns at once).

@@ -5,7 +5,7 @@ the HIP kernels of libmessi.so behind the C ABI declared in
 include/messi.h.  Torch is used for device memory and streams.  If the
 library is not built, importing works but every call raises.
 
-Names follow the C ABI: messi_build, messi_query, messi_query_stats,
+Names follow the C ABI: messi_build, messi_build_ex, messi_query, messi_query_stats,
 messi_query_batch, messi_prepare_screen, messi_classify, messi_set_stream,
 messi_free, messi_breakpoints, messi_get_words,
 messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
@@ -34,7 +34,7 @@ EXPORTS = [
     "messi_get_words", "messi_get_perm", "messi_get_leaves", "messi_breakpoints", "messi_free",
     "messi_last_error", "messi_query_batch", "messi_prepare_screen",
     "messi_server_start", "messi_server_submit", "messi_server_poll", "messi_server_get_stats",
-    "messi_server_stop", "messi_classify",
+    "messi_server_stop", "messi_classify", "messi_build_ex",
 ]
 
 
@@ -91,6 +91,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.messi_build.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(P)]
+        L.messi_build_ex.argtypes = [P, i64, i32, i32, i32, i32, P, ctypes.POINTER(P)]
         L.messi_query.argtypes = [P, P, i32, i32, i32, i32, P, P]
         L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
         L.messi_query_batch.argtypes = [P, P, i32, P, P, P, i32, i32, P, P, P]
@@ -111,7 +112,7 @@ def lib():
         L.messi_free.argtypes = [P]
         L.messi_free.restype = None
         L.messi_last_error.restype = ctypes.c_char_p
-        for name in ["messi_build", "messi_query", "messi_query_stats", "messi_query_batch",
+        for name in ["messi_build", "messi_build_ex", "messi_query", "messi_query_stats", "messi_query_batch",
                      "messi_prepare_screen", "messi_classify", "messi_server_start",
                      "messi_server_submit",
                      "messi_server_poll", "messi_server_get_stats", "messi_set_stream",
@@ -153,6 +154,29 @@ def messi_build(series, segments: int = 16, cardinality: int = 256, leaf_size: i
     _check(lib().messi_build(_dev_ptr(series), n, length, segments, cardinality, leaf_size,
                              ctypes.byref(h)))
     return Index(h, n, length, segments)
+
+
+class MessiOptions(ctypes.Structure):
+    _fields_ = [("inplace", ctypes.c_int32), ("bf16_screen", ctypes.c_int32)]
+
+
+def messi_build_ex(series, segments: int = 16, cardinality: int = 256, leaf_size: int = 2000,
+                   inplace: bool = False, bf16_screen: bool = False):
+    """messi_build with options.  inplace: `series` (float32 CUDA [n, len]) is
+    z-normalised in place and becomes the store; keep it alive and unmodified
+    while the index lives (the returned Index holds a reference)."""
+    import torch
+
+    assert series.dtype == torch.float32 and series.dim() == 2
+    n, length = series.shape
+    h = ctypes.c_void_p()
+    o = MessiOptions(int(inplace), int(bf16_screen))
+    _check(lib().messi_build_ex(_dev_ptr(series), n, length, segments, cardinality, leaf_size,
+                                ctypes.cast(ctypes.pointer(o), ctypes.c_void_p), ctypes.byref(h)))
+    idx = Index(h, n, length, segments)
+    if inplace:
+        idx.store = series
+    return idx
 
 
 def messi_query(index, queries, k: int = 1, distance: int = MESSI_ED, window: int = 0,

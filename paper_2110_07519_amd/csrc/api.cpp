@@ -199,6 +199,7 @@ struct messi_index {
   NodeDev* nodes = nullptr;
   int4* tree = nullptr;
   int* root_node = nullptr;
+  bool inplace = false;      // Z is the caller's buffer, normalised in place, rows in id order
   int* shard_off = nullptr;  // [kShards + 1] first chunk of each shard
   int64_t n_chunks = 0;
   uint4* sh_sym = nullptr;   // leaf table in shard-major order
@@ -223,6 +224,7 @@ struct messi_index {
     v.card_bits = card_bits;
     v.n_leaves = n_leaves;
     v.Z = Z;
+    v.zrow = inplace ? perm : nullptr;
     v.words = words;
     v.perm = perm;
     v.leaf_begin = leaf_begin;
@@ -403,10 +405,16 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   tmp.release(d.W0);
   tmp.release(d.W1);
 
-  // (5) leaf-ordered words and z-normalised store
+  // (5) leaf-ordered words and z-normalised store (a leaf-ordered copy, or
+  // the caller's rows normalised in place)
   ix->words = ix->mem.alloc<uint4>(n);
-  ix->Z = ix->mem.alloc<float>((size_t)n * len);
-  launch_gather_store(series, n, len, ix->perm, musd, words_id, ix->Z, ix->words, st);
+  if (ix->inplace) {
+    ix->Z = const_cast<float*>(series);
+    launch_store_inplace(const_cast<float*>(series), n, len, ix->perm, musd, words_id, ix->words, st);
+  } else {
+    ix->Z = ix->mem.alloc<float>((size_t)n * len);
+    launch_gather_store(series, n, len, ix->perm, musd, words_id, ix->Z, ix->words, st);
+  }
   launch_check();
   ix->nodes = d.nodes;
   ix->root_node = d.root_node;
@@ -498,7 +506,8 @@ void ensure_screen(messi_index* ix) {
   if (ix->Zb) return;
   ix->Zb = ix->screen_mem.alloc<uint16_t>((size_t)ix->n * ix->len);
   ix->xn = ix->screen_mem.alloc<float>((size_t)ix->n);
-  launch_bf16_rows(ix->Z, ix->n, ix->len, ix->Zb, ix->xn, ix->ctx.stream);
+  launch_bf16_rows(ix->Z, ix->inplace ? ix->perm : nullptr, ix->n, ix->len, ix->Zb, ix->xn,
+                   ix->ctx.stream);
   launch_check();
   HIP_OR_THROW(hipStreamSynchronize(ix->ctx.stream));
 }
@@ -620,7 +629,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     launch_stage1(v, p, qs, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[2], st));
     if (screen) {
-      launch_bf16_rows(qs.zq, nq, len, sc.qb, sc.qn, st);
+      launch_bf16_rows(qs.zq, nullptr, nq, len, sc.qb, sc.qn, st);
       if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
       launch_screen(v, p, qs, sc, screen_blocks, st);
     } else {
@@ -920,7 +929,15 @@ int messi_breakpoints(int32_t card_bits, float* beta) {
 
 int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
                 int32_t cardinality, int32_t leaf_size, messi_index** out) {
+  return messi_build_ex(const_cast<float*>(series), n, len, segments, cardinality, leaf_size, nullptr,
+                        out);
+}
+
+int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int32_t cardinality,
+                   int32_t leaf_size, const messi_options* opts, messi_index** out) {
   g_err.clear();
+  messi_options o{};
+  if (opts) o = *opts;
   if (!out) return fail(MESSI_EINVAL, "out is NULL");
   if (n < 1 || n >= ((int64_t)1 << 31) - 1) return fail(MESSI_EINVAL, "n must be in [1, 2^31-2]");
   if (segments < 1 || segments > kMaxSeg) return fail(MESSI_EINVAL, "segments must be in [1, 16]");
@@ -931,7 +948,10 @@ int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
   if (leaf_size < 1) return fail(MESSI_EINVAL, "leaf_size must be >= 1");
   if (!is_device_ptr(series)) return fail(MESSI_EINVAL, "series is not a device pointer");
 
+  if (o.inplace && (reinterpret_cast<uintptr_t>(series) & 15))
+    return fail(MESSI_EINVAL, "an in-place series buffer must be 16-byte aligned");
   messi_index* ix = new messi_index();
+  ix->inplace = o.inplace != 0;
   ix->n = n;
   ix->len = len;
   ix->w = segments;
@@ -939,7 +959,7 @@ int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
   ix->leaf_size = leaf_size;
   size_t free_b = 0, total_b = 0;
   (void)hipMemGetInfo(&free_b, &total_b);
-  const size_t need = (size_t)n * len * 4 + (size_t)n * (16 * 4 + 8 * 2 + 8 + 4 * 3);
+  const size_t need = (ix->inplace ? 0 : (size_t)n * len * 4) + (size_t)n * (16 * 4 + 8 * 2 + 8 + 4 * 3);
   if (need > free_b) {
     delete ix;
     return fail(MESSI_ENOMEM, "index needs about %zu bytes, %zu free", need, free_b);
@@ -965,6 +985,17 @@ int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
   } catch (const HipError& e) {
     delete ix;
     return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  if (o.bf16_screen && screen_supported(len)) {
+    try {
+      ensure_screen(ix);
+    } catch (const OomError& e) {
+      delete ix;
+      return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+    } catch (const HipError& e) {
+      delete ix;
+      return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+    }
   }
   *out = ix;
   return MESSI_OK;

@@ -77,6 +77,8 @@ void launch_leaf_sort(int n_leaves, const int64_t* leaf_begin, const int64_t* le
 void launch_leaf_sort_global(int64_t b, int cnt, int p2, const int32_t* I, int32_t* scratch,
                              int32_t* perm, hipStream_t st);
 void launch_make_tree(const NodeDev* nodes, int n_nodes, int card_bits, int4* tree, hipStream_t st);
+void launch_store_inplace(float* raw, int64_t n, int len, const int32_t* perm, const float2* musd,
+                          const uint4* words, uint4* words_sorted, hipStream_t st);
 void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* perm,
                          const float2* musd, const uint4* words, float* Z, uint4* words_sorted,
                          hipStream_t st);

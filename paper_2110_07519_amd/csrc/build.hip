@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
     const float d = at(t) - mu;
     v = v + d * d;
   }
-  const float sd = __fsqrt_rn(__fdiv_rn(v, flen));
+  const float sd = sqrtf(__fdiv_rn(v, flen));
   const bool flat = !(sd > 0.0f);
   const int m = len / w;
   const float fm = (float)m;
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
       const float d = v[i] - mu;
       sq[i] = d * d;
     }
-    const float sd = __fsqrt_rn(__fdiv_rn(chain_sum16<C>(sq, g), flen));
+    const float sd = sqrtf(__fdiv_rn(chain_sum16<C>(sq, g), flen));
     const bool flat = !(sd > 0.0f);
     float a = 0.0f;
     if (!flat) {
@@ -623,6 +623,39 @@ __global__ __launch_bounds__(256) void k_gather_store(const float* __restrict__ 
   }
 }
 
+// In-place store: the caller's rows are z-normalised where they are (id
+// order, the same arithmetic as the leaf-ordered copy) and only the words
+// are gathered into leaf order.
+__global__ __launch_bounds__(256) void k_store_inplace(float* __restrict__ raw, int64_t n, int len,
+                                                        const int32_t* __restrict__ perm,
+                                                        const float2* __restrict__ musd,
+                                                        const uint4* __restrict__ words,
+                                                        uint4* __restrict__ words_sorted) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t p = wave; p < n; p += nwaves) {
+    const int32_t id = perm[p];
+    if (lane == 0) words_sorted[p] = words[id];
+    const float2 ms = musd[id];
+    float* __restrict__ x = raw + (int64_t)id * len;
+    const bool flat = !(ms.y > 0.0f);
+    if ((len & 3) == 0) {
+      for (int t = 4 * lane; t < len; t += 4 * kWave) {
+        const float4 v = *reinterpret_cast<const float4*>(x + t);
+        float4 o;
+        o.x = flat ? 0.0f : __fdiv_rn(v.x - ms.x, ms.y);
+        o.y = flat ? 0.0f : __fdiv_rn(v.y - ms.x, ms.y);
+        o.z = flat ? 0.0f : __fdiv_rn(v.z - ms.x, ms.y);
+        o.w = flat ? 0.0f : __fdiv_rn(v.w - ms.x, ms.y);
+        *reinterpret_cast<float4*>(x + t) = o;
+      }
+    } else {
+      for (int t = lane; t < len; t += kWave) x[t] = flat ? 0.0f : __fdiv_rn(x[t] - ms.x, ms.y);
+    }
+  }
+}
+
 // Compact tree for the approximate-search descent: one 16-byte record per
 // node, so each level of the descent is a single load.
 __global__ void k_make_tree(const NodeDev* __restrict__ nodes, int n_nodes, int card_bits,
@@ -734,6 +767,13 @@ void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* pe
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_gather_store, dim3((unsigned)blocks), dim3(256), 0, st, raw, n, len, perm,
                      musd, words, Z, words_sorted);
+}
+
+void launch_store_inplace(float* raw, int64_t n, int len, const int32_t* perm, const float2* musd,
+                          const uint4* words, uint4* words_sorted, hipStream_t st) {
+  const int64_t blocks = std::min<int64_t>((n + 3) / 4, 65536);
+  hipLaunchKernelGGL(k_store_inplace, dim3((unsigned)blocks), dim3(256), 0, st, raw, n, len, perm, musd,
+                     words, words_sorted);
 }
 
 }  // namespace messi

@@ -17,7 +17,9 @@ constexpr int kMaxBand = 64;       // largest DTW radius served by the register-
 struct IndexDev {
   int64_t n;
   int len, w, m, card_bits, n_leaves;
-  const float* Z;            // [n][len] z-normalised series in leaf order
+  const float* Z;            // [n][len] z-normalised series: in leaf order, or in id order when
+                             // zrow is set (the caller's buffer, normalised in place)
+  const int32_t* zrow;       // null, or [n]: the row of Z holding leaf-order position p
   const uint4* words;        // [n] words in leaf order
   const int32_t* perm;       // [n] id at each leaf-order position
   const int64_t* leaf_begin; // [L]
@@ -34,6 +36,11 @@ struct IndexDev {
   const int2* sh_rng;
   const int* leaf_sh_off;    // [kShards + 1]
 };
+
+// Row of Z holding leaf-order position pos.
+__device__ __forceinline__ const float* zrow_ptr(const IndexDev& ix, int64_t pos) {
+  return ix.Z + (ix.zrow ? (int64_t)ix.zrow[pos] : pos) * ix.len;
+}
 
 // BF16 screen of batched ED queries: a BF16 shadow of the store with the
 // squared norm of every row, the queries' BF16 rows and norms, the leaves'
@@ -54,8 +61,8 @@ struct ScreenDev {
 
 bool screen_supported(int len);
 int screen_blocks_per_cu(int len);
-void launch_bf16_rows(const float* src, int64_t rows, int len, uint16_t* dst, float* norms,
-                      hipStream_t st);
+void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, int len, uint16_t* dst,
+                      float* norms, hipStream_t st);
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
                    const ScreenDev& sc, int blocks, hipStream_t st);
 

@@ -46,7 +46,7 @@ __device__ __forceinline__ float kth_dist(const unsigned long long* slots, int k
 // rounding of this expression itself.
 __device__ __forceinline__ float lb_threshold(float thr, const QueryParams& p) {
   if (!(thr < INFINITY)) return INFINITY;
-  const float r = __fsqrt_rn(thr * p.lb_rel) + p.eta;
+  const float r = sqrtf(thr * p.lb_rel) + p.eta;
   return r * r * 1.0001f;
 }
 
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
       var = var + d * d;
     }
     s_mu = mu;
-    s_sd = __fsqrt_rn(__fdiv_rn(var, (float)len));
+    s_sd = sqrtf(__fdiv_rn(var, (float)len));
   }
   __syncthreads();
   const float mu = s_mu, sd = s_sd;
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     const int nw = approx_blocks * (blockDim.x / kWave);
     for (int j = gw; j < cnt; j += nw) {
       const int64_t pos = P0 + j;
-      const float d2 = ed_wave(zl, ix.Z + pos * len, len, lane);
+      const float d2 = ed_wave(zl, zrow_ptr(ix, pos), len, lane);
       if (lane == 0) {
         approx_d2[j] = d2;
         topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
@@ -634,7 +634,8 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     const int gw = blockIdx.x * 4 + wv, nw = approx_blocks * 4;
     for (int j = gw; j < cnt; j += nw) {
       const int64_t pos = P0 + j;
-      for (int t = lane; t < len; t += kWave) xl[wv * len + t] = ix.Z[pos * len + t];
+      const float* xr = zrow_ptr(ix, pos);
+      for (int t = lane; t < len; t += kWave) xl[wv * len + t] = xr[t];
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
       const float d2 = dtw_wave<float>(ql, xl + wv * len, len, p.window, buf + wv * 3 * len,
@@ -651,7 +652,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     __syncthreads();
     for (int j = blockIdx.x * blockDim.x + tid; j < cnt; j += approx_blocks * blockDim.x) {
       const int64_t pos = P0 + j;
-      const float d2 = dtw_band<R, MASK>(qpad, ix.Z + pos * len, len, p.window, INFINITY);
+      const float d2 = dtw_band<R, MASK>(qpad, zrow_ptr(ix, pos), len, p.window, INFINITY);
       approx_d2[j] = d2;
       topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
     }
@@ -779,7 +780,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       unsigned long long mine = ck;
       if (tid < cnt) {
         const int pp = pend[tid];
-        const float e = dtw_band<(R >= 0 ? R : 0), MASK>(ql, ix.Z + (int64_t)pp * len, len, p.window, cut);
+        const float e = dtw_band<(R >= 0 ? R : 0), MASK>(ql, zrow_ptr(ix, pp), len, p.window, cut);
         ++c_ref;
         if (e < INFINITY) ch = offer(ix, p, s, q, e, pp, ck, true);
       }
@@ -915,8 +916,11 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       }
       if (!act) continue;
       float dv[kGroup];
+      int gr[kGroup];  // rows of Z (the positions themselves unless Z is in id order)
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) gr[c] = ix.zrow ? ix.zrow[gp[c]] : gp[c];
       if constexpr (!dtw) {
-        ed_group(ql, ix.Z, len, gp, act, lane, dv);
+        ed_group(ql, ix.Z, len, gr, act, lane, dv);
         c_ref += (lane == 0) ? __popc(act) : 0;
         // distances are wave-uniform: the rare ones inside the window of
         // the k-th best are offered by lane 0
@@ -928,7 +932,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
         if (__ballot(ch)) ckey = umin64(ckey, load_key(&slots[k - 1]));
       } else {
         // LB_Keogh on the raw values (Algorithm 10, second test)
-        lbk_group(U, Lw, ix.Z, len, gp, act, lane, dv);
+        lbk_group(U, Lw, ix.Z, len, gr, act, lane, dv);
         c_lbk += (lane == 0) ? __popc(act) : 0;
         const float tk = key_dist(ckey) * p.win * p.win;
         if constexpr (R >= 0) {
@@ -952,7 +956,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
           for (int c = 0; c < kGroup; ++c) {
             if (!((act >> c) & 1u) || !(dv[c] <= tk)) continue;
             const int pos = gp[c];
-            const float* x = ix.Z + (int64_t)pos * len;
+            const float* x = zrow_ptr(ix, pos);
             for (int t = lane; t < len; t += kWave) wx[wv * len + t] = x[t];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -1084,7 +1088,7 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
       for (int c0 = topn; c0 < cnt; c0 += nw) {
         const int c = c0 + wv;
         if (c < cnt) {
-          const float* x = ix.Z + (int64_t)pos_l[c] * len;
+          const float* x = zrow_ptr(ix, pos_l[c]);
           double acc = 0.0;
           for (int t0 = 0; t0 < len; t0 += kWave) {
             double sq = 0.0;
@@ -1111,7 +1115,7 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
       for (int c0 = topn; c0 < cnt; c0 += p.fin_waves) {
         const int c = c0 + wv;
         if (wv < p.fin_waves && c < cnt) {
-          const float* x = ix.Z + (int64_t)pos_l[c] * len;
+          const float* x = zrow_ptr(ix, pos_l[c]);
           for (int t = lane; t < len; t += kWave) xl[wv * len + t] = x[t];
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -1200,14 +1204,15 @@ __device__ __forceinline__ uint32_t bf16_bits(float f) {  // finite f, round to 
 }
 
 // One wave per row: BF16 copy and FP64 squared norm (len % 4 == 0).
-__global__ __launch_bounds__(256) void k_bf16_rows(const float* __restrict__ src, int64_t rows,
+__global__ __launch_bounds__(256) void k_bf16_rows(const float* __restrict__ src,
+                                                   const int32_t* __restrict__ src_row, int64_t rows,
                                                    int len, uint16_t* __restrict__ dst,
                                                    float* __restrict__ norms) {
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t r = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); r < rows;
        r += waves) {
-    const float* x = src + r * len;
+    const float* x = src + (src_row ? (int64_t)src_row[r] : r) * len;
     uint2* y = reinterpret_cast<uint2*>(dst + r * len);
     double acc = 0.0;
     for (int t = 4 * lane; t < len; t += 4 * kWave) {
@@ -1368,7 +1373,7 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
           const float qn = sc.qn[pq];
           const float thr = kth_dist(s.slots + (int64_t)pq * p.k, k_of(p, s, pq)) * p.win;
           pR = qn * one_m - thr;
-          pA = sc.c_dot * __fsqrt_rn(qn);
+          pA = sc.c_dot * sqrtf(qn);
         }
       }
     };
@@ -1396,7 +1401,7 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
         const bool v = j < e;
         const float xn = v ? sc.xn[j] : 0.0f;
         cx[t] = v ? xn * one_m : INFINITY;
-        sx[t] = __fsqrt_rn(xn);
+        sx[t] = sqrtf(xn);
         const uint4* src = reinterpret_cast<const uint4*>(sc.Zb + j * len + kb);
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
@@ -1451,7 +1456,7 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
                 const int64_t jsel = wbase + 16 * t + (src_lane & 15);
                 if (qsel < 0 || jsel >= e) continue;
                 if (jsel >= s.approx_range[2 * qsel] && jsel < s.approx_range[2 * qsel + 1]) continue;
-                const float d2 = ed_wave(s.zq + (int64_t)qsel * len, ix.Z + jsel * len, len, lane);
+                const float d2 = ed_wave(s.zq + (int64_t)qsel * len, zrow_ptr(ix, jsel), len, lane);
                 if (lane == 0) {
                   const int kk = k_of(p, s, qsel);
                   const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
@@ -1680,11 +1685,12 @@ int screen_blocks_per_cu(int len) {
   return per < 1 ? 1 : per;
 }
 
-void launch_bf16_rows(const float* src, int64_t rows, int len, uint16_t* dst, float* norms,
-                      hipStream_t st) {
+void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, int len, uint16_t* dst,
+                      float* norms, hipStream_t st) {
   if (rows <= 0) return;
   const int64_t blocks = std::min<int64_t>((rows + 3) / 4, 65536);
-  hipLaunchKernelGGL(k_bf16_rows, dim3((unsigned)blocks), dim3(256), 0, st, src, rows, len, dst, norms);
+  hipLaunchKernelGGL(k_bf16_rows, dim3((unsigned)blocks), dim3(256), 0, st, src, src_row, rows, len,
+                     dst, norms);
 }
 
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,

@@ -6,6 +6,7 @@
  * One thread per series; a block of 64 series is staged in LDS (row stride
  * len+1 floats, so the 64 lanes writing point t hit distinct banks) and then
  * written out row-major with consecutive lanes on consecutive addresses.
+ * Series longer than 512 points are written row by row from registers.
  */
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -34,14 +35,27 @@ __global__ __launch_bounds__(SYNTH_BLOCK) void synth_randomwalk_kernel(uint64_t 
   }
 }
 
+/* Longer series: one thread per series writing its own row directly (the
+ * writes are strided, which only costs generation speed). */
+__global__ __launch_bounds__(SYNTH_BLOCK) void synth_randomwalk_rows_kernel(uint64_t seed, uint64_t id0,
+                                                                            int64_t count, int len,
+                                                                            float* __restrict__ out) {
+  const int64_t mine = (int64_t)blockIdx.x * SYNTH_BLOCK + threadIdx.x;
+  if (mine < count) synth_randomwalk_one(seed, id0 + (uint64_t)mine, len, out + mine * (int64_t)len);
+}
+
 /* Returns 0 on success, -1 on bad arguments, -3 on a launch error. */
 extern "C" int synth_dev_randomwalk(uint64_t seed, uint64_t id0, int64_t count, int32_t len,
                                     float* dev_out, void* stream) {
-  if (count < 0 || len < 1 || len > SYNTH_MAX_LEN || (count > 0 && dev_out == nullptr)) return -1;
+  if (count < 0 || len < 1 || (count > 0 && dev_out == nullptr)) return -1;
   if (count == 0) return 0;
   const int64_t blocks = (count + SYNTH_BLOCK - 1) / SYNTH_BLOCK;
-  hipLaunchKernelGGL(synth_randomwalk_kernel, dim3((unsigned)blocks), dim3(SYNTH_BLOCK), 0,
-                     (hipStream_t)stream, seed, id0, count, (int)len, dev_out);
+  if (len <= SYNTH_MAX_LEN)
+    hipLaunchKernelGGL(synth_randomwalk_kernel, dim3((unsigned)blocks), dim3(SYNTH_BLOCK), 0,
+                       (hipStream_t)stream, seed, id0, count, (int)len, dev_out);
+  else
+    hipLaunchKernelGGL(synth_randomwalk_rows_kernel, dim3((unsigned)blocks), dim3(SYNTH_BLOCK), 0,
+                       (hipStream_t)stream, seed, id0, count, (int)len, dev_out);
   return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 

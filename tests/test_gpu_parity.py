@@ -47,7 +47,7 @@ def _check_answers(ids, d, oids, od2):
 
 
 def test_device_generator_matches_host():
-    for count, length in [(10_000, 256), (1001, 128), (65, 100)]:
+    for count, length in [(10_000, 256), (1001, 128), (65, 100), (130, 1024)]:
         t = torch.empty((count, length), dtype=torch.float32, device="cuda")
         synth.randomwalk_device(t, seed=1, id0=7)
         torch.cuda.synchronize()
