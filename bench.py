@@ -147,9 +147,10 @@ def run_batched(pm, idx, n, length, nq, reps):
     return out
 
 
-SWEEP_SHAPES = [  # (series, length): about 100 GB at every length, then sizes at 256
-    (200_000_000, 128), (100_000_000, 256), (50_000_000, 512), (25_000_000, 1024),
-    (12_500_000, 2048), (50_000_000, 256),
+SWEEP_SHAPES = [  # (series, length, in place): about 100 GB at every length, then sizes at 256
+    (200_000_000, 128, 0), (100_000_000, 256, 0), (50_000_000, 512, 0), (25_000_000, 1024, 0),
+    (12_500_000, 2048, 0), (50_000_000, 256, 0), (100_000_000, 256, 1), (150_000_000, 256, 1),
+    (200_000_000, 256, 1),
 ]
 
 
@@ -161,15 +162,15 @@ def sweep_one(pm, args):
     import synth
 
     parts = [int(x) for x in args.sweep_one.split(",")]
-    n, length = parts[0], parts[1]
+    n, length, inplace = parts[0], parts[1], (parts[2] if len(parts) > 2 else 0)
     data = torch.empty((n, length), dtype=torch.float32, device="cuda")
     synth.randomwalk_device(data, seed=synth.SEED_DATA)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    idx = pm.messi_build(data, 16, 256, args.leaf)
+    idx = pm.messi_build_ex(data, 16, 256, args.leaf, inplace=bool(inplace))
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
-    del data
+    del data  # the in-place index keeps its own reference to the store
     torch.cuda.empty_cache()
     qt = torch.from_numpy(synth.random_queries(args.warmup + 50, length)).cuda()
     run_queries(pm, idx, qt[:args.warmup], 1, pm.MESSI_ED, 0)
@@ -177,7 +178,8 @@ def sweep_one(pm, args):
     st = query_stats(pm, idx, qt[args.warmup:], 1, pm.MESSI_ED, 0)
     nqs = len(lat)
     idx.free()
-    return {"n": n, "len": length, "gb": n * length * 4 / 1e9, "build_s": build_s,
+    return {"n": n, "len": length, "inplace": bool(inplace), "gb": n * length * 4 / 1e9,
+            "build_s": build_s,
             "queries_per_s": nqs / wall, "p50_ms": float(np.percentile(lat, 50) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "series_lb_per_query": st["series_lb"] / nqs, "refined_per_query": st["refined"] / nqs}
@@ -189,17 +191,18 @@ def run_sweep(args):
     import subprocess
 
     rows = []
-    for n, length in SWEEP_SHAPES:
-        cmd = [sys.executable, os.path.abspath(__file__), "--sweep-one", f"{n},{length}",
+    for n, length, inplace in SWEEP_SHAPES:
+        cmd = [sys.executable, os.path.abspath(__file__), "--sweep-one", f"{n},{length},{inplace}",
                "--leaf", str(args.leaf), "--warmup", str(args.warmup)]
         res = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=600)
         if res.returncode != 0:
             raise RuntimeError(f"sweep shape {n} x {length} failed ({res.returncode})")
         row = json.loads(res.stdout.strip().splitlines()[-1])
         rows.append(row)
-        log(f"sweep {n} x {length}: build {row['build_s']:.3f} s, {row['queries_per_s']:.0f} q/s, "
+        log(f"sweep {n} x {length}{' in place' if inplace else ''}: build {row['build_s']:.3f} s, "
+            f"{row['queries_per_s']:.0f} q/s, "
             f"p50 {row['p50_ms']:.3f} ms")
-    ref = [r for r in rows if r["n"] == 100_000_000 and r["len"] == 256][0]
+    ref = [r for r in rows if r["n"] == 100_000_000 and r["len"] == 256 and not r["inplace"]][0]
     return {"metric": "exact 1-NN queries/s (ED, one query at a time), size and length sweep",
             "value": ref["queries_per_s"], "unit": "queries/s", "n_gpus": 1, "steps": 50,
             "warmup": args.warmup, "ms_per_step": 1e3 / ref["queries_per_s"],
