@@ -80,6 +80,7 @@ def lib():
         L.oracle_breakpoints.argtypes = [i32, P]
         L.oracle_symbol.argtypes = [ctypes.c_float, P, i32]
         L.oracle_threads.restype = i32
+        L.oracle_set_normalise.argtypes = [i32]
         L.oracle_symbol.restype = i32
         L.oracle_words.argtypes = [P, i64, i32, i32, i32, P]
         L.oracle_leaf_partition.argtypes = [P, i64, i32, i32, i32, P, P, i64]
@@ -110,6 +111,26 @@ def _f32(a):
 
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class raw_mode:
+    """Context: series and queries are taken as given, not z-normalised."""
+
+    def __enter__(self):
+        lib().oracle_set_normalise(0)
+        return self
+
+    def __exit__(self, *exc):
+        lib().oracle_set_normalise(1)
+        return False
+
+
+def windows(series, length, stride=1):
+    """Rows of a subsequence index: the windows of `length` points of one
+    long series, starting every `stride` points (Section 2.1)."""
+    series = _f32(series)
+    n = (len(series) - length) // stride + 1
+    return np.stack([series[i * stride:i * stride + length] for i in range(n)])
 
 
 def threads():

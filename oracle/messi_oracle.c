@@ -28,6 +28,11 @@ int32_t oracle_threads(void) {
 #endif
 }
 
+/* Whether series and queries are z-normalised before anything else (the
+ * paper's default) or taken as they are (its non-normalised variant). */
+static int g_normalise = 1;
+void oracle_set_normalise(int32_t on) { g_normalise = on ? 1 : 0; }
+
 void oracle_znorm(const float* x, int32_t len, float* z) {
   float s = 0.0f;
   for (int32_t t = 0; t < len; ++t) s = s + x[t];
@@ -89,6 +94,15 @@ int32_t oracle_symbol(float p, const float* beta, int32_t card_bits) {
   return c;
 }
 
+/* A series as the index sees it: z-normalised, or as given. */
+static void prep_row(const float* x, int32_t len, float* z) {
+  if (g_normalise) {
+    oracle_znorm(x, len, z);
+  } else {
+    for (int32_t t = 0; t < len; ++t) z[t] = x[t];
+  }
+}
+
 void oracle_words(const float* raw, int64_t n, int32_t len, int32_t w, int32_t card_bits,
                   uint8_t* words) {
   float beta[255];
@@ -96,7 +110,7 @@ void oracle_words(const float* raw, int64_t n, int32_t len, int32_t w, int32_t c
   float* z = (float*)malloc(sizeof(float) * (size_t)len);
   float paa[ORACLE_MAX_SEGMENTS];
   for (int64_t i = 0; i < n; ++i) {
-    oracle_znorm(raw + i * len, len, z);
+    prep_row(raw + i * len, len, z);
     oracle_paa(z, len, w, paa);
     for (int32_t s = 0; s < w; ++s) words[i * w + s] = (uint8_t)oracle_symbol(paa[s], beta, card_bits);
   }
@@ -382,7 +396,7 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
                      const float* raw_queries, int32_t nq, int32_t k, int32_t distance,
                      int32_t r, int64_t* ids, double* d2) {
   float* zq = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
-  for (int32_t j = 0; j < nq; ++j) oracle_znorm(raw_queries + (int64_t)j * len, len, zq + (int64_t)j * len);
+  for (int32_t j = 0; j < nq; ++j) prep_row(raw_queries + (int64_t)j * len, len, zq + (int64_t)j * len);
 #pragma omp parallel
   {
     int64_t* lid = (int64_t*)malloc(sizeof(int64_t) * (size_t)nq * (size_t)k);
@@ -394,7 +408,7 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
     }
 #pragma omp for schedule(static)
     for (int64_t i = 0; i < count; ++i) {
-      oracle_znorm(raw_chunk + i * len, len, z);
+      prep_row(raw_chunk + i * len, len, z);
       for (int32_t j = 0; j < nq; ++j) {
         const double d = pair_dist2(zq + (int64_t)j * len, z, len, distance, r);
         knn_insert(lid + (int64_t)j * k, ld + (int64_t)j * k, k, d, id0 + i);
@@ -428,7 +442,7 @@ void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int
   float* up = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
   float* lo = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
   for (int32_t j = 0; j < nq; ++j) {
-    oracle_znorm(raw_queries + (int64_t)j * len, len, zq + (int64_t)j * len);
+    prep_row(raw_queries + (int64_t)j * len, len, zq + (int64_t)j * len);
     oracle_envelope(zq + (int64_t)j * len, len, r, up + (int64_t)j * len, lo + (int64_t)j * len);
   }
   double* bound = (double*)malloc(sizeof(double) * (size_t)nq);  /* k-th best before this chunk */
@@ -444,7 +458,7 @@ void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int
     }
 #pragma omp for schedule(dynamic, 256)
     for (int64_t i = 0; i < count; ++i) {
-      oracle_znorm(raw_chunk + i * len, len, z);
+      prep_row(raw_chunk + i * len, len, z);
       for (int32_t j = 0; j < nq; ++j) {
         const double own = ld[(int64_t)j * k + k - 1];
         const double kth = own < bound[j] ? own : bound[j];
@@ -500,26 +514,46 @@ static int pruned(double lb2, double kth, double eta) {
   return sqrt(lb2) > sqrt(kth) + eta;
 }
 
+static double norm2_of(const float* v, int32_t len) {
+  double a = 0.0;
+  for (int32_t t = 0; t < len; ++t) a += (double)v[t] * (double)v[t];
+  return a;
+}
+
 void oracle_index_search(const float* raw, int64_t n, int32_t len, int32_t w, int32_t card_bits,
                          const uint8_t* words, const int32_t* perm, const oracle_leaf* leaves,
                          int64_t n_leaves, const float* raw_query, int32_t k, int32_t distance,
                          int32_t r, int64_t* ids, double* d2, oracle_search_stats* stats) {
-  (void)n;
   float beta[255];
   oracle_breakpoints(card_bits, beta);
-  const double eta = 16.0 * ldexp(1.0, -24) * (double)len * sqrt((double)(len / w));
   float* q = (float*)malloc(sizeof(float) * (size_t)len);
   float* z = (float*)malloc(sizeof(float) * (size_t)len);
   float* U = (float*)malloc(sizeof(float) * (size_t)len);
   float* L = (float*)malloc(sizeof(float) * (size_t)len);
   float qpaa[ORACLE_MAX_SEGMENTS], upaa[ORACLE_MAX_SEGMENTS], lpaa[ORACLE_MAX_SEGMENTS];
-  oracle_znorm(raw_query, len, q);
+  prep_row(raw_query, len, q);
   oracle_paa(q, len, w, qpaa);
   if (distance == ORACLE_DTW) { /* PAA of the query's LB_Keogh envelope */
     oracle_envelope(q, len, r, U, L);
     oracle_paa(U, len, w, upaa);
     oracle_paa(L, len, w, lpaa);
   }
+  /* The words and PAAs are FP32 segment means: one is off from the exact
+   * mean of a row v by at most 2u sqrt(m)|v|, so a bound moves by at most
+   * 2u sqrt(len m)(|x| + |q|), with |x| the largest series norm and |q|
+   * the largest of the query and envelope norms.  eta takes 4x that. */
+  double xmax = 0.0, qmax = norm2_of(q, len);
+  for (int64_t i = 0; i < n; ++i) {
+    prep_row(raw + i * len, len, z);
+    const double v = norm2_of(z, len);
+    if (v > xmax) xmax = v;
+  }
+  if (distance == ORACLE_DTW) {
+    const double nu = norm2_of(U, len), nl = norm2_of(L, len);
+    if (nu > qmax) qmax = nu;
+    if (nl > qmax) qmax = nl;
+  }
+  const double eta = 8.0 * ldexp(1.0, -24) * sqrt((double)len * (double)(len / w)) * (sqrt(xmax) + sqrt(qmax));
   memset(stats, 0, sizeof(*stats));
   stats->leaves_total = n_leaves;
   stats->bsf_monotone = 1;
@@ -570,7 +604,7 @@ void oracle_index_search(const float* raw, int64_t n, int32_t len, int32_t w, in
           stats->series_lb += 1;
           if (pruned(slb, d2[k - 1], eta)) continue;
         }
-        oracle_znorm(raw + id * len, len, z);
+        prep_row(raw + id * len, len, z);
         if (distance == ORACLE_DTW && pass == 1) {
           const double lbk = oracle_lb_keogh2(U, L, z, len);
           stats->lb_keogh += 1;

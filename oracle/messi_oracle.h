@@ -49,6 +49,10 @@ typedef struct oracle_search_stats {
 
 /* Z-normalisation (Section 2.1): mean 0, population standard deviation 1,
  * FP32, sums taken in index order.  A constant series maps to zeros. */
+/* 0: series and queries are used as given (no z-normalisation) by every
+ * function below that takes raw data; 1 (default): z-normalised first. */
+void oracle_set_normalise(int32_t on);
+
 /* Number of threads the OpenMP scans use. */
 int32_t oracle_threads(void);
 
