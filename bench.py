@@ -334,6 +334,44 @@ def run_serving(pm, idx, n, length, seconds, cap_requests):
     return out
 
 
+def run_subsequence(pm, total, length, nq):
+    """Subsequence search (Section 2.1): every window of `length` points of
+    one long series, indexed by messi_build_windows, raw values and
+    z-normalised windows; exact 1-NN ED of noisy window copies, one query
+    at a time."""
+    import torch
+    import synth
+
+    s = synth.ar1_series(total)
+    st = torch.from_numpy(s).cuda()
+    rng = np.random.default_rng(synth.SEED_MIX)
+    starts = rng.integers(0, total - length, nq + 3)
+    qs = np.stack([s[a:a + length] for a in starts])
+    qs += (0.1 * rng.standard_normal(qs.shape)).astype(np.float32)
+    qt = torch.from_numpy(qs).cuda()
+    out = {"workload": f"AR(1) series (phi 0.995, unit variance) of {total} points, every window "
+                       f"of {length} (stride 1); {nq} window copies + N(0, 0.1^2) noise, "
+                       "exact 1-NN ED one at a time", "modes": []}
+    for as_given in (True, False):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        idx = pm.messi_build_windows(st, length, 1, leaf_size=2000, raw=as_given)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        run_queries(pm, idx, qt[:3], 1, pm.MESSI_ED, 0)
+        wall, lat = run_queries(pm, idx, qt[3:], 1, pm.MESSI_ED, 0, budget_s=60)
+        k = len(lat)
+        stt = query_stats(pm, idx, qt[3:3 + k], 1, pm.MESSI_ED, 0)
+        row = {"raw": as_given, "windows": idx.n, "build_s": build_s, "queries_per_s": k / wall,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+               "refined_per_query": stt["refined"] / k, "leaves_kept_per_query": stt["leaves_kept"] / k}
+        out["modes"].append(row)
+        log(f"subsequence raw={as_given}: {idx.n} windows, build {build_s:.3f} s, "
+            f"{k / wall:.0f} q/s, refined {row['refined_per_query']:.0f}/query")
+        idx.free()
+    return out
+
+
 def cpu_baseline(n, length, queries, sample):
     """The oracle's brute-force scan on the host cores over the first
     `sample` series (regenerated on the host in chunks; only the scans are
@@ -376,6 +414,9 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=6.0,
                     help="length of each Poisson arrival stream of the serving run (0: skip)")
     ap.add_argument("--serve-capacity-requests", type=int, default=40)
+    ap.add_argument("--subseq-points", type=int, default=20_000_000,
+                    help="length of the long series of the subsequence run (0 = skip)")
+    ap.add_argument("--subseq-queries", type=int, default=100)
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
     ap.add_argument("--cpu-queries", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -488,6 +529,10 @@ def main():
     if args.serve_seconds > 0:
         serving = run_serving(pm, idx, n, length, args.serve_seconds, args.serve_capacity_requests)
 
+    subsequence = None
+    if args.subseq_points > 0:
+        subsequence = run_subsequence(pm, args.subseq_points, length, args.subseq_queries)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(n, length, qs[args.warmup:args.warmup + args.cpu_queries],
@@ -530,6 +575,7 @@ def main():
         "batched": batched,
         "classification": classification,
         "serving": serving,
+        "subsequence": subsequence,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

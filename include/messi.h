@@ -100,12 +100,35 @@ typedef struct messi_options {
                           allocated and unmodified until messi_free.  It
                           must be 16-byte aligned. */
   int32_t bf16_screen; /* 1: also make the BF16 copy used by MESSI_SCREEN_BF16 */
+  int32_t raw;         /* 1: index the series as given, without z-normalising
+                          them (the non-normalised search the paper's
+                          Section 1 names); queries on such an index are not normalised
+                          either.  Breakpoints, bounds and distances are
+                          unchanged.  Values must be finite with squared
+                          row norms below FP32's range. */
 } messi_options;
 
 /* messi_build with options (NULL = defaults).  With inplace, `series` is
  * overwritten with its z-normalised rows; otherwise it is only read. */
 int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int32_t cardinality,
                    int32_t leaf_size, const messi_options* opts, messi_index** out);
+
+/* Subsequence matching (Section 2.1; the sliding-window adaptation noted
+ * with the related work in Section 6): index every window of length `len`
+ * of one long device series.
+ *   series      device float32[total], the long series (only read).
+ *   total       its number of points, >= len.
+ *   stride      distance between window starts (1 = every window).
+ *   segments, cardinality, leaf_size, opts: as for messi_build_ex; opts->raw
+ *               selects raw windows (the usual setting of subsequence
+ *               search) or z-normalised ones; opts->inplace is ignored.
+ * The index materialises the (total - len) / stride + 1 windows in device
+ * memory it owns and frees in messi_free; id i of a query answer is the
+ * window starting at point i * stride.  Errors: MESSI_EINVAL on bad
+ * arguments, MESSI_ENOMEM if the windows or the index do not fit. */
+int messi_build_windows(const float* series, int64_t total, int32_t len, int32_t stride,
+                        int32_t segments, int32_t cardinality, int32_t leaf_size,
+                        const messi_options* opts, messi_index** out);
 
 /* Exact k-NN (Algorithms 5-10; k-NN per Section 5.4).
  *   queries    device pointer, float32 [nq][len] (raw; z-normalised here).

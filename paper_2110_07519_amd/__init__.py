@@ -5,7 +5,7 @@ the HIP kernels of libmessi.so behind the C ABI declared in
 include/messi.h.  Torch is used for device memory and streams.  If the
 library is not built, importing works but every call raises.
 
-Names follow the C ABI: messi_build, messi_build_ex, messi_query, messi_query_stats,
+Names follow the C ABI: messi_build, messi_build_ex, messi_build_windows, messi_query, messi_query_stats,
 messi_query_batch, messi_prepare_screen, messi_classify, messi_set_stream,
 messi_free, messi_breakpoints, messi_get_words,
 messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
@@ -34,7 +34,7 @@ EXPORTS = [
     "messi_get_words", "messi_get_perm", "messi_get_leaves", "messi_breakpoints", "messi_free",
     "messi_last_error", "messi_query_batch", "messi_prepare_screen",
     "messi_server_start", "messi_server_submit", "messi_server_poll", "messi_server_get_stats",
-    "messi_server_stop", "messi_classify", "messi_build_ex",
+    "messi_server_stop", "messi_classify", "messi_build_ex", "messi_build_windows",
 ]
 
 
@@ -92,6 +92,7 @@ def lib():
         P, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.messi_build.argtypes = [P, i64, i32, i32, i32, i32, ctypes.POINTER(P)]
         L.messi_build_ex.argtypes = [P, i64, i32, i32, i32, i32, P, ctypes.POINTER(P)]
+        L.messi_build_windows.argtypes = [P, i64, i32, i32, i32, i32, i32, P, ctypes.POINTER(P)]
         L.messi_query.argtypes = [P, P, i32, i32, i32, i32, P, P]
         L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
         L.messi_query_batch.argtypes = [P, P, i32, P, P, P, i32, i32, P, P, P]
@@ -112,7 +113,7 @@ def lib():
         L.messi_free.argtypes = [P]
         L.messi_free.restype = None
         L.messi_last_error.restype = ctypes.c_char_p
-        for name in ["messi_build", "messi_build_ex", "messi_query", "messi_query_stats", "messi_query_batch",
+        for name in ["messi_build", "messi_build_ex", "messi_build_windows", "messi_query", "messi_query_stats", "messi_query_batch",
                      "messi_prepare_screen", "messi_classify", "messi_server_start",
                      "messi_server_submit",
                      "messi_server_poll", "messi_server_get_stats", "messi_set_stream",
@@ -157,26 +158,46 @@ def messi_build(series, segments: int = 16, cardinality: int = 256, leaf_size: i
 
 
 class MessiOptions(ctypes.Structure):
-    _fields_ = [("inplace", ctypes.c_int32), ("bf16_screen", ctypes.c_int32)]
+    _fields_ = [("inplace", ctypes.c_int32), ("bf16_screen", ctypes.c_int32),
+                ("raw", ctypes.c_int32)]
 
 
 def messi_build_ex(series, segments: int = 16, cardinality: int = 256, leaf_size: int = 2000,
-                   inplace: bool = False, bf16_screen: bool = False):
+                   inplace: bool = False, bf16_screen: bool = False, raw: bool = False):
     """messi_build with options.  inplace: `series` (float32 CUDA [n, len]) is
     z-normalised in place and becomes the store; keep it alive and unmodified
-    while the index lives (the returned Index holds a reference)."""
+    while the index lives (the returned Index holds a reference).  raw: the
+    series (and later the queries) are used as given, not z-normalised."""
     import torch
 
     assert series.dtype == torch.float32 and series.dim() == 2
     n, length = series.shape
     h = ctypes.c_void_p()
-    o = MessiOptions(int(inplace), int(bf16_screen))
+    o = MessiOptions(int(inplace), int(bf16_screen), int(raw))
     _check(lib().messi_build_ex(_dev_ptr(series), n, length, segments, cardinality, leaf_size,
                                 ctypes.cast(ctypes.pointer(o), ctypes.c_void_p), ctypes.byref(h)))
     idx = Index(h, n, length, segments)
     if inplace:
         idx.store = series
     return idx
+
+
+def messi_build_windows(series, length: int, stride: int = 1, segments: int = 16,
+                        cardinality: int = 256, leaf_size: int = 2000, raw: bool = True,
+                        bf16_screen: bool = False):
+    """Index every window of `length` points (window starts `stride` apart)
+    of one long float32 CUDA series [total]; id i of an answer is the window
+    starting at i * stride.  raw (the default here): windows as given."""
+    import torch
+
+    assert series.dtype == torch.float32 and series.dim() == 1 and series.is_contiguous()
+    total = series.shape[0]
+    h = ctypes.c_void_p()
+    o = MessiOptions(1, int(bf16_screen), int(raw))
+    _check(lib().messi_build_windows(_dev_ptr(series), total, length, stride, segments, cardinality,
+                                     leaf_size, ctypes.cast(ctypes.pointer(o), ctypes.c_void_p),
+                                     ctypes.byref(h)))
+    return Index(h, (total - length) // stride + 1, length, segments)
 
 
 def messi_query(index, queries, k: int = 1, distance: int = MESSI_ED, window: int = 0,

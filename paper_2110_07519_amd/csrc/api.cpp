@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstring>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -200,6 +201,9 @@ struct messi_index {
   int4* tree = nullptr;
   int* root_node = nullptr;
   bool inplace = false;      // Z is the caller's buffer, normalised in place, rows in id order
+  bool raw = false;          // series indexed as given, without z-normalisation
+  float xnorm = 0.0f;        // largest 2-norm of a stored row, rounded up
+  DevMem own;                // rows the index materialised itself (sliding windows)
   int* shard_off = nullptr;  // [kShards + 1] first chunk of each shard
   int64_t n_chunks = 0;
   uint4* sh_sym = nullptr;   // leaf table in shard-major order
@@ -296,8 +300,25 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   int dev = 0;
   HIP_OR_THROW(hipGetDevice(&dev));
   HIP_OR_THROW(hipDeviceGetAttribute(&ix->n_cus, hipDeviceAttributeMultiprocessorCount, dev));
-  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, st, ix->n_cus);
+  unsigned int* norm2 = nullptr;  // raw: largest squared row norm (FP32 bits)
+  if (ix->raw) {
+    norm2 = tmp.alloc<unsigned int>(1);
+    HIP_OR_THROW(hipMemsetAsync(norm2, 0, sizeof(unsigned int), st));
+  }
+  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, norm2, st, ix->n_cus);
   launch_check();
+  {
+    // z-normalised rows have |z|^2 = len up to a relative len u; a raw
+    // row's squared norm is an FP32 sum of len squares, off by at most the
+    // same factor.  2^-10 covers both for len <= 4096.
+    float n2 = (float)len;
+    if (ix->raw) {
+      unsigned int bits = 0;
+      d2h(&bits, norm2, 1, st);
+      std::memcpy(&n2, &bits, sizeof(n2));
+    }
+    ix->xnorm = (float)(std::sqrt((double)n2) * (1.0 + std::ldexp(1.0, -10)));
+  }
 
   // (2) root grouping
   int64_t* key_begin = tmp.alloc<int64_t>(nkeys + 1);
@@ -410,7 +431,8 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   ix->words = ix->mem.alloc<uint4>(n);
   if (ix->inplace) {
     ix->Z = const_cast<float*>(series);
-    launch_store_inplace(const_cast<float*>(series), n, len, ix->perm, musd, words_id, ix->words, st);
+    launch_store_inplace(const_cast<float*>(series), n, len, ix->perm, musd, words_id, ix->words,
+                         ix->raw ? 1 : 0, st);
   } else {
     ix->Z = ix->mem.alloc<float>((size_t)n * len);
     launch_gather_store(series, n, len, ix->perm, musd, words_id, ix->Z, ix->words, st);
@@ -475,6 +497,7 @@ void ensure_workspace(messi_index* ix, QueryCtx& c, int nq, int k) {
   QueryState& s = ws.qs;
   const int len = ix->len, L = ix->n_leaves;
   s.zq = ws.mem.alloc<float>((size_t)NQ * len);
+  s.eta = ws.mem.alloc<float>(NQ);
   s.upper = ws.mem.alloc<float>((size_t)NQ * len);
   s.lower = ws.mem.alloc<float>((size_t)NQ * len);
   s.paa = ws.mem.alloc<float>((size_t)NQ * 3 * kMaxSeg);
@@ -559,9 +582,20 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   const double rho = (4.0 * len + 64.0) * u;
   p.win = std::nextafter((float)((1.0 + rho) / (1.0 - rho) * (1.0 + std::ldexp(1.0, -20))), INFINITY);
   p.lb_rel = std::nextafter((float)((1.0 + rho) * (1.0 + std::ldexp(1.0, -16))), INFINITY);
-  // PAA rounding: |PAA_fp32 - mean| <= 2 u sqrt(m len); the bound's error is
-  // at most 4 u len sqrt(m) (series side plus query side), 8x margin here.
-  p.eta = (float)(32.0 * u * len * std::sqrt((double)p.m));
+  // PAA rounding: a segment mean of a row v is off by at most
+  // 2 u sqrt(m) |v|, so a bound moves by at most 2 u sqrt(len m) (|x| + |q|)
+  // (series side plus query side); eta_c carries an 8x margin and k_prep
+  // completes eta with the query's own norm.
+  p.eta_c = (float)(16.0 * u * std::sqrt((double)len * p.m));
+  p.xnorm = ix->xnorm;
+  p.raw = ix->raw ? 1 : 0;
+  // bucket range [2^-16, 2^16) against bounds up to (2 |x|max)^2: a raw
+  // index scales them so that the largest possible bound lands near 2^16
+  p.lb_scale = 1.0f;
+  if (ix->raw && ix->xnorm > 0.0f) {
+    const int e = (int)std::ceil(std::log2(4.0 * (double)ix->xnorm * ix->xnorm));
+    p.lb_scale = (float)std::ldexp(1.0, std::max(-100, std::min(100, 16 - e)));
+  }
   int fin_waves = 0;
   if (distance == MESSI_DTW) {
     fin_waves = 1;
@@ -952,6 +986,7 @@ int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int3
     return fail(MESSI_EINVAL, "an in-place series buffer must be 16-byte aligned");
   messi_index* ix = new messi_index();
   ix->inplace = o.inplace != 0;
+  ix->raw = o.raw != 0;
   ix->n = n;
   ix->len = len;
   ix->w = segments;
@@ -998,6 +1033,41 @@ int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int3
     }
   }
   *out = ix;
+  return MESSI_OK;
+}
+
+int messi_build_windows(const float* series, int64_t total, int32_t len, int32_t stride,
+                        int32_t segments, int32_t cardinality, int32_t leaf_size,
+                        const messi_options* opts, messi_index** out) {
+  g_err.clear();
+  if (!out) return fail(MESSI_EINVAL, "out is NULL");
+  if (len < 1 || stride < 1 || total < len)
+    return fail(MESSI_EINVAL, "need len >= 1, stride >= 1 and total >= len");
+  if (!is_device_ptr(series)) return fail(MESSI_EINVAL, "series is not a device pointer");
+  const int64_t n = (total - len) / stride + 1;
+  if (n >= ((int64_t)1 << 31) - 1) return fail(MESSI_EINVAL, "more than 2^31-2 windows");
+  if (len > kMaxLen || segments < 1 || len % segments)
+    return fail(MESSI_EINVAL, "len must be in [1, %d] and a multiple of segments", kMaxLen);
+  messi_options o{};
+  if (opts) o = *opts;
+  o.inplace = 1;  // the window rows are the index's own store
+  DevMem rows_mem;
+  float* rows = nullptr;
+  try {
+    rows = rows_mem.alloc<float>((size_t)n * len);
+    launch_windows(series, n, len, stride, rows, nullptr);
+    launch_check();
+    HIP_OR_THROW(hipStreamSynchronize(nullptr));
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+  const int rc = messi_build_ex(rows, n, len, segments, cardinality, leaf_size, &o, out);
+  if (rc != MESSI_OK) return rc;  // rows_mem frees the windows
+  std::swap((*out)->own.ptrs, rows_mem.ptrs);
+  (*out)->own.bytes = rows_mem.bytes;
+  rows_mem.bytes = 0;
   return MESSI_OK;
 }
 
@@ -1130,7 +1200,7 @@ int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t
   if (card_bits) *card_bits = index->card_bits;
   if (n_leaves) *n_leaves = index->n_leaves;
   if (device_bytes)
-    *device_bytes = (int64_t)(index->mem.bytes + index->ctx.ws.mem.bytes +
+    *device_bytes = (int64_t)(index->mem.bytes + index->own.bytes + index->ctx.ws.mem.bytes +
                               index->screen_mem.bytes + index->ctx.batch_mem.bytes);
   return MESSI_OK;
 }

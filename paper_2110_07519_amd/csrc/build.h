@@ -54,7 +54,7 @@ struct BuildDev {
 
 void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
                       const float* bp, uint4* words, float2* musd, unsigned int* hist,
-                      hipStream_t st, int n_cus);
+                      unsigned int* norm2_max, hipStream_t st, int n_cus);
 void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
                       unsigned long long* cursor, hipStream_t st);
 void launch_root_scatter(const uint4* words, int64_t n, int w, int card_bits,
@@ -77,8 +77,9 @@ void launch_leaf_sort(int n_leaves, const int64_t* leaf_begin, const int64_t* le
 void launch_leaf_sort_global(int64_t b, int cnt, int p2, const int32_t* I, int32_t* scratch,
                              int32_t* perm, hipStream_t st);
 void launch_make_tree(const NodeDev* nodes, int n_nodes, int card_bits, int4* tree, hipStream_t st);
+void launch_windows(const float* series, int64_t n, int len, int stride, float* rows, hipStream_t st);
 void launch_store_inplace(float* raw, int64_t n, int len, const int32_t* perm, const float2* musd,
-                          const uint4* words, uint4* words_sorted, hipStream_t st);
+                          const uint4* words, uint4* words_sorted, int raw_mode, hipStream_t st);
 void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* perm,
                          const float2* musd, const uint4* words, float* Z, uint4* words_sorted,
                          hipStream_t st);

@@ -29,7 +29,8 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
                                                       const float* __restrict__ bp_g,
                                                       uint4* __restrict__ words,
                                                       float2* __restrict__ musd,
-                                                      unsigned int* __restrict__ hist) {
+                                                      unsigned int* __restrict__ hist,
+                                                      unsigned int* __restrict__ norm2_max) {
   extern __shared__ float smem[];
   float* bp = smem;               // card + 1 entries (bp[0] = -inf, bp[card] = +inf)
   float* tile = smem + 257;       // spw rows of len floats, rotated
@@ -60,16 +61,23 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
     c = c >= len ? c - len : c;
     return row[c];
   };
-  float s = 0.0f;
-  for (int t = 0; t < len; ++t) s = s + at(t);
+  // as given (norm2_max set): mu = 0 and sd = 1, so z = x exactly, and v is
+  // the squared norm of the row
+  const bool as_given = norm2_max != nullptr;
   const float flen = (float)len;
-  const float mu = __fdiv_rn(s, flen);
+  float mu = 0.0f;
+  if (!as_given) {
+    float s = 0.0f;
+    for (int t = 0; t < len; ++t) s = s + at(t);
+    mu = __fdiv_rn(s, flen);
+  }
   float v = 0.0f;
   for (int t = 0; t < len; ++t) {
     const float d = at(t) - mu;
     v = v + d * d;
   }
-  const float sd = sqrtf(__fdiv_rn(v, flen));
+  const float sd = as_given ? 1.0f : sqrtf(__fdiv_rn(v, flen));
+  if (as_given) atomicMax(norm2_max, __float_as_uint(v));
   const bool flat = !(sd > 0.0f);
   const int m = len / w;
   const float fm = (float)m;
@@ -143,7 +151,8 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
                                                      int card_bits, const float* __restrict__ bp_g,
                                                      uint8_t* __restrict__ words,
                                                      float2* __restrict__ musd,
-                                                     unsigned int* __restrict__ hist) {
+                                                     unsigned int* __restrict__ hist,
+                                                     unsigned int* __restrict__ norm2_max) {
   __shared__ float bp[257];
   const int card = 1 << card_bits;
   for (int j = threadIdx.x; j <= card; j += blockDim.x) bp[j] = bp_g[j];
@@ -154,6 +163,8 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   const float flen = (float)len;
   const float fm = (float)C;
+  const bool as_given = norm2_max != nullptr;  // mu = 0, sd = 1: z = x exactly
+  float n2 = 0.0f;  // largest squared row norm seen (as-given rows)
   for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); grp * 4 < n;
        grp += waves) {
     const int64_t id = grp * 4 + (lane >> 4);
@@ -173,14 +184,16 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
 #pragma unroll
       for (int i = 0; i < C; ++i) v[i] = 0.0f;
     }
-    const float mu = __fdiv_rn(chain_sum16<C>(v, g), flen);
+    const float mu = as_given ? 0.0f : __fdiv_rn(chain_sum16<C>(v, g), flen);
     float sq[C];
 #pragma unroll
     for (int i = 0; i < C; ++i) {
       const float d = v[i] - mu;
       sq[i] = d * d;
     }
-    const float sd = sqrtf(__fdiv_rn(chain_sum16<C>(sq, g), flen));
+    const float ss = chain_sum16<C>(sq, g);
+    if (valid) n2 = fmaxf(n2, ss);
+    const float sd = as_given ? 1.0f : sqrtf(__fdiv_rn(ss, flen));
     const bool flat = !(sd > 0.0f);
     float a = 0.0f;
     if (!flat) {
@@ -206,6 +219,10 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
         atomicAdd(&hist[key], 1u);
       }
     }
+  }
+  if (as_given) {  // one atomic per wave
+    for (int o = 32; o >= 1; o >>= 1) n2 = fmaxf(n2, __shfl_xor(n2, o));
+    if (lane == 0) atomicMax(norm2_max, __float_as_uint(n2));
   }
 }
 
@@ -630,13 +647,14 @@ __global__ __launch_bounds__(256) void k_store_inplace(float* __restrict__ raw, 
                                                         const int32_t* __restrict__ perm,
                                                         const float2* __restrict__ musd,
                                                         const uint4* __restrict__ words,
-                                                        uint4* __restrict__ words_sorted) {
+                                                        uint4* __restrict__ words_sorted, int as_given) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t p = wave; p < n; p += nwaves) {
     const int32_t id = perm[p];
     if (lane == 0) words_sorted[p] = words[id];
+    if (as_given) continue;  // the rows already are what the index holds
     const float2 ms = musd[id];
     float* __restrict__ x = raw + (int64_t)id * len;
     const bool flat = !(ms.y > 0.0f);
@@ -676,7 +694,7 @@ __global__ void k_make_tree(const NodeDev* __restrict__ nodes, int n_nodes, int 
 
 void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
                       const float* bp, uint4* words, float2* musd, unsigned int* hist,
-                      hipStream_t st, int n_cus) {
+                      unsigned int* norm2_max, hipStream_t st, int n_cus) {
   // the register path reads float4s: the rows must start 16-byte aligned
   if (w == 16 && len % 64 == 0 && len <= 256 && (reinterpret_cast<uintptr_t>(raw) & 15) == 0) {
     const int64_t groups = (n + 3) / 4;  // 4 series per wave, 4 waves per block
@@ -684,17 +702,17 @@ void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits
     const unsigned blocks = (unsigned)std::min<int64_t>(want, (int64_t)n_cus * 32);
     uint8_t* wb = reinterpret_cast<uint8_t*>(words);
     switch (len / 16) {
-      case 4: hipLaunchKernelGGL(k_summarize16<4>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
-      case 8: hipLaunchKernelGGL(k_summarize16<8>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
-      case 12: hipLaunchKernelGGL(k_summarize16<12>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
-      default: hipLaunchKernelGGL(k_summarize16<16>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist); break;
+      case 4: hipLaunchKernelGGL(k_summarize16<4>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
+      case 8: hipLaunchKernelGGL(k_summarize16<8>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
+      case 12: hipLaunchKernelGGL(k_summarize16<12>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
+      default: hipLaunchKernelGGL(k_summarize16<16>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
     }
     return;
   }
   const int64_t blocks = (n + spw - 1) / spw;
   const size_t lds = (257 + (size_t)spw * len) * sizeof(float);
   hipLaunchKernelGGL(k_summarize, dim3((unsigned)blocks), dim3(kWave), lds, st, raw, n, len, w,
-                     card_bits, spw, bp, words, musd, hist);
+                     card_bits, spw, bp, words, musd, hist, norm2_max);
 }
 
 void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
@@ -769,11 +787,31 @@ void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* pe
                      musd, words, Z, words_sorted);
 }
 
+// Sliding windows of a long series: row i holds points [i stride, i stride
+// + len).  Consecutive threads write consecutive floats of a row and read
+// consecutive points of the series.
+__global__ __launch_bounds__(256) void k_windows(const float* __restrict__ series, int64_t n, int len,
+                                                  int stride, float* __restrict__ rows) {
+  const int64_t total = n * (int64_t)len;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / len;
+    const int t = (int)(e - i * len);
+    rows[e] = series[i * stride + t];
+  }
+}
+
+void launch_windows(const float* series, int64_t n, int len, int stride, float* rows, hipStream_t st) {
+  const int64_t want = (n * (int64_t)len + 255) / 256;
+  const unsigned blocks = (unsigned)std::min<int64_t>(want, 65536);
+  hipLaunchKernelGGL(k_windows, dim3(blocks), dim3(256), 0, st, series, n, len, stride, rows);
+}
+
 void launch_store_inplace(float* raw, int64_t n, int len, const int32_t* perm, const float2* musd,
-                          const uint4* words, uint4* words_sorted, hipStream_t st) {
+                          const uint4* words, uint4* words_sorted, int raw_mode, hipStream_t st) {
   const int64_t blocks = std::min<int64_t>((n + 3) / 4, 65536);
   hipLaunchKernelGGL(k_store_inplace, dim3((unsigned)blocks), dim3(256), 0, st, raw, n, len, perm, musd,
-                     words, words_sorted);
+                     words, words_sorted, raw_mode);
 }
 
 }  // namespace messi

@@ -39,7 +39,10 @@ struct QueryParams {
   int64_t n;
   float win;         // near-tie window factor (1+rho)/(1-rho), rounded up
   float lb_rel;      // (1+rho)(1+2^-16): relative slack on the k-th best
-  float eta;         // absolute slack (distance units) of PAA-based bounds
+  float eta_c;       // PAA-bound slack per unit of series norm (k_prep turns it into eta[q])
+  float xnorm;       // largest 2-norm of an indexed series, rounded up
+  float lb_scale;    // power of two that brings bounds into the bucket range
+  int raw;           // 1: the index holds series as given (no z-normalisation)
   int log_cap;       // near-tie log entries per query
   int fin_waves;     // waves used by the FP64 DTW recheck
   int item_cap;      // leaf chunks per query (all shards)
@@ -50,7 +53,8 @@ struct QueryParams {
 
 // Per-query device state, one entry per query (all arrays sized by nq).
 struct QueryState {
-  float* zq;                  // [nq][len]   z-normalised query
+  float* zq;                  // [nq][len]   query as the index sees it (z-normalised unless raw)
+  float* eta;                 // [nq] absolute slack (distance units) of the PAA-based bounds
   float* upper;               // [nq][len]   LB_Keogh envelope (DTW)
   float* lower;               // [nq][len]
   float* paa;                 // [nq][3][16] query PAA, envelope PAA upper, lower

@@ -43,15 +43,16 @@ __device__ __forceinline__ float kth_dist(const unsigned long long* slots, int k
 
 // Bound threshold: a series whose bound exceeds it cannot be among the k
 // best.  (sqrt(kth (1+rho)) + eta)^2, with a last relative margin for the
-// rounding of this expression itself.
-__device__ __forceinline__ float lb_threshold(float thr, const QueryParams& p) {
+// rounding of this expression itself; eta is the query's own slack.
+__device__ __forceinline__ float lb_threshold(float thr, float eta, const QueryParams& p) {
   if (!(thr < INFINITY)) return INFINITY;
-  const float r = sqrtf(thr * p.lb_rel) + p.eta;
+  const float r = sqrtf(thr * p.lb_rel) + eta;
   return r * r * 1.0001f;
 }
 
 // Logarithmic bound buckets: exponent and top 6 mantissa bits of the FP32
-// bound, over [2^-16, 2^16); monotone in the bound.
+// bound, over [2^-16, 2^16); monotone in the bound.  Callers pass the bound
+// times p.lb_scale (a power of two, so the product is exact).
 constexpr int kBucketBase = (127 - 16) << 6;
 __device__ __forceinline__ int lb_bucket(float lb) {
   const int b = (int)(__float_as_uint(lb) >> 17) - kBucketBase;
@@ -295,7 +296,12 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
   for (int t = tid; t < len; t += blockDim.x) x[t] = src[t];
   for (int j = tid; j <= card; j += blockDim.x) bp[j] = ix.bp[j];
   __syncthreads();
-  if (tid == 0) {  // same order and rounding as the build's summary pass
+  if (p.raw) {  // series are indexed as given: z = x exactly below
+    if (tid == 0) {
+      s_mu = 0.0f;
+      s_sd = 1.0f;
+    }
+  } else if (tid == 0) {  // same order and rounding as the build's summary pass
     // (values read 16 at a time so the LDS reads overlap the add chain)
     float sum = 0.0f;
     int t = 0;
@@ -352,6 +358,39 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
       s.lower[(int64_t)q * len + t] = l;
     }
     __syncthreads();
+  }
+  {
+    // Slack of the PAA-based bounds.  A segment mean computed in FP32 is off
+    // by at most 2 u sqrt(m) |v| for a row v, so a bound sqrt(m sum gap^2)
+    // moves by at most 2 u sqrt(len m) (|x| + |q'|), with q' the largest of
+    // the query and its envelope rows; eta_c carries an 8x margin on that.
+    __shared__ float red[3][256 / kWave];
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+    for (int t = tid; t < len; t += blockDim.x) {
+      a0 += z[t] * z[t];
+      if (p.distance == 1) {
+        a1 += U[t] * U[t];
+        a2 += L[t] * L[t];
+      }
+    }
+    a0 = wave_sum(a0);
+    a1 = wave_sum(a1);
+    a2 = wave_sum(a2);
+    if ((tid & (kWave - 1)) == 0) {
+      red[0][tid / kWave] = a0;
+      red[1][tid / kWave] = a1;
+      red[2][tid / kWave] = a2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      float n2 = 0.0f;
+      for (int j = 0; j < 3; ++j) {
+        float t2 = 0.0f;
+        for (int v = 0; v < (int)(blockDim.x / kWave); ++v) t2 += red[j][v];
+        n2 = fmaxf(n2, t2);
+      }
+      s.eta[q] = p.eta_c * (p.xnorm + sqrtf(n2) * 1.001f);
+    }
   }
   if (tid < w) {
     const float fm = (float)m;
@@ -546,7 +585,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
             const float lb = leaf_bound(sy[u], bi[u]);
             lbq[sh + (jb + u * bs) * kShards] = lb;
             if (p.order_leaves)
-              atomicAdd(&cnt[lb_bucket(lb)], (rg[u].y - rg[u].x + kChunkSeries - 1) / kChunkSeries);
+              atomicAdd(&cnt[lb_bucket(lb * p.lb_scale)], (rg[u].y - rg[u].x + kChunkSeries - 1) / kChunkSeries);
           }
       }
     }
@@ -592,7 +631,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
         if (jb + u * bs >= nl) continue;
         const float lb = leaf_bound(sy[u], bi[u]);  // the same value as in the count pass
         const int nc = (rg[u].y - rg[u].x + kChunkSeries - 1) / kChunkSeries;
-        const int at = atomicAdd(&cnt[lb_bucket(lb)], nc);
+        const int at = atomicAdd(&cnt[lb_bucket(lb * p.lb_scale)], nc);
         const unsigned long long it = ((unsigned long long)__float_as_uint(lb) << 32) |
                                       (unsigned)(shard + (jb + u * bs) * kShards);
         for (int c = 0; c < nc; ++c) {
@@ -764,6 +803,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   __syncthreads();
 
   const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
+  const float eta = s.eta[q];
   const unsigned long long* items = s.items + (int64_t)q * p.item_cap;
   const int2* ranges = s.ranges + (int64_t)q * p.item_cap;
 
@@ -830,7 +870,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       have_next = true;
     }
     unsigned long long ckey = s_ckey;
-    const float tadj = lb_threshold(key_dist(ckey), p);
+    const float tadj = lb_threshold(key_dist(ckey), eta, p);
     // one chunk per wave, consecutive in the shard's bound order
     const int i = ix.shard_off[shard] + s_batch * kW + wv;
     bool take = false;
@@ -840,7 +880,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       rg = ranges[i];
       const float lb = key_dist(item);
       take = lb <= tadj;
-      if (!take && bucket_floor(lb_bucket(lb)) > tadj && lane == 0) {  // all later chunks above too
+      if (!take && bucket_floor(lb_bucket(lb * p.lb_scale)) > tadj * p.lb_scale && lane == 0) {  // all later chunks above too
         atomicOr(finished, 1ull << shard);
         s_shard_done = 1;
       }
@@ -905,7 +945,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
     // against the latest k-th best this wave knows
     const int ns = s_nsurv;
     for (int g = wv * kGroup; g < ns; g += kW * kGroup) {
-      const float tcur = lb_threshold(key_dist(ckey), p);
+      const float tcur = lb_threshold(key_dist(ckey), eta, p);
       int gp[kGroup];
       unsigned act = 0;
 #pragma unroll
@@ -1239,7 +1279,8 @@ __global__ __launch_bounds__(256) void k_leaf_lists(QueryParams p, QueryState s,
   for (int q0 = 0; q0 < p.nq; q0 += 256) {
     __syncthreads();
     const int q = q0 + (int)threadIdx.x;
-    if (q < p.nq) thr[threadIdx.x] = lb_threshold(kth_dist(s.slots + (int64_t)q * p.k, k_of(p, s, q)), p);
+    if (q < p.nq)
+      thr[threadIdx.x] = lb_threshold(kth_dist(s.slots + (int64_t)q * p.k, k_of(p, s, q)), s.eta[q], p);
     __syncthreads();
     const int nn = min(256, p.nq - q0);
     if (l < p.n_leaves) {

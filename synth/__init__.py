@@ -150,6 +150,20 @@ def normals(count, seed=7, stream=0):
     return out
 
 
+def ar1_series(total, phi=0.995, seed=SEED_DATA, stream=11):
+    """One long stationary series x_t = phi x_{t-1} + sqrt(1 - phi^2) e_t with
+    e_t ~ N(0, 1) (x_0 = e_0): unit variance, locally like a random walk.
+    The long input of subsequence search over values taken as they are."""
+    from scipy.signal import lfilter
+
+    e = normals(total, seed=seed, stream=stream)
+    x = np.empty(total, dtype=np.float64)
+    x[0] = e[0]
+    if total > 1:  # the recursion as a one-pole filter started from x_0
+        x[1:] = lfilter([np.sqrt(1.0 - phi * phi)], [1.0, -phi], e[1:], zi=[phi * e[0]])[0]
+    return x.astype(np.float32)
+
+
 def uniforms(count, seed=7, stream=0):
     out = np.empty(count, dtype=np.float64)
     host().synth_host_uniforms(seed, stream, count, _p(out))

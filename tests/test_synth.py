@@ -57,3 +57,14 @@ def test_noisy_queries_recipe():
         x = base[src[j]].astype(np.float64)
         noise = q[j].astype(np.float64) - x
         assert abs(noise.std() / x.std() - sig[j]) < 0.35 * sig[j]
+
+
+def test_ar1_series_follows_its_recursion():
+    x = synth.ar1_series(5000, phi=0.99)
+    e = synth.normals(5000, seed=synth.SEED_DATA, stream=11)
+    y = np.empty(5000)
+    y[0] = e[0]
+    for t in range(1, 5000):
+        y[t] = 0.99 * y[t - 1] + np.sqrt(1.0 - 0.99 * 0.99) * e[t]
+    assert np.allclose(x, y.astype(np.float32), rtol=1e-5, atol=1e-5)
+    assert np.array_equal(x, synth.ar1_series(5000, phi=0.99))  # seeded
