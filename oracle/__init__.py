@@ -98,6 +98,9 @@ def lib():
         L.oracle_mindist2_dtw.restype = f64
         L.oracle_knn_scan.argtypes = [P, i64, i64, i32, P, i32, i32, i32, i32, P, P]
         L.oracle_knn_scan_lbk.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P]
+        L.oracle_knn_scan_lbi.argtypes = [P, i64, i64, i32, P, i32, i32, i32, P, P]
+        L.oracle_lb_improved2.argtypes = [P, P, P, P, i32, i32]
+        L.oracle_lb_improved2.restype = f64
         L.oracle_knn_vote.argtypes = [P, i32, i32, P, i32, P]
         L.oracle_index_search.argtypes = [P, i64, i32, i32, i32, P, P, P, i64, P, i32, i32, i32,
                                           P, P, P]
@@ -220,6 +223,11 @@ def lb_keogh2(U, L, x):
     return lib().oracle_lb_keogh2(_p(U), _p(L), _p(x), x.shape[-1])
 
 
+def lb_improved2(q, U, L, x, r):
+    q, U, L, x = _f32(q), _f32(U), _f32(L), _f32(x)
+    return lib().oracle_lb_improved2(_p(q), _p(U), _p(L), _p(x), x.shape[-1], int(r))
+
+
 def mindist2_ed(qpaa, sym, bits, beta, length, card_bits=8):
     qpaa, beta = _f32(qpaa), _f32(beta)
     sym = np.ascontiguousarray(sym, dtype=np.uint8)
@@ -239,10 +247,12 @@ def mindist2_dtw(upaa, lpaa, sym, bits, beta, length, card_bits=8):
 class KnnState:
     """Running brute-force k-NN over a collection fed in chunks."""
 
-    def __init__(self, raw_queries, k, distance=ED, r=0, lb_keogh=False):
-        """lb_keogh: for DTW, skip pairs by LB_Keogh against the running
-        k-th best (same lists, fewer DTW evaluations)."""
+    def __init__(self, raw_queries, k, distance=ED, r=0, lb_keogh=False, lb_improved=False):
+        """lb_keogh / lb_improved: for DTW, skip pairs by LB_Keogh or by
+        LB_Improved against the running k-th best (same lists, fewer DTW
+        evaluations)."""
         self.lb_keogh = bool(lb_keogh) and int(distance) == DTW
+        self.lb_improved = bool(lb_improved) and int(distance) == DTW
         self.q = _f32(raw_queries)
         self.nq, self.len = self.q.shape
         self.k, self.distance, self.r = int(k), int(distance), int(r)
@@ -251,6 +261,11 @@ class KnnState:
 
     def scan(self, raw_chunk, id0):
         raw_chunk = _f32(raw_chunk)
+        if self.lb_improved:
+            lib().oracle_knn_scan_lbi(_p(raw_chunk), int(id0), raw_chunk.shape[0], self.len,
+                                      _p(self.q), self.nq, self.k, self.r, _p(self.ids),
+                                      _p(self.d2))
+            return self
         if self.lb_keogh:
             lib().oracle_knn_scan_lbk(_p(raw_chunk), int(id0), raw_chunk.shape[0], self.len,
                                       _p(self.q), self.nq, self.k, self.r, _p(self.ids),

@@ -429,6 +429,29 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
   free(zq);
 }
 
+/* LB_Improved (Lemire, Pattern Recognition 42(9), 2009), the tighter DTW
+ * bound Section 3.4 names beside LB_Keogh: LB_Keogh of x against the
+ * query's envelope, plus LB_Keogh of the query against the envelope (same
+ * radius r) of h, where h is x clamped into the query's envelope. */
+double oracle_lb_improved2(const float* q, const float* upper, const float* lower, const float* x,
+                           int32_t len, int32_t r) {
+  float* h = (float*)malloc(sizeof(float) * (size_t)len);
+  float* hu = (float*)malloc(sizeof(float) * (size_t)len);
+  float* hl = (float*)malloc(sizeof(float) * (size_t)len);
+  for (int32_t t = 0; t < len; ++t)
+    h[t] = x[t] > upper[t] ? upper[t] : (x[t] < lower[t] ? lower[t] : x[t]);
+  oracle_envelope(h, len, r, hu, hl);
+  const double v = oracle_lb_keogh2(upper, lower, x, len) + oracle_lb_keogh2(hu, hl, q, len);
+  free(h);
+  free(hu);
+  free(hl);
+  return v;
+}
+
+static void knn_scan_filtered(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
+                              const float* raw_queries, int32_t nq, int32_t k, int32_t r,
+                              int32_t improved, int64_t* ids, double* d2);
+
 /* Brute-force DTW k-NN with the LB_Keogh filter (Section 3.4): a pair is
  * skipped only when its LB_Keogh exceeds the running k-th best by more than
  * FP64 rounding of two length-len sums can explain (relative 1e-12), so the
@@ -438,6 +461,19 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
 void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
                          const float* raw_queries, int32_t nq, int32_t k, int32_t r,
                          int64_t* ids, double* d2) {
+  knn_scan_filtered(raw_chunk, id0, count, len, raw_queries, nq, k, r, 0, ids, d2);
+}
+
+/* The same scan filtered by LB_Improved instead of LB_Keogh. */
+void oracle_knn_scan_lbi(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
+                         const float* raw_queries, int32_t nq, int32_t k, int32_t r,
+                         int64_t* ids, double* d2) {
+  knn_scan_filtered(raw_chunk, id0, count, len, raw_queries, nq, k, r, 1, ids, d2);
+}
+
+static void knn_scan_filtered(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
+                              const float* raw_queries, int32_t nq, int32_t k, int32_t r,
+                              int32_t improved, int64_t* ids, double* d2) {
   float* zq = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
   float* up = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
   float* lo = (float*)malloc(sizeof(float) * (size_t)nq * (size_t)len);
@@ -462,7 +498,10 @@ void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int
       for (int32_t j = 0; j < nq; ++j) {
         const double own = ld[(int64_t)j * k + k - 1];
         const double kth = own < bound[j] ? own : bound[j];
-        const double lb = oracle_lb_keogh2(up + (int64_t)j * len, lo + (int64_t)j * len, z, len);
+        const float* qj = zq + (int64_t)j * len;
+        const double lb = improved
+                              ? oracle_lb_improved2(qj, up + (int64_t)j * len, lo + (int64_t)j * len, z, len, r)
+                              : oracle_lb_keogh2(up + (int64_t)j * len, lo + (int64_t)j * len, z, len);
         if (lb > kth * (1.0 + 1e-12)) continue;
         const double d = oracle_dtw2(zq + (int64_t)j * len, z, len, r);
         knn_insert(lid + (int64_t)j * k, ld + (int64_t)j * k, k, d, id0 + i);

@@ -89,6 +89,11 @@ double oracle_dtw2(const float* q, const float* x, int32_t len, int32_t r);
 /* LB_Keogh envelope (Section 3.4) with radius r, clipped to the series. */
 void oracle_envelope(const float* q, int32_t len, int32_t r, float* upper, float* lower);
 double oracle_lb_keogh2(const float* upper, const float* lower, const float* x, int32_t len);
+/* LB_Improved (Lemire 2009; named in Section 3.4): LB_Keogh of x plus
+ * LB_Keogh of q against the radius-r envelope of x clamped into [lower,
+ * upper].  Squared, like the DTW here. */
+double oracle_lb_improved2(const float* q, const float* upper, const float* lower, const float* x,
+                           int32_t len, int32_t r);
 
 /* mindist_PAA_iSAX, squared: (len / w) * sum over segments of the squared
  * gap between the query PAA and the box of the node's symbol at its bits.
@@ -110,6 +115,10 @@ void oracle_knn_scan(const float* raw_chunk, int64_t id0, int64_t count, int32_t
 /* The same lists for DTW, with LB_Keogh (Section 3.4) skipping pairs whose
  * bound exceeds the running k-th best beyond FP64 rounding. */
 void oracle_knn_scan_lbk(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
+                         const float* raw_queries, int32_t nq, int32_t k, int32_t r,
+                         int64_t* ids, double* d2);
+/* The same scan with the LB_Improved filter. */
+void oracle_knn_scan_lbi(const float* raw_chunk, int64_t id0, int64_t count, int32_t len,
                          const float* raw_queries, int32_t nq, int32_t k, int32_t r,
                          int64_t* ids, double* d2);
 

@@ -460,6 +460,57 @@ def test_lb_keogh_filtered_scan_equals_plain_scan():
             assert np.array_equal(a.ids, b.ids) and np.array_equal(a.d2, b.d2)
 
 
+def test_lb_improved_hand_case():
+    """Worked by hand: q = (0, 3, 0, 0), r = 1 gives U = (3, 3, 3, 0),
+    L = (0, 0, 0, 0).  For x = (1, 1, 1, 1), LB_Keogh = 1 (only x_3 leaves
+    the envelope); x clamped into it is h = (1, 1, 1, 0), whose envelope is
+    U' = (1, 1, 1, 1), L' = (1, 1, 0, 0), and q leaves that by 1 at t = 0 and
+    by 2 at t = 1, so LB_Improved = 1 + 1 + 4 = 6.  Every warping path
+    visits each q_t, so DTW = 1 + 4 + 1 + 1 = 7 (the diagonal)."""
+    q = np.array([0, 3, 0, 0], dtype=np.float32)
+    x = np.ones(4, dtype=np.float32)
+    U, L = oracle.envelope(q, 1)
+    assert list(U) == [3, 3, 3, 0] and list(L) == [0, 0, 0, 0]
+    assert oracle.lb_keogh2(U, L, x) == 1.0
+    assert oracle.lb_improved2(q, U, L, x, 1) == 6.0
+    assert oracle.dtw2(q, x, 1) == 7.0
+
+
+def test_lb_improved_between_lb_keogh_and_dtw():
+    """LB_Keogh <= LB_Improved <= DTW (Lemire 2009, the alternative bound
+    of Section 3.4) over random pairs and windows; with r = 0 both bounds
+    and DTW coincide with ED."""
+    z = oracle.znorm(synth.randomwalk(30, 64, seed=43))
+    tighter = 0
+    for j in range(0, 30, 3):
+        for r in (0, 2, 6, 16):
+            U, L = oracle.envelope(z[j], r)
+            for i in range(30):
+                lbk = oracle.lb_keogh2(U, L, z[i])
+                lbi = oracle.lb_improved2(z[j], U, L, z[i], r)
+                d = oracle.dtw2(z[j], z[i], r)
+                assert lbk <= lbi * (1 + 1e-12) and lbi <= d * (1 + 1e-12)
+                tighter += lbi > lbk * (1 + 1e-9)
+                if r == 0:
+                    assert abs(lbi - oracle.ed2(z[j], z[i])) <= 1e-9 * max(1.0, lbi)
+    assert tighter > 100  # the second pass adds something on most pairs
+
+
+def test_lb_improved_filtered_scan_equals_plain_scan():
+    x = synth.randomwalk(4000, 64, seed=2)
+    x = np.concatenate([x, x[:30]])
+    q = np.concatenate([synth.noisy_queries(5, 4000, 64, data_seed=2)[0],
+                        synth.random_queries(2, 64)])
+    for r in (3, 12):
+        for k in (1, 4):
+            a = oracle.KnnState(q, k, oracle.DTW, r)
+            b = oracle.KnnState(q, k, oracle.DTW, r, lb_improved=True)
+            for c in range(0, len(x), 1500):
+                a.scan(x[c:c + 1500], c)
+                b.scan(x[c:c + 1500], c)
+            assert np.array_equal(a.ids, b.ids) and np.array_equal(a.d2, b.d2)
+
+
 def test_knn_vote_hand_cases():
     """Majority class of the k nearest neighbours (Section 5.4), worked by
     hand: plain majority, a two-way tie going to the class met first,
