@@ -334,6 +334,37 @@ def run_serving(pm, idx, n, length, seconds, cap_requests):
     return out
 
 
+def dtw_filters(pm, idx, qt, window):
+    """The same DTW queries one per messi_query_batch call, with LB_Keogh
+    alone and with LB_Improved after it (MESSI_LB_IMPROVED): queries/s and
+    the work each filter leaves."""
+    import torch
+
+    nq = qt.shape[0]
+    out = {}
+    for name, flags in (("lb_keogh", 0), ("lb_improved", pm.MESSI_LB_IMPROVED)):
+        pm.messi_query_batch(idx, qt[:1], [1], [1], [window], flags=flags)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(nq):
+            pm.messi_query_batch(idx, qt[j:j + 1], [1], [1], [window], flags=flags)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tot = {}
+        for j in range(nq):
+            _, _, st = pm.messi_query_batch(idx, qt[j:j + 1], [1], [1], [window], flags=flags,
+                                            stats=True)
+            for key, v in st.items():
+                tot[key] = tot.get(key, 0) + v
+        out[name] = {"queries_per_s": nq / dt, "lb_keogh_per_query": tot["lb_keogh"] / nq,
+                     "lb_improved_per_query": tot["lb_improved"] / nq,
+                     "dtw_per_query": tot["refined"] / nq,
+                     "process_us": tot["us_process"] / nq}
+        log(f"DTW {name}: {nq / dt:.1f} q/s, DTW {tot['refined'] / nq:.0f}/query, "
+            f"LB_Improved {tot['lb_improved'] / nq:.0f}/query")
+    return out
+
+
 def run_subsequence(pm, total, length, nq):
     """Subsequence search (Section 2.1): every window of `length` points of
     one long series, indexed by messi_build_windows, raw values and
@@ -514,6 +545,7 @@ def main():
                "refined_per_query": dst["refined"] / dk, "lb_keogh_per_query": dst["lb_keogh"] / dk,
                "series_lb_per_query": dst["series_lb"] / dk}
         log(f"DTW: {dtw['value']:.2f} q/s, p50 {dtw['p50_ms']:.2f} ms, p99 {dtw['p99_ms']:.2f} ms")
+        dtw["filters"] = dtw_filters(pm, didx, dt[3:3 + dk], args.window)
         didx.free()
 
     batched = None

@@ -42,8 +42,8 @@ enum {
 
 enum { MESSI_ED = 0, MESSI_DTW = 1 };
 
-/* Flags of messi_query_batch. */
-enum { MESSI_SCREEN_BF16 = 1 };
+/* Flags of messi_query_batch, messi_classify and the server. */
+enum { MESSI_SCREEN_BF16 = 1, MESSI_LB_IMPROVED = 2 };
 
 typedef struct messi_index messi_index; /* opaque; owned by the library */
 
@@ -72,6 +72,7 @@ typedef struct messi_stats {
    * refinement; FP64 recheck and output */
   double us_prep, us_stage1, us_stage2, us_process, us_finalize;
   int64_t screened;         /* (query, series) pairs through the BF16 screen */
+  int64_t lb_improved;      /* LB_Improved second passes (DTW, MESSI_LB_IMPROVED) */
 } messi_stats;
 
 /* Build an index (Section 3.2: iSAX summaries, then the leaves of the
@@ -168,6 +169,11 @@ int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int3
  *              device memory for a BF16 copy of the store, made on first
  *              use (or ahead of time by messi_prepare_screen).  Answers are
  *              identical with and without the flag.
+ *              MESSI_LB_IMPROVED: DTW candidates that pass LB_Keogh are
+ *              also tested with LB_Improved (Lemire 2009, named in Section
+ *              3.4 as the tighter, costlier alternative) before DTW.  Same
+ *              answers; ignored where its LDS buffers do not fit (long
+ *              series with a small window).
  *   out_ids    device pointer, int64 [nq][kmax]; out_dists device pointer,
  *              float32 [nq][kmax]: row i holds query i's k[i] neighbours
  *              ascending by (distance, id), then (-1, +inf) up to kmax.
@@ -210,7 +216,8 @@ typedef struct messi_server_options { /* zero-initialised = defaults */
   int32_t workers;          /* concurrent batches, 1..8 (0: 2) */
   int32_t max_batch;        /* most requests per batch (0: 1024) */
   int64_t mem_budget_bytes; /* device bytes in-flight requests may hold (0: no limit) */
-  int32_t flags;            /* MESSI_SCREEN_BF16: screen ED requests */
+  int32_t flags;            /* MESSI_SCREEN_BF16: screen ED requests;
+                               MESSI_LB_IMPROVED: LB_Improved for DTW requests */
   int32_t kmax;             /* largest k a request may ask (0: 64) */
 } messi_server_options;
 

@@ -28,6 +28,7 @@ MESSI_EBUSY = -4
 MESSI_ED = 0
 MESSI_DTW = 1
 MESSI_SCREEN_BF16 = 1
+MESSI_LB_IMPROVED = 2
 
 EXPORTS = [
     "messi_build", "messi_query", "messi_query_stats", "messi_set_stream", "messi_index_info",
@@ -56,7 +57,8 @@ class MessiStats(ctypes.Structure):
                 ("rechecked_fp64", ctypes.c_int64), ("log_overflows", ctypes.c_int64),
                 ("us_prep", ctypes.c_double), ("us_stage1", ctypes.c_double),
                 ("us_stage2", ctypes.c_double), ("us_process", ctypes.c_double),
-                ("us_finalize", ctypes.c_double), ("screened", ctypes.c_int64)]
+                ("us_finalize", ctypes.c_double), ("screened", ctypes.c_int64),
+                ("lb_improved", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -557,8 +557,8 @@ void ensure_batch(messi_index* ix, QueryCtx& c, int nq) {
 // plain call: rows 0..nq-1, every k = kmax).  Slots are kmax apart and
 // output rows out_stride = kmax entries long.
 int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int kmax, int distance,
-              int window, const int* d_kq, const int* d_qmap, bool screen, int64_t* out_ids,
-              float* out_dists, messi_stats* stats) {
+              int window, const int* d_kq, const int* d_qmap, bool screen, bool lb_improved,
+              int64_t* out_ids, float* out_dists, messi_stats* stats) {
   hipStream_t st = c.stream;
   const int len = ix->len;
   const double u = std::ldexp(1.0, -24);
@@ -608,6 +608,10 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     }
   }
   p.fin_waves = fin_waves;
+  // LB_Improved only filters: where its projection buffers do not fit the
+  // process kernel's LDS, the queries run with LB_Keogh alone
+  p.lb_improved = (lb_improved && distance == MESSI_DTW) ? 1 : 0;
+  if (p.lb_improved && process_lds_bytes(p) > 64 * 1024) p.lb_improved = 0;
   if (process_lds_bytes(p) > 64 * 1024 || finalize_lds_bytes(p) > 64 * 1024)
     return fail(MESSI_EINVAL, "series length %d too long for the query kernels", len);
 
@@ -697,6 +701,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
           stats->lb_keogh += (int64_t)r[kStatLbKeogh];
           stats->refined += (int64_t)r[kStatRefined];
           stats->rechecked_fp64 += (int64_t)r[kStatRecheck];
+          stats->lb_improved += (int64_t)r[kStatLbImproved];
         }
         if (screen) {
           unsigned long long t[2];
@@ -717,7 +722,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
 
 int run_query(messi_index* ix, const float* queries, int nq, int k, int distance, int window,
               int64_t* out_ids, float* out_dists, messi_stats* stats) {
-  return run_group(ix, ix->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, out_ids,
+  return run_group(ix, ix->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, false, out_ids,
                    out_dists, stats);
 }
 
@@ -762,7 +767,8 @@ int run_batch(messi_index* index, QueryCtx& ctx, const float* queries, int nq, c
       const bool screen = want_screen && keys[g].first == MESSI_ED && cnt >= kScreenMinGroup;
       if (screen && !index->Zb) return fail(MESSI_EINVAL, "the BF16 screen copy is not prepared");
       const int rc = run_group(index, ctx, queries, cnt, kmax, keys[g].first, keys[g].second,
-                               ctx.bk + at, ctx.bmap + at, screen, out_ids, out_dists, stats);
+                               ctx.bk + at, ctx.bmap + at, screen, (flags & MESSI_LB_IMPROVED) != 0,
+                               out_ids, out_dists, stats);
       if (rc != MESSI_OK) return rc;
       at += cnt;
     }
@@ -1127,7 +1133,7 @@ int messi_query_batch(messi_index* index, const float* queries, int32_t nq, cons
   if (!k || !distance || !window) return fail(MESSI_EINVAL, "k, distance and window are required");
   if (is_device_ptr(k) || is_device_ptr(distance) || is_device_ptr(window))
     return fail(MESSI_EINVAL, "k, distance and window must be host arrays");
-  if (flags & ~MESSI_SCREEN_BF16) return fail(MESSI_EINVAL, "unknown flags");
+  if (flags & ~(MESSI_SCREEN_BF16 | MESSI_LB_IMPROVED)) return fail(MESSI_EINVAL, "unknown flags");
   if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
     return fail(MESSI_EINVAL, "queries and outputs must be device pointers");
   for (int i = 0; i < nq; ++i) {
@@ -1162,7 +1168,7 @@ int messi_classify(messi_index* index, const int32_t* labels, int32_t n_classes,
   if (k < 1 || k > 1024) return fail(MESSI_EINVAL, "k must be in [1, 1024]");
   if (distance != MESSI_ED && distance != MESSI_DTW) return fail(MESSI_EINVAL, "unknown distance");
   if (window < 0) return fail(MESSI_EINVAL, "window must be >= 0");
-  if (flags & ~MESSI_SCREEN_BF16) return fail(MESSI_EINVAL, "unknown flags");
+  if (flags & ~(MESSI_SCREEN_BF16 | MESSI_LB_IMPROVED)) return fail(MESSI_EINVAL, "unknown flags");
   if (!is_device_ptr(labels) || !is_device_ptr(queries) || !is_device_ptr(out_class) ||
       !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
     return fail(MESSI_EINVAL, "labels, queries and outputs must be device pointers");
@@ -1274,7 +1280,7 @@ int messi_server_start(messi_index* index, const messi_server_options* opts, mes
   if (max_batch < 1 || max_batch > 65536) return fail(MESSI_EINVAL, "max_batch must be in [1, 65536]");
   if (kmax < 1 || kmax > 1024) return fail(MESSI_EINVAL, "kmax must be in [1, 1024]");
   if (o.mem_budget_bytes < 0) return fail(MESSI_EINVAL, "mem_budget_bytes must be >= 0");
-  if (o.flags & ~MESSI_SCREEN_BF16) return fail(MESSI_EINVAL, "unknown flags");
+  if (o.flags & ~(MESSI_SCREEN_BF16 | MESSI_LB_IMPROVED)) return fail(MESSI_EINVAL, "unknown flags");
   std::unique_ptr<messi_server> S(new messi_server());
   S->ix = index;
   S->kmax = kmax;

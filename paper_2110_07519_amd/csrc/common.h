@@ -43,6 +43,7 @@ struct QueryParams {
   float xnorm;       // largest 2-norm of an indexed series, rounded up
   float lb_scale;    // power of two that brings bounds into the bucket range
   int raw;           // 1: the index holds series as given (no z-normalisation)
+  int lb_improved;   // 1 (DTW): LB_Improved's second pass after LB_Keogh
   int log_cap;       // near-tie log entries per query
   int fin_waves;     // waves used by the FP64 DTW recheck
   int item_cap;      // leaf chunks per query (all shards)
@@ -80,7 +81,8 @@ __device__ __forceinline__ int k_of(const QueryParams& p, const QueryState& s, i
 }
 __device__ __forceinline__ int row_of(const QueryState& s, int q) { return s.qmap ? s.qmap[q] : q; }
 
-enum { kStatLeavesKept = 0, kStatSeriesLb, kStatLbKeogh, kStatRefined, kStatRecheck, kStatCount = 8 };
+enum { kStatLeavesKept = 0, kStatSeriesLb, kStatLbKeogh, kStatRefined, kStatRecheck, kStatLbImproved,
+       kStatCount = 8 };
 
 // iSAX symbol of a PAA value: the number of breakpoints beta_1..beta_{card-1}
 // that are <= p, given bp[j] = beta_j (bp[0] = -inf).

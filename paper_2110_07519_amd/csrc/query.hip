@@ -157,6 +157,37 @@ __device__ __forceinline__ void lbk_group(const float* __restrict__ U, const flo
   for (int c = 0; c < kGroup; ++c) out[c] = ((act >> c) & 1u) ? wave_sum(acc[c]) : 0.0f;
 }
 
+// LB_Improved's second pass (Lemire 2009) for one row, by one wave: the row
+// clamped into the query's envelope [L, U] goes to hb (len floats of the
+// wave's LDS), and the query is measured against that projection's
+// radius-r envelope.  The squared sum is returned to every lane; adding it
+// to the row's LB_Keogh gives LB_Improved, still a lower bound of DTW.
+__device__ __forceinline__ float lbi_second(const float* __restrict__ q, const float* __restrict__ U,
+                                            const float* __restrict__ L, const float* __restrict__ x,
+                                            int len, int r, float* __restrict__ hb, int lane) {
+  for (int t = lane; t < len; t += kWave) hb[t] = fminf(fmaxf(x[t], L[t]), U[t]);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  float acc = 0.0f;
+  for (int t = lane; t < len; t += kWave) {
+    const int a = t - r < 0 ? 0 : t - r;
+    const int b = t + r > len - 1 ? len - 1 : t + r;
+    float hu = hb[a], hl = hb[a];
+    for (int j = a + 1; j <= b; ++j) {
+      const float v = hb[j];
+      hu = fmaxf(hu, v);
+      hl = fminf(hl, v);
+    }
+    const float v = q[t];
+    const float e = fmaxf(v - hu, 0.0f) + fmaxf(hl - v, 0.0f);  // one of the two is zero
+    acc = __builtin_fmaf(e, e, acc);
+  }
+  const float tot = wave_sum(acc);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();  // hb is rewritten for the next row
+  return tot;
+}
+
 // Banded DTW, squared costs, FP32, one pair per thread.  Rows run over the
 // candidate x (j), the band over the query (i = j - R + b, b in [0, 2R]); in
 // band coordinates D(j,i) needs old D[b] (diagonal), old D[b+1] (up) and new
@@ -737,7 +768,7 @@ struct ProcShape {
   static constexpr int pend_cap = (R >= 0) ? surv_cap + threads : 0;
 };
 
-template <int R, bool MASK>
+template <int R, bool MASK, bool LBI>
 __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryParams& p,
                                              const QueryState& s) {
   using Sh = ProcShape<R>;
@@ -754,7 +785,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   int* surv = reinterpret_cast<int*>(Lw + (dtw ? len : 0));     // survivors of a grab
   float* survlb = reinterpret_cast<float*>(surv + Sh::surv_cap);  // their bounds
   int* pend = reinterpret_cast<int*>(survlb + Sh::surv_cap);    // DTW pairs waiting
-  float* wx = reinterpret_cast<float*>(pend + Sh::pend_cap);     // wave DTW rows [kW][len]
+  float* wx = reinterpret_cast<float*>(pend + Sh::pend_cap);     // wave DTW rows / LB_Improved [kW][len]
   float* wbuf = wx + (R == -2 ? kW * len : 0);                   // wave DTW [kW][3 len]
   __shared__ int s_batch, s_shard, s_stop, s_nsurv, s_npend, s_skip;
   __shared__ unsigned long long s_ckey;
@@ -810,7 +841,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   int* counters = s.next + (int64_t)q * kCounterInts;
   unsigned long long* finished =
       reinterpret_cast<unsigned long long*>(counters + kShards * kCounterStride);
-  unsigned long long c_lb = 0, c_lbk = 0, c_ref = 0, c_leaf = 0;
+  unsigned long long c_lb = 0, c_lbk = 0, c_lbi = 0, c_ref = 0, c_leaf = 0;
 
   // DTW pairs in the pending list, one per thread, first `cnt` entries
   auto run_pairs = [&](int cnt, unsigned long long ck) {
@@ -975,11 +1006,34 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
         lbk_group(U, Lw, ix.Z, len, gr, act, lane, dv);
         c_lbk += (lane == 0) ? __popc(act) : 0;
         const float tk = key_dist(ckey) * p.win * p.win;
-        if constexpr (R >= 0) {
-          unsigned pass = 0;
+        unsigned pass = 0;
 #pragma unroll
-          for (int c = 0; c < kGroup; ++c)
-            pass |= (((act >> c) & 1u) && dv[c] <= tk) ? (1u << c) : 0u;
+        for (int c = 0; c < kGroup; ++c)
+          pass |= (((act >> c) & 1u) && dv[c] <= tk) ? (1u << c) : 0u;
+        if (LBI && pass) {
+          // LB_Improved (the tighter bound Section 3.4 names) on the
+          // LB_Keogh survivors, same test against the k-th best.  The
+          // group's LB_Keogh values wait in the survivors' LDS slots, so
+          // no per-row registers stay live across the pass.
+          if (lane == 0) {
+#pragma unroll
+            for (int c = 0; c < kGroup; ++c)
+              if ((pass >> c) & 1u) survlb[g + c] = dv[c];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          const float* qv = ql + (R >= 0 ? R : 0);
+#pragma unroll 1
+          for (int c = 0; c < kGroup; ++c) {
+            if (!((pass >> c) & 1u)) continue;
+            const int pos = surv[g + c];
+            const float* x = zrow_ptr(ix, pos);
+            const float e2 = lbi_second(qv, U, Lw, x, len, p.window, wx + wv * len, lane);
+            c_lbi += (lane == 0) ? 1 : 0;
+            if (!(survlb[g + c] + e2 <= tk)) pass &= ~(1u << c);
+          }
+        }
+        if constexpr (R >= 0) {
           if (pass) {
             int at = 0;
             if (lane == 0) at = atomicAdd(&s_npend, __popc(pass));
@@ -987,15 +1041,15 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
 #pragma unroll
             for (int c = 0; c < kGroup; ++c)
               if ((pass >> c) & 1u) {
-                if (lane == 0) pend[at] = gp[c];
+                if (lane == 0) pend[at] = surv[g + c];
                 ++at;
               }
           }
         } else {
 #pragma unroll 1
           for (int c = 0; c < kGroup; ++c) {
-            if (!((act >> c) & 1u) || !(dv[c] <= tk)) continue;
-            const int pos = gp[c];
+            if (!((pass >> c) & 1u)) continue;
+            const int pos = surv[g + c];
             const float* x = zrow_ptr(ix, pos);
             for (int t = lane; t < len; t += kWave) wx[wv * len + t] = x[t];
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -1047,6 +1101,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   for (int o = 32; o >= 1; o >>= 1) {
     c_lb += __shfl_xor(c_lb, o, kWave);
     c_lbk += __shfl_xor(c_lbk, o, kWave);
+    c_lbi += __shfl_xor(c_lbi, o, kWave);
     c_ref += __shfl_xor(c_ref, o, kWave);
     c_leaf += __shfl_xor(c_leaf, o, kWave);
   }
@@ -1055,21 +1110,24 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
     if (c_leaf) atomicAdd(&stq[kStatLeavesKept], c_leaf);
     if (c_lb) atomicAdd(&stq[kStatSeriesLb], c_lb);
     if (c_lbk) atomicAdd(&stq[kStatLbKeogh], c_lbk);
+    if (c_lbi) atomicAdd(&stq[kStatLbImproved], c_lbi);
     if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
   }
   __syncthreads();  // LDS is reloaded for the next query
   }
 }
 
-template <int R, bool MASK>
+// LBI: LB_Improved after LB_Keogh.  Its own instances (masked bands and
+// the wave kernel only), so the default kernels keep their registers.
+template <int R, bool MASK, bool LBI = false>
 __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, QueryParams p,
                                                                    QueryState s) {
-  process_body<R, MASK>(ix, p, s);
+  process_body<R, MASK, LBI>(ix, p, s);
 }
 
 __global__ __launch_bounds__(ProcShape<-1>::threads) void k_process_ed(IndexDev ix, QueryParams p,
                                                                        QueryState s) {
-  process_body<-1, false>(ix, p, s);
+  process_body<-1, false, false>(ix, p, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1597,9 +1655,23 @@ static int pick_band(int r, bool* mask) {
   return -2;
 }
 
+// LB_Improved runs on the masked bands (any radius below the band) and on
+// the wave kernel only.
+static int pick_band_lbi(int r, bool* mask) {
+  static const int masked[] = {8, 16, 32, 64};
+  for (int e : masked)
+    if (r < e) {
+      *mask = true;
+      return e;
+    }
+  *mask = false;
+  return -2;
+}
+
 static int band_of(const QueryParams& p, bool* mask) {
   *mask = false;
-  return p.distance == 0 ? -1 : pick_band(p.window, mask);
+  if (p.distance == 0) return -1;
+  return p.lb_improved ? pick_band_lbi(p.window, mask) : pick_band(p.window, mask);
 }
 
 template <int R>
@@ -1611,6 +1683,7 @@ static size_t process_lds_words(const QueryParams& p) {
   size_t words = (size_t)kMaxSeg * card + qlen + (dtw ? 2 * p.len : 0) + 2 * (size_t)Sh::surv_cap +
                  Sh::pend_cap;
   if (R == -2) words += (size_t)Sh::waves * 4 * p.len;
+  if (R >= 0 && p.lb_improved) words += (size_t)Sh::waves * p.len;  // LB_Improved projections
   return words;
 }
 
@@ -1683,6 +1756,16 @@ void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState&
   const size_t lds = process_lds_bytes(qp);
   if (R == -1) {
     hipLaunchKernelGGL(k_process_ed, g, b, lds, st, ix, qp, qs);
+    return;
+  }
+  if (qp.lb_improved) {
+    switch (R) {
+      case 8: hipLaunchKernelGGL((k_process<8, true, true>), g, b, lds, st, ix, qp, qs); break;
+      case 16: hipLaunchKernelGGL((k_process<16, true, true>), g, b, lds, st, ix, qp, qs); break;
+      case 32: hipLaunchKernelGGL((k_process<32, true, true>), g, b, lds, st, ix, qp, qs); break;
+      case 64: hipLaunchKernelGGL((k_process<64, true, true>), g, b, lds, st, ix, qp, qs); break;
+      default: hipLaunchKernelGGL((k_process<-2, false, true>), g, b, lds, st, ix, qp, qs); break;
+    }
     return;
   }
   if (R == -2) {
@@ -1759,6 +1842,14 @@ int process_blocks_per_cu(const QueryParams& qp) {
   hipError_t e = hipSuccess;
   if (R == -1) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process_ed, th, lds);
+  } else if (qp.lb_improved) {
+    switch (R) {
+      case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<8, true, true>, th, lds); break;
+      case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<16, true, true>, th, lds); break;
+      case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<32, true, true>, th, lds); break;
+      case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<64, true, true>, th, lds); break;
+      default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<-2, false, true>, th, lds); break;
+    }
   } else if (R == -2) {
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<-2, false>, th, lds);
   }
