@@ -333,28 +333,29 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
       s_sd = 1.0f;
     }
   } else if (tid == 0) {  // same order and rounding as the build's summary pass
-    // (values read 16 at a time so the LDS reads overlap the add chain)
+    // (values read kB at a time, so one LDS wait covers kB adds)
+    constexpr int kB = 64;
     float sum = 0.0f;
     int t = 0;
-    for (; t + 16 <= len; t += 16) {
-      float v[16];
+    for (; t + kB <= len; t += kB) {
+      float v[kB];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) v[i] = x[t + i];
+      for (int i = 0; i < kB; ++i) v[i] = x[t + i];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) sum = sum + v[i];
+      for (int i = 0; i < kB; ++i) sum = sum + v[i];
     }
     for (; t < len; ++t) sum = sum + x[t];
     const float mu = __fdiv_rn(sum, (float)len);
     float var = 0.0f;
-    for (t = 0; t + 16 <= len; t += 16) {
-      float v[16];
+    for (t = 0; t + kB <= len; t += kB) {
+      float v[kB];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+      for (int i = 0; i < kB; ++i) {
         const float d = x[t + i] - mu;
         v[i] = d * d;
       }
 #pragma unroll
-      for (int i = 0; i < 16; ++i) var = var + v[i];
+      for (int i = 0; i < kB; ++i) var = var + v[i];
     }
     for (; t < len; ++t) {
       const float d = x[t] - mu;
@@ -444,21 +445,9 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
     s_sym[tid] = symbol_of(paa[0][tid], bp, card);
   }
   __syncthreads();
-  // bound table: T[s][sym] = m * gap(PAA, box of sym)^2 (mindist, Section
-  // 2.2 / Property 1; DTW: the envelope PAA against the box, Section 3.4)
-  const float fm = (float)m;
-  float* table = s.table + (int64_t)q * kMaxSeg * card;
-  for (int idx = tid; idx < kMaxSeg * card; idx += blockDim.x) {
-    const int sg = idx / card, j = idx - sg * card;
-    float v = 0.0f;  // segments past w contribute nothing (their symbols are 0)
-    if (sg < w) {
-      const float lo = bp[j], hi = bp[j + 1];
-      const float g = fmaxf(lo - paa[1][sg], 0.0f) + fmaxf(paa[2][sg] - hi, 0.0f);
-      v = fm * (g * g);
-    }
-    table[idx] = v;
-  }
-  // approximate search leaf: descend the tree along the query's word
+  // approximate search leaf: descend the tree along the query's word (the
+  // walk is a chain of dependent loads by thread 0; the other waves fill
+  // the bound table below meanwhile)
   uint8_t word[kMaxSeg];
   uint32_t key = 0;
   for (int sg = 0; sg < w; ++sg) {
@@ -507,6 +496,20 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
     s.approx_range[2 * q + 1] = e;
     s.log_count[q] = 0;
     s.status[q] = 0;
+  }
+  // bound table: T[s][sym] = m * gap(PAA, box of sym)^2 (mindist, Section
+  // 2.2 / Property 1; DTW: the envelope PAA against the box, Section 3.4)
+  const float fm = (float)m;
+  float* table = s.table + (int64_t)q * kMaxSeg * card;
+  for (int idx = tid - kWave; tid >= kWave && idx < kMaxSeg * card; idx += blockDim.x - kWave) {
+    const int sg = idx >> cb, j = idx & (card - 1);
+    float v = 0.0f;  // segments past w contribute nothing (their symbols are 0)
+    if (sg < w) {
+      const float lo = bp[j], hi = bp[j + 1];
+      const float g = fmaxf(lo - paa[1][sg], 0.0f) + fmaxf(paa[2][sg] - hi, 0.0f);
+      v = fm * (g * g);
+    }
+    table[idx] = v;
   }
   for (int j = tid; j < p.k; j += blockDim.x) s.slots[(int64_t)q * p.k + j] = kEmptyKey;
   for (int j = tid; j < kStatCount; j += blockDim.x) s.stats[(int64_t)q * kStatCount + j] = 0;
@@ -1136,6 +1139,8 @@ __global__ __launch_bounds__(ProcShape<-1>::threads) void k_process_ed(IndexDev 
 // candidates in the window are recomputed in FP64 and merged with the
 // running k best by rank, so any number of ties fits.
 
+constexpr int kFinBatch = 4;  // points per lane per step of the FP64 ED recheck
+
 __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryParams p, QueryState s,
                                                            int64_t* __restrict__ out_ids,
                                                            float* __restrict__ out_dists) {
@@ -1180,28 +1185,47 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
     rechecked += (unsigned long long)(cnt - topn);
     // exact distances of the new entries, FP64, index order, unfused
     if (p.distance == 0) {
-      // one wave per candidate: lanes load and square 64 points at a time,
-      // the sum runs in index order, unfused, through the lanes in turn
+      // one wave per candidate: the lanes load and square kFinBatch
+      // points each, the squares go to the wave's LDS strip in index order,
+      // and lane 0 adds them in that order, unfused
       const int nw = blockDim.x / kWave;
+      double* sqb = dbuf + wv * (kFinBatch * kWave);
       for (int c0 = topn; c0 < cnt; c0 += nw) {
         const int c = c0 + wv;
         if (c < cnt) {
           const float* x = zrow_ptr(ix, pos_l[c]);
           double acc = 0.0;
-          for (int t0 = 0; t0 < len; t0 += kWave) {
-            double sq = 0.0;
-            if (t0 + lane < len) {
-              const double d = (double)ql[t0 + lane] - (double)x[t0 + lane];
-              sq = __dmul_rn(d, d);
+          for (int t0 = 0; t0 < len; t0 += kFinBatch * kWave) {
+            float xv[kFinBatch];
+#pragma unroll
+            for (int u = 0; u < kFinBatch; ++u) {
+              const int t = t0 + u * kWave + lane;
+              xv[u] = t < len ? x[t] : 0.0f;
             }
-            const long long bits = __double_as_longlong(sq);
-            const int lo = (int)bits, hi = (int)(bits >> 32);
-            const int nn = len - t0 < kWave ? len - t0 : kWave;
-            for (int i = 0; i < nn; ++i) {
-              const long long b2 = ((long long)__builtin_amdgcn_readlane(hi, i) << 32) |
-                                   (unsigned)__builtin_amdgcn_readlane(lo, i);
-              acc = __dadd_rn(acc, __longlong_as_double(b2));
+#pragma unroll
+            for (int u = 0; u < kFinBatch; ++u) {
+              const int t = t0 + u * kWave + lane;
+              if (t < len) {
+                const double d = (double)ql[t] - (double)xv[u];
+                sqb[u * kWave + lane] = __dmul_rn(d, d);
+              }
             }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) {  // 16 reads in flight before their 16 adds
+              const int nn = len - t0 < kFinBatch * kWave ? len - t0 : kFinBatch * kWave;
+              int i = 0;
+              for (; i + 16 <= nn; i += 16) {
+                double v[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) v[j] = sqb[i + j];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) acc = __dadd_rn(acc, v[j]);
+              }
+              for (; i < nn; ++i) acc = __dadd_rn(acc, sqb[i]);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();  // the strip is rewritten next
           }
           if (lane == 0) {
             E[c] = acc;
@@ -1702,8 +1726,11 @@ static int process_threads(int R) {
 }
 
 size_t finalize_lds_bytes(const QueryParams& p) {
+  // DTW: fin_waves rows and FP64 wave buffers; ED: a strip of squares per wave
+  const size_t dwords = p.distance == 0 ? (size_t)(kProcThreads / kWave) * kFinBatch * kWave
+                                        : (size_t)p.fin_waves * 3 * p.len;
   const size_t words = ((((size_t)4 * kTopCap + p.len + (size_t)p.fin_waves * p.len) + 1) & ~(size_t)1) +
-                       (size_t)p.fin_waves * 3 * p.len * 2;
+                       dwords * 2;
   return words * sizeof(float);
 }
 
