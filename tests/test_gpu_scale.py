@@ -15,6 +15,7 @@
 The device collection comes from the seeded device generator, which is
 bitwise equal to the host generator (test_device_generator_matches_host).
 """
+import contextlib
 import sys
 import time
 
@@ -115,3 +116,38 @@ def test_dtw_10m_noisy_queries(pm):
         for other in (int(src[j]), int(st_ed.ids[t, 0])):
             x_o = oracle.znorm(synth.randomwalk(1, length, seed=synth.SEED_DATA, id0=other))[0]
             assert d_ans <= oracle.dtw2(zq[t], x_o, r)
+
+
+def test_subsequence_windows_20m_points(pm):
+    """Subsequence search at the benchmark's size: every window of 256 points
+    (stride 1) of a 20,000,000-point AR(1) series, raw and z-normalised,
+    window copies plus N(0, 0.1^2) noise as queries, exact 5-NN ED against
+    the oracle's scan over the same windows (cut from the host series in
+    chunks)."""
+    total, length = 20_000_000, 256
+    s = synth.ar1_series(total)
+    st_dev = torch.from_numpy(s).cuda()
+    rng = np.random.default_rng(synth.SEED_MIX)
+    starts = rng.integers(0, total - length, 6)
+    qs = np.stack([s[a:a + length] for a in starts])
+    qs[3:] += (0.1 * rng.standard_normal((3, length))).astype(np.float32)
+    qt = torch.from_numpy(qs).cuda()
+    nwin = total - length + 1
+    view = np.lib.stride_tricks.sliding_window_view(s, length)
+    for as_given in (True, False):
+        _say(f"windows: building the {'raw' if as_given else 'z-normalised'} index over {nwin} windows")
+        idx = pm.messi_build_windows(st_dev, length, 1, leaf_size=2000, raw=as_given)
+        assert idx.n == nwin
+        one = [pm.messi_query(idx, qt[j:j + 1], 5) for j in range(len(qs))]
+        ids = np.concatenate([o[0].cpu().numpy() for o in one])
+        d = np.concatenate([o[1].cpu().numpy() for o in one])
+        idx.free()
+        st = oracle.KnnState(qs, 5)
+        t0 = time.perf_counter()
+        with (oracle.raw_mode() if as_given else contextlib.nullcontext()):
+            for c in range(0, nwin, CHUNK):
+                st.scan(np.ascontiguousarray(view[c:c + CHUNK]), c)
+        _say(f"windows: oracle scan {time.perf_counter() - t0:.0f} s")
+        _check(ids, d, st.ids, st.d2)
+        assert np.all(ids[:3, 0] == starts[:3]) and np.all(d[:3, 0] == 0.0)  # exact copies
+
