@@ -1,8 +1,8 @@
 """GPU parity at the benchmark sizes, in the benchmark's launch configuration.
 
 * Exact 1-NN ED over 100,000,000 random walks of length 256 (16 segments,
-  8-bit symbols, leaves of 2000), queries answered one at a time, and a
-  10-NN call over the same queries.  The oracle scans the whole collection,
+  8-bit symbols, leaves of 2000), queries answered one at a time, a 10-NN
+  call over the same queries, and the 10-NN classifier's vote.  The oracle scans the whole collection,
   regenerated on the host in chunks by the seeded generator.
 * Exact 1-NN DTW (radius 25) over 10,000,000 random walks of length 256 with
   noisy dataset copies as queries.  For noise 0.01 and 0.1 the oracle's
@@ -45,9 +45,11 @@ def pm():
     return pm
 
 
-def _device_index(pm, n, length, leaf):
+def _device_index(pm, n, length, leaf, labels=None):
     data = torch.empty((n, length), dtype=torch.float32, device="cuda")
     synth.randomwalk_device(data, seed=synth.SEED_DATA)
+    if labels is not None:  # trend classes of the collection, for the classifier
+        synth.trend_labels_device(data, labels)
     idx = pm.messi_build(data, 16, 256, leaf)
     torch.cuda.synchronize()
     del data
@@ -74,7 +76,8 @@ def _check(ids, d, oids, od2):
 def test_ed_100m_one_query_at_a_time(pm):
     n, length = 100_000_000, 256
     _say(f"ED: building the index over {n} x {length}")
-    idx = _device_index(pm, n, length, 2000)
+    labels = torch.empty(n, dtype=torch.int32, device="cuda")
+    idx = _device_index(pm, n, length, 2000, labels)
     qn, _, _ = synth.noisy_queries(3, n, length)  # noise 0.01, 0.1, 1.0
     qs = np.concatenate([synth.random_queries(3, length), qn[[0, 2]]])
     qt = torch.from_numpy(qs).cuda()
@@ -82,12 +85,22 @@ def test_ed_100m_one_query_at_a_time(pm):
     ids1 = np.concatenate([o[0].cpu().numpy() for o in one])
     d1 = np.concatenate([o[1].cpu().numpy() for o in one])
     ids10, d10 = (t.cpu().numpy() for t in pm.messi_query(idx, qt, 10))
+    cls, cids, _ = pm.messi_classify(idx, labels, 4, qt, 10)  # k-NN classifier, k = 10
+    cls, cids = cls.cpu().numpy(), cids.cpu().numpy()
     idx.free()
+    del labels
     _say("ED: GPU answers ready; oracle scan of the whole collection")
     st = oracle.KnnState(qs, 10)
     _host_scan([st], n, length)
     _check(ids1, d1, st.ids[:, :1], st.d2[:, :1])
     _check(ids10, d10, st.ids, st.d2)
+    # the classifier's vote against the oracle's over the oracle's neighbours
+    # (labels computed on the host for just those series; -1 elsewhere)
+    assert np.array_equal(cids, st.ids)
+    host_labels = np.full(n, -1, dtype=np.int32)
+    for i in np.unique(st.ids):
+        host_labels[i] = synth.trend_labels(synth.randomwalk(1, length, seed=synth.SEED_DATA, id0=int(i)))[0]
+    assert np.array_equal(cls, oracle.knn_vote(st.ids, host_labels, 4))
 
 
 def test_dtw_10m_noisy_queries(pm):
