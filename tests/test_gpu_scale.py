@@ -2,7 +2,8 @@
 
 * Exact 1-NN ED over 100,000,000 random walks of length 256 (16 segments,
   8-bit symbols, leaves of 2000), queries answered one at a time, a 10-NN
-  call over the same queries, and the 10-NN classifier's vote.  The oracle scans the whole collection,
+  call over the same queries, the 10-NN classifier's vote, and a screened
+  batch (rows equal to single calls; the oracle's queries among them).  The oracle scans the whole collection,
   regenerated on the host in chunks by the seeded generator.
 * Exact 1-NN DTW (radius 25) over 10,000,000 random walks of length 256 with
   noisy dataset copies as queries.  For noise 0.01 and 0.1 the oracle's
@@ -87,6 +88,18 @@ def test_ed_100m_one_query_at_a_time(pm):
     ids10, d10 = (t.cpu().numpy() for t in pm.messi_query(idx, qt, 10))
     cls, cids, _ = pm.messi_classify(idx, labels, 4, qt, 10)  # k-NN classifier, k = 10
     cls, cids = cls.cpu().numpy(), cids.cpu().numpy()
+    # a screened batch of 37 (these 5 and 32 noisy copies, k 10 / 3): rows
+    # equal to one call per query, and the first 5 checked by the oracle below
+    qb = np.concatenate([qs, synth.noisy_queries(32, n, length, j0=1000)[0]])
+    qbt = torch.from_numpy(qb).cuda()
+    kb = [10] * 5 + [3] * 32
+    bids, bd, bst = pm.messi_query_batch(idx, qbt, kb, [0] * 37, [0] * 37, flags=pm.MESSI_SCREEN_BF16,
+                                         stats=True)
+    bids, bd = bids.cpu().numpy(), bd.cpu().numpy()
+    assert bst["screened"] > 0
+    for j in range(5, 37, 4):
+        sid, sd = pm.messi_query(idx, qbt[j:j + 1], 3)
+        assert np.array_equal(bids[j, :3], sid.cpu().numpy()[0]) and np.array_equal(bd[j, :3], sd.cpu().numpy()[0])
     idx.free()
     del labels
     _say("ED: GPU answers ready; oracle scan of the whole collection")
@@ -94,6 +107,7 @@ def test_ed_100m_one_query_at_a_time(pm):
     _host_scan([st], n, length)
     _check(ids1, d1, st.ids[:, :1], st.d2[:, :1])
     _check(ids10, d10, st.ids, st.d2)
+    _check(bids[:5], bd[:5], st.ids, st.d2)
     # the classifier's vote against the oracle's over the oracle's neighbours
     # (labels computed on the host for just those series; -1 elsewhere)
     assert np.array_equal(cids, st.ids)
