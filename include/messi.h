@@ -7,7 +7,8 @@
  * query of that length, find the series at the smallest distance, under
  * Euclidean distance or DTW with a Sakoe-Chiba window (Section 3.4); the
  * k-NN form keeps the k best (Section 5.4).  Series and queries are
- * z-normalised by the library (mean 0, standard deviation 1, Section 2.1).
+ * z-normalised by the library (mean 0, standard deviation 1, Section 2.1),
+ * unless the index was built with messi_options.raw.
  *
  * Conventions for every call:
  *   - Returns MESSI_OK (0) or a negative MESSI_E* code; on error the output
@@ -17,7 +18,8 @@
  *     torch CUDA tensor); "host pointer" = ordinary process memory.
  *     Passing a host pointer where a device pointer is required is rejected
  *     with MESSI_EINVAL (checked with hipPointerGetAttributes).
- *   - ids are 0-based row numbers of the collection passed to messi_build.
+ *   - ids are 0-based row numbers of the collection passed to messi_build
+ *     (window numbers for messi_build_windows).
  *   - Work is ordered on the index's stream (messi_set_stream; default the
  *     null stream); every call returns after its outputs are complete.
  *   - One index may be queried from one host thread at a time; calls that
@@ -103,9 +105,10 @@ typedef struct messi_options {
   int32_t bf16_screen; /* 1: also make the BF16 copy used by MESSI_SCREEN_BF16 */
   int32_t raw;         /* 1: index the series as given, without z-normalising
                           them (the non-normalised search the paper's
-                          Section 1 names); queries on such an index are not normalised
-                          either.  Breakpoints, bounds and distances are
-                          unchanged.  Values must be finite with squared
+                          Section 1 names); queries on such an index are
+                          not normalised either.  Breakpoints, bounds and
+                          distances are unchanged; with inplace the rows
+                          are left as they are.  Values must be finite with squared
                           row norms below FP32's range. */
 } messi_options;
 
