@@ -767,7 +767,11 @@ template <int R>
 struct ProcShape {
   static constexpr int waves = (R == -1) ? kGrab : 4;  // one chunk per wave (DTW: LDS for its lists)
   static constexpr int threads = waves * kWave;
-  static constexpr int surv_cap = waves * kChunkSeries;
+  // ED: survivors wait across grabs until there are two groups per wave to
+  // refine (fewer refinement passes; each is re-checked against the k-th
+  // best of its own time)
+  static constexpr int defer = (R == -1) ? 2 * waves * kGroup : 0;
+  static constexpr int surv_cap = waves * kChunkSeries + defer;
   static constexpr int pend_cap = (R >= 0) ? surv_cap + threads : 0;
 };
 
@@ -865,119 +869,9 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
     }
   };
 
-  // Thread 0 keeps one grab in flight: right after a grab is published to
-  // the block it already asks for the next batch of the same shard and for
-  // the current k-th best, so both round trips overlap the chunk work.  The
-  // finished-shard mask is consulted only when the shard has to change.
-  int next_batch = 0;
-  bool have_next = false;
-  unsigned long long next_key = ~0ull;
-  for (;;) {
-    if (tid == 0) {
-      s_stop = 0;
-      s_shard_done = 0;
-      if (!have_next) {
-        const unsigned long long fin = load_relaxed(finished);
-        if (fin == ~0ull) {
-          s_stop = 1;
-        } else {
-          int shard = s_shard;
-          if ((fin >> shard) & 1ull) {  // next unfinished shard after this one
-            const unsigned long long rot = ~((fin >> shard) | (fin << ((kShards - shard) & 63)));
-            shard = (shard + __ffsll((long long)rot) - 1) & (kShards - 1);
-          }
-          s_shard = shard;
-          next_batch = atomicAdd(&counters[shard * kCounterStride], 1);
-          next_key = load_key(&slots[k - 1]);
-        }
-      }
-      s_batch = next_batch;
-      s_ckey = umin64(s_ckey, next_key);
-      have_next = false;
-    }
-    __syncthreads();
-    if (s_stop) break;
-    const int shard = s_shard;
-    if (tid == 0) {  // prefetch the next grab of this shard
-      next_batch = atomicAdd(&counters[shard * kCounterStride], 1);
-      next_key = load_key(&slots[k - 1]);
-      have_next = true;
-    }
-    unsigned long long ckey = s_ckey;
-    const float tadj = lb_threshold(key_dist(ckey), eta, p);
-    // one chunk per wave, consecutive in the shard's bound order
-    const int i = ix.shard_off[shard] + s_batch * kW + wv;
-    bool take = false;
-    int2 rg = make_int2(0, 0);
-    if (i < ix.shard_off[shard + 1]) {
-      const unsigned long long item = items[i];
-      rg = ranges[i];
-      const float lb = key_dist(item);
-      take = lb <= tadj;
-      if (!take && bucket_floor(lb_bucket(lb * p.lb_scale)) > tadj * p.lb_scale && lane == 0) {  // all later chunks above too
-        atomicOr(finished, 1ull << shard);
-        s_shard_done = 1;
-      }
-    } else if (lane == 0) {
-      atomicOr(finished, 1ull << shard);
-      s_shard_done = 1;
-    }
-    if (take) {
-      c_leaf += (lane == 0) ? 1 : 0;
-      // series bounds (Algorithm 9 / Algorithm 10, first test)
-      uint4 wd[kUnroll];
-      bool ok[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int pos = rg.x + lane + u * kWave;
-        ok[u] = pos < rg.y && !(pos >= P0 && pos < P1);
-        if (ok[u]) wd[u] = ix.words[pos];
-      }
-      float lbv[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        lbv[u] = 0.0f;
-        if (ok[u]) {
-          // all sixteen lookups are independent; summed pairwise
-          float t[kMaxSeg];
-#pragma unroll
-          for (int sg = 0; sg < kMaxSeg; ++sg) t[sg] = table[sg * card + (int)byte_of(wd[u], sg)];
-#pragma unroll
-          for (int h = kMaxSeg / 2; h >= 1; h >>= 1)
-#pragma unroll
-            for (int sg = 0; sg < h; ++sg) t[sg] = t[sg] + t[sg + h];
-          ++c_lb;
-          lbv[u] = t[0];
-          ok[u] = lbv[u] <= tadj;
-        }
-      }
-      int nmine = 0;
-      unsigned long long msk[kUnroll];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        msk[u] = __ballot(ok[u]);
-        nmine += __popcll(msk[u]);
-      }
-      if (nmine) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&s_nsurv, nmine);
-        base = __shfl(base, 0, kWave);
-        const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-          if (ok[u]) {
-            const int at = base + __popcll(msk[u] & below);
-            surv[at] = rg.x + lane + u * kWave;
-            survlb[at] = lbv[u];
-          }
-          base += __popcll(msk[u]);
-        }
-      }
-    }
-    __syncthreads();
-    // refine the grab's survivors, eight rows per wave; bounds re-checked
-    // against the latest k-th best this wave knows
-    const int ns = s_nsurv;
+  // refine survivors [0, ns), eight rows per wave; bounds re-checked
+  // against the latest k-th best this wave knows
+  auto refine = [&](int ns, unsigned long long& ckey) {
     for (int g = wv * kGroup; g < ns; g += kW * kGroup) {
       const float tcur = lb_threshold(key_dist(ckey), eta, p);
       int gp[kGroup];
@@ -1070,6 +964,128 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
         }
       }
     }
+  };
+
+  // Thread 0 keeps one grab in flight: right after a grab is published to
+  // the block it already asks for the next batch of the same shard and for
+  // the current k-th best, so both round trips overlap the chunk work.  The
+  // finished-shard mask is consulted only when the shard has to change.
+  int next_batch = 0;
+  bool have_next = false;
+  unsigned long long next_key = ~0ull;
+  for (;;) {
+    if (tid == 0) {
+      s_stop = 0;
+      s_shard_done = 0;
+      if (!have_next) {
+        const unsigned long long fin = load_relaxed(finished);
+        if (fin == ~0ull) {
+          s_stop = 1;
+        } else {
+          int shard = s_shard;
+          if ((fin >> shard) & 1ull) {  // next unfinished shard after this one
+            const unsigned long long rot = ~((fin >> shard) | (fin << ((kShards - shard) & 63)));
+            shard = (shard + __ffsll((long long)rot) - 1) & (kShards - 1);
+          }
+          s_shard = shard;
+          next_batch = atomicAdd(&counters[shard * kCounterStride], 1);
+          next_key = load_key(&slots[k - 1]);
+        }
+      }
+      s_batch = next_batch;
+      s_ckey = umin64(s_ckey, next_key);
+      have_next = false;
+    }
+    __syncthreads();
+    if (s_stop) {
+      if constexpr (!dtw) {  // the survivors still waiting
+        unsigned long long ck = s_ckey;
+        if (s_nsurv > 0) refine(s_nsurv, ck);
+      }
+      break;
+    }
+    const int shard = s_shard;
+    if (tid == 0) {  // prefetch the next grab of this shard
+      next_batch = atomicAdd(&counters[shard * kCounterStride], 1);
+      next_key = load_key(&slots[k - 1]);
+      have_next = true;
+    }
+    unsigned long long ckey = s_ckey;
+    const float tadj = lb_threshold(key_dist(ckey), eta, p);
+    // one chunk per wave, consecutive in the shard's bound order
+    const int i = ix.shard_off[shard] + s_batch * kW + wv;
+    bool take = false;
+    int2 rg = make_int2(0, 0);
+    if (i < ix.shard_off[shard + 1]) {
+      const unsigned long long item = items[i];
+      rg = ranges[i];
+      const float lb = key_dist(item);
+      take = lb <= tadj;
+      if (!take && bucket_floor(lb_bucket(lb * p.lb_scale)) > tadj * p.lb_scale && lane == 0) {  // all later chunks above too
+        atomicOr(finished, 1ull << shard);
+        s_shard_done = 1;
+      }
+    } else if (lane == 0) {
+      atomicOr(finished, 1ull << shard);
+      s_shard_done = 1;
+    }
+    if (take) {
+      c_leaf += (lane == 0) ? 1 : 0;
+      // series bounds (Algorithm 9 / Algorithm 10, first test)
+      uint4 wd[kUnroll];
+      bool ok[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int pos = rg.x + lane + u * kWave;
+        ok[u] = pos < rg.y && !(pos >= P0 && pos < P1);
+        if (ok[u]) wd[u] = ix.words[pos];
+      }
+      float lbv[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        lbv[u] = 0.0f;
+        if (ok[u]) {
+          // all sixteen lookups are independent; summed pairwise
+          float t[kMaxSeg];
+#pragma unroll
+          for (int sg = 0; sg < kMaxSeg; ++sg) t[sg] = table[sg * card + (int)byte_of(wd[u], sg)];
+#pragma unroll
+          for (int h = kMaxSeg / 2; h >= 1; h >>= 1)
+#pragma unroll
+            for (int sg = 0; sg < h; ++sg) t[sg] = t[sg] + t[sg + h];
+          ++c_lb;
+          lbv[u] = t[0];
+          ok[u] = lbv[u] <= tadj;
+        }
+      }
+      int nmine = 0;
+      unsigned long long msk[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        msk[u] = __ballot(ok[u]);
+        nmine += __popcll(msk[u]);
+      }
+      if (nmine) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_nsurv, nmine);
+        base = __shfl(base, 0, kWave);
+        const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          if (ok[u]) {
+            const int at = base + __popcll(msk[u] & below);
+            surv[at] = rg.x + lane + u * kWave;
+            survlb[at] = lbv[u];
+          }
+          base += __popcll(msk[u]);
+        }
+      }
+    }
+    __syncthreads();
+    // ED keeps survivors across grabs until there are two groups per wave
+    const int ns = s_nsurv;
+    const bool flush = dtw || ns >= Sh::defer;
+    if (flush) refine(ns, ckey);
     if (lane == 0) atomicMin(&s_ckey, ckey);
     __syncthreads();
     if constexpr (R >= 0) {
@@ -1091,7 +1107,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       if (tid == 0) s_npend = np;
     }
     if (tid == 0) {
-      s_nsurv = 0;
+      if (flush) s_nsurv = 0;
       if (s_shard_done) have_next = false;  // the prefetched batch lies past the shard's end
     }
     __syncthreads();
