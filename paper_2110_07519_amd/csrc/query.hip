@@ -566,12 +566,26 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     float* tree = sm;                                          // [16][2 card - 1]
     int* cnt = reinterpret_cast<int*>(tree + kMaxSeg * tw);    // [kLbBuckets] chunks, then cursors
     __shared__ int part[256];
-    const float* T = s.table + (int64_t)q * kMaxSeg * card;
-    for (int i = tid; i < kMaxSeg * card; i += blockDim.x) {
-      const int sg = i >> cb, j = i & (card - 1);
-      tree[sg * tw + card - 1 + j] = T[i];
+    __shared__ float s_bp[257], s_pu[kMaxSeg], s_pl[kMaxSeg];
+    for (int j = tid; j <= card; j += blockDim.x) s_bp[j] = ix.bp[j];
+    if (tid < kMaxSeg) {
+      s_pu[tid] = s.paa[((int64_t)q * 3 + 1) * kMaxSeg + tid];
+      s_pl[tid] = s.paa[((int64_t)q * 3 + 2) * kMaxSeg + tid];
     }
     for (int j = tid; j < kLbBuckets; j += blockDim.x) cnt[j] = 0;
+    __syncthreads();
+    // the trees' bottom level is the series table, computed here from the
+    // query's PAA with the same arithmetic as k_prep (no reload of it)
+    const float fm = (float)p.m;
+    for (int i = tid; i < kMaxSeg * card; i += blockDim.x) {
+      const int sg = i >> cb, j = i & (card - 1);
+      float v = 0.0f;
+      if (sg < w) {
+        const float g = fmaxf(s_bp[j] - s_pu[sg], 0.0f) + fmaxf(s_pl[sg] - s_bp[j + 1], 0.0f);
+        v = fm * (g * g);
+      }
+      tree[sg * tw + card - 1 + j] = v;
+    }
     __syncthreads();
     for (int b = cb - 1; b >= 0; --b) {
       for (int i = tid; i < (kMaxSeg << b); i += blockDim.x) {
