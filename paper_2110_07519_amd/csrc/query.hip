@@ -831,8 +831,22 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
     if (skip) continue;
   }
 
-  const float* tq = s.table + (int64_t)q * kMaxSeg * card;
-  for (int i = tid; i < kMaxSeg * card; i += blockDim.x) table[i] = tq[i];
+  {
+    // the series table from the query's PAA (the same arithmetic as k_prep)
+    const float* pu = s.paa + ((int64_t)q * 3 + 1) * kMaxSeg;
+    const float* pl = s.paa + ((int64_t)q * 3 + 2) * kMaxSeg;
+    const int cb = p.card_bits;
+    const float fm = (float)p.m;
+    for (int i = tid; i < kMaxSeg * card; i += blockDim.x) {
+      const int sg = i >> cb, j = i & (card - 1);
+      float v = 0.0f;
+      if (sg < p.w) {
+        const float g = fmaxf(ix.bp[j] - pu[sg], 0.0f) + fmaxf(pl[sg] - ix.bp[j + 1], 0.0f);
+        v = fm * (g * g);
+      }
+      table[i] = v;
+    }
+  }
   const float* zq = s.zq + (int64_t)q * len;
   if (R >= 0) {
     for (int t = tid; t < qlen; t += blockDim.x) ql[t] = (t >= R && t < R + len) ? zq[t - R] : INFINITY;
