@@ -501,7 +501,6 @@ void ensure_workspace(messi_index* ix, QueryCtx& c, int nq, int k) {
   s.upper = ws.mem.alloc<float>((size_t)NQ * len);
   s.lower = ws.mem.alloc<float>((size_t)NQ * len);
   s.paa = ws.mem.alloc<float>((size_t)NQ * 3 * kMaxSeg);
-  s.table = ws.mem.alloc<float>((size_t)NQ * kMaxSeg * card);
   s.approx_range = ws.mem.alloc<int64_t>((size_t)NQ * 2);
   s.approx_d2 = ws.mem.alloc<float>((size_t)NQ * kApproxCap);
   s.slots = ws.mem.alloc<unsigned long long>((size_t)NQ * K);

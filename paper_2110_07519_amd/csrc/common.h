@@ -59,7 +59,6 @@ struct QueryState {
   float* upper;               // [nq][len]   LB_Keogh envelope (DTW)
   float* lower;               // [nq][len]
   float* paa;                 // [nq][3][16] query PAA, envelope PAA upper, lower
-  float* table;               // [nq][16][card] series-bound table
   int64_t* approx_range;      // [nq][2] positions refined by the approximate search
   float* approx_d2;           // [nq][kApproxCap] their FP32 distances
   unsigned long long* slots;  // [nq][k] running k best (packed keys)

@@ -445,9 +445,8 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
     s_sym[tid] = symbol_of(paa[0][tid], bp, card);
   }
   __syncthreads();
-  // approximate search leaf: descend the tree along the query's word (the
-  // walk is a chain of dependent loads by thread 0; the other waves fill
-  // the bound table below meanwhile)
+  // approximate search leaf: descend the tree along the query's word (a
+  // chain of dependent loads by thread 0)
   uint8_t word[kMaxSeg];
   uint32_t key = 0;
   for (int sg = 0; sg < w; ++sg) {
@@ -496,20 +495,6 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
     s.approx_range[2 * q + 1] = e;
     s.log_count[q] = 0;
     s.status[q] = 0;
-  }
-  // bound table: T[s][sym] = m * gap(PAA, box of sym)^2 (mindist, Section
-  // 2.2 / Property 1; DTW: the envelope PAA against the box, Section 3.4)
-  const float fm = (float)m;
-  float* table = s.table + (int64_t)q * kMaxSeg * card;
-  for (int idx = tid - kWave; tid >= kWave && idx < kMaxSeg * card; idx += blockDim.x - kWave) {
-    const int sg = idx >> cb, j = idx & (card - 1);
-    float v = 0.0f;  // segments past w contribute nothing (their symbols are 0)
-    if (sg < w) {
-      const float lo = bp[j], hi = bp[j + 1];
-      const float g = fmaxf(lo - paa[1][sg], 0.0f) + fmaxf(paa[2][sg] - hi, 0.0f);
-      v = fm * (g * g);
-    }
-    table[idx] = v;
   }
   for (int j = tid; j < p.k; j += blockDim.x) s.slots[(int64_t)q * p.k + j] = kEmptyKey;
   for (int j = tid; j < kStatCount; j += blockDim.x) s.stats[(int64_t)q * kStatCount + j] = 0;
