@@ -1800,7 +1800,7 @@ void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& 
                    hipStream_t st) {
   bool mask;
   const int R = band_of(qp, &mask);
-  const int approx_blocks = R == -1 ? 32 : (R == -2 ? 64 : (kApproxCap + 255) / 256);
+  const int approx_blocks = R == -1 ? 64 : (R == -2 ? 64 : (kApproxCap + 255) / 256);
   // one bound block per shard when the chunk order is written, else eight
   const dim3 g(approx_blocks + (qp.order_leaves ? kShards : 8), qp.nq);
   const size_t lds = stage1_lds_bytes(qp, R);
