@@ -570,6 +570,9 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   p.k = kmax;
   p.out_stride = kmax;
   p.order_leaves = screen ? 0 : 1;
+  // the approximate leaf: found by stage1's approximate blocks for a few
+  // queries (shorter prep), once per query in k_prep for batches
+  p.leaf_in_prep = nq > 8 ? 1 : 0;
   p.distance = distance;
   p.window = distance == MESSI_DTW ? std::min(window, len - 1) : 0;
   p.n_leaves = ix->n_leaves;

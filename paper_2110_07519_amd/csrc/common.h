@@ -44,6 +44,7 @@ struct QueryParams {
   float lb_scale;    // power of two that brings bounds into the bucket range
   int raw;           // 1: the index holds series as given (no z-normalisation)
   int lb_improved;   // 1 (DTW): LB_Improved's second pass after LB_Keogh
+  int leaf_in_prep;  // 1: k_prep finds the approximate leaf (batches), 0: stage1 does
   int log_cap;       // near-tie log entries per query
   int fin_waves;     // waves used by the FP64 DTW recheck
   int item_cap;      // leaf chunks per query (all shards)

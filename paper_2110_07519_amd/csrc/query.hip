@@ -304,6 +304,71 @@ __device__ T dtw_wave(const float* __restrict__ q, const float* __restrict__ x, 
   return __shfl(result, (len - 1) % kWave, kWave);
 }
 
+// The approximate search's leaf (Algorithm 5): descend the split tree along
+// the query's word (computed again from its PAA, as k_prep does); a word
+// whose root key holds no series starts from the root with the smallest
+// bound.  Called by every thread of a block; the leaf's position range,
+// clamped to kApproxCap series and widened to at least k, is left in rng.
+__device__ void approx_leaf_range(const IndexDev& ix, const QueryParams& p, const QueryState& s, int q,
+                                  int64_t* rng) {
+  __shared__ float bpl[257];
+  __shared__ int wsym[kMaxSeg];
+  __shared__ unsigned long long best_s;
+  const int tid = threadIdx.x, w = p.w, cb = p.card_bits, card = 1 << cb;
+  for (int j = tid; j <= card; j += blockDim.x) bpl[j] = ix.bp[j];
+  if (tid == 0) best_s = ~0ull;
+  __syncthreads();
+  const float* pq = s.paa + (int64_t)q * 3 * kMaxSeg;  // PAA, envelope PAA upper, lower
+  if (tid < w) wsym[tid] = symbol_of(pq[tid], bpl, card);
+  __syncthreads();
+  uint8_t word[kMaxSeg];
+  uint32_t key = 0;
+  for (int sg = 0; sg < w; ++sg) {
+    word[sg] = (uint8_t)wsym[sg];
+    key = (key << 1) | (word[sg] >> (cb - 1));
+  }
+  int node = ix.root_node[key];
+  if (node < 0) {  // no series under that root: the root with the smallest bound
+    unsigned long long best = ~0ull;
+    const int nkeys = 1 << w;
+    for (int kk = tid; kk < nkeys; kk += blockDim.x) {
+      if (ix.root_node[kk] < 0) continue;
+      float lb = 0.0f;
+      for (int sg = 0; sg < w; ++sg) {
+        const int b = (kk >> (w - 1 - sg)) & 1;
+        const float lo = bpl[b << (cb - 1)], hi = bpl[(b + 1) << (cb - 1)];
+        const float g = fmaxf(lo - pq[kMaxSeg + sg], 0.0f) + fmaxf(pq[2 * kMaxSeg + sg] - hi, 0.0f);
+        lb += g * g;
+      }
+      const unsigned long long c = ((unsigned long long)__float_as_uint(lb) << 32) | (unsigned)kk;
+      best = c < best ? c : best;
+    }
+    best = wave_min_u64(best);
+    if ((tid & (kWave - 1)) == 0) atomicMin(&best_s, best);
+    __syncthreads();
+    node = ix.root_node[(int)(best_s & 0xffffffffu)];
+  }
+  if (tid == 0) {
+    int4 t = ix.tree[node];
+    for (int guard = 0; guard < 4096 && t.x >= 0; ++guard) {
+      const int bit = (word[t.x & 0xff] >> (t.x >> 8)) & 1;
+      int ch = bit ? t.w : t.z;
+      if (ch < 0) ch = bit ? t.z : t.w;
+      t = ix.tree[ch];
+    }
+    int64_t b = t.y, e = t.z;
+    const int kk = k_of(p, s, q);
+    if (e - b > kApproxCap) e = b + kApproxCap;
+    if (e - b < kk) {
+      e = b + kk < ix.n ? b + kk : ix.n;
+      if (e - b < kk) b = e - kk > 0 ? e - kk : 0;
+    }
+    rng[0] = b;
+    rng[1] = e;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // prep: one block per query: z-normalisation (unless raw), envelope (DTW),
 // the bound slack eta, PAAs, and the reset of the query's state.
@@ -445,6 +510,14 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
     s.log_count[q] = 0;
     s.status[q] = 0;
   }
+  if (p.leaf_in_prep) {  // batches: here once per query (stage1 has many blocks per query)
+    __shared__ int64_t rng[2];
+    approx_leaf_range(ix, p, s, q, rng);
+    if (tid == 0) {
+      s.approx_range[2 * q] = rng[0];
+      s.approx_range[2 * q + 1] = rng[1];
+    }
+  }
   for (int j = tid; j < p.k; j += blockDim.x) s.slots[(int64_t)q * p.k + j] = kEmptyKey;
   for (int j = tid; j < kStatCount; j += blockDim.x) s.stats[(int64_t)q * kStatCount + j] = 0;
   for (int j = tid; j < kCounterInts; j += blockDim.x) s.next[(int64_t)q * kCounterInts + j] = 0;
@@ -476,71 +549,6 @@ __device__ __forceinline__ bool offer(const IndexDev& ix, const QueryParams& p, 
 // ---------------------------------------------------------------------------
 // stage1: blocks [0, A) refine the approximate range, blocks [A, ..) compute
 // the bound of every leaf and its bucket histogram.
-
-// The approximate search's leaf (Algorithm 5): descend the split tree along
-// the query's word (computed again from its PAA, as k_prep does); a word
-// whose root key holds no series starts from the root with the smallest
-// bound.  Called by every thread of a block; the leaf's position range,
-// clamped to kApproxCap series and widened to at least k, is left in rng.
-__device__ void approx_leaf_range(const IndexDev& ix, const QueryParams& p, const QueryState& s, int q,
-                                  int64_t* rng) {
-  __shared__ float bpl[257];
-  __shared__ int wsym[kMaxSeg];
-  __shared__ unsigned long long best_s;
-  const int tid = threadIdx.x, w = p.w, cb = p.card_bits, card = 1 << cb;
-  for (int j = tid; j <= card; j += blockDim.x) bpl[j] = ix.bp[j];
-  if (tid == 0) best_s = ~0ull;
-  __syncthreads();
-  const float* pq = s.paa + (int64_t)q * 3 * kMaxSeg;  // PAA, envelope PAA upper, lower
-  if (tid < w) wsym[tid] = symbol_of(pq[tid], bpl, card);
-  __syncthreads();
-  uint8_t word[kMaxSeg];
-  uint32_t key = 0;
-  for (int sg = 0; sg < w; ++sg) {
-    word[sg] = (uint8_t)wsym[sg];
-    key = (key << 1) | (word[sg] >> (cb - 1));
-  }
-  int node = ix.root_node[key];
-  if (node < 0) {  // no series under that root: the root with the smallest bound
-    unsigned long long best = ~0ull;
-    const int nkeys = 1 << w;
-    for (int kk = tid; kk < nkeys; kk += blockDim.x) {
-      if (ix.root_node[kk] < 0) continue;
-      float lb = 0.0f;
-      for (int sg = 0; sg < w; ++sg) {
-        const int b = (kk >> (w - 1 - sg)) & 1;
-        const float lo = bpl[b << (cb - 1)], hi = bpl[(b + 1) << (cb - 1)];
-        const float g = fmaxf(lo - pq[kMaxSeg + sg], 0.0f) + fmaxf(pq[2 * kMaxSeg + sg] - hi, 0.0f);
-        lb += g * g;
-      }
-      const unsigned long long c = ((unsigned long long)__float_as_uint(lb) << 32) | (unsigned)kk;
-      best = c < best ? c : best;
-    }
-    best = wave_min_u64(best);
-    if ((tid & (kWave - 1)) == 0) atomicMin(&best_s, best);
-    __syncthreads();
-    node = ix.root_node[(int)(best_s & 0xffffffffu)];
-  }
-  if (tid == 0) {
-    int4 t = ix.tree[node];
-    for (int guard = 0; guard < 4096 && t.x >= 0; ++guard) {
-      const int bit = (word[t.x & 0xff] >> (t.x >> 8)) & 1;
-      int ch = bit ? t.w : t.z;
-      if (ch < 0) ch = bit ? t.z : t.w;
-      t = ix.tree[ch];
-    }
-    int64_t b = t.y, e = t.z;
-    const int kk = k_of(p, s, q);
-    if (e - b > kApproxCap) e = b + kApproxCap;
-    if (e - b < kk) {
-      e = b + kk < ix.n ? b + kk : ix.n;
-      if (e - b < kk) b = e - kk > 0 ? e - kk : 0;
-    }
-    rng[0] = b;
-    rng[1] = e;
-  }
-  __syncthreads();
-}
 
 template <int R, bool MASK>
 __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, QueryState s,
@@ -691,15 +699,24 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     return;
   }
   // approximate search (Algorithm 5, approxSearch): real distances of the
-  // series of the query's leaf (found here, off the bound blocks' path);
-  // block 0 records its range for the later phases
+  // series of the query's leaf.  For a few queries the leaf is found here,
+  // off the bound blocks' path (block 0 records its range for the later
+  // phases); for batches k_prep found it once per query.
   __shared__ int64_t s_rng[2];
-  approx_leaf_range(ix, p, s, q, s_rng);
-  const int64_t P0 = s_rng[0], P1 = s_rng[1];
-  if (blockIdx.x == 0 && tid == 0) {
-    s.approx_range[2 * q] = P0;
-    s.approx_range[2 * q + 1] = P1;
+  if (p.leaf_in_prep) {
+    if (tid == 0) {
+      s_rng[0] = s.approx_range[2 * q];
+      s_rng[1] = s.approx_range[2 * q + 1];
+    }
+    __syncthreads();
+  } else {
+    approx_leaf_range(ix, p, s, q, s_rng);
+    if (blockIdx.x == 0 && tid == 0) {
+      s.approx_range[2 * q] = s_rng[0];
+      s.approx_range[2 * q + 1] = s_rng[1];
+    }
   }
+  const int64_t P0 = s_rng[0], P1 = s_rng[1];
   const int cnt = (int)(P1 - P0);
   float* approx_d2 = s.approx_d2 + (int64_t)q * kApproxCap;
   unsigned long long* slots = s.slots + (int64_t)q * p.k;
@@ -1800,7 +1817,7 @@ void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& 
                    hipStream_t st) {
   bool mask;
   const int R = band_of(qp, &mask);
-  const int approx_blocks = R == -1 ? 64 : (R == -2 ? 64 : (kApproxCap + 255) / 256);
+  const int approx_blocks = R == -1 ? (qp.leaf_in_prep ? 32 : 64) : (R == -2 ? 64 : (kApproxCap + 255) / 256);
   // one bound block per shard when the chunk order is written, else eight
   const dim3 g(approx_blocks + (qp.order_leaves ? kShards : 8), qp.nq);
   const size_t lds = stage1_lds_bytes(qp, R);
