@@ -148,7 +148,12 @@ int messi_build_windows(const float* series, int64_t total, int32_t len, int32_t
  *              neighbours hold id -1, distance +inf.
  * Answers are exact: equal, id for id, to a brute-force scan that computes
  * every distance in FP64 from the z-normalised FP32 values, ties broken by
- * the lower id. */
+ * the lower id.
+ * Long series: the query kernels keep the query and per-wave rows in LDS,
+ * up to what one block may use on the device (160 KB on gfx950).  There,
+ * ED accepts every len up to 4096, DTW with r <= 64 up to len 3968, and
+ * DTW with a wider window up to len 1670; longer ones fail with
+ * MESSI_EINVAL. */
 int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k,
                 int32_t distance, int32_t window, int64_t* out_ids, float* out_dists);
 

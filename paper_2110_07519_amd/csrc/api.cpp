@@ -215,6 +215,7 @@ struct messi_index {
   uint16_t* Zb = nullptr;
   float* xn = nullptr;
   int n_cus = 0;
+  size_t lds_max = 64 * 1024;  // LDS a block may use on this device
   std::mutex screen_mu;  // first-use construction of the BF16 copy
   QueryCtx ctx;  // the index's own calls (messi_query, messi_query_batch)
   std::atomic<int> busy{0};
@@ -300,6 +301,11 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   int dev = 0;
   HIP_OR_THROW(hipGetDevice(&dev));
   HIP_OR_THROW(hipDeviceGetAttribute(&ix->n_cus, hipDeviceAttributeMultiprocessorCount, dev));
+  {
+    int lds = 0;
+    HIP_OR_THROW(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    ix->lds_max = (size_t)lds;
+  }
   unsigned int* norm2 = nullptr;  // raw: largest squared row norm (FP32 bits)
   if (ix->raw) {
     norm2 = tmp.alloc<unsigned int>(1);
@@ -598,6 +604,10 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     const int e = (int)std::ceil(std::log2(4.0 * (double)ix->xnorm * ix->xnorm));
     p.lb_scale = (float)std::ldexp(1.0, std::max(-100, std::min(100, 16 - e)));
   }
+  // LDS: the kernels prefer 64 KB (occupancy); longer series may use up
+  // to what a block can have on this device (160 KB on gfx950), less 4 KB
+  // for the kernels' static shared variables
+  const size_t lds_max = ix->lds_max - 4096;
   int fin_waves = 0;
   if (distance == MESSI_DTW) {
     fin_waves = 1;
@@ -613,9 +623,10 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   // LB_Improved only filters: where its projection buffers do not fit the
   // process kernel's LDS, the queries run with LB_Keogh alone
   p.lb_improved = (lb_improved && distance == MESSI_DTW) ? 1 : 0;
-  if (p.lb_improved && process_lds_bytes(p) > 64 * 1024) p.lb_improved = 0;
-  if (process_lds_bytes(p) > 64 * 1024 || finalize_lds_bytes(p) > 64 * 1024)
-    return fail(MESSI_EINVAL, "series length %d too long for the query kernels", len);
+  if (p.lb_improved && process_lds_bytes(p) > lds_max) p.lb_improved = 0;
+  if (process_lds_bytes(p) > lds_max || finalize_lds_bytes(p) > lds_max || stage1_lds_bytes(p) > lds_max)
+    return fail(MESSI_EINVAL, "series length %d too long for the query kernels (window %d)", len,
+                p.window);
 
   int per_cu = 0;
   if (distance == MESSI_DTW) {

@@ -78,6 +78,7 @@ void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState
                      int64_t* out_ids, float* out_dists, hipStream_t st);
 size_t process_lds_bytes(const QueryParams& qp);
 size_t finalize_lds_bytes(const QueryParams& qp);
+size_t stage1_lds_bytes(const QueryParams& qp);
 int process_blocks_per_cu(const QueryParams& qp);
 
 }  // namespace messi

@@ -1801,6 +1801,13 @@ size_t finalize_lds_bytes(const QueryParams& p) {
   return words * sizeof(float);
 }
 
+static size_t stage1_lds_bytes(const QueryParams& p, int R);
+
+size_t stage1_lds_bytes(const QueryParams& p) {
+  bool mask;
+  return stage1_lds_bytes(p, band_of(p, &mask));
+}
+
 static size_t stage1_lds_bytes(const QueryParams& p, int R) {
   const size_t lb_words = (size_t)kMaxSeg * (2 * ((size_t)1 << p.card_bits) - 1) + kLbBuckets;
   const size_t ap_words = R == -1 ? (size_t)p.len : (R == -2 ? 17 * (size_t)p.len : (size_t)p.len + 2 * R);
