@@ -83,6 +83,35 @@ def test_build_matches_oracle(pm, n, length, w, card, leaf):
     idx.free()
 
 
+@pytest.mark.parametrize("n,length,w,card,leaf", [
+    (3001, 128, 16, 256, 50),
+    (1003, 64, 16, 256, 30),
+    (517, 192, 16, 16, 25),
+    (777, 96, 8, 16, 20),
+    (500, 100, 4, 4, 7),
+    (300, 16, 16, 2, 5),
+])
+def test_query_odd_shapes(pm, n, length, w, card, leaf):
+    """k-NN on the build shapes above (fewer segments, small alphabets, a
+    length not a multiple of 4, over-full leaves) under ED and DTW.  The
+    queries add a flat one: z-normalised to zeros, it is at distance 0 from
+    the flat series and every other series is a near tie at about
+    sqrt(len), so the near-tie log and the FP64 recheck see all of them."""
+    raw = synth.randomwalk(n, length, seed=11)
+    raw[3] = 5.0
+    idx, _ = _build(pm, raw, w, card, leaf)
+    qn, _, _ = synth.noisy_queries(6, n, length, data_seed=11)
+    flat = np.full((1, length), -2.0, np.float32)
+    qs = np.concatenate([qn, synth.random_queries(3, length, seed=12), flat, raw[[3, 9]]])
+    for k in (1, 4):
+        oids, od2 = oracle.knn(raw, qs, k)
+        _check_answers(*_query(pm, idx, qs, k), oids, od2)
+    for r in (3, length):
+        oids, od2 = oracle.knn(raw, qs, 2, distance=oracle.DTW, r=r)
+        _check_answers(*_query(pm, idx, qs, 2, 1, r), oids, od2)
+    idx.free()
+
+
 def test_query_ed_tiny_configuration(pm):
     """100,000 x 256 random walks, 100 random-walk queries, exact 1-NN and
     10-NN under ED against the brute-force scan."""
