@@ -1089,6 +1089,9 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       for (int u = 0; u < kUnroll; ++u) {
         const int pos = rg.x + lane + u * kWave;
         ok[u] = pos < rg.y && !(pos >= P0 && pos < P1);
+        // DTW: defined words on skipped lanes keep them from staying live
+        // across the refinement (occupancy); ED runs best as it is
+        if constexpr (dtw) wd[u] = make_uint4(0u, 0u, 0u, 0u);
         if (ok[u]) wd[u] = ix.words[pos];
       }
       float lbv[kUnroll];
