@@ -194,8 +194,20 @@ __device__ __forceinline__ float lbi_second(const float* __restrict__ q, const f
 // D[b-1] (left), so one in-place ascending sweep per row suffices.  qpad is
 // the query in LDS with R +inf pads on each side (matrix edges cost +inf).
 // A path crosses every row, so a row minimum above `cutoff` ends the pair.
+// dtw_band is not inlined, so its pointers arrive untyped; it gives them
+// their address spaces (the query in LDS, the row in global memory).  With
+// generic pointers every query read is a flat load that also counts as a
+// vector-memory access, and waiting for it stalls on the row load too;
+// typed, the query reads are LDS reads and the next four points of the row
+// load while the current four are processed.
+typedef __attribute__((address_space(3))) const float lds_float;
+typedef __attribute__((address_space(1))) const float glb_float;
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f4v glb_f4v;
+__device__ __forceinline__ float4 as_float4(f4v v) { return make_float4(v.x, v.y, v.z, v.w); }
+
 template <int R, bool MASK>
-__device__ __forceinline__ void dtw_row(float (&D)[2 * R + 1], const float* __restrict__ qpad,
+__device__ __forceinline__ void dtw_row(float (&D)[2 * R + 1], const lds_float* __restrict__ qpad,
                                         int j, float xj, int r) {
   float left = INFINITY;
 #pragma unroll
@@ -210,15 +222,19 @@ __device__ __forceinline__ void dtw_row(float (&D)[2 * R + 1], const float* __re
 }
 
 template <int R, bool MASK>
-__device__ float dtw_band(const float* __restrict__ qpad, const float* __restrict__ x, int len,
-                          int r, float cutoff) {
+__device__ float dtw_band(const float* __restrict__ qpad_any, const float* __restrict__ x_any,
+                          int len, int r, float cutoff) {
+  const lds_float* qpad = (const lds_float*)qpad_any;
+  const glb_float* x = (const glb_float*)x_any;
   float D[2 * R + 1];
 #pragma unroll
   for (int b = 0; b <= 2 * R; ++b) D[b] = (b == R) ? 0.0f : INFINITY;
   if ((len & 3) == 0) {
+    float4 xn = as_float4(*(const glb_f4v*)x);
 #pragma unroll 1
     for (int j = 0; j < len; j += 4) {
-      const float4 xa = *reinterpret_cast<const float4*>(x + j);
+      const float4 xa = xn;
+      if (j + 4 < len) xn = as_float4(*(const glb_f4v*)(x + j + 4));
       dtw_row<R, MASK>(D, qpad, j + 0, xa.x, r);
       dtw_row<R, MASK>(D, qpad, j + 1, xa.y, r);
       dtw_row<R, MASK>(D, qpad, j + 2, xa.z, r);
