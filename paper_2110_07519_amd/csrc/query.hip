@@ -172,12 +172,26 @@ __device__ __forceinline__ float lbi_second(const float* __restrict__ q, const f
   for (int t = lane; t < len; t += kWave) {
     const int a = t - r < 0 ? 0 : t - r;
     const int b = t + r > len - 1 ? len - 1 : t + r;
-    float hu = hb[a], hl = hb[a];
-    for (int j = a + 1; j <= b; ++j) {
+    // eight reads in flight per step, two independent max / min chains
+    // (max and min are exact, so the grouping does not change the result)
+    float hu = hb[a], hl = hu, hu2 = hu, hl2 = hu;
+    int j = a + 1;
+    for (; j + 8 <= b + 1; j += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = hb[j + u];
+      hu = fmaxf(hu, fmaxf(fmaxf(v[0], v[1]), fmaxf(v[2], v[3])));
+      hu2 = fmaxf(hu2, fmaxf(fmaxf(v[4], v[5]), fmaxf(v[6], v[7])));
+      hl = fminf(hl, fminf(fminf(v[0], v[1]), fminf(v[2], v[3])));
+      hl2 = fminf(hl2, fminf(fminf(v[4], v[5]), fminf(v[6], v[7])));
+    }
+    for (; j <= b; ++j) {
       const float v = hb[j];
       hu = fmaxf(hu, v);
       hl = fminf(hl, v);
     }
+    hu = fmaxf(hu, hu2);
+    hl = fminf(hl, hl2);
     const float v = q[t];
     const float e = fmaxf(v - hu, 0.0f) + fmaxf(hl - v, 0.0f);  // one of the two is zero
     acc = __builtin_fmaf(e, e, acc);
