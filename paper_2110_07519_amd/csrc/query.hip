@@ -229,7 +229,12 @@ __device__ __forceinline__ void dtw_row(float (&D)[2 * R + 1], const lds_float* 
     const float d = xj - qpad[j + b];
     const float up = (b < 2 * R) ? D[b + 1] : INFINITY;
     float c = __builtin_fmaf(d, d, fminf(fminf(D[b], up), left));
-    if (MASK && (b - R > r || R - b > r)) c = INFINITY;
+    if (MASK) {
+      // outside the band +inf, inside c: the median of (c, pen, +inf),
+      // with pen chosen by a scalar select, so no branch per cell
+      const float pen = (b - R > r || R - b > r) ? INFINITY : -INFINITY;
+      c = __builtin_amdgcn_fmed3f(c, pen, INFINITY);
+    }
     D[b] = c;
     left = c;
   }
@@ -240,6 +245,7 @@ __device__ float dtw_band(const float* __restrict__ qpad_any, const float* __res
                           int len, int r, float cutoff) {
   const lds_float* qpad = (const lds_float*)qpad_any;
   const glb_float* x = (const glb_float*)x_any;
+  if (MASK) r = __builtin_amdgcn_readfirstlane(r);  // the same for every lane
   float D[2 * R + 1];
 #pragma unroll
   for (int b = 0; b <= 2 * R; ++b) D[b] = (b == R) ? 0.0f : INFINITY;
@@ -1760,10 +1766,10 @@ void launch_vote(const int64_t* ids, int64_t stride, int nq, int k, const int* l
 // the common windows, else the next larger band with a mask, else the wave
 // anti-diagonal kernels.
 
-#define MESSI_BANDS(X) X(0) X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(25) X(32) X(51) X(64)
+#define MESSI_BANDS(X) X(0) X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(13) X(16) X(25) X(26) X(32) X(51) X(64)
 
 static int pick_band(int r, bool* mask) {
-  static const int exact[] = {0, 1, 2, 3, 4, 6, 8, 12, 16, 25, 32, 51, 64};
+  static const int exact[] = {0, 1, 2, 3, 4, 6, 8, 12, 13, 16, 25, 26, 32, 51, 64};
   for (int e : exact)
     if (e == r) {
       *mask = false;

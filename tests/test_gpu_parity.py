@@ -145,7 +145,8 @@ def test_query_ed_noisy_and_exact_copies(pm):
     idx.free()
 
 
-@pytest.mark.parametrize("length,r", [(256, 25), (128, 12), (128, 0), (128, 3), (64, 10), (64, 70)])
+@pytest.mark.parametrize("length,r", [(256, 25), (256, 26), (256, 20), (128, 12), (128, 13), (128, 0),
+                                      (128, 3), (64, 10), (64, 70)])
 def test_query_dtw(pm, length, r):
     n = 8000 if length == 256 else 6000
     raw = synth.randomwalk(n, length, seed=21)
