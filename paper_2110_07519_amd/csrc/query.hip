@@ -208,12 +208,12 @@ __device__ __forceinline__ float lbi_second(const float* __restrict__ q, const f
 // D[b-1] (left), so one in-place ascending sweep per row suffices.  qpad is
 // the query in LDS with R +inf pads on each side (matrix edges cost +inf).
 // A path crosses every row, so a row minimum above `cutoff` ends the pair.
-// dtw_band is not inlined, so its pointers arrive untyped; it gives them
-// their address spaces (the query in LDS, the row in global memory).  With
-// generic pointers every query read is a flat load that also counts as a
-// vector-memory access, and waiting for it stalls on the row load too;
-// typed, the query reads are LDS reads and the next four points of the row
-// load while the current four are processed.
+// Wide bands run as a call, where pointers arrive untyped; the body gives
+// them their address spaces (the query in LDS, the row in global memory).
+// With generic pointers every query read is a flat load that also counts
+// as a vector-memory access, and waiting for it stalls on the row load
+// too; typed, the query reads are LDS reads and the next four points of
+// the row load while the current four are processed.
 typedef __attribute__((address_space(3))) const float lds_float;
 typedef __attribute__((address_space(1))) const float glb_float;
 typedef float f4v __attribute__((ext_vector_type(4)));
@@ -241,8 +241,9 @@ __device__ __forceinline__ void dtw_row(float (&D)[2 * R + 1], const lds_float* 
 }
 
 template <int R, bool MASK>
-__device__ float dtw_band(const float* __restrict__ qpad_any, const float* __restrict__ x_any,
-                          int len, int r, float cutoff) {
+__device__ __forceinline__ float dtw_band_body(const float* __restrict__ qpad_any,
+                                               const float* __restrict__ x_any, int len, int r,
+                                               float cutoff) {
   const lds_float* qpad = (const lds_float*)qpad_any;
   const glb_float* x = (const glb_float*)x_any;
   if (MASK) r = __builtin_amdgcn_readfirstlane(r);  // the same for every lane
@@ -279,6 +280,26 @@ __device__ float dtw_band(const float* __restrict__ qpad_any, const float* __res
     }
   }
   return D[R];
+}
+
+// Bands up to 32 are inlined (the kernel allocates the band with its own
+// registers, no call overhead); wider ones stay a call, where their
+// registers are counted apart from the kernel's and the kernel keeps its
+// own occupancy.
+template <int R, bool MASK>
+__device__ __attribute__((noinline)) float dtw_band_call(const float* __restrict__ qpad,
+                                                        const float* __restrict__ x, int len, int r,
+                                                        float cutoff) {
+  return dtw_band_body<R, MASK>(qpad, x, len, r, cutoff);
+}
+
+template <int R, bool MASK>
+__device__ __forceinline__ float dtw_band(const float* __restrict__ qpad, const float* __restrict__ x,
+                                          int len, int r, float cutoff) {
+  if constexpr (R >= 48)
+    return dtw_band_call<R, MASK>(qpad, x, len, r, cutoff);
+  else
+    return dtw_band_body<R, MASK>(qpad, x, len, r, cutoff);
 }
 
 // Wave-cooperative DTW over anti-diagonals d = i + j; cells of one diagonal
