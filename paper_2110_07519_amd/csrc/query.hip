@@ -250,7 +250,7 @@ __device__ __forceinline__ float dtw_band_body(const float* __restrict__ qpad_an
   float D[2 * R + 1];
 #pragma unroll
   for (int b = 0; b <= 2 * R; ++b) D[b] = (b == R) ? 0.0f : INFINITY;
-  if (R < 48 && (len & 3) == 0) {
+  if (R < 24 && (len & 3) == 0) {
     float4 xn = as_float4(*(const glb_f4v*)x);
 #pragma unroll 1
     for (int j = 0; j < len; j += 4) {
@@ -268,8 +268,9 @@ __device__ __forceinline__ float dtw_band_body(const float* __restrict__ qpad_an
       }
     }
   } else {
-    // one row per step (the wide bands keep to two waves per SIMD this
-    // way), the next point loading while the current row is computed
+    // one row per step from radius 24 (four rows at once keep their shared
+    // query values live beside the band: r = 25 needs 198 VGPRs that way,
+    // 128 this way), the next point loading while the current row runs
     float xn = x[0];
 #pragma unroll 1
     for (int j = 0; j < len; ++j) {
