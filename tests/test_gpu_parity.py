@@ -90,6 +90,7 @@ def test_build_matches_oracle(pm, n, length, w, card, leaf):
     (777, 96, 8, 16, 20),
     (500, 100, 4, 4, 7),
     (300, 16, 16, 2, 5),
+    (400, 55, 5, 16, 10),            # length not a multiple of 4: DTW steps one row at a time
 ])
 def test_query_odd_shapes(pm, n, length, w, card, leaf):
     """k-NN on the build shapes above (fewer segments, small alphabets, a
@@ -106,7 +107,7 @@ def test_query_odd_shapes(pm, n, length, w, card, leaf):
     for k in (1, 4):
         oids, od2 = oracle.knn(raw, qs, k)
         _check_answers(*_query(pm, idx, qs, k), oids, od2)
-    for r in (3, length):
+    for r in (3, 25, length):
         oids, od2 = oracle.knn(raw, qs, 2, distance=oracle.DTW, r=r)
         _check_answers(*_query(pm, idx, qs, 2, 1, r), oids, od2)
     idx.free()
