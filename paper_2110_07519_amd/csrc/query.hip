@@ -309,11 +309,14 @@ __device__ __forceinline__ float dtw_band(const float* __restrict__ qpad, const 
 
 // Wave-cooperative DTW over anti-diagonals d = i + j; cells of one diagonal
 // are independent, so lanes share them.  buf holds three diagonals (d, d-1,
-// d-2) of len values each, indexed by i; every index is rewritten each step
-// (+inf outside the band and the matrix).  Each cell is computed from the
-// same three neighbours as in row order, so the result is bit-identical to
-// the sequential recurrence.  Used in FP64 for the near-tie recheck and in
-// FP32 for radii beyond the register band.
+// d-2) of len values each, indexed by i.  A diagonal's cells inside the
+// band and the matrix lie in one index range [lo, hi]; the lanes cover it
+// plus one index on each side, written +inf, so the next two diagonals
+// read +inf wherever they step outside the band (older values there are
+// never read).  Each cell is computed from the same three neighbours as in
+// row order, so the result is bit-identical to the sequential recurrence.
+// Used in FP64 for the near-tie recheck and in FP32 for radii beyond the
+// register band.
 template <typename T>
 __device__ T dtw_wave(const float* __restrict__ q, const float* __restrict__ x, int len, int r,
                       T* __restrict__ buf, T cutoff, int lane) {
@@ -322,16 +325,20 @@ __device__ T dtw_wave(const float* __restrict__ q, const float* __restrict__ x, 
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
   const int last = 2 * (len - 1);
-  T result = inf;
+  T result = inf, prev_min = inf;
   for (int d = 0; d <= last; ++d) {
     T* cur = buf + (d % 3) * len;
     const T* p1 = buf + ((d + 2) % 3) * len;  // diagonal d-1
     const T* p2 = buf + ((d + 1) % 3) * len;  // diagonal d-2
+    // band |i - j| <= r on this diagonal: ceil((d - r) / 2) <= i <= floor((d + r) / 2)
+    const int lo = max(max(0, d - len + 1), (d - r + 1) >> 1);
+    const int hi = min(min(len - 1, d), (d + r) >> 1);
+    const int wlo = max(0, lo - 1), whi = min(len - 1, hi + 1);
     T local_min = inf;
-    for (int i = lane; i < len; i += kWave) {
+    for (int i = wlo + lane; i <= whi; i += kWave) {
       const int j = d - i;
       T v = inf;
-      if (j >= 0 && j < len && (i - j <= r) && (j - i <= r)) {
+      if (i >= lo && i <= hi) {
         const T diff = (T)q[i] - (T)x[j];
         const T c = diff * diff;
         if (d == 0) {
@@ -353,17 +360,21 @@ __device__ T dtw_wave(const float* __restrict__ q, const float* __restrict__ x, 
     if (cutoff < inf && (d & 7) == 7) {
       // min over diagonals d and d-1: every path visits one of any two
       // consecutive anti-diagonals
-      T mn = local_min;
-      for (int i = lane; i < len; i += kWave) mn = p1[i] < mn ? p1[i] : mn;
+      T mn = local_min < prev_min ? local_min : prev_min;
       for (int o = 32; o >= 1; o >>= 1) {
         const T u = __shfl_xor(mn, o, kWave);
         mn = u < mn ? u : mn;
       }
       if (mn > cutoff) return inf;
     }
+    prev_min = local_min;
   }
-  // the final cell was written by the lane owning index len-1
-  return __shfl(result, (len - 1) % kWave, kWave);
+  // the final cell was written by one lane; every other lane holds +inf
+  for (int o = 32; o >= 1; o >>= 1) {
+    const T u = __shfl_xor(result, o, kWave);
+    result = u < result ? u : result;
+  }
+  return result;
 }
 
 // The approximate search's leaf (Algorithm 5): descend the split tree along
