@@ -33,8 +33,8 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA, published
 # timed queries, from two rocprofv3 --pmc runs of this script (FETCH_SIZE x
 # 2.0 + WRITE_SIZE x 1.0 KiB; factors from a 1 GiB device copy and fill).
 # Valid only for the query kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256": "b464b9f9441471ad61333b92eb05ea769810606a13d3f90ee0ab65de4093dfee",
-                    "bytes_per_launch": 296980834}
+MEASURED_TRAFFIC = {"sources_sha256": "5e452423c2bdba50e258cf4d487d2e2e3ea883a034e256acf9e734c5172599d5",
+                    "bytes_per_launch": 298156081}
 QUERY_SOURCES = ["paper_2110_07519_amd/csrc/query.hip", "paper_2110_07519_amd/csrc/query.h",
                  "paper_2110_07519_amd/csrc/common.h"]
 PHASES = ["prep", "stage1", "stage2", "process", "finalize"]

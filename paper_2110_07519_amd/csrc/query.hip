@@ -377,6 +377,44 @@ __device__ T dtw_wave(const float* __restrict__ q, const float* __restrict__ x, 
   return result;
 }
 
+// FP64 DTW of one pair by one wave when the band fits the wave
+// (2r + 1 <= 64): lane k holds the cells of band offset k = i - j + r, one
+// on every other anti-diagonal (d + k - r even), so a cell's neighbours
+// (i-1, j-1), (i-1, j) and (i, j-1) are the lane's own previous value and
+// the latest values of lanes k-1 and k+1, exchanged by lane shuffles with
+// no LDS and no barrier.  The same operations as the row-order recurrence:
+// bit-identical to it.
+__device__ double dtw_reg64(const float* __restrict__ q, const float* __restrict__ x, int len,
+                            int r, int lane) {
+  const double inf = (double)INFINITY;
+  double own = inf;
+  const bool in_band = lane <= 2 * r;
+  const int last = 2 * (len - 1);
+  for (int d = 0; d <= last; ++d) {
+    const double up = __shfl_up(own, 1, kWave);    // lane k-1: cell (i-1, j)
+    const double dn = __shfl_down(own, 1, kWave);  // lane k+1: cell (i, j-1)
+    if (in_band && !((d + lane - r) & 1)) {
+      const int i = (d + lane - r) >> 1, j = d - i;
+      if (i < 0 || j < 0 || i >= len || j >= len) {
+        own = inf;
+      } else {
+        const double diff = (double)q[i] - (double)x[j];
+        const double c = diff * diff;
+        if (d == 0) {
+          own = c;
+        } else {
+          double m = inf;
+          if (i > 0 && j > 0 && own < m) m = own;
+          if (i > 0 && lane > 0 && up < m) m = up;
+          if (j > 0 && lane < kWave - 1 && dn < m) m = dn;
+          own = c + m;
+        }
+      }
+    }
+  }
+  return __shfl(own, r, kWave);  // the last cell (len-1, len-1) has offset r
+}
+
 // The approximate search's leaf (Algorithm 5): descend the split tree along
 // the query's word (computed again from its PAA, as k_prep does); a word
 // whose root key holds no series starts from the root with the smallest
@@ -1384,8 +1422,11 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
           for (int t = lane; t < len; t += kWave) xl[wv * len + t] = x[t];
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
-          const double v = dtw_wave<double>(ql, xl + wv * len, len, p.window, dbuf + wv * 3 * len,
-                                            (double)INFINITY, lane);
+          const double v =
+              2 * p.window + 1 <= kWave
+                  ? dtw_reg64(ql, xl + wv * len, len, p.window, lane)
+                  : dtw_wave<double>(ql, xl + wv * len, len, p.window, dbuf + wv * 3 * len,
+                                     (double)INFINITY, lane);
           if (lane == 0) {
             E[c] = v;
             id_l[c] = ix.perm[pos_l[c]];
