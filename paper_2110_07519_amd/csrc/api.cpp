@@ -171,6 +171,8 @@ struct QueryCtx {
   int proc_blocks_ed = 0;  // cached occupancy of the ED process kernel
   hipEvent_t ev[6] = {};
   bool events_ready = false;
+  int* h_status = nullptr;  // pinned copy of the per-query status words
+  int h_status_cap = 0;
 
   QueryCtx() = default;
   QueryCtx(const QueryCtx&) = delete;
@@ -178,6 +180,7 @@ struct QueryCtx {
   ~QueryCtx() {
     if (events_ready)
       for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (h_status) (void)hipHostFree(h_status);
   }
 };
 
@@ -657,7 +660,15 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     sc.c_abs = (float)std::ldexp(1.0, -17);
   }
   const int screen_blocks = screen ? screen_blocks_per_cu(len) * ix->n_cus : 0;
-  std::vector<int> status(nq);
+  // the status words come back into pinned memory: a copy to pageable
+  // memory would be staged through a runtime buffer on every call
+  if (c.h_status_cap < nq) {
+    if (c.h_status) HIP_OR_THROW(hipHostFree(c.h_status));
+    c.h_status = nullptr;
+    c.h_status_cap = 0;
+    HIP_OR_THROW(hipHostMalloc((void**)&c.h_status, sizeof(int) * (size_t)nq, hipHostMallocDefault));
+    c.h_status_cap = nq;
+  }
   // phase timing (only when the caller asks for statistics)
   hipEvent_t ev[6] = {};
   if (stats) {
@@ -691,9 +702,9 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     launch_finalize(v, p, qs, out_ids, out_dists, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[5], st));
     launch_check();
-    d2h(status.data(), qs.status, nq, st);
+    d2h(c.h_status, qs.status, nq, st);
     int worst = 0;
-    for (int s : status) worst |= s;
+    for (int i = 0; i < nq; ++i) worst |= c.h_status[i];
     if (!(worst & 1)) {
       if (stats) {
         float ms[5] = {0, 0, 0, 0, 0};
