@@ -200,6 +200,36 @@ def test_mindist_hand_case():
     assert lb2 == pytest.approx(exp, rel=1e-12)
 
 
+def test_mindist_dtw_hand_case():
+    """The envelope form of the node bound (Section 3.4) on 1-bit boxes,
+    whose edges are -inf, beta_128 = 0 and +inf, so every term is exact:
+    segment 0's box [0, inf) lies above the upper envelope mean -0.5 (gap
+    0.5); segment 1's box (-inf, 0) lies below the lower envelope mean 0.75
+    (gap 0.75); segments 2 and 3 overlap their envelope; the rest sit inside
+    (-inf, 0).  LB^2 = (256 / 16) (0.5^2 + 0.75^2) = 13."""
+    beta = oracle.breakpoints(8)
+    assert beta[127] == 0.0
+    sym = np.zeros(16, np.uint8)
+    sym[[0, 2]] = 1
+    bits = np.ones(16, np.uint8)
+    up = np.full(16, -1.0, np.float32)
+    lp = np.full(16, -1.0, np.float32)
+    up[:4] = [-0.5, 1.5, 1.0, 0.5]
+    lp[:4] = [-1.0, 0.75, -1.0, -0.25]
+    assert oracle.mindist2_dtw(up, lp, sym, bits, beta, 256) == 13.0
+    # a swapped envelope would measure segment 0 from -1.0 and segment 1
+    # from 1.5 (16 (1 + 2.25) = 52): the roles of U and L are pinned
+    assert oracle.mindist2_dtw(lp, up, sym, bits, beta, 256) != 13.0
+    # with U = L = the query PAA it is the ED form
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        qp = rng.standard_normal(16).astype(np.float32)
+        s8 = rng.integers(0, 256, 16).astype(np.uint8)
+        b8 = rng.integers(1, 9, 16).astype(np.uint8)
+        s8 = (s8 >> (8 - b8)).astype(np.uint8)
+        assert oracle.mindist2_dtw(qp, qp, s8, b8, beta, 256) == oracle.mindist2_ed(qp, s8, b8, beta, 256)
+
+
 # ------------------------------------------------------------------- DTW ---
 def _golden_dtw():
     rows = []
@@ -411,6 +441,66 @@ def test_leaf_partition_independent_of_input_order():
     perm2, leaves2 = oracle.leaf_partition(W[shuf], 60)
     boxes = lambda Ls: sorted((tuple(L["sym"]), tuple(L["bits"]), int(L["end"] - L["begin"])) for L in Ls)
     assert boxes(leaves) == boxes(leaves2)
+
+
+def _hand_words(cols, n):
+    """n words whose symbols are 0 except the given segment columns."""
+    W = np.zeros((n, 16), np.uint8)
+    for sg, col in cols.items():
+        W[:, sg] = col
+    return W
+
+
+def _leaf_boxes(leaves):
+    return [(int(L["begin"]), int(L["end"]), L["sym"][:16].tolist(), L["bits"][:16].tolist())
+            for L in leaves]
+
+
+def _box(changes):
+    sym, bits = [0] * 16, [1] * 16
+    for sg, (sv, bv) in changes.items():
+        sym[sg], bits[sg] = sv, bv
+    return sym, bits
+
+
+def test_leaf_split_most_balanced_segment_hand_case():
+    """Section 2.2: a node over the leaf size splits on the segment whose
+    next bit divides it most evenly.  Five words under one root key (first
+    bit 0 in every segment), leaf size 4.  Second bits (symbol value 64):
+    segment 0 has 1s at ids 0 and 2 (|2*2 - 5| = 1), segment 1 at id 1
+    (|2 - 5| = 3), the others none (|0 - 5| = 5).  Segment 0 wins; its
+    0-child holds ids 1, 3, 4 and its 1-child ids 0, 2, both leaves."""
+    W = _hand_words({0: [64, 0, 64, 0, 0], 1: [0, 64, 0, 0, 0]}, 5)
+    perm, leaves = oracle.leaf_partition(W, 4)
+    assert perm.tolist() == [1, 3, 4, 0, 2]
+    assert _leaf_boxes(leaves) == [(0, 3, *_box({0: (0b00, 2)})), (3, 5, *_box({0: (0b01, 2)}))]
+
+
+def test_leaf_split_ties_to_lowest_segment_hand_case():
+    """Segments 2 and 5 both split the five words 2 / 3 (|4 - 5| = 1),
+    segment 0 splits them 1 / 4: the tie goes to segment 2, the lower one."""
+    W = _hand_words({0: [64, 0, 0, 0, 0], 2: [64, 64, 0, 0, 0], 5: [0, 0, 64, 64, 0]}, 5)
+    perm, leaves = oracle.leaf_partition(W, 4)
+    assert perm.tolist() == [2, 3, 4, 0, 1]
+    assert _leaf_boxes(leaves) == [(0, 3, *_box({2: (0b00, 2)})), (3, 5, *_box({2: (0b01, 2)}))]
+
+
+def test_leaf_split_two_levels_hand_case():
+    """Six words, leaf size 2.  Level 1: segment 1's second bit (64) splits
+    ids {0, 2, 4} from {1, 3, 5} evenly (gap 0), beating segment 0 (ids 0, 1:
+    gap 2).  Level 2, node {1, 3, 5}: segment 0's second bit (id 1) and
+    segment 1's third bit (32; ids 3, 5) both give gap 1: segment 0, the
+    lower, splits it into {3, 5} and {1}.  Node {0, 2, 4}: segment 0 (id 0)
+    and segment 1's third bit (ids 0, 4) tie again: {2, 4} and {0}."""
+    W = _hand_words({0: [64, 64, 0, 0, 0, 0], 1: [96, 0, 64, 32, 96, 32]}, 6)
+    perm, leaves = oracle.leaf_partition(W, 2)
+    assert perm.tolist() == [3, 5, 1, 2, 4, 0]
+    assert _leaf_boxes(leaves) == [
+        (0, 2, *_box({0: (0b00, 2), 1: (0b00, 2)})),
+        (2, 3, *_box({0: (0b01, 2), 1: (0b00, 2)})),
+        (3, 5, *_box({0: (0b00, 2), 1: (0b01, 2)})),
+        (5, 6, *_box({0: (0b01, 2), 1: (0b01, 2)})),
+    ]
 
 
 # ------------------------------------------------- index search (Thm 2) ---

@@ -124,3 +124,135 @@ def test_bf16_rounding_is_nearest_even():
     # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties go to the even 1
     v = np.array([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -9, -(1.0 + 2.0 ** -8)], np.float32)
     assert bf16(v).tolist() == [1.0, 1.0 + 2.0 ** -6, 1.0, -1.0]
+
+
+# ----------------------------------------------------------------------------
+# The whole folded drop test, simulated in FP32 step by step.
+#
+# The screen keeps a pair unless
+#   x = fma(-2, s~, fma(-a_q, s_x, R_q + C_x)) > 0,
+#   R_q = fl(fl(|q|^2) (1 - c_abs)) - thr   (two FP32 roundings),
+#   C_x = fl(fl(|x|^2) (1 - c_abs)),  a_q = fl(c_dot sqrt(fl(|q|^2))),
+#   s_x = sqrt(fl(|x|^2)),
+# with the squared norms summed in FP64 and rounded to FP32 once, and
+# c_abs = 2^-17 covering those roundings and the FP32 evaluation.  A drop
+# is sound iff it implies |q - x|^2 > thr for the FP32 rows.  The cases
+# below stress the c_abs term: zero and tiny rows (no dot-product slack at
+# all), identical rows at BF16 rounding midpoints (the dot-product slack
+# used up), near copies (large norms, small distance) and rows with a large
+# offset (raw indexes), each with the threshold at the smallest FP32 value
+# not below the exact distance, where a drop would be wrong.
+
+from fractions import Fraction
+
+C_ABS = 2.0 ** -17
+
+
+def c_dot(n):
+    ub = U_B
+    g = n * U_32 / (1.0 - n * U_32)
+    return np.float32(np.nextafter(np.float32(2.0 * ((2 * ub + ub * ub) + g * (1 + ub) ** 2)
+                                              * (1.0 + 2.0 ** -10)), np.float32(np.inf)))
+
+
+def rn32(fr):
+    """Round a Fraction to the nearest FP32 value (ties to even)."""
+    if fr == 0:
+        return np.float32(0.0)
+    sign = -1 if fr < 0 else 1
+    a = abs(fr)
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    if Fraction(2) ** e > a:
+        e -= 1
+    e = max(e, -126)
+    scale = Fraction(2) ** (23 - e)
+    m = a * scale
+    fl = m.numerator // m.denominator
+    rem = m - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return np.float32(sign * float(Fraction(fl) / scale))
+
+
+def fma32(a, b, c):
+    return rn32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def ru32(v):
+    """Smallest FP32 value not below the float64 v."""
+    f = np.float32(v)
+    return f if float(f) >= v else np.nextafter(f, np.float32(np.inf))
+
+
+def folded_drop(q, x, s, thr, one_m=np.float32(1.0 - C_ABS), cd=None):
+    """The screen's drop decision for one pair, FP32 step by step."""
+    n = q.shape[0]
+    cd = c_dot(n) if cd is None else cd
+    qn = np.float32(np.sum(q.astype(np.float64) ** 2))
+    xn = np.float32(np.sum(x.astype(np.float64) ** 2))
+    R = np.float32(np.float32(qn * one_m) - thr)
+    a = np.float32(cd * np.sqrt(qn, dtype=np.float32))
+    cx = np.float32(xn * one_m)
+    sx = np.sqrt(xn, dtype=np.float32)
+    inner = fma32(-a, sx, np.float32(R + cx))
+    return fma32(np.float32(-2.0), s, inner) > 0
+
+
+def screen_cases():
+    rng = np.random.default_rng(11)
+    out = []
+    for n in (128, 256):
+        zq = znorm(np.cumsum(rng.standard_normal((6, n)), axis=1))
+        out += [(zq[i], np.zeros(n, np.float32)) for i in range(3)]  # flat rows
+        out += [(zq[i], (1e-4 * rng.standard_normal(n)).astype(np.float32)) for i in range(3)]
+        out += [(zq[i], (zq[i] + np.float32(1e-3) * rng.standard_normal(n)).astype(np.float32))
+                for i in range(6)]  # near copies
+        mant = rng.integers(0, 4, size=(3, n))
+        v = ((1.0 + (mant + 0.5 - 2.0 ** -6) / 128.0) * 2.0 ** rng.integers(-2, 2, size=(3, n)))
+        out += [(r.astype(np.float32), r.astype(np.float32)) for r in v]  # midpoints, q = x
+        off = (100.0 + rng.standard_normal((4, n))).astype(np.float32)
+        out += [(off[0], off[1]), (off[2], off[2] + np.float32(0.01)), (off[3], np.zeros(n, np.float32))]
+    return out
+
+
+def test_folded_test_never_drops_a_pair_at_the_threshold():
+    for q, x in screen_cases():
+        d2 = float(np.sum((q.astype(np.float64) - x.astype(np.float64)) ** 2))
+        prods = (bf16(q) * bf16(x)).astype(np.float32)[None, :]
+        for s in sums(prods):
+            for thr in (ru32(d2), np.nextafter(ru32(d2), np.float32(np.inf)), ru32(d2 * 1.001)):
+                assert not folded_drop(q, x, s[0], thr), (d2, float(thr))
+
+
+def test_folded_test_still_drops_far_pairs():
+    # the slack is small: pairs well beyond the threshold are dropped
+    rng = np.random.default_rng(12)
+    q = znorm(np.cumsum(rng.standard_normal((20, 256)), axis=1))
+    x = znorm(np.cumsum(rng.standard_normal((20, 256)), axis=1))
+    dropped = 0
+    for i in range(20):
+        d2 = float(np.sum((q[i].astype(np.float64) - x[i].astype(np.float64)) ** 2))
+        s = np.sum((bf16(q[i]) * bf16(x[i])).astype(np.float32), dtype=np.float32)
+        dropped += folded_drop(q[i], x[i], s, np.float32(0.9 * d2))
+    assert dropped == 20
+
+
+def test_norm_terms_need_the_lower_factor():
+    # scaling the norms up by (1 + c_abs) instead of down drops a flat row
+    # exactly at the threshold: the sign of the c_abs term matters
+    wrong = 0
+    for q, x in screen_cases():
+        d2 = float(np.sum((q.astype(np.float64) - x.astype(np.float64)) ** 2))
+        s = np.sum((bf16(q) * bf16(x)).astype(np.float32), dtype=np.float32)
+        wrong += folded_drop(q, x, s, ru32(d2), one_m=np.float32(1.0 + C_ABS))
+    assert wrong > 0
+
+
+def test_rn32_rounds_like_the_fp32_conversion():
+    rng = np.random.default_rng(14)
+    v = rng.standard_normal(2000) * 10.0 ** rng.integers(-8, 8, 2000)
+    for x in v:
+        assert rn32(Fraction(float(x))) == np.float32(x)
+    # exact halfway cases go to the even neighbour
+    assert rn32(Fraction(1) + Fraction(1, 2 ** 24)) == np.float32(1.0)
+    assert rn32(Fraction(1) + Fraction(3, 2 ** 24)) == np.float32(1.0 + 2.0 ** -22)
