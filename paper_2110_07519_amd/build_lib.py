@@ -2,8 +2,11 @@
 
 FP contraction is off everywhere: the summary pass must round every FP32
 step exactly once to give the words the index is defined by; where a kernel
-wants a fused multiply-add it calls it explicitly.  Packed FP32 ops are
-disabled (the kernels use scalar FP32/FP64 arithmetic only).
+wants a fused multiply-add it calls it explicitly.  FP32 division and
+square root are correctly rounded (the z-normalisation's standard deviation
+is a sqrtf whose result must equal IEEE's), which the flag pins rather than
+leaving it to the compiler's default.  Packed FP32 ops are disabled (the
+kernels use scalar FP32/FP64 arithmetic only).
 """
 import os
 import subprocess
@@ -13,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmessi.so")
 SOURCES = ["build.hip", "query.hip", "api.cpp"]
-FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-ffp-contract=off", "-fPIC",
+FLAGS = ["-std=c++17", "-O3", "--offload-arch=gfx950", "-ffp-contract=off",
+         "-fhip-fp32-correctly-rounded-divide-sqrt", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wall"]
 
 

@@ -641,6 +641,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   const int resident = per_cu * ix->n_cus;
   int blocks = resident / std::max(1, nq);
   blocks = std::max(2, std::min(blocks, resident));
+  if (distance == MESSI_ED) blocks = ed_process_blocks(resident);  // the whole grid visits every query
   ScreenDev sc{};
   if (screen) {
     sc.Zb = ix->Zb;

@@ -80,5 +80,6 @@ size_t process_lds_bytes(const QueryParams& qp);
 size_t finalize_lds_bytes(const QueryParams& qp);
 size_t stage1_lds_bytes(const QueryParams& qp);
 int process_blocks_per_cu(const QueryParams& qp);
+int ed_process_blocks(int resident);  // grid of the ED process kernel (every block visits every query)
 
 }  // namespace messi

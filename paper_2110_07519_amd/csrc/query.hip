@@ -12,12 +12,14 @@
 //            writes its leaves' 512-series chunks in ascending order of
 //            2048 logarithmic bound buckets: the ascending-bound order the
 //            paper's priority queues give, kept per shard.
-//   process  waves take chunks in that order through the shards' atomic
-//            counters (the queues' DeleteMin); per chunk: series bounds from the table
-//            in LDS, [LB_Keogh,] FP32 refinement, the k best kept by a
-//            lock-free atomicMin cascade.  A wave stops at the first leaf
-//            whose bucket starts above the current k-th best (every later
-//            leaf is at least that far).
+//   process  chunks are taken in that order (the queues' DeleteMin): for
+//            DTW by blocks through the shards' atomic counters, for ED by
+//            the waves of a block from the block's share of every shard,
+//            through counters in LDS; per chunk: series bounds from the
+//            table in LDS, [LB_Keogh,] FP32 refinement, the k best kept by
+//            a lock-free atomicMin cascade.  A shard (or a block's share of
+//            it) stops at the first chunk whose bucket starts above the
+//            current k-th best (every later chunk is at least that far).
 //   finalize FP64 recheck of the near ties and the exact (distance, id)
 //            order of the answer.
 //
@@ -71,6 +73,30 @@ __device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsig
   return a < b ? a : b;
 }
 
+// Workgroup-scope atomics on LDS words shared by the waves of a block.
+__device__ __forceinline__ int lds_add(int* a, int v) {
+  return __hip_atomic_fetch_add(a, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ int lds_load_acq(int* a) {
+  return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_store_rel(int* a, int v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ unsigned lds_load_acq_u(unsigned* a) {
+  return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_or_u(unsigned* a, unsigned v) {
+  __hip_atomic_fetch_or(a, v, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Lane 0's 64-bit value, to every lane (lane 0 must be active).
+__device__ __forceinline__ unsigned long long first_lane_u64(unsigned long long v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+
 // Squared ED between an LDS query and a global row, one wave.
 __device__ __forceinline__ float ed_wave(const float* __restrict__ zq, const float* __restrict__ x,
                                          int len, int lane) {
@@ -96,61 +122,89 @@ __device__ __forceinline__ float ed_wave(const float* __restrict__ zq, const flo
 
 // Squared ED (or LB_Keogh) of up to eight rows at once, their loads in
 // flight together.  Rows are given by wave-uniform positions and an active
-// mask; results for inactive rows are undefined.
+// mask; results for inactive rows are undefined.  Every row is loaded,
+// active or not (an inactive row reads the first active one, which the
+// caches then serve): a load under a per-row branch would be waited for
+// before the next one issues, one memory round trip per row.
 constexpr int kGroup = 8;
 
-__device__ __forceinline__ void ed_group(const float* __restrict__ zq, const float* __restrict__ Z,
-                                         int len, const int (&pos)[kGroup], unsigned act, int lane,
-                                         float (&out)[kGroup]) {
-  float acc[kGroup];
+template <int G>
+__device__ __forceinline__ void group_rows(const float* __restrict__ Z, int len, const int (&pos)[G],
+                                           unsigned& act, const float* (&row)[G]) {
+  act = __builtin_amdgcn_readfirstlane(act);
+  const int lead = pos[__builtin_ctz(act | (1u << (G - 1)))];
 #pragma unroll
-  for (int c = 0; c < kGroup; ++c) acc[c] = 0.0f;
+  for (int c = 0; c < G; ++c) {
+    const int pc = __builtin_amdgcn_readfirstlane(((act >> c) & 1u) ? pos[c] : lead);
+    row[c] = Z + (int64_t)pc * len;
+  }
+}
+
+template <int G>
+__device__ __forceinline__ void ed_rows(const float* __restrict__ zq, const float* __restrict__ Z,
+                                        int len, const int (&pos)[G], unsigned act, int lane,
+                                        float (&out)[G]) {
+  const float* row[G];
+  group_rows<G>(Z, len, pos, act, row);
+  float acc[G];
+#pragma unroll
+  for (int c = 0; c < G; ++c) acc[c] = 0.0f;
   if ((len & 3) == 0) {
     for (int t = 4 * lane; t < len; t += 4 * kWave) {
       const float4 b = *reinterpret_cast<const float4*>(zq + t);
+      float4 x[G];
 #pragma unroll
-      for (int c = 0; c < kGroup; ++c) {
-        if ((act >> c) & 1u) {
-          const float4 x = *reinterpret_cast<const float4*>(Z + (int64_t)pos[c] * len + t);
-          const float e0 = x.x - b.x, e1 = x.y - b.y, e2 = x.z - b.z, e3 = x.w - b.w;
-          acc[c] = __builtin_fmaf(e0, e0, acc[c]);
-          acc[c] = __builtin_fmaf(e1, e1, acc[c]);
-          acc[c] = __builtin_fmaf(e2, e2, acc[c]);
-          acc[c] = __builtin_fmaf(e3, e3, acc[c]);
-        }
+      for (int c = 0; c < G; ++c) x[c] = *reinterpret_cast<const float4*>(row[c] + t);
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        const float e0 = x[c].x - b.x, e1 = x[c].y - b.y, e2 = x[c].z - b.z, e3 = x[c].w - b.w;
+        acc[c] = __builtin_fmaf(e0, e0, acc[c]);
+        acc[c] = __builtin_fmaf(e1, e1, acc[c]);
+        acc[c] = __builtin_fmaf(e2, e2, acc[c]);
+        acc[c] = __builtin_fmaf(e3, e3, acc[c]);
       }
     }
   } else {
     for (int t = lane; t < len; t += kWave) {
       const float b = zq[t];
+      float x[G];
 #pragma unroll
-      for (int c = 0; c < kGroup; ++c) {
-        if ((act >> c) & 1u) {
-          const float e = Z[(int64_t)pos[c] * len + t] - b;
-          acc[c] = __builtin_fmaf(e, e, acc[c]);
-        }
+      for (int c = 0; c < G; ++c) x[c] = row[c][t];
+#pragma unroll
+      for (int c = 0; c < G; ++c) {
+        const float e = x[c] - b;
+        acc[c] = __builtin_fmaf(e, e, acc[c]);
       }
     }
   }
 #pragma unroll
-  for (int c = 0; c < kGroup; ++c) out[c] = ((act >> c) & 1u) ? wave_sum(acc[c]) : 0.0f;
+  for (int c = 0; c < G; ++c) out[c] = ((act >> c) & 1u) ? wave_sum(acc[c]) : 0.0f;
+}
+
+__device__ __forceinline__ void ed_group(const float* __restrict__ zq, const float* __restrict__ Z,
+                                         int len, const int (&pos)[kGroup], unsigned act, int lane,
+                                         float (&out)[kGroup]) {
+  ed_rows<kGroup>(zq, Z, len, pos, act, lane, out);
 }
 
 __device__ __forceinline__ void lbk_group(const float* __restrict__ U, const float* __restrict__ L,
                                           const float* __restrict__ Z, int len, const int (&pos)[kGroup],
                                           unsigned act, int lane, float (&out)[kGroup]) {
+  const float* row[kGroup];
+  group_rows<kGroup>(Z, len, pos, act, row);
   float acc[kGroup];
 #pragma unroll
   for (int c = 0; c < kGroup; ++c) acc[c] = 0.0f;
   for (int t = lane; t < len; t += kWave) {
     const float u = U[t], l = L[t];
+    float x[kGroup];
+#pragma unroll
+    for (int c = 0; c < kGroup; ++c) x[c] = row[c][t];
 #pragma unroll
     for (int c = 0; c < kGroup; ++c) {
-      if ((act >> c) & 1u) {
-        const float v = Z[(int64_t)pos[c] * len + t];
-        const float e = fmaxf(v - u, 0.0f) + fmaxf(l - v, 0.0f);  // one of the two is zero
-        acc[c] = __builtin_fmaf(e, e, acc[c]);
-      }
+      const float v = x[c];
+      const float e = fmaxf(v - u, 0.0f) + fmaxf(l - v, 0.0f);  // one of the two is zero
+      acc[c] = __builtin_fmaf(e, e, acc[c]);
     }
   }
 #pragma unroll
@@ -911,6 +965,17 @@ __device__ __forceinline__ void log_approx(const QueryParams& p, const QueryStat
 
 constexpr int kUnroll = kChunkSeries / kWave;  // words per lane per chunk
 
+// ED process kernel shape: waves per block, and each wave's survivor list
+// (refined once it holds kEdDefer entries, so a whole chunk always fits)
+constexpr int kEdWaves = 16;
+constexpr int kEdThreads = kEdWaves * kWave;
+static_assert(kShards % kEdWaves == 0, "a shard's waves come from whole blocks");
+constexpr int kEdRows = 8;               // rows refined together (their loads in flight at once)
+constexpr int kEdLoad = 8;  // words per lane loaded together in the bound pass
+constexpr unsigned kEdTick = 16;  // wave-steps of a block per read of the global k-th best
+constexpr int kEdDefer = 2 * kEdRows;
+constexpr int kEdList = kChunkSeries + kEdDefer;
+
 template <int R>
 struct ProcShape {
   static constexpr int waves = (R == -1) ? kGrab : 4;  // one chunk per wave (DTW: LDS for its lists)
@@ -1309,9 +1374,347 @@ __global__ __launch_bounds__(ProcShape<R>::threads) void k_process(IndexDev ix, 
   process_body<R, MASK, LBI>(ix, p, s);
 }
 
-__global__ __launch_bounds__(ProcShape<-1>::threads) void k_process_ed(IndexDev ix, QueryParams p,
-                                                                       QueryState s) {
-  process_body<-1, false, false>(ix, p, s);
+// ---------------------------------------------------------------------------
+// ED process kernel.  Every wave runs on its own, with no block barrier
+// between chunks: while some waves wait on memory, others compute bounds,
+// so the loads of many chunks are in flight on every CU at once.  The
+// chunks of a shard are dealt to waves statically: of the grid's G waves,
+// G / kShards take each shard, and wave j of a shard takes its chunks
+// j, j + G / kShards, ... in the shard's ascending bound order, so the
+// waves sweep every shard's order together and later chunks meet a
+// tighter k-th best.  A wave stops at its first chunk whose bucket starts
+// above the k-th best (all its later chunks are above too).  Per chunk it
+// computes the series bounds from the table in LDS, appends the survivors
+// to its own list in LDS and refines them eight rows at a time once the
+// list holds two groups.  Every block visits every query of the launch
+// (starting with query blockIdx.x mod nq), building the query's table once
+// per visit.
+
+// CB: the symbols' bits when known at compile time (8, the paper's
+// cardinality: the table's segment offsets become immediates), else 0.
+template <int CB>
+__global__ __launch_bounds__(kEdThreads) void k_process_ed(IndexDev ix, QueryParams p,
+                                                         QueryState s) {
+  constexpr int kW = kEdWaves;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+  const int len = p.len, card = CB ? (1 << CB) : (1 << p.card_bits);
+  extern __shared__ float sm[];
+  // the block's copy of the k-th best: waves read it here, and only one
+  // wave-step in kEdTick reads the global slot (every wave of the grid
+  // reading that one address would queue at the memory channel holding it)
+  __shared__ unsigned long long s_ckey;
+  __shared__ unsigned s_tick;
+  // work sharing of the refinement: wave w's published list holds s_n[w]
+  // entries, handed out from s_h[w] on; s_busy[w] counts other waves
+  // copying from it, s_done the waves whose own chunks are all done
+  __shared__ int s_n[kW], s_h[kW], s_busy[kW], s_done;
+  // the [16][card] table: in static LDS when the cardinality is known at
+  // compile time (its place, and so every lookup's offset, is then a
+  // constant), else at the head of the dynamic LDS
+  __shared__ float s_table[CB ? kMaxSeg << CB : 1];
+  float* table = CB ? s_table : sm;
+  float* ql = sm + kMaxSeg * card;                             // query row [len]
+  int* const lpos_all = reinterpret_cast<int*>(ql + len);       // survivors [kW][kEdList]
+  float* const llb_all = reinterpret_cast<float*>(lpos_all + kW * kEdList);  // their bounds
+  int* lpos = lpos_all + wv * kEdList;                         // this wave's list
+  float* llb = llb_all + wv * kEdList;
+  const unsigned long long below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  // The block's kW streams of chunks: stream x is shard
+  // (blockIdx.x mod kBpS) kW + x from its chunk `place` on, every stride-th
+  // chunk, where stride is the number of blocks that share a shard.  The
+  // places of a block's streams lie stride / kW apart, so the front of
+  // the shards (the chunks of lowest bound, which hold most survivors)
+  // falls on different blocks.  The block's waves take the streams' chunks
+  // through counters in LDS, so the block's chunks are shared out evenly.
+  constexpr int kBpS = kShards / kW;  // blocks whose streams cover every shard once
+  constexpr unsigned kAllStreams = (1u << kW) - 1;
+  const int stride = (int)gridDim.x / kBpS;
+  __shared__ int s_first[kW], s_end[kW], s_idx[kW];
+  __shared__ unsigned s_sdone;
+  if (tid < kW) {
+    const int shx = ((int)blockIdx.x % kBpS) * kW + tid;
+    const int plx = ((int)blockIdx.x / kBpS + tid * (stride / kW > 0 ? stride / kW : 1)) % stride;
+    s_first[tid] = ix.shard_off[shx] + plx;
+    s_end[tid] = ix.shard_off[shx + 1];
+  }
+
+  for (int visit = 0; visit < p.nq; ++visit) {
+    const int q = (int)((blockIdx.x + (unsigned)visit) % (unsigned)p.nq);
+    const int k = k_of(p, s, q);
+    if (visit == 0 && (int)blockIdx.x == q) log_approx(p, s, q, tid, blockDim.x);
+    {
+      // the series table from the query's PAA (the same arithmetic as k_prep)
+      const float* pu = s.paa + ((int64_t)q * 3 + 1) * kMaxSeg;
+      const float* pl = s.paa + ((int64_t)q * 3 + 2) * kMaxSeg;
+      const int cb = p.card_bits;
+      const float fm = (float)p.m;
+      for (int i = tid; i < kMaxSeg * card; i += blockDim.x) {
+        const int sg = i >> cb, j = i & (card - 1);
+        float v = 0.0f;
+        if (sg < p.w) {
+          const float g = fmaxf(ix.bp[j] - pu[sg], 0.0f) + fmaxf(pl[sg] - ix.bp[j + 1], 0.0f);
+          v = fm * (g * g);
+        }
+        table[i] = v;
+      }
+      const float* zq = s.zq + (int64_t)q * len;
+      for (int t = tid; t < len; t += blockDim.x) ql[t] = zq[t];
+      if (tid == 0) {
+        s_ckey = load_key(&s.slots[(int64_t)q * p.k + k - 1]);
+        s_tick = 0;
+        s_done = 0;
+      }
+      if (tid < kW) {
+        s_n[tid] = 0;
+        s_h[tid] = 0;
+        s_busy[tid] = 0;
+        s_idx[tid] = 0;
+      }
+      if (tid == 0) s_sdone = 0;
+    }
+    __syncthreads();
+    unsigned long long* slots = s.slots + (int64_t)q * p.k;
+    const int P0 = (int)s.approx_range[2 * q], P1 = (int)s.approx_range[2 * q + 1];
+    const float eta = s.eta[q];
+    const unsigned long long* items = s.items + (int64_t)q * p.item_cap;
+    const int2* ranges = s.ranges + (int64_t)q * p.item_cap;
+    unsigned long long c_lb = 0, c_ref = 0, c_leaf = 0;
+    unsigned long long ckey = s_ckey;
+    int nl = 0;  // survivors in this wave's list (wave-uniform)
+
+    // refinement of up to kEdRows entries taken from a list, each bound
+    // re-checked against the latest k-th best the wave knows
+    auto refine_rows = [&](const int (&gp)[kEdRows], const float (&gl)[kEdRows], int cnt) {
+      const float tcur = lb_threshold(key_dist(ckey), eta, p);
+      unsigned act = 0;
+#pragma unroll
+      for (int c = 0; c < kEdRows; ++c) act |= (c < cnt && gl[c] <= tcur) ? (1u << c) : 0u;
+      if (!act) return;
+      int gr[kEdRows];
+#pragma unroll
+      for (int c = 0; c < kEdRows; ++c) gr[c] = ix.zrow ? ix.zrow[gp[c]] : gp[c];
+      float dv[kEdRows];
+      ed_rows<kEdRows>(ql, ix.Z, len, gr, act, lane, dv);
+      c_ref += (lane == 0) ? __popc(act) : 0;
+      // the rare rows within the window of the k-th best, one at a time
+      // (one copy of the offer's code)
+      unsigned win = 0;
+#pragma unroll
+      for (int c = 0; c < kEdRows; ++c) win |= (((act >> c) & 1u) && dv[c] <= key_dist(ckey) * p.win) ? (1u << c) : 0u;
+      win = __builtin_amdgcn_readfirstlane(win);
+      bool ch = false;
+      if (win) {
+        // lane c holds row c's distance and position
+        float dl = 0.0f;
+        int gl2 = 0;
+#pragma unroll
+        for (int c = 0; c < kEdRows; ++c) {
+          dl = lane == c ? dv[c] : dl;
+          gl2 = lane == c ? gp[c] : gl2;
+        }
+        while (win) {
+          const int c = __builtin_ctz(win);
+          win &= win - 1;
+          const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dl), c));
+          const int gc = __builtin_amdgcn_readlane(gl2, c);
+          if (lane == 0) ch |= offer(ix, p, s, q, d, gc, ckey, true);
+        }
+      }
+      if (__ballot(ch)) {
+        ckey = umin64(ckey, load_key(&slots[k - 1]));
+        if (lane == 0) atomicMin(&s_ckey, ckey);
+      }
+    };
+    // take up to kEdRows entries of wave w's published list; returns how many
+    auto take = [&](int w, int (&gp)[kEdRows], float (&gl)[kEdRows]) {
+      int n = 0, h = 0;
+      if (lane == 0) {
+        n = lds_load_acq(&s_n[w]);
+        h = n > 0 ? lds_add(&s_h[w], kEdRows) : 0;
+      }
+      n = __builtin_amdgcn_readfirstlane(n);
+      h = __builtin_amdgcn_readfirstlane(h);
+      const int cnt = n - h < 0 ? 0 : (n - h > kEdRows ? kEdRows : n - h);
+#pragma unroll
+      for (int c = 0; c < kEdRows; ++c) {
+        gp[c] = c < cnt ? lpos_all[w * kEdList + h + c] : 0;
+        gl[c] = c < cnt ? llb_all[w * kEdList + h + c] : INFINITY;
+      }
+      return cnt;
+    };
+    // the owner's refinement of its full list: publish it, take groups from
+    // it until none is left (other waves may take some), wait until no
+    // other wave is still copying from it, then start a new list
+    auto refine_own = [&]() {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) lds_store_rel(&s_n[wv], nl);
+      for (;;) {
+        int gp[kEdRows];
+        float gl[kEdRows];
+        const int cnt = take(wv, gp, gl);
+        if (cnt == 0) break;
+        refine_rows(gp, gl, cnt);
+      }
+      if (lane == 0) {
+        while (lds_load_acq(&s_busy[wv]) != 0) __builtin_amdgcn_s_sleep(1);
+        lds_store_rel(&s_n[wv], 0);
+        lds_store_rel(&s_h[wv], 0);
+      }
+      nl = 0;
+    };
+    // one group taken from another wave's published list, if any has
+    // entries left (the first such wave after this one)
+    auto steal = [&]() {
+      int rem = 0;
+      if (lane < kW && lane != wv) rem = lds_load_acq(&s_n[lane]) - lds_load_acq(&s_h[lane]);
+      const unsigned long long any = __ballot(rem > 0);
+      if (!any) return false;
+      const unsigned long long rot = (any >> (wv + 1)) | (any << (kW - wv - 1));
+      const int v = (wv + 1 + __ffsll((long long)(rot & ((1ull << kW) - 1))) - 1) % kW;
+      if (lane == 0) lds_add(&s_busy[v], 1);
+      int gp[kEdRows];
+      float gl[kEdRows];
+      const int cnt = take(v, gp, gl);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      if (lane == 0) lds_add(&s_busy[v], -1);
+      if (cnt > 0) refine_rows(gp, gl, cnt);
+      return true;
+    };
+
+    // the next chunk of a stream not yet done, the streams visited from a
+    // place that rotates with the wave and the step; false once every
+    // stream is done (each failed try marks one, so at most kW + 1 tries)
+    unsigned rot = (unsigned)wv;
+    auto grab = [&](int& x, int& c) {
+      int rx = 0, rc = -1;
+      if (lane == 0) {
+#pragma unroll 1
+        for (int tries = 0; tries <= kW; ++tries) {
+          const unsigned dn = lds_load_acq_u(&s_sdone);
+          if (dn == kAllStreams) break;
+          const int x0 = (int)(rot++ % kW);
+          const unsigned free = ~((dn >> x0) | (dn << (kW - x0))) & kAllStreams;
+          const int xx = (x0 + __ffs((int)free) - 1) % kW;
+          const int cc = s_first[xx] + lds_add(&s_idx[xx], 1) * stride;
+          if (cc < s_end[xx]) {
+            rx = xx;
+            rc = cc;
+            break;
+          }
+          lds_or_u(&s_sdone, 1u << xx);  // stream exhausted
+        }
+      }
+      x = __builtin_amdgcn_readfirstlane(rx);
+      c = __builtin_amdgcn_readfirstlane(rc);
+      return c >= 0;
+    };
+    // the first chunk's record; each step loads the next one's (and, now
+    // and then, the global k-th best) while the current chunk is worked on
+    int x = 0, c = -1;
+    grab(x, c);
+    unsigned long long item = 0;
+    int2 rg = make_int2(0, 0);
+    if (c >= 0) {
+      item = items[c];
+      rg = ranges[c];
+    }
+    for (;;) {
+      // stop: every stream of the block is done
+      const bool stop = c < 0;
+      int nx = 0, cn = -1;
+      unsigned long long n_item = 0, nkey = ~0ull;
+      int2 n_rg = make_int2(0, 0);
+      if (!stop) {
+        if (grab(nx, cn)) {
+          n_item = items[cn];
+          n_rg = ranges[cn];
+        }
+        // one wave-step in kEdTick of the block refreshes the block's copy
+        unsigned tick = 0;
+        if (lane == 0) tick = atomicAdd(&s_tick, 1u);
+        if (lane == 0 && tick % kEdTick == 0) nkey = load_key(&slots[k - 1]);
+        const float tadj = lb_threshold(key_dist(ckey), eta, p);
+        const float lb = key_dist(item);
+        if (lb <= tadj) {
+          ++c_leaf;
+          // series bounds (Algorithm 9): sixteen table lookups, summed
+          // pairwise; kEdLoad words per lane in flight at once, each
+          // bound's survivor appended to the wave's list once known
+#pragma unroll
+          for (int h = 0; h < kUnroll; h += kEdLoad) {
+            uint4 wd[kEdLoad];
+#pragma unroll
+            for (int u = 0; u < kEdLoad; ++u) {
+              const int pos = rg.x + lane + (h + u) * kWave;
+              wd[u] = ix.words[pos < rg.y ? pos : rg.x];
+            }
+#pragma unroll
+            for (int u = 0; u < kEdLoad; ++u) {
+              const int pos = rg.x + lane + (h + u) * kWave;
+              bool ok = pos < rg.y && !(pos >= P0 && pos < P1);
+              float lbv = 0.0f;
+              if (ok) {
+                float t[kMaxSeg];
+#pragma unroll
+                for (int sg = 0; sg < kMaxSeg; ++sg) t[sg] = table[sg * card + (int)byte_of(wd[u], sg)];
+#pragma unroll
+                for (int w2 = kMaxSeg / 2; w2 >= 1; w2 >>= 1)
+#pragma unroll
+                  for (int sg = 0; sg < w2; ++sg) t[sg] = t[sg] + t[sg + w2];
+                lbv = t[0];
+                ++c_lb;
+                ok = lbv <= tadj;
+              }
+              const unsigned long long m = __ballot(ok);
+              if (ok) {
+                const int at = nl + __popcll(m & below);
+                lpos[at] = pos;
+                llb[at] = lbv;
+              }
+              nl += __popcll(m);
+            }
+          }
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        } else if (bucket_floor(lb_bucket(lb * p.lb_scale)) > tadj * p.lb_scale) {
+          // this chunk's bucket starts above the k-th best: so do those of
+          // the stream's later chunks
+          if (lane == 0) lds_or_u(&s_sdone, 1u << x);
+        }
+      }
+      if (nl >= kEdDefer || (stop && nl > 0)) refine_own();
+      if (stop) break;
+      nkey = first_lane_u64(nkey);
+      if (nkey != ~0ull && lane == 0) atomicMin(&s_ckey, nkey);
+      ckey = umin64(ckey, first_lane_u64(s_ckey));
+      x = nx;
+      c = cn;
+      item = n_item;
+      rg = n_rg;
+    }
+    // this wave's chunks are done: help the others until every wave of
+    // the block is done and no list has entries left
+    if (lane == 0) lds_add(&s_done, 1);
+    for (;;) {
+      if (steal()) continue;
+      int done = 0;
+      if (lane == 0) done = lds_load_acq(&s_done);
+      if (__builtin_amdgcn_readfirstlane(done) == kW) break;
+      __builtin_amdgcn_s_sleep(16);
+    }
+    // statistics
+    for (int o = 32; o >= 1; o >>= 1) {
+      c_lb += __shfl_xor(c_lb, o, kWave);
+      c_ref += __shfl_xor(c_ref, o, kWave);
+    }
+    if (lane == 0) {
+      unsigned long long* stq = s.stats + (int64_t)q * kStatCount;
+      if (c_leaf) atomicAdd(&stq[kStatLeavesKept], c_leaf);
+      if (c_lb) atomicAdd(&stq[kStatSeriesLb], c_lb);
+      if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
+    }
+    __syncthreads();  // LDS is reloaded for the next query
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1899,14 +2302,14 @@ size_t process_lds_bytes(const QueryParams& p) {
   bool mask;
   const int R = band_of(p, &mask);
   size_t w = 0;
-  if (R == -1) w = process_lds_words<-1>(p);
+  if (R == -1) w = (size_t)kMaxSeg * (1 << p.card_bits) + p.len + 2 * (size_t)kEdWaves * kEdList;
   else if (R == -2) w = process_lds_words<-2>(p);
   else w = process_lds_words<0>(p) + 2 * (size_t)R;  // the padded query grows with R
   return w * sizeof(float);
 }
 
 static int process_threads(int R) {
-  return R == -2 ? ProcShape<-2>::threads : (R == -1 ? ProcShape<-1>::threads : ProcShape<0>::threads);
+  return R == -2 ? ProcShape<-2>::threads : (R == -1 ? kEdThreads : ProcShape<0>::threads);
 }
 
 size_t finalize_lds_bytes(const QueryParams& p) {
@@ -1972,8 +2375,11 @@ void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState&
   const dim3 g((unsigned)blocks_per_query * (unsigned)qp.nq);  // block b starts on query b % nq
   const dim3 b(process_threads(R));
   const size_t lds = process_lds_bytes(qp);
-  if (R == -1) {
-    hipLaunchKernelGGL(k_process_ed, g, b, lds, st, ix, qp, qs);
+  if (R == -1) {  // one grid for all queries: blocks_per_query is its size
+    if (qp.card_bits == 8)
+      hipLaunchKernelGGL(k_process_ed<8>, dim3((unsigned)blocks_per_query), b, lds, st, ix, qp, qs);
+    else
+      hipLaunchKernelGGL(k_process_ed<0>, dim3((unsigned)blocks_per_query), b, lds, st, ix, qp, qs);
     return;
   }
   if (qp.lb_improved) {
@@ -2051,6 +2457,12 @@ void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& 
   }
 }
 
+int ed_process_blocks(int resident) {
+  // the ED kernel deals every shard's chunks to gridDim.x * kEdWaves / kShards waves
+  constexpr int unit = kShards / kEdWaves;
+  return resident < unit ? unit : resident - resident % unit;
+}
+
 int process_blocks_per_cu(const QueryParams& qp) {
   bool mask;
   const int R = band_of(qp, &mask);
@@ -2059,7 +2471,8 @@ int process_blocks_per_cu(const QueryParams& qp) {
   int nb = 0;
   hipError_t e = hipSuccess;
   if (R == -1) {
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process_ed, th, lds);
+    e = qp.card_bits == 8 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process_ed<8>, th, lds)
+                          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process_ed<0>, th, lds);
   } else if (qp.lb_improved) {
     switch (R) {
       case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_process<8, true, true>, th, lds); break;
