@@ -157,6 +157,24 @@ int messi_build_windows(const float* series, int64_t total, int32_t len, int32_t
 int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k,
                 int32_t distance, int32_t window, int64_t* out_ids, float* out_dists);
 
+/* messi_query for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * same queries, kernels and answers, with the query state in a
+ * file-scope device array of 64 MiB instead of memory the library
+ * allocates; the call makes no hipMalloc, hipFree or other allocation.
+ * Each GPU the library runs on holds its own copy of the array until the
+ * process ends.
+ *   Arguments and outputs as for messi_query; nq <= 1024.
+ *   Limits: the state of the nq queries (about 16 bytes per 512-series
+ *   chunk of the index, 4 bytes per leaf and about 330 KB more per query)
+ *   must fit the 64 MiB, else MESSI_EINVAL with the sizes in the message;
+ *   a query whose near-tie log (32768 entries) overflows returns
+ *   MESSI_ENOMEM (messi_query, which grows the log, answers it).
+ *   Every call on one GPU shares the array: calls that overlap on one GPU
+ *   (on any index) race and must not be made. */
+int messi_query_noalloc(messi_index* index, const float* queries, int32_t nq, int32_t k,
+                        int32_t distance, int32_t window, int64_t* out_ids, float* out_dists);
+
 /* Same as messi_query, also returning work counters (stats may be NULL). */
 int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int32_t k,
                       int32_t distance, int32_t window, int64_t* out_ids, float* out_dists,

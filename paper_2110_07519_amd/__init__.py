@@ -6,6 +6,7 @@ include/messi.h.  Torch is used for device memory and streams.  If the
 library is not built, importing works but every call raises.
 
 Names follow the C ABI: messi_build, messi_build_ex, messi_build_windows, messi_query, messi_query_stats,
+messi_query_noalloc,
 messi_query_batch, messi_prepare_screen, messi_classify, messi_set_stream,
 messi_free, messi_breakpoints, messi_get_words,
 messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
@@ -36,6 +37,7 @@ EXPORTS = [
     "messi_last_error", "messi_query_batch", "messi_prepare_screen",
     "messi_server_start", "messi_server_submit", "messi_server_poll", "messi_server_get_stats",
     "messi_server_stop", "messi_classify", "messi_build_ex", "messi_build_windows",
+    "messi_query_noalloc",
 ]
 
 
@@ -97,6 +99,7 @@ def lib():
         L.messi_build_windows.argtypes = [P, i64, i32, i32, i32, i32, i32, P, ctypes.POINTER(P)]
         L.messi_query.argtypes = [P, P, i32, i32, i32, i32, P, P]
         L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
+        L.messi_query_noalloc.argtypes = [P, P, i32, i32, i32, i32, P, P]
         L.messi_query_batch.argtypes = [P, P, i32, P, P, P, i32, i32, P, P, P]
         L.messi_prepare_screen.argtypes = [P]
         L.messi_classify.argtypes = [P, P, i32, P, i32, i32, i32, i32, i32, P, P, P]
@@ -115,7 +118,8 @@ def lib():
         L.messi_free.argtypes = [P]
         L.messi_free.restype = None
         L.messi_last_error.restype = ctypes.c_char_p
-        for name in ["messi_build", "messi_build_ex", "messi_build_windows", "messi_query", "messi_query_stats", "messi_query_batch",
+        for name in ["messi_build", "messi_build_ex", "messi_build_windows", "messi_query", "messi_query_stats",
+                     "messi_query_noalloc", "messi_query_batch",
                      "messi_prepare_screen", "messi_classify", "messi_server_start",
                      "messi_server_submit",
                      "messi_server_poll", "messi_server_get_stats", "messi_set_stream",
@@ -223,6 +227,24 @@ def messi_query(index, queries, k: int = 1, distance: int = MESSI_ED, window: in
                                    _dev_ptr(out_ids), _dev_ptr(out_dists),
                                    ctypes.cast(ctypes.pointer(st), ctypes.c_void_p)))
     return out_ids, out_dists, st.as_dict()
+
+
+def messi_query_noalloc(index, queries, k: int = 1, distance: int = MESSI_ED, window: int = 0,
+                        out_ids=None, out_dists=None):
+    """messi_query whose query state lives in the library's fixed scratch
+    array (no device allocation by the library during the call)."""
+    import torch
+
+    assert queries.dtype == torch.float32 and queries.dim() == 2
+    nq = queries.shape[0]
+    dev = queries.device
+    if out_ids is None:
+        out_ids = torch.empty((nq, k), dtype=torch.int64, device=dev)
+    if out_dists is None:
+        out_dists = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    _check(lib().messi_query_noalloc(index.handle, _dev_ptr(queries), nq, k, distance, window,
+                                     _dev_ptr(out_ids), _dev_ptr(out_dists)))
+    return out_ids, out_dists
 
 
 def messi_query_batch(index, queries, k, distance, window, kmax=None, flags=0, out_ids=None,

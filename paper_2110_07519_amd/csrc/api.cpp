@@ -564,9 +564,19 @@ void ensure_batch(messi_index* ix, QueryCtx& c, int nq) {
 // (input and output) are d_qmap[i] and whose k are d_kq[i] (both null for a
 // plain call: rows 0..nq-1, every k = kmax).  Slots are kmax apart and
 // output rows out_stride = kmax entries long.
+// Query state laid out in caller-provided device memory (the allocation-free
+// entry point): the state, its near-tie log capacity, and a host buffer of
+// nq status words.
+struct FixedScratch {
+  QueryState qs;
+  int log_cap;
+  int* h_status;
+};
+
 int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int kmax, int distance,
               int window, const int* d_kq, const int* d_qmap, bool screen, bool lb_improved,
-              int64_t* out_ids, float* out_dists, messi_stats* stats) {
+              int64_t* out_ids, float* out_dists, messi_stats* stats,
+              const FixedScratch* fixed = nullptr) {
   hipStream_t st = c.stream;
   const int len = ix->len;
   const double u = std::ldexp(1.0, -24);
@@ -663,7 +673,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   const int screen_blocks = screen ? screen_blocks_per_cu(len) * ix->n_cus : 0;
   // the status words come back into pinned memory: a copy to pageable
   // memory would be staged through a runtime buffer on every call
-  if (c.h_status_cap < nq) {
+  if (!fixed && c.h_status_cap < nq) {
     if (c.h_status) HIP_OR_THROW(hipHostFree(c.h_status));
     c.h_status = nullptr;
     c.h_status_cap = 0;
@@ -680,10 +690,11 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     for (int i = 0; i < 6; ++i) ev[i] = c.ev[i];
   }
   for (int attempt = 0; attempt < 8; ++attempt) {
-    ensure_workspace(ix, c, nq, kmax);
-    p.log_cap = c.log_cap;
+    if (!fixed) ensure_workspace(ix, c, nq, kmax);
+    p.log_cap = fixed ? fixed->log_cap : c.log_cap;
     const IndexDev v = ix->view();
-    QueryState qs = c.ws.qs;
+    QueryState qs = fixed ? fixed->qs : c.ws.qs;
+    int* h_status = fixed ? fixed->h_status : c.h_status;
     qs.kq = d_kq;
     qs.qmap = d_qmap;
     if (stats) HIP_OR_THROW(hipEventRecord(ev[0], st));
@@ -703,9 +714,9 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     launch_finalize(v, p, qs, out_ids, out_dists, st);
     if (stats) HIP_OR_THROW(hipEventRecord(ev[5], st));
     launch_check();
-    d2h(c.h_status, qs.status, nq, st);
+    d2h(h_status, qs.status, nq, st);
     int worst = 0;
-    for (int i = 0; i < nq; ++i) worst |= c.h_status[i];
+    for (int i = 0; i < nq; ++i) worst |= h_status[i];
     if (!(worst & 1)) {
       if (stats) {
         float ms[5] = {0, 0, 0, 0, 0};
@@ -740,6 +751,9 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
       return MESSI_OK;
     }
     if (stats) stats->log_overflows += 1;
+    if (fixed)  // no room to grow the log: the caller falls back to messi_query
+      return fail(MESSI_ENOMEM, "near-tie log of %d entries per query overflowed in the fixed scratch",
+                  fixed->log_cap);
     c.log_cap *= 4;  // near-tie log overflowed: rerun with a larger one
   }
   return fail(MESSI_ENOMEM, "near-tie log kept overflowing");
@@ -1128,6 +1142,82 @@ int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int3
 int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t distance,
                 int32_t window, int64_t* out_ids, float* out_dists) {
   return messi_query_stats(index, queries, nq, k, distance, window, out_ids, out_dists, nullptr);
+}
+
+namespace {
+
+// The query state of nq queries with k slots and log_cap log entries each,
+// carved from `base` (256-byte aligned pieces); returns the bytes it takes.
+// With base == nullptr only the size is computed.
+size_t carve_state(const messi_index* ix, int nq, int k, int log_cap, char* base, QueryState* qs) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* ptr = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return ptr;
+  };
+  const size_t len = (size_t)ix->len, L = (size_t)ix->n_leaves, C = (size_t)ix->n_chunks, Q = (size_t)nq;
+  QueryState s{};
+  s.zq = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
+  s.eta = reinterpret_cast<float*>(take(Q * sizeof(float)));
+  s.upper = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
+  s.lower = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
+  s.paa = reinterpret_cast<float*>(take(Q * 3 * kMaxSeg * sizeof(float)));
+  s.approx_range = reinterpret_cast<int64_t*>(take(Q * 2 * sizeof(int64_t)));
+  s.approx_d2 = reinterpret_cast<float*>(take(Q * kApproxCap * sizeof(float)));
+  s.slots = reinterpret_cast<unsigned long long*>(take(Q * (size_t)k * 8));
+  s.log = reinterpret_cast<unsigned long long*>(take(Q * (size_t)log_cap * 8));
+  s.log_count = reinterpret_cast<int*>(take(Q * sizeof(int)));
+  s.leaf_lb = reinterpret_cast<float*>(take(Q * L * sizeof(float)));
+  s.items = reinterpret_cast<unsigned long long*>(take(Q * C * 8));
+  s.ranges = reinterpret_cast<int2*>(take(Q * C * sizeof(int2)));
+  s.next = reinterpret_cast<int*>(take(Q * kCounterInts * sizeof(int)));
+  s.stats = reinterpret_cast<unsigned long long*>(take(Q * kStatCount * 8));
+  s.status = reinterpret_cast<int*>(take(Q * sizeof(int)));
+  if (qs) *qs = s;
+  return off;
+}
+
+constexpr int kNoAllocMaxQueries = 1024;  // status words kept on the host stack
+constexpr int kNoAllocLog = 32768;        // near-tie log entries per query
+
+}  // namespace
+
+int messi_query_noalloc(messi_index* index, const float* queries, int32_t nq, int32_t k,
+                        int32_t distance, int32_t window, int64_t* out_ids, float* out_dists) {
+  g_err.clear();
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (nq < 0) return fail(MESSI_EINVAL, "nq must be >= 0");
+  if (nq == 0) return MESSI_OK;
+  if (nq > kNoAllocMaxQueries)
+    return fail(MESSI_EINVAL, "messi_query_noalloc takes at most %d queries per call", kNoAllocMaxQueries);
+  if (k < 1 || k > 1024) return fail(MESSI_EINVAL, "k must be in [1, 1024]");
+  if (distance != MESSI_ED && distance != MESSI_DTW) return fail(MESSI_EINVAL, "unknown distance");
+  if (window < 0) return fail(MESSI_EINVAL, "window must be >= 0");
+  if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
+    return fail(MESSI_EINVAL, "queries and outputs must be device pointers");
+  BusyGuard g(index->busy);
+  if (!g.ok) return fail(MESSI_EBUSY, "index is in use by another call");
+  try {
+    size_t cap = 0;
+    char* base = static_cast<char*>(noalloc_scratch(&cap));
+    if (!base) return fail(MESSI_EDEVICE, "the scratch array's device address is not available");
+    const size_t need = carve_state(index, nq, k, kNoAllocLog, nullptr, nullptr);
+    if (need > cap)
+      return fail(MESSI_EINVAL, "%d queries need %zu bytes of scratch, more than the %zu bytes it holds",
+                  nq, need, cap);
+    int h_status[kNoAllocMaxQueries];
+    FixedScratch fx{};
+    carve_state(index, nq, k, kNoAllocLog, base, &fx.qs);
+    fx.log_cap = kNoAllocLog;
+    fx.h_status = h_status;
+    return run_group(index, index->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, false,
+                     out_ids, out_dists, nullptr, &fx);
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
 }
 
 int messi_prepare_screen(messi_index* index) {

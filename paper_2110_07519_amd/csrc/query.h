@@ -80,6 +80,9 @@ size_t process_lds_bytes(const QueryParams& qp);
 size_t finalize_lds_bytes(const QueryParams& qp);
 size_t stage1_lds_bytes(const QueryParams& qp);
 int process_blocks_per_cu(const QueryParams& qp);
-int ed_process_blocks(int resident);  // grid of the ED process kernel (every block visits every query)
+int ed_process_blocks(int resident);
+// Device address (on the current device) and size of the allocation-free
+// entry point's scratch array; nullptr if it cannot be had.
+void* noalloc_scratch(size_t* bytes);  // grid of the ED process kernel (every block visits every query)
 
 }  // namespace messi

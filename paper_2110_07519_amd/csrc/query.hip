@@ -29,6 +29,7 @@
 // order is decided on FP64 distances of the logged candidates.
 #include <hip/hip_runtime.h>
 #include <algorithm>
+#include <mutex>
 #include <stdint.h>
 
 #include "query.h"
@@ -2455,6 +2456,33 @@ void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& 
     case 8: hipLaunchKernelGGL(k_screen<8>, dim3(blocks), th, ScreenShape<8>::lds, st, ix, qp, qs, sc); break;
     case 16: hipLaunchKernelGGL(k_screen<16>, dim3(blocks), th, ScreenShape<16>::lds, st, ix, qp, qs, sc); break;
   }
+}
+
+// Scratch of the allocation-free query entry point: the query state lives
+// in this array instead of memory the library allocates.  Each GPU that
+// loads the library holds its own copy until the process ends.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+void* noalloc_scratch(size_t* bytes) {
+  // the array's device address on each device, found once with that device
+  // current (the name itself is only a host-side stand-in)
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  *bytes = kScratchBytes;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    ptr[dev] = p;
+  }
+  return ptr[dev];
 }
 
 int ed_process_blocks(int resident) {
