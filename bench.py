@@ -28,16 +28,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 MFMA, published
+# Plain (unpacked) FP32 VALU issue: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz,
+# in tera lane-instructions per second (the DTW kernels use no packed ops)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU instructions of one DTW band cell on gfx950: the difference, the
+# minimum of the three neighbours (one v_min3) and the fused square-and-add
+# (the masked bands, which the default radius does not use, add a median)
+DTW_OPS_PER_CELL = 3
 
-# HBM bytes per launch of the leaf-processing kernel over this benchmark's
-# timed queries, from two rocprofv3 --pmc runs of this script (FETCH_SIZE x
-# 2.0 + WRITE_SIZE x 1.0 KiB; factors from a 1 GiB device copy and fill).
-# Valid only for the query kernel sources they were taken on.
-MEASURED_TRAFFIC = {"sources_sha256": "5e452423c2bdba50e258cf4d487d2e2e3ea883a034e256acf9e734c5172599d5",
-                    "bytes_per_launch": 298156081}
+# HBM bytes per launch of the ED process kernel, from two rocprofv3 --pmc
+# runs of this script (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 KiB; factors from
+# a 1 GiB device copy and fill), keyed by the timed query set (steps,
+# warmup): valid only for those queries and for the query kernel sources
+# they were taken on.
+MEASURED_TRAFFIC = {"sources_sha256": "", "by_queries": {}}
 QUERY_SOURCES = ["paper_2110_07519_amd/csrc/query.hip", "paper_2110_07519_amd/csrc/query.h",
                  "paper_2110_07519_amd/csrc/common.h"]
-PHASES = ["prep", "stage1", "stage2", "process", "finalize"]
+PHASES = ["prep", "stage1", "process", "finalize"]
 
 
 def query_sources_digest():
@@ -54,16 +61,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def phase_bytes(st, length, n_leaves, queries):
-    """Algorithmic bytes per launch of each phase (per query), from the
-    work counters: a series word is 16 B, a series row 4*len B, a leaf
-    record (symbols, bits, range) 48 B."""
+def process_bytes(st, length, queries):
+    """Algorithmic bytes per launch of the process kernel (one query per
+    launch): the work the search needs once its final k-th best is known --
+    the 16 B word of every series in a leaf whose bound is within it, and
+    the 4 len B row of every such series whose own bound is within it.
+    Also the bytes of the work the kernel did with its running k-th best."""
     q = max(queries, 1)
     row = 4 * length
-    return {
-        "stage2": 48.0 * n_leaves,
-        "process": (16.0 * st["series_lb"] + row * (st["refined"] + st["lb_keogh"])) / q,
-    }
+    minimal = (16.0 * st["min_series"] + row * st["min_refined"]) / q
+    running = (16.0 * st["series_lb"] + row * (st["refined"] + st["lb_keogh"])) / q
+    return minimal, running
 
 
 def run_queries(pm, idx, qt, k, distance, window, budget_s=None):
@@ -426,6 +434,35 @@ def cpu_baseline(n, length, queries, sample):
                       f"{sample} of the {n} series: {dt:.1f} s of scanning, scaled by {sample}/{n}"}
 
 
+def cpu_baseline_dtw(n, length, window, nq, sample):
+    """The oracle's LB_Keogh-filtered DTW scan (exact; LB_Keogh against the
+    running k-th best prunes pairs before the banded DTW) on the host cores,
+    nq of the DTW run's noisy queries (noise 0.01/0.1/1.0 round robin) over
+    the first `sample` of its n series (regenerated on the host; only the
+    scans are timed), scaled to the n series.  A scan over fewer series
+    prunes less, so the scaled rate understates the host."""
+    import oracle
+    import synth
+
+    dq, _, _ = synth.noisy_queries(nq + 3, n, length)
+    queries = dq[3:]
+    log(f"cpu baseline: oracle LB_Keogh-filtered DTW (r={window}) of {nq} queries over "
+        f"{sample} x {length}")
+    st = oracle.KnnState(queries, 1, distance=oracle.DTW, r=window, lb_keogh=True)
+    dt = 0.0
+    chunk = 500_000
+    for c in range(0, sample, chunk):
+        raw = synth.randomwalk(min(chunk, sample - c), length, seed=synth.SEED_DATA, id0=c)
+        t0 = time.perf_counter()
+        st.scan(raw, c)
+        dt += time.perf_counter() - t0
+    return {"value": nq / dt * (sample / n), "unit": "queries/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"LB_Keogh-filtered exact 1-NN DTW (FP64, r={window}) of {nq} noisy queries "
+                      f"over the first {sample} of the {n} series: {dt:.1f} s of scanning, "
+                      f"scaled by {sample}/{n}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -450,6 +487,8 @@ def main():
     ap.add_argument("--subseq-queries", type=int, default=100)
     ap.add_argument("--cpu-sample", type=int, default=16_000_000)
     ap.add_argument("--cpu-queries", type=int, default=100)
+    ap.add_argument("--cpu-dtw-sample", type=int, default=1_000_000)
+    ap.add_argument("--cpu-dtw-queries", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweep", action="store_true",
                     help="size and length sweep instead of the default run (one JSON line)")
@@ -520,10 +559,8 @@ def main():
     st = query_stats(pm, idx, qt[args.warmup:args.warmup + k_done], 1, pm.MESSI_ED, 0)
     value = k_done / wall
     phases_us = {p: st[f"us_{p}"] / k_done for p in PHASES}
-    pb = phase_bytes(st, length, info["n_leaves"], k_done)
-    dom = max(phases_us, key=phases_us.get)
-    dom_bytes = pb.get(dom)
-    achieved = (dom_bytes / (phases_us[dom] * 1e-6) / 1e9) if dom_bytes else None
+    dom_bytes, run_bytes = process_bytes(st, length, k_done)
+    achieved = dom_bytes / (phases_us["process"] * 1e-6) / 1e9
     log(f"ED: {value:.1f} q/s, p50 {np.percentile(lat, 50) * 1e3:.3f} ms, phases {phases_us}")
 
     dtw = None
@@ -536,6 +573,17 @@ def main():
         dk = len(dlat)
         dst = query_stats(pm, didx, dt[3:3 + dk], 1, pm.MESSI_DTW, args.window)
         dph = {p: dst[f"us_{p}"] / dk for p in PHASES}
+        ops = dst["dtw_cells"] / dk * DTW_OPS_PER_CELL
+        dach = ops / (dph["process"] * 1e-6) / 1e12
+        dtw_roof = {"kernel": f"k_process (register band, radius {args.window})", "bound": "alu",
+                    "achieved": dach, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                    "frac": dach / VALU_PEAK_TOPS, "traffic": None,
+                    "ops_per_launch": ops, "cells_per_launch": dst["dtw_cells"] / dk,
+                    "note": f"{DTW_OPS_PER_CELL} VALU instructions per band cell computed (v_sub, v_min3, "
+                            "v_fmac; cells "
+                            "counted in the kernel: rows done before each pair ended, within the "
+                            "band and the matrix) over the process phase; peak = plain FP32 VALU "
+                            "issue of 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz"}
         dtw = {"metric": "exact 1-NN DTW queries/s (one query at a time)", "value": dk / dwall,
                "unit": "queries/s", "queries": dk, "window": args.window,
                "workload": f"first {dtw_n} of the random walks, noisy dataset copies "
@@ -543,7 +591,9 @@ def main():
                "p50_ms": float(np.percentile(dlat, 50) * 1e3),
                "p99_ms": float(np.percentile(dlat, 99) * 1e3), "phases_us": dph,
                "refined_per_query": dst["refined"] / dk, "lb_keogh_per_query": dst["lb_keogh"] / dk,
-               "series_lb_per_query": dst["series_lb"] / dk}
+               "series_lb_per_query": dst["series_lb"] / dk,
+               "bsf_updates_per_query": dst["bsf_updates"] / dk,
+               "roofline": dtw_roof}
         log(f"DTW: {dtw['value']:.2f} q/s, p50 {dtw['p50_ms']:.2f} ms, p99 {dtw['p99_ms']:.2f} ms")
         dtw["filters"] = dtw_filters(pm, didx, dt[3:3 + dk], args.window)
         didx.free()
@@ -570,10 +620,14 @@ def main():
         cpu = cpu_baseline(n, length, qs[args.warmup:args.warmup + args.cpu_queries],
                            min(args.cpu_sample, n))
         log(f"cpu baseline {cpu['value']:.4f} q/s")
+        if args.dtw_queries > 0 and args.cpu_dtw_queries > 0:
+            cpu["dtw"] = cpu_baseline_dtw(dtw_n, length, args.window, args.cpu_dtw_queries,
+                                          min(args.cpu_dtw_sample, dtw_n))
+            log(f"cpu baseline DTW {cpu['dtw']['value']:.4f} q/s")
 
     traffic = None
-    if dom == "process" and MEASURED_TRAFFIC["sources_sha256"] == query_sources_digest():
-        traffic = MEASURED_TRAFFIC["bytes_per_launch"]
+    if MEASURED_TRAFFIC["sources_sha256"] == query_sources_digest():
+        traffic = MEASURED_TRAFFIC["by_queries"].get(f"{args.steps},{args.warmup}")
     out = {
         "metric": "exact 1-NN queries/s (ED, one query at a time)",
         "value": value,
@@ -599,10 +653,19 @@ def main():
         "work_per_query": {"leaves_kept": st["leaves_kept"] / k_done,
                            "series_lb": st["series_lb"] / k_done,
                            "refined": st["refined"] / k_done,
-                           "rechecked_fp64": st["rechecked_fp64"] / k_done},
-        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-                     "traffic": traffic, "bytes_per_launch": dom_bytes},
+                           "rechecked_fp64": st["rechecked_fp64"] / k_done,
+                           "bsf_updates": st["bsf_updates"] / k_done,
+                           "min_leaves": st["min_leaves"] / k_done,
+                           "min_series": st["min_series"] / k_done,
+                           "min_refined": st["min_refined"] / k_done},
+        "roofline": {"kernel": "k_process_ed", "bound": "hbm", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "bytes_per_launch": dom_bytes,
+                     "bytes_per_launch_running_kth": run_bytes,
+                     "note": "bytes_per_launch: 16 B per series in a leaf within the final k-th "
+                             "best + 4 len B per series whose own bound is within it (the work "
+                             "the search needs once the answer is known); the kernel did "
+                             "bytes_per_launch_running_kth with its running k-th best"},
         "dtw": dtw,
         "batched": batched,
         "classification": classification,

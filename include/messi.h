@@ -62,7 +62,7 @@ typedef struct messi_leaf {
 typedef struct messi_stats {
   int64_t queries;
   int64_t leaves_total;     /* leaves in the index, times queries */
-  int64_t leaves_kept;      /* leaves processed (bound within the k-th best) */
+  int64_t leaves_kept;      /* 512-series chunks of leaves processed (bound within the k-th best) */
   int64_t series_lb;        /* series-level lower bounds computed */
   int64_t lb_keogh;         /* LB_Keogh bounds computed (DTW) */
   int64_t refined;          /* real distances computed in FP32 */
@@ -70,11 +70,24 @@ typedef struct messi_stats {
   int64_t log_overflows;    /* reruns forced by a full near-tie log */
   /* device time of each phase in microseconds (HIP events on the index's
    * stream), summed over calls: query preparation; approximate search with
-   * the leaf bounds; ordering of the leaves by bound; leaf processing with
-   * refinement; FP64 recheck and output */
-  double us_prep, us_stage1, us_stage2, us_process, us_finalize;
+   * the leaf bounds and their order; leaf processing with refinement (for
+   * screened batches: the BF16 rows and the screen); FP64 recheck and
+   * output */
+  double us_prep, us_stage1, us_process, us_finalize;
   int64_t screened;         /* (query, series) pairs through the BF16 screen */
   int64_t lb_improved;      /* LB_Improved second passes (DTW, MESSI_LB_IMPROVED) */
+  int64_t bsf_updates;      /* insertions into the k best after the approximate
+                               search (the BSF updates of Section 5.4) */
+  int64_t dtw_cells;        /* band cells computed by the FP32 register-band DTW
+                               (rows computed before the pair ended, within
+                               |i - j| <= r and the matrix) */
+  /* the work the search needs once its final k-th best is known, counted
+   * by a separate pass of messi_query_stats (its time is in no phase
+   * above; batches leave these 0): leaves whose bound is within it, the
+   * series of those leaves, and those series whose own bound is within it
+   * (the series the approximate search refined are left out of the last
+   * two) */
+  int64_t min_leaves, min_series, min_refined;
 } messi_stats;
 
 /* Build an index (Section 3.2: iSAX summaries, then the leaves of the

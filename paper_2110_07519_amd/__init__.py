@@ -58,9 +58,11 @@ class MessiStats(ctypes.Structure):
                 ("lb_keogh", ctypes.c_int64), ("refined", ctypes.c_int64),
                 ("rechecked_fp64", ctypes.c_int64), ("log_overflows", ctypes.c_int64),
                 ("us_prep", ctypes.c_double), ("us_stage1", ctypes.c_double),
-                ("us_stage2", ctypes.c_double), ("us_process", ctypes.c_double),
-                ("us_finalize", ctypes.c_double), ("screened", ctypes.c_int64),
-                ("lb_improved", ctypes.c_int64)]
+                ("us_process", ctypes.c_double), ("us_finalize", ctypes.c_double),
+                ("screened", ctypes.c_int64), ("lb_improved", ctypes.c_int64),
+                ("bsf_updates", ctypes.c_int64), ("dtw_cells", ctypes.c_int64),
+                ("min_leaves", ctypes.c_int64), ("min_series", ctypes.c_int64),
+                ("min_refined", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

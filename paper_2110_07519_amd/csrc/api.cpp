@@ -169,7 +169,7 @@ struct QueryCtx {
   unsigned long long* tally = nullptr;
   int log_cap = 4096;
   int proc_blocks_ed = 0;  // cached occupancy of the ED process kernel
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[5] = {};
   bool events_ready = false;
   int* h_status = nullptr;  // pinned copy of the per-query status words
   int h_status_cap = 0;
@@ -576,7 +576,7 @@ struct FixedScratch {
 int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int kmax, int distance,
               int window, const int* d_kq, const int* d_qmap, bool screen, bool lb_improved,
               int64_t* out_ids, float* out_dists, messi_stats* stats,
-              const FixedScratch* fixed = nullptr) {
+              const FixedScratch* fixed = nullptr, bool min_work = false) {
   hipStream_t st = c.stream;
   const int len = ix->len;
   const double u = std::ldexp(1.0, -24);
@@ -681,13 +681,13 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     c.h_status_cap = nq;
   }
   // phase timing (only when the caller asks for statistics)
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[5] = {};
   if (stats) {
     if (!c.events_ready) {
-      for (int i = 0; i < 6; ++i) HIP_OR_THROW(hipEventCreate(&c.ev[i]));
+      for (int i = 0; i < 5; ++i) HIP_OR_THROW(hipEventCreate(&c.ev[i]));
       c.events_ready = true;
     }
-    for (int i = 0; i < 6; ++i) ev[i] = c.ev[i];
+    for (int i = 0; i < 5; ++i) ev[i] = c.ev[i];
   }
   for (int attempt = 0; attempt < 8; ++attempt) {
     if (!fixed) ensure_workspace(ix, c, nq, kmax);
@@ -704,28 +704,29 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     if (stats) HIP_OR_THROW(hipEventRecord(ev[2], st));
     if (screen) {
       launch_bf16_rows(qs.zq, nullptr, nq, len, sc.qb, sc.qn, st);
-      if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
       launch_screen(v, p, qs, sc, screen_blocks, st);
     } else {
-      if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
       launch_process(v, p, qs, blocks, st);
     }
-    if (stats) HIP_OR_THROW(hipEventRecord(ev[4], st));
+    if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
     launch_finalize(v, p, qs, out_ids, out_dists, st);
-    if (stats) HIP_OR_THROW(hipEventRecord(ev[5], st));
+    if (stats) {
+      HIP_OR_THROW(hipEventRecord(ev[4], st));
+      // the minimal work, once the final k-th best is known (untimed)
+      if (min_work) launch_min_work(v, p, qs, std::max(1, ix->n_cus), st);
+    }
     launch_check();
     d2h(h_status, qs.status, nq, st);
     int worst = 0;
     for (int i = 0; i < nq; ++i) worst |= h_status[i];
     if (!(worst & 1)) {
       if (stats) {
-        float ms[5] = {0, 0, 0, 0, 0};
-        for (int i = 0; i < 5; ++i) HIP_OR_THROW(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
+        float ms[4] = {0, 0, 0, 0};
+        for (int i = 0; i < 4; ++i) HIP_OR_THROW(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
         stats->us_prep += 1e3 * ms[0];
         stats->us_stage1 += 1e3 * ms[1];
-        stats->us_stage2 += 1e3 * ms[2];
-        stats->us_process += 1e3 * ms[3];
-        stats->us_finalize += 1e3 * ms[4];
+        stats->us_process += 1e3 * ms[2];
+        stats->us_finalize += 1e3 * ms[3];
         std::vector<unsigned long long> sv((size_t)nq * kStatCount);
         d2h(sv.data(), qs.stats, sv.size(), st);
         stats->queries += nq;
@@ -738,6 +739,11 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
           stats->refined += (int64_t)r[kStatRefined];
           stats->rechecked_fp64 += (int64_t)r[kStatRecheck];
           stats->lb_improved += (int64_t)r[kStatLbImproved];
+          stats->bsf_updates += (int64_t)r[kStatBsf];
+          stats->dtw_cells += (int64_t)r[kStatCells];
+          stats->min_leaves += (int64_t)r[kStatMinLeaves];
+          stats->min_series += (int64_t)r[kStatMinSeries];
+          stats->min_refined += (int64_t)r[kStatMinRefined];
         }
         if (screen) {
           unsigned long long t[2];
@@ -762,7 +768,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
 int run_query(messi_index* ix, const float* queries, int nq, int k, int distance, int window,
               int64_t* out_ids, float* out_dists, messi_stats* stats) {
   return run_group(ix, ix->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, false, out_ids,
-                   out_dists, stats);
+                   out_dists, stats, nullptr, true);
 }
 
 constexpr int kScreenMinGroup = 32;  // fewer ED queries go the unscreened way

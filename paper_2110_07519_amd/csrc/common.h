@@ -12,7 +12,6 @@ constexpr int kWave = 64;         // CDNA wavefront width
 constexpr int kLbBuckets = 2048;  // logarithmic bound buckets that order the leaves
 constexpr int kShards = 64;       // work counters per query (leaves dealt round robin)
 constexpr int kChunkSeries = 512; // series per work item of the process phase
-constexpr int kGrab = 8;          // work items taken per atomic grab
 constexpr int kCounterStride = 64;  // ints between two shard counters (own 256-byte line)
 constexpr int kCounterInts = kShards * kCounterStride + kCounterStride;
 constexpr int kApproxCap = 8192;  // most series refined by the approximate search
@@ -69,7 +68,7 @@ struct QueryState {
   unsigned long long* items;  // [nq][item_cap] leaf chunks, shard by shard in bucket order (lb bits, leaf)
   int2* ranges;               // [nq][item_cap] their position ranges
   int* next;                  // [nq][kCounterInts]: kShards counters kCounterStride apart, then a finished-shard mask
-  unsigned long long* stats;  // [nq][8] counters (see kStat*)
+  unsigned long long* stats;  // [nq][kStatCount] counters (see kStat*)
   int* status;                // [nq] bit 0: near-tie log overflow
   const int* kq;              // [nq] k of each query (batches), or null: every query uses p.k
   const int* qmap;            // [nq] input / output row of each query (batches), or null: row q
@@ -81,8 +80,10 @@ __device__ __forceinline__ int k_of(const QueryParams& p, const QueryState& s, i
 }
 __device__ __forceinline__ int row_of(const QueryState& s, int q) { return s.qmap ? s.qmap[q] : q; }
 
+// Per-query work counters.  The kStatMin* ones are the work the search
+// needs once the final k-th best is known (counted only for statistics).
 enum { kStatLeavesKept = 0, kStatSeriesLb, kStatLbKeogh, kStatRefined, kStatRecheck, kStatLbImproved,
-       kStatCount = 8 };
+       kStatBsf, kStatCells, kStatMinLeaves, kStatMinSeries, kStatMinRefined, kStatCount = 16 };
 
 // iSAX symbol of a PAA value: the number of breakpoints beta_1..beta_{card-1}
 // that are <= p, given bp[j] = beta_j (bp[0] = -inf).

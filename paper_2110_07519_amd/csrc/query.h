@@ -76,6 +76,9 @@ void launch_process(const IndexDev& ix, const QueryParams& qp, const QueryState&
                     int blocks_per_query, hipStream_t st);
 void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
                      int64_t* out_ids, float* out_dists, hipStream_t st);
+// statistics: the work the search needs once the final k-th best is known
+void launch_min_work(const IndexDev& ix, const QueryParams& qp, const QueryState& qs, int blocks,
+                     hipStream_t st);
 size_t process_lds_bytes(const QueryParams& qp);
 size_t finalize_lds_bytes(const QueryParams& qp);
 size_t stage1_lds_bytes(const QueryParams& qp);

@@ -262,7 +262,9 @@ __device__ __forceinline__ float lbi_second(const float* __restrict__ q, const f
 // band coordinates D(j,i) needs old D[b] (diagonal), old D[b+1] (up) and new
 // D[b-1] (left), so one in-place ascending sweep per row suffices.  qpad is
 // the query in LDS with R +inf pads on each side (matrix edges cost +inf).
-// A path crosses every row, so a row minimum above `cutoff` ends the pair.
+// A path crosses every row, so a row minimum above `cutoff` ends the pair;
+// the result is then minus the number of rows computed (a distance is
+// never negative).
 // Wide bands run as a call, where pointers arrive untyped; the body gives
 // them their address spaces (the query in LDS, the row in global memory).
 // With generic pointers every query read is a flat load that also counts
@@ -319,7 +321,7 @@ __device__ __forceinline__ float dtw_band_body(const float* __restrict__ qpad_an
         float mn = D[0];
 #pragma unroll
         for (int b = 1; b <= 2 * R; ++b) mn = fminf(mn, D[b]);
-        if (mn > cutoff) return INFINITY;
+        if (mn > cutoff) return -(float)(j + 4);
       }
     }
   } else {
@@ -336,11 +338,23 @@ __device__ __forceinline__ float dtw_band_body(const float* __restrict__ qpad_an
         float mn = D[0];
 #pragma unroll
         for (int b = 1; b <= 2 * R; ++b) mn = fminf(mn, D[b]);
-        if (mn > cutoff) return INFINITY;
+        if (mn > cutoff) return -(float)(j + 1);
       }
     }
   }
   return D[R];
+}
+
+// Cells of the band |i - j| <= r inside the len x len matrix in its first
+// `rows` rows: the DTW work of a pair abandoned after `rows` rows (all len
+// rows when it completes).
+__device__ __forceinline__ unsigned long long band_cells(int rows, int len, int r) {
+  const long long R1 = rows, L = len, rr = r;
+  long long a = L - rr;  // rows whose band reaches j + r <= len - 1
+  a = a < 0 ? 0 : (a > R1 ? R1 : a);
+  const long long upper = a * (a - 1) / 2 + a * (rr + 1) + (R1 - a) * L;
+  const long long lower = R1 > rr ? (R1 - rr - 1) * (R1 - rr) / 2 : 0;
+  return (unsigned long long)(upper - lower);
 }
 
 // Bands below 48 (up to 32 among the instances) are inlined: the kernel
@@ -954,14 +968,14 @@ __device__ __forceinline__ void log_approx(const QueryParams& p, const QueryStat
 }
 
 // ---------------------------------------------------------------------------
-// process: persistent blocks over the ordered leaf chunks.
-// R = -1: ED; R >= 0: DTW with a register band of radius R; R = -2: DTW by
-// wave anti-diagonals (radius beyond the register band).
+// process (DTW): persistent blocks over the ordered leaf chunks.
+// R >= 0: a register band of radius R; R = -2: wave anti-diagonals (radius
+// beyond the register band).
 //
-// A block takes kGrab consecutive chunks of one shard with one atomic (one
-// chunk per wave).  Each wave computes the series bounds of its chunk and
-// appends the survivors to the block's list in LDS; then all waves refine
-// the list together, eight rows per wave at a time.  For DTW the LB_Keogh
+// A block takes kDtwWaves consecutive chunks of one shard with one atomic
+// (one chunk per wave).  Each wave computes the series bounds of its chunk
+// and appends the survivors to the block's list in LDS; then all waves take
+// LB_Keogh of the list together, eight rows per wave at a time, and its
 // survivors wait in a block list until there is one pair per thread.
 
 constexpr int kUnroll = kChunkSeries / kWave;  // words per lane per chunk
@@ -979,13 +993,9 @@ constexpr int kEdList = kChunkSeries + kEdDefer;
 
 template <int R>
 struct ProcShape {
-  static constexpr int waves = (R == -1) ? kGrab : 4;  // one chunk per wave (DTW: LDS for its lists)
+  static constexpr int waves = 4;  // one chunk per wave
   static constexpr int threads = waves * kWave;
-  // ED: survivors wait across grabs until there are two groups per wave to
-  // refine (fewer refinement passes; each is re-checked against the k-th
-  // best of its own time)
-  static constexpr int defer = (R == -1) ? 2 * waves * kGroup : 0;
-  static constexpr int surv_cap = waves * kChunkSeries + defer;
+  static constexpr int surv_cap = waves * kChunkSeries;
   static constexpr int pend_cap = (R >= 0) ? surv_cap + threads : 0;
 };
 
@@ -996,14 +1006,13 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   constexpr int kW = Sh::waves;
   const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
   const int len = p.len, card = 1 << p.card_bits;
-  constexpr bool dtw = R != -1;
   extern __shared__ float sm[];
   float* table = sm;                          // [16][card]
   float* ql = table + kMaxSeg * card;         // query (ED, wave DTW) / padded query (band DTW)
   const int qlen = (R >= 0) ? len + 2 * R : len;
   float* U = ql + qlen;                       // envelope (DTW)
-  float* Lw = U + (dtw ? len : 0);
-  int* surv = reinterpret_cast<int*>(Lw + (dtw ? len : 0));     // survivors of a grab
+  float* Lw = U + len;
+  int* surv = reinterpret_cast<int*>(Lw + len);                 // survivors of a grab
   float* survlb = reinterpret_cast<float*>(surv + Sh::surv_cap);  // their bounds
   int* pend = reinterpret_cast<int*>(survlb + Sh::surv_cap);    // DTW pairs waiting
   float* wx = reinterpret_cast<float*>(pend + Sh::pend_cap);     // wave DTW rows / LB_Improved [kW][len]
@@ -1053,7 +1062,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   } else {
     for (int t = tid; t < len; t += blockDim.x) ql[t] = zq[t];
   }
-  if (dtw) {
+  {
     for (int t = tid; t < len; t += blockDim.x) {
       U[t] = s.upper[(int64_t)q * len + t];
       Lw[t] = s.lower[(int64_t)q * len + t];
@@ -1076,7 +1085,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   int* counters = s.next + (int64_t)q * kCounterInts;
   unsigned long long* finished =
       reinterpret_cast<unsigned long long*>(counters + kShards * kCounterStride);
-  unsigned long long c_lb = 0, c_lbk = 0, c_lbi = 0, c_ref = 0, c_leaf = 0;
+  unsigned long long c_lb = 0, c_lbk = 0, c_lbi = 0, c_ref = 0, c_leaf = 0, c_bsf = 0, c_cells = 0;
 
   // DTW pairs in the pending list, one per thread, first `cnt` entries
   auto run_pairs = [&](int cnt, unsigned long long ck) {
@@ -1088,7 +1097,9 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
         const int pp = pend[tid];
         const float e = dtw_band<(R >= 0 ? R : 0), MASK>(ql, zrow_ptr(ix, pp), len, p.window, cut);
         ++c_ref;
-        if (e < INFINITY) ch = offer(ix, p, s, q, e, pp, ck, true);
+        c_cells += band_cells(e >= 0.0f ? len : (int)-e, len, p.window);
+        if (e >= 0.0f) ch = offer(ix, p, s, q, e, pp, ck, true);
+        c_bsf += ch ? 1 : 0;
       }
       if (__ballot(ch) && lane == 0) {
         mine = load_key(&slots[k - 1]);
@@ -1115,18 +1126,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       int gr[kGroup];  // rows of Z (the positions themselves unless Z is in id order)
 #pragma unroll
       for (int c = 0; c < kGroup; ++c) gr[c] = ix.zrow ? ix.zrow[gp[c]] : gp[c];
-      if constexpr (!dtw) {
-        ed_group(ql, ix.Z, len, gr, act, lane, dv);
-        c_ref += (lane == 0) ? __popc(act) : 0;
-        // distances are wave-uniform: the rare ones inside the window of
-        // the k-th best are offered by lane 0
-        bool ch = false;
-#pragma unroll
-        for (int c = 0; c < kGroup; ++c)
-          if (((act >> c) & 1u) && dv[c] <= key_dist(ckey) * p.win && lane == 0)
-            ch |= offer(ix, p, s, q, dv[c], gp[c], ckey, true);
-        if (__ballot(ch)) ckey = umin64(ckey, load_key(&slots[k - 1]));
-      } else {
+      {
         // LB_Keogh on the raw values (Algorithm 10, second test)
         lbk_group(U, Lw, ix.Z, len, gr, act, lane, dv);
         c_lbk += (lane == 0) ? __popc(act) : 0;
@@ -1186,6 +1186,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
             if (lane == 0) {
               ++c_ref;
               ch = e < INFINITY && offer(ix, p, s, q, e, pos, ckey, true);
+              c_bsf += ch ? 1 : 0;
             }
             if (__ballot(ch)) ckey = umin64(ckey, load_key(&slots[k - 1]));
           }
@@ -1225,13 +1226,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       have_next = false;
     }
     __syncthreads();
-    if (s_stop) {
-      if constexpr (!dtw) {  // the survivors still waiting
-        unsigned long long ck = s_ckey;
-        if (s_nsurv > 0) refine(s_nsurv, ck);
-      }
-      break;
-    }
+    if (s_stop) break;
     const int shard = s_shard;
     if (tid == 0) {  // prefetch the next grab of this shard
       next_batch = atomicAdd(&counters[shard * kCounterStride], 1);
@@ -1266,9 +1261,9 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       for (int u = 0; u < kUnroll; ++u) {
         const int pos = rg.x + lane + u * kWave;
         ok[u] = pos < rg.y && !(pos >= P0 && pos < P1);
-        // DTW: defined words on skipped lanes keep them from staying live
-        // across the refinement (occupancy); ED runs best as it is
-        if constexpr (dtw) wd[u] = make_uint4(0u, 0u, 0u, 0u);
+        // defined words on skipped lanes keep them from staying live
+        // across the refinement (occupancy)
+        wd[u] = make_uint4(0u, 0u, 0u, 0u);
         if (ok[u]) wd[u] = ix.words[pos];
       }
       float lbv[kUnroll];
@@ -1313,10 +1308,8 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       }
     }
     __syncthreads();
-    // ED keeps survivors across grabs until there are two groups per wave
     const int ns = s_nsurv;
-    const bool flush = dtw || ns >= Sh::defer;
-    if (flush) refine(ns, ckey);
+    refine(ns, ckey);
     if (lane == 0) atomicMin(&s_ckey, ckey);
     __syncthreads();
     if constexpr (R >= 0) {
@@ -1338,7 +1331,7 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
       if (tid == 0) s_npend = np;
     }
     if (tid == 0) {
-      if (flush) s_nsurv = 0;
+      s_nsurv = 0;
       if (s_shard_done) have_next = false;  // the prefetched batch lies past the shard's end
     }
     __syncthreads();
@@ -1354,6 +1347,8 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
     c_lbi += __shfl_xor(c_lbi, o, kWave);
     c_ref += __shfl_xor(c_ref, o, kWave);
     c_leaf += __shfl_xor(c_leaf, o, kWave);
+    c_bsf += __shfl_xor(c_bsf, o, kWave);
+    c_cells += __shfl_xor(c_cells, o, kWave);
   }
   if (lane == 0) {
     unsigned long long* stq = s.stats + (int64_t)q * kStatCount;
@@ -1362,6 +1357,8 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
     if (c_lbk) atomicAdd(&stq[kStatLbKeogh], c_lbk);
     if (c_lbi) atomicAdd(&stq[kStatLbImproved], c_lbi);
     if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
+    if (c_bsf) atomicAdd(&stq[kStatBsf], c_bsf);
+    if (c_cells) atomicAdd(&stq[kStatCells], c_cells);
   }
   __syncthreads();  // LDS is reloaded for the next query
   }
@@ -1479,7 +1476,7 @@ __global__ __launch_bounds__(kEdThreads) void k_process_ed(IndexDev ix, QueryPar
     const float eta = s.eta[q];
     const unsigned long long* items = s.items + (int64_t)q * p.item_cap;
     const int2* ranges = s.ranges + (int64_t)q * p.item_cap;
-    unsigned long long c_lb = 0, c_ref = 0, c_leaf = 0;
+    unsigned long long c_lb = 0, c_ref = 0, c_leaf = 0, c_bsf = 0;
     unsigned long long ckey = s_ckey;
     int nl = 0;  // survivors in this wave's list (wave-uniform)
 
@@ -1518,7 +1515,11 @@ __global__ __launch_bounds__(kEdThreads) void k_process_ed(IndexDev ix, QueryPar
           win &= win - 1;
           const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dl), c));
           const int gc = __builtin_amdgcn_readlane(gl2, c);
-          if (lane == 0) ch |= offer(ix, p, s, q, d, gc, ckey, true);
+          if (lane == 0) {
+            const bool in = offer(ix, p, s, q, d, gc, ckey, true);
+            c_bsf += in ? 1 : 0;
+            ch |= in;
+          }
         }
       }
       if (__ballot(ch)) {
@@ -1713,9 +1714,77 @@ __global__ __launch_bounds__(kEdThreads) void k_process_ed(IndexDev ix, QueryPar
       if (c_leaf) atomicAdd(&stq[kStatLeavesKept], c_leaf);
       if (c_lb) atomicAdd(&stq[kStatSeriesLb], c_lb);
       if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
+      if (c_bsf) atomicAdd(&stq[kStatBsf], c_bsf);
     }
     __syncthreads();  // LDS is reloaded for the next query
   }
+}
+
+// ---------------------------------------------------------------------------
+// The work the search needs once its final k-th best is known (statistics
+// only, run after finalize): the leaves whose bound is within it, their
+// series, and those series whose own bound is within it (rows to refine,
+// or LB_Keogh to take for DTW).  The approximate search's series are left
+// out, as the process kernel leaves them out.  grid.y = query.
+
+__global__ __launch_bounds__(256) void k_min_work(IndexDev ix, QueryParams p, QueryState s) {
+  const int q = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int card = 1 << p.card_bits;
+  extern __shared__ float table[];  // [16][card]
+  {
+    const float* pu = s.paa + ((int64_t)q * 3 + 1) * kMaxSeg;
+    const float* pl = s.paa + ((int64_t)q * 3 + 2) * kMaxSeg;
+    const float fm = (float)p.m;
+    for (int i = tid; i < kMaxSeg * card; i += blockDim.x) {
+      const int sg = i >> p.card_bits, j = i & (card - 1);
+      float v = 0.0f;
+      if (sg < p.w) {
+        const float g = fmaxf(ix.bp[j] - pu[sg], 0.0f) + fmaxf(pl[sg] - ix.bp[j + 1], 0.0f);
+        v = fm * (g * g);
+      }
+      table[i] = v;
+    }
+  }
+  __syncthreads();
+  const float thr = lb_threshold(kth_dist(s.slots + (int64_t)q * p.k, k_of(p, s, q)), s.eta[q], p);
+  const int64_t P0 = s.approx_range[2 * q], P1 = s.approx_range[2 * q + 1];
+  const float* lbq = s.leaf_lb + (int64_t)q * p.n_leaves;
+  unsigned long long n_leaf = 0, n_series = 0, n_pass = 0;
+  for (int l = blockIdx.x; l < p.n_leaves; l += gridDim.x) {
+    if (!(lbq[l] <= thr)) continue;
+    n_leaf += tid == 0 ? 1 : 0;
+    for (int64_t pos = ix.leaf_begin[l] + tid; pos < ix.leaf_end[l]; pos += blockDim.x) {
+      if (pos >= P0 && pos < P1) continue;
+      const uint4 wd = ix.words[pos];
+      float t[kMaxSeg];
+#pragma unroll
+      for (int sg = 0; sg < kMaxSeg; ++sg) t[sg] = table[sg * card + (int)byte_of(wd, sg)];
+#pragma unroll
+      for (int h = kMaxSeg / 2; h >= 1; h >>= 1)
+#pragma unroll
+        for (int sg = 0; sg < h; ++sg) t[sg] = t[sg] + t[sg + h];
+      ++n_series;
+      n_pass += t[0] <= thr ? 1 : 0;
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    n_leaf += __shfl_xor(n_leaf, o, kWave);
+    n_series += __shfl_xor(n_series, o, kWave);
+    n_pass += __shfl_xor(n_pass, o, kWave);
+  }
+  if ((tid & (kWave - 1)) == 0) {
+    unsigned long long* stq = s.stats + (int64_t)q * kStatCount;
+    if (n_leaf) atomicAdd(&stq[kStatMinLeaves], n_leaf);
+    if (n_series) atomicAdd(&stq[kStatMinSeries], n_series);
+    if (n_pass) atomicAdd(&stq[kStatMinRefined], n_pass);
+  }
+}
+
+void launch_min_work(const IndexDev& ix, const QueryParams& qp, const QueryState& qs, int blocks,
+                     hipStream_t st) {
+  const size_t lds = (size_t)kMaxSeg * ((size_t)1 << qp.card_bits) * sizeof(float);
+  hipLaunchKernelGGL(k_min_work, dim3((unsigned)blocks, (unsigned)qp.nq), dim3(256), lds, st, ix, qp, qs);
 }
 
 // ---------------------------------------------------------------------------
@@ -2171,7 +2240,8 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
                 if (lane == 0) {
                   const int kk = k_of(p, s, qsel);
                   const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
-                  offer(ix, p, s, qsel, d2, jsel, ck, true);
+                  if (offer(ix, p, s, qsel, d2, jsel, ck, true))
+                    atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatBsf], 1ull);
                   atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
                 }
                 ++passed;
@@ -2290,9 +2360,8 @@ template <int R>
 static size_t process_lds_words(const QueryParams& p) {
   using Sh = ProcShape<R>;
   const int card = 1 << p.card_bits;
-  const bool dtw = R != -1;
   const int qlen = R >= 0 ? p.len + 2 * R : p.len;
-  size_t words = (size_t)kMaxSeg * card + qlen + (dtw ? 2 * p.len : 0) + 2 * (size_t)Sh::surv_cap +
+  size_t words = (size_t)kMaxSeg * card + qlen + 2 * (size_t)p.len + 2 * (size_t)Sh::surv_cap +
                  Sh::pend_cap;
   if (R == -2) words += (size_t)Sh::waves * 4 * p.len;
   if (R >= 0 && p.lb_improved) words += (size_t)Sh::waves * p.len;  // LB_Improved projections
