@@ -589,6 +589,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   p.k = kmax;
   p.out_stride = kmax;
   p.order_leaves = screen ? 0 : 1;
+  p.count_work = stats ? 1 : 0;
   // the approximate leaf: found by stage1's approximate blocks for a few
   // queries (shorter prep), once per query in k_prep for batches
   p.leaf_in_prep = nq > 8 ? 1 : 0;
@@ -637,7 +638,8 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   // process kernel's LDS, the queries run with LB_Keogh alone
   p.lb_improved = (lb_improved && distance == MESSI_DTW) ? 1 : 0;
   if (p.lb_improved && process_lds_bytes(p) > lds_max) p.lb_improved = 0;
-  if (process_lds_bytes(p) > lds_max || finalize_lds_bytes(p) > lds_max || stage1_lds_bytes(p) > lds_max)
+  const size_t proc_lds = process_lds_bytes(p) + process_lds_static(p);
+  if (proc_lds > ix->lds_max || finalize_lds_bytes(p) > lds_max || stage1_lds_bytes(p) > lds_max)
     return fail(MESSI_EINVAL, "series length %d too long for the query kernels (window %d)", len,
                 p.window);
 

@@ -50,6 +50,7 @@ struct QueryParams {
   int lds_words;     // floats of dynamic LDS of the process kernel
   int out_stride;    // output row stride (k of the call, or kmax of a batch)
   int order_leaves;  // 1: stage1 also writes the chunk order of the process kernel
+  int count_work;    // 1: the kernels add up their work counters (statistics asked for)
 };
 
 // Per-query device state, one entry per query (all arrays sized by nq).
@@ -84,6 +85,28 @@ __device__ __forceinline__ int row_of(const QueryState& s, int q) { return s.qma
 // needs once the final k-th best is known (counted only for statistics).
 enum { kStatLeavesKept = 0, kStatSeriesLb, kStatLbKeogh, kStatRefined, kStatRecheck, kStatLbImproved,
        kStatBsf, kStatCells, kStatMinLeaves, kStatMinSeries, kStatMinRefined, kStatCount = 16 };
+
+// Adds a block's work counters to query q's, one device atomic per counter
+// per block: each wave first adds its (wave-reduced, lane 0) counts into
+// `part` in LDS, which thread 0 then adds to the query's counters.  Device
+// atomics on a few addresses from every wave of the grid would queue at the
+// memory channel that holds them, so the kernels count only when asked
+// (QueryParams::count_work).  Called by every thread of the block.
+template <int N>
+__device__ __forceinline__ void add_block_counts(unsigned long long* stq, const int (&which)[N],
+                                                 const unsigned long long (&val)[N],
+                                                 unsigned long long* part) {
+  const int tid = threadIdx.x;
+  if (tid < N) part[tid] = 0;
+  __syncthreads();
+  if ((tid & 63) == 0)
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      if (val[i]) atomicAdd(&part[i], val[i]);
+  __syncthreads();
+  if (tid < N && part[tid]) atomicAdd(&stq[which[tid]], part[tid]);
+  __syncthreads();
+}
 
 // iSAX symbol of a PAA value: the number of breakpoints beta_1..beta_{card-1}
 // that are <= p, given bp[j] = beta_j (bp[0] = -inf).

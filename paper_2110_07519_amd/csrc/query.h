@@ -79,7 +79,8 @@ void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState
 // statistics: the work the search needs once the final k-th best is known
 void launch_min_work(const IndexDev& ix, const QueryParams& qp, const QueryState& qs, int blocks,
                      hipStream_t st);
-size_t process_lds_bytes(const QueryParams& qp);
+size_t process_lds_bytes(const QueryParams& qp);   // dynamic LDS of the process kernel
+size_t process_lds_static(const QueryParams& qp);  // its static LDS (upper bound)
 size_t finalize_lds_bytes(const QueryParams& qp);
 size_t stage1_lds_bytes(const QueryParams& qp);
 int process_blocks_per_cu(const QueryParams& qp);

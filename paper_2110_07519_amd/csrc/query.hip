@@ -726,6 +726,18 @@ __device__ __forceinline__ bool offer(const IndexDev& ix, const QueryParams& p, 
   return false;
 }
 
+// Insertion of an approximate-search distance into the k best, skipped when
+// it is not below `known`, the caller's last view of slot k-1 (slots only
+// decrease, so such a key could not enter); returns the new view.  Keeps
+// most candidates off the slots' few addresses.
+__device__ __forceinline__ unsigned long long approx_insert(unsigned long long* slots, int k,
+                                                            unsigned long long key,
+                                                            unsigned long long known) {
+  if (key >= known) return known;
+  topk_insert(slots, k, key);
+  return load_key(&slots[k - 1]);
+}
+
 // ---------------------------------------------------------------------------
 // stage1: blocks [0, A) refine the approximate range, blocks [A, ..) compute
 // the bound of every leaf and its bucket histogram.
@@ -907,12 +919,13 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     __syncthreads();
     const int gw = blockIdx.x * (blockDim.x / kWave) + wv;
     const int nw = approx_blocks * (blockDim.x / kWave);
+    unsigned long long known = kEmptyKey;  // this wave's view of slot k-1 (never below it)
     for (int j = gw; j < cnt; j += nw) {
       const int64_t pos = P0 + j;
       const float d2 = ed_wave(zl, zrow_ptr(ix, pos), len, lane);
       if (lane == 0) {
         approx_d2[j] = d2;
-        topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
+        known = approx_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]), known);
       }
     }
   } else if constexpr (R == -2) {  // DTW, wide band: one wave per series
@@ -922,6 +935,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     for (int t = tid; t < len; t += blockDim.x) ql[t] = zq[t];
     __syncthreads();
     const int gw = blockIdx.x * 4 + wv, nw = approx_blocks * 4;
+    unsigned long long known = kEmptyKey;
     for (int j = gw; j < cnt; j += nw) {
       const int64_t pos = P0 + j;
       const float* xr = zrow_ptr(ix, pos);
@@ -932,7 +946,7 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
                                        (float)INFINITY, lane);
       if (lane == 0) {
         approx_d2[j] = d2;
-        topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
+        known = approx_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]), known);
       }
     }
   } else {  // DTW, register band: one thread per series
@@ -940,11 +954,12 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     for (int t = tid; t < len + 2 * R; t += blockDim.x)
       qpad[t] = (t >= R && t < R + len) ? zq[t - R] : INFINITY;
     __syncthreads();
+    unsigned long long known = kEmptyKey;
     for (int j = blockIdx.x * blockDim.x + tid; j < cnt; j += approx_blocks * blockDim.x) {
       const int64_t pos = P0 + j;
       const float d2 = dtw_band<R, MASK>(qpad, zrow_ptr(ix, pos), len, p.window, INFINITY);
       approx_d2[j] = d2;
-      topk_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]));
+      known = approx_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]), known);
     }
   }
 }
@@ -1350,15 +1365,12 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
     c_bsf += __shfl_xor(c_bsf, o, kWave);
     c_cells += __shfl_xor(c_cells, o, kWave);
   }
-  if (lane == 0) {
-    unsigned long long* stq = s.stats + (int64_t)q * kStatCount;
-    if (c_leaf) atomicAdd(&stq[kStatLeavesKept], c_leaf);
-    if (c_lb) atomicAdd(&stq[kStatSeriesLb], c_lb);
-    if (c_lbk) atomicAdd(&stq[kStatLbKeogh], c_lbk);
-    if (c_lbi) atomicAdd(&stq[kStatLbImproved], c_lbi);
-    if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
-    if (c_bsf) atomicAdd(&stq[kStatBsf], c_bsf);
-    if (c_cells) atomicAdd(&stq[kStatCells], c_cells);
+  if (p.count_work) {
+    __shared__ unsigned long long s_part[7];
+    const int which[7] = {kStatLeavesKept, kStatSeriesLb, kStatLbKeogh, kStatLbImproved, kStatRefined,
+                          kStatBsf, kStatCells};
+    const unsigned long long val[7] = {c_leaf, c_lb, c_lbk, c_lbi, c_ref, c_bsf, c_cells};
+    add_block_counts<7>(s.stats + (int64_t)q * kStatCount, which, val, s_part);
   }
   __syncthreads();  // LDS is reloaded for the next query
   }
@@ -1709,12 +1721,11 @@ __global__ __launch_bounds__(kEdThreads) void k_process_ed(IndexDev ix, QueryPar
       c_lb += __shfl_xor(c_lb, o, kWave);
       c_ref += __shfl_xor(c_ref, o, kWave);
     }
-    if (lane == 0) {
-      unsigned long long* stq = s.stats + (int64_t)q * kStatCount;
-      if (c_leaf) atomicAdd(&stq[kStatLeavesKept], c_leaf);
-      if (c_lb) atomicAdd(&stq[kStatSeriesLb], c_lb);
-      if (c_ref) atomicAdd(&stq[kStatRefined], c_ref);
-      if (c_bsf) atomicAdd(&stq[kStatBsf], c_bsf);
+    if (p.count_work) {
+      __shared__ unsigned long long s_part[4];
+      const int which[4] = {kStatLeavesKept, kStatSeriesLb, kStatRefined, kStatBsf};
+      const unsigned long long val[4] = {lane == 0 ? c_leaf : 0ull, c_lb, c_ref, c_bsf};
+      add_block_counts<4>(s.stats + (int64_t)q * kStatCount, which, val, s_part);
     }
     __syncthreads();  // LDS is reloaded for the next query
   }
@@ -2089,6 +2100,8 @@ __global__ __launch_bounds__(1024) void k_list_scan(QueryParams p, ScreenDev sc)
 constexpr int kScreenWaves = 8;
 constexpr int kScreenChunk = 64;
 
+constexpr int kScreenGrab = 4;  // leaves taken per grab of the screen's work counter
+
 template <int KS>
 struct ScreenShape {
   static constexpr int len = 32 * KS;
@@ -2116,11 +2129,16 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
   __shared__ int s_leaf;
   const float one_m = 1.0f - sc.c_abs;
   unsigned long long screened = 0, passed = 0;
-  for (;;) {
-    if (tid == 0) s_leaf = atomicAdd(sc.counter, 1);
-    __syncthreads();
-    const int leaf = s_leaf;
-    __syncthreads();
+  // leaves are taken kScreenGrab at a time (one device atomic each: the
+  // counter is one address for the whole grid)
+  for (int leaf = 0, grab_end = 0;; ++leaf) {
+    if (leaf >= grab_end) {
+      if (tid == 0) s_leaf = atomicAdd(sc.counter, kScreenGrab);
+      __syncthreads();
+      leaf = s_leaf;
+      __syncthreads();
+      grab_end = leaf + kScreenGrab;
+    }
     if (leaf >= p.n_leaves) break;
     const int64_t l0 = sc.off[leaf], l1 = sc.off[leaf + 1];
     if (l0 == l1) continue;
@@ -2240,9 +2258,11 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
                 if (lane == 0) {
                   const int kk = k_of(p, s, qsel);
                   const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
-                  if (offer(ix, p, s, qsel, d2, jsel, ck, true))
-                    atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatBsf], 1ull);
-                  atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
+                  const bool in = offer(ix, p, s, qsel, d2, jsel, ck, true);
+                  if (p.count_work) {
+                    if (in) atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatBsf], 1ull);
+                    atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
+                  }
                 }
                 ++passed;
               }
@@ -2255,7 +2275,7 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
     }
   }
   // lanes of a wave counted the same tiles: one add per wave
-  if (lane == 0) {
+  if (lane == 0 && p.count_work) {
     atomicAdd(&sc.tally[0], screened);
     atomicAdd(&sc.tally[1], passed);
   }
@@ -2372,7 +2392,8 @@ size_t process_lds_bytes(const QueryParams& p) {
   bool mask;
   const int R = band_of(p, &mask);
   size_t w = 0;
-  if (R == -1) w = (size_t)kMaxSeg * (1 << p.card_bits) + p.len + 2 * (size_t)kEdWaves * kEdList;
+  if (R == -1)  // the table is static LDS for 8-bit symbols
+    w = (p.card_bits == 8 ? 0 : (size_t)kMaxSeg * (1 << p.card_bits)) + p.len + 2 * (size_t)kEdWaves * kEdList;
   else if (R == -2) w = process_lds_words<-2>(p);
   else w = process_lds_words<0>(p) + 2 * (size_t)R;  // the padded query grows with R
   return w * sizeof(float);
@@ -2552,6 +2573,19 @@ void* noalloc_scratch(size_t* bytes) {
     ptr[dev] = p;
   }
   return ptr[dev];
+}
+
+size_t process_lds_static(const QueryParams& p) {
+  bool mask;
+  if (band_of(p, &mask) != -1) return 4096;  // a few shared scalars
+  hipFuncAttributes a{};
+  const hipError_t e = p.card_bits == 8 ? hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_process_ed<8>))
+                                        : hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_process_ed<0>));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 48 * 1024;  // above the kernel's own (a refusal rather than a failed launch)
+  }
+  return a.sharedSizeBytes;
 }
 
 int ed_process_blocks(int resident) {
