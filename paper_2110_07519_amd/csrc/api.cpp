@@ -171,7 +171,8 @@ struct QueryCtx {
   int proc_blocks_ed = 0;  // cached occupancy of the ED process kernel
   hipEvent_t ev[5] = {};
   bool events_ready = false;
-  int* h_status = nullptr;  // pinned copy of the per-query status words
+  int* h_status = nullptr;  // per-query status words in pinned, device-mapped host memory
+  int* d_status = nullptr;  // their device address
   int h_status_cap = 0;
 
   QueryCtx() = default;
@@ -673,13 +674,15 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     sc.c_abs = (float)std::ldexp(1.0, -17);
   }
   const int screen_blocks = screen ? screen_blocks_per_cu(len) * ix->n_cus : 0;
-  // the status words come back into pinned memory: a copy to pageable
-  // memory would be staged through a runtime buffer on every call
+  // the status words live in pinned host memory the kernels write through
+  // its device mapping, so no copy follows the kernels
   if (!fixed && c.h_status_cap < nq) {
     if (c.h_status) HIP_OR_THROW(hipHostFree(c.h_status));
     c.h_status = nullptr;
+    c.d_status = nullptr;
     c.h_status_cap = 0;
-    HIP_OR_THROW(hipHostMalloc((void**)&c.h_status, sizeof(int) * (size_t)nq, hipHostMallocDefault));
+    HIP_OR_THROW(hipHostMalloc((void**)&c.h_status, sizeof(int) * (size_t)nq, hipHostMallocMapped));
+    HIP_OR_THROW(hipHostGetDevicePointer((void**)&c.d_status, c.h_status, 0));
     c.h_status_cap = nq;
   }
   // phase timing (only when the caller asks for statistics)
@@ -697,6 +700,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
     const IndexDev v = ix->view();
     QueryState qs = fixed ? fixed->qs : c.ws.qs;
     int* h_status = fixed ? fixed->h_status : c.h_status;
+    if (!fixed) qs.status = c.d_status;
     qs.kq = d_kq;
     qs.qmap = d_qmap;
     if (stats) HIP_OR_THROW(hipEventRecord(ev[0], st));
@@ -718,7 +722,10 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
       if (min_work) launch_min_work(v, p, qs, std::max(1, ix->n_cus), st);
     }
     launch_check();
-    d2h(h_status, qs.status, nq, st);
+    if (fixed)
+      d2h(h_status, qs.status, nq, st);
+    else
+      HIP_OR_THROW(hipStreamSynchronize(st));
     int worst = 0;
     for (int i = 0; i < nq; ++i) worst |= h_status[i];
     if (!(worst & 1)) {

@@ -917,15 +917,30 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
     float* zl = sm;
     for (int t = tid; t < len; t += blockDim.x) zl[t] = zq[t];
     __syncthreads();
+    // eight consecutive rows per wave at a time, their loads in flight
+    // together
     const int gw = blockIdx.x * (blockDim.x / kWave) + wv;
     const int nw = approx_blocks * (blockDim.x / kWave);
     unsigned long long known = kEmptyKey;  // this wave's view of slot k-1 (never below it)
-    for (int j = gw; j < cnt; j += nw) {
-      const int64_t pos = P0 + j;
-      const float d2 = ed_wave(zl, zrow_ptr(ix, pos), len, lane);
+    for (int j0 = gw * kGroup; j0 < cnt; j0 += nw * kGroup) {
+      int gr[kGroup];
+      unsigned act = 0;
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c) {
+        const bool in = j0 + c < cnt;
+        const int64_t pos = P0 + (in ? j0 + c : j0);
+        gr[c] = ix.zrow ? ix.zrow[pos] : (int)pos;
+        act |= in ? (1u << c) : 0u;
+      }
+      float dv[kGroup];
+      ed_rows<kGroup>(zl, ix.Z, len, gr, act, lane, dv);
       if (lane == 0) {
-        approx_d2[j] = d2;
-        known = approx_insert(slots, kk, pack_key(d2, (uint32_t)ix.perm[pos]), known);
+#pragma unroll
+        for (int c = 0; c < kGroup; ++c)
+          if ((act >> c) & 1u) {
+            approx_d2[j0 + c] = dv[c];
+            known = approx_insert(slots, kk, pack_key(dv[c], (uint32_t)ix.perm[P0 + j0 + c]), known);
+          }
       }
     }
   } else if constexpr (R == -2) {  // DTW, wide band: one wave per series
