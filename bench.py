@@ -103,55 +103,91 @@ def query_stats(pm, idx, qt, k, distance, window):
     return tot
 
 
-def run_batched(pm, idx, n, length, nq, reps):
-    """One call per batch of nq noisy-copy queries (noise 0.01/0.1/1.0 round
-    robin), ED, k alternating 1 and 10: plain FP32 path vs the BF16 screen.
-    Returns queries/s of each and whether their answers are identical."""
+def run_c4(pm, idx, n, length, nq, reps):
+    """The batched configuration on one index: one call per batch of nq
+    noisy-copy queries (noise 0.01/0.1/1.0 round robin), ED, k alternating
+    1 and 10.  The autotuner first picks the batch knobs for this shape
+    (or finds them in its cache); then, best of reps: the plain FP32 path
+    with the default knobs, the BF16 screen with the tuned knobs, and the
+    same replayed from a HIP graph.  Answers of all three must be
+    identical."""
     import torch
     import synth
 
     bq, _, _ = synth.noisy_queries(nq, n, length, j0=100_000)
     ks = [1 if i % 2 == 0 else 10 for i in range(nq)]
     bt = torch.from_numpy(bq).cuda()
+    out = {"workload": f"{nq} noisy dataset copies per call over {n} x {length}, ED, k alternating 1 and 10",
+           "n": n, "len": length, "batch": nq}
     t0 = time.perf_counter()
     pm.messi_prepare_screen(idx)
     torch.cuda.synchronize()
-    prep_s = time.perf_counter() - t0
-    out = {"workload": f"{nq} noisy dataset copies per call, ED, k alternating 1 and 10",
-           "screen_prepare_s": prep_s}
+    out["screen_prepare_s"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    tune = pm.messi_autotune(idx, bt, ks, 0, 0, kmax=10, flags=pm.MESSI_SCREEN_BF16)
+    out["autotune"] = dict(tune, seconds=time.perf_counter() - t0)
+    log(f"C4 {n} x {length}: autotune {out['autotune']}")
+    oi = torch.empty((nq, 10), dtype=torch.int64, device="cuda")
+    od = torch.empty((nq, 10), dtype=torch.float32, device="cuda")
     answers = {}
-    for name, flags in (("plain", 0), ("screen", pm.MESSI_SCREEN_BF16)):
-        pm.messi_query_batch(idx, bt[:32], ks[:32], 0, 0, kmax=10, flags=flags)  # warm up
+    runs = (("plain", 0), ("screen", pm.MESSI_SCREEN_BF16), ("screen_graph", pm.MESSI_SCREEN_BF16 | pm.MESSI_GRAPH))
+    for name, flags in runs:
+        pm.messi_query_batch(idx, bt, ks, 0, 0, kmax=10, flags=flags, out_ids=oi, out_dists=od)  # warm / capture
+        torch.cuda.synchronize()
         best = None
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            ids, d, st = pm.messi_query_batch(idx, bt, ks, 0, 0, kmax=10, flags=flags, stats=True)
+            pm.messi_query_batch(idx, bt, ks, 0, 0, kmax=10, flags=flags, out_ids=oi, out_dists=od)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            if best is None or dt < best[0]:
-                best = (dt, st)
-        dt, st = best
-        answers[name] = (ids.cpu().numpy(), d.cpu().numpy())
-        out[name] = {"queries_per_s": nq / dt, "ms_per_batch": dt * 1e3,
-                     "phases_us": {p: st[f"us_{p}"] for p in PHASES},
-                     "refined_per_query": st["refined"] / nq,
-                     "series_lb_per_query": st["series_lb"] / nq,
-                     "screened_pairs_per_query": st["screened"] / nq}
-        log(f"batched {name}: {nq / dt:.0f} q/s ({dt * 1e3:.1f} ms per {nq}), phases "
-            f"{ {p: round(st[f'us_{p}']) for p in PHASES} }, refined/q {st['refined'] / nq:.0f}")
+            best = dt if best is None else min(best, dt)
+        answers[name] = (oi.cpu().numpy(), od.cpu().numpy())
+        out[name] = {"queries_per_s": nq / best, "ms_per_batch": best * 1e3}
+        if name != "screen_graph":  # phase times and counters from one more (untimed) call
+            _, _, st = pm.messi_query_batch(idx, bt, ks, 0, 0, kmax=10, flags=flags, stats=True)
+            out[name].update({"phases_us": {p: st[f"us_{p}"] for p in PHASES},
+                              "refined_per_query": st["refined"] / nq,
+                              "series_lb_per_query": st["series_lb"] / nq,
+                              "screened_pairs_per_query": st["screened"] / nq})
+        log(f"C4 {n} x {length} {name}: {nq / best:.0f} q/s ({best * 1e3:.1f} ms per {nq})")
     sc = out["screen"]
-    flops = sc["screened_pairs_per_query"] * nq * 2.0 * length
-    us = sc["phases_us"]["process"]
-    sc["mfma_roofline"] = {"bound": "mfma", "achieved": flops / (us * 1e-6) / 1e12,
-                           "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                           "frac": flops / (us * 1e-6) / 1e12 / BF16_PEAK_TFLOPS,
-                           "flops_per_launch": flops,
-                           "note": "algorithmic q.x flops (2 len per screened pair) over the screen "
-                                   "phase (leaf lists + screen kernel)"}
-    out["identical_answers"] = bool(np.array_equal(answers["plain"][0], answers["screen"][0]) and
-                                    np.array_equal(answers["plain"][1], answers["screen"][1]))
+    if sc["screened_pairs_per_query"] > 0:
+        flops = sc["screened_pairs_per_query"] * nq * 2.0 * length
+        us = sc["phases_us"]["process"]
+        sc["mfma_roofline"] = {"bound": "mfma", "achieved": flops / (us * 1e-6) / 1e12,
+                               "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": flops / (us * 1e-6) / 1e12 / BF16_PEAK_TFLOPS,
+                               "flops_per_launch": flops,
+                               "note": "algorithmic q.x flops (2 len per screened pair) over the screen "
+                                       "phase (leaf lists + screen kernel)"}
+    ref = answers["plain"]
+    out["identical_answers"] = bool(all(np.array_equal(ref[0], a[0]) and np.array_equal(ref[1], a[1])
+                                        for a in answers.values()))
     out["screen_speedup"] = out["screen"]["queries_per_s"] / out["plain"]["queries_per_s"]
+    out["graph_speedup"] = out["screen_graph"]["queries_per_s"] / out["screen"]["queries_per_s"]
+    return out
+
+
+def run_c4_200m(pm, n, length, nq, reps, cache):
+    """The batched configuration at 200,000,000 x 128 (the SALD shape),
+    generated in HBM and indexed in place."""
+    import torch
+    import synth
+
+    log(f"C4: generating {n} x {length} random walks in HBM")
+    data = torch.empty((n, length), dtype=torch.float32, device="cuda")
+    synth.randomwalk_device(data, seed=synth.SEED_DATA)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx = pm.messi_build_ex(data, 16, 256, 2000, inplace=True, autotune_cache=cache)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    out = run_c4(pm, idx, n, length, nq, reps)
+    out["build_s"] = build_s
+    idx.free()
+    del data
+    torch.cuda.empty_cache()
     return out
 
 
@@ -477,6 +513,10 @@ def main():
     ap.add_argument("--batch", type=int, default=1024,
                     help="queries of the batched run (noisy copies, k alternating 1 and 10)")
     ap.add_argument("--batch-reps", type=int, default=2)
+    ap.add_argument("--c4-200m", type=int, default=200_000_000,
+                    help="series of the 128-point batched configuration (0: skip it)")
+    ap.add_argument("--autotune-cache", type=str, default=os.path.join("/tmp", "messi_autotune.json"),
+                    help="JSON file of tuned batch knobs (read at build, written by the autotuner)")
     ap.add_argument("--classify", type=int, default=1024,
                     help="queries per k-NN classification call (0: skip)")
     ap.add_argument("--serve-seconds", type=float, default=6.0,
@@ -540,7 +580,7 @@ def main():
         synth.trend_labels_device(data, labels)
     log("building the index")
     t0 = time.perf_counter()
-    idx = pm.messi_build(data, 16, 256, args.leaf)
+    idx = pm.messi_build_ex(data, 16, 256, args.leaf, autotune_cache=args.autotune_cache)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     info = idx.info()
@@ -600,7 +640,7 @@ def main():
 
     batched = None
     if args.batch > 0:
-        batched = run_batched(pm, idx, n, length, args.batch, args.batch_reps)
+        batched = {f"{n // 1_000_000}Mx{length}": run_c4(pm, idx, n, length, args.batch, args.batch_reps)}
 
     classification = None
     if labels is not None:
@@ -610,6 +650,12 @@ def main():
     serving = None
     if args.serve_seconds > 0:
         serving = run_serving(pm, idx, n, length, args.serve_seconds, args.serve_capacity_requests)
+
+    idx.free()
+    torch.cuda.empty_cache()
+    if args.batch > 0 and args.c4_200m > 0:
+        batched[f"{args.c4_200m // 1_000_000}Mx128"] = run_c4_200m(pm, args.c4_200m, 128, args.batch,
+                                                                  args.batch_reps, args.autotune_cache)
 
     subsequence = None
     if args.subseq_points > 0:
@@ -674,7 +720,6 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
-    idx.free()
 
 
 if __name__ == "__main__":

@@ -44,8 +44,9 @@ enum {
 
 enum { MESSI_ED = 0, MESSI_DTW = 1 };
 
-/* Flags of messi_query_batch, messi_classify and the server. */
-enum { MESSI_SCREEN_BF16 = 1, MESSI_LB_IMPROVED = 2 };
+/* Flags of messi_query_batch, messi_classify and the server
+ * (MESSI_GRAPH: messi_query_batch only). */
+enum { MESSI_SCREEN_BF16 = 1, MESSI_LB_IMPROVED = 2, MESSI_GRAPH = 4 };
 
 typedef struct messi_index messi_index; /* opaque; owned by the library */
 
@@ -113,8 +114,14 @@ typedef struct messi_options {
                           leaf permutation); the index keeps no copy, so a
                           collection may take most of the device memory.
                           The caller keeps ownership: the buffer must stay
-                          allocated and unmodified until messi_free.  It
-                          must be 16-byte aligned. */
+                          allocated and unmodified until messi_free.
+                          2: the same, and the index takes the buffer over:
+                          messi_free releases it with hipFree, so it must
+                          be the start of a hipMalloc allocation (checked
+                          with hipMemGetAddressRange; MESSI_EINVAL
+                          otherwise) that the caller no longer uses.  If
+                          the build fails the caller keeps it.
+                          Either way it must be 16-byte aligned. */
   int32_t bf16_screen; /* 1: also make the BF16 copy used by MESSI_SCREEN_BF16 */
   int32_t raw;         /* 1: index the series as given, without z-normalising
                           them (the non-normalised search the paper's
@@ -123,6 +130,19 @@ typedef struct messi_options {
                           distances are unchanged; with inplace the rows
                           are left as they are.  Values must be finite with squared
                           row norms below FP32's range. */
+  int64_t mem_budget_bytes; /* 0: no limit beyond the device.  Otherwise the
+                          device bytes the index may hold - its tables, a
+                          store it owns (its copy, or an inplace = 2
+                          buffer), the BF16 copy and the buffers of its own
+                          calls; a build or call that would exceed it
+                          fails with MESSI_ENOMEM.  A server started with
+                          mem_budget_bytes 0 takes what is left of it. */
+  const char* autotune_cache; /* NULL: none.  Path of a JSON file of tuned
+                          knobs (messi_autotune): read here (a missing file
+                          is an empty cache; a file this library did not
+                          write is MESSI_EINVAL) and written back by every
+                          messi_autotune that measures; its entries steer
+                          messi_query_batch for the batch shapes they name. */
 } messi_options;
 
 /* messi_build with options (NULL = defaults).  With inplace, `series` is
@@ -164,9 +184,9 @@ int messi_build_windows(const float* series, int64_t total, int32_t len, int32_t
  * the lower id.
  * Long series: the query kernels keep the query and per-wave rows in LDS,
  * up to what one block may use on the device (160 KB on gfx950).  There,
- * ED accepts every len up to 4096, DTW with r <= 64 up to len 3968, and
- * DTW with a wider window up to len 1670; longer ones fail with
- * MESSI_EINVAL. */
+ * ED and DTW with r <= 31 accept every len up to 4096, DTW with r <= 64
+ * up to len 3968, and DTW with a wider window up to len 1670; longer ones
+ * fail with MESSI_EINVAL. */
 int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k,
                 int32_t distance, int32_t window, int64_t* out_ids, float* out_dists);
 
@@ -213,13 +233,59 @@ int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int3
  *              3.4 as the tighter, costlier alternative) before DTW.  Same
  *              answers; ignored where its LDS buffers do not fit (long
  *              series with a small window).
+ *              MESSI_GRAPH: the batch's launches are captured in a HIP
+ *              graph, kept (up to 8 per index) and replayed by later calls
+ *              whose launches would be identical, argument for argument
+ *              (same queries and output pointers, nq, kmax, k, distance,
+ *              window, flags and buffers); ignored when stats is given.
+ *              Same answers.
  *   out_ids    device pointer, int64 [nq][kmax]; out_dists device pointer,
  *              float32 [nq][kmax]: row i holds query i's k[i] neighbours
  *              ascending by (distance, id), then (-1, +inf) up to kmax.
- *   stats      may be NULL; counters and phase times summed over groups. */
+ *   stats      may be NULL; counters and phase times summed over groups
+ *              (groups may run concurrently, so the times may add up to
+ *              more than the call took).
+ * Groups of different (distance, window) run concurrently on streams of
+ * their own, joined back into the index's stream, unless the tuned knobs
+ * for this batch shape say otherwise (messi_autotune). */
 int messi_query_batch(messi_index* index, const float* queries, int32_t nq, const int32_t* k,
                       const int32_t* distance, const int32_t* window, int32_t kmax, int32_t flags,
                       int64_t* out_ids, float* out_dists, messi_stats* stats);
+
+/* Knobs of messi_query_batch for one batch shape, as messi_autotune
+ * chose them (the defaults are the built-in choices). */
+typedef struct messi_tune {
+  int32_t screen;      /* 1: ED groups take the BF16 screen when asked for */
+  int32_t screen_min;  /* fewest ED queries in a screened group (32) */
+  int32_t screen_nt;   /* 16-series column tiles per wave of the screen
+                          kernel (0: 4, or 1 for len 512) */
+  int32_t screen_occ;  /* screen blocks per CU (0: the occupancy limit) */
+  int32_t ed_scale;    /* ED process grid, in resident grids (1) */
+  int32_t dtw_scale;   /* DTW process blocks per query, in multiples of an
+                          even share of the resident grid (1) */
+  int32_t overlap;     /* 1: groups run concurrently (1) */
+  int32_t from_cache;  /* 1: found in the cache, nothing measured */
+  int32_t candidates;  /* knob settings timed */
+  int32_t reserved;
+  double ms;           /* batch time with these knobs (best of up to 2 runs) */
+  double ms_default;   /* batch time with the defaults */
+} messi_tune;
+
+/* Autotuner of messi_query_batch (not part of the paper's method): times
+ * the batch (arguments as for messi_query_batch) with the default knobs
+ * and then one knob at a time - screen on / off, the screen kernel's
+ * column tiles and blocks per CU, the ED grid, DTW blocks per query,
+ * concurrent groups - keeping a setting only if it is at least 2% faster,
+ * and checks that every setting's answers equal the defaults' bit for bit
+ * (MESSI_EDEVICE if not).  The choice is kept in the index for batches of
+ * the same shape (device, index shape, nq rounded up to a power of two,
+ * (distance, window) mix, flags) and written to messi_options'
+ * autotune_cache file if one was given.  A shape already tuned (in this
+ * index or the file) returns its entry with from_cache = 1 at once.
+ * The runs write to buffers of the library's own (2 nq kmax x 12 bytes). */
+int messi_autotune(messi_index* index, const float* queries, int32_t nq, const int32_t* k,
+                   const int32_t* distance, const int32_t* window, int32_t kmax, int32_t flags,
+                   messi_tune* out);
 
 /* k-NN classifier (Section 5.4): each query takes the class held by most of
  * its k nearest neighbours (as messi_query_batch computes them, flags
@@ -254,7 +320,14 @@ typedef struct messi_server messi_server;
 typedef struct messi_server_options { /* zero-initialised = defaults */
   int32_t workers;          /* concurrent batches, 1..8 (0: 2) */
   int32_t max_batch;        /* most requests per batch (0: 1024) */
-  int64_t mem_budget_bytes; /* device bytes in-flight requests may hold (0: no limit) */
+  int64_t mem_budget_bytes; /* device bytes the workers may hold (0: what the
+                               index's budget leaves, or no limit): every
+                               worker holds the buffers of its batch
+                               capacity from the start, which is cut until
+                               all workers fit; a batch whose near-tie log
+                               grows charges the growth to the in-flight
+                               bytes and returns it when the log is shrunk
+                               back after the batch */
   int32_t flags;            /* MESSI_SCREEN_BF16: screen ED requests;
                                MESSI_LB_IMPROVED: LB_Improved for DTW requests */
   int32_t kmax;             /* largest k a request may ask (0: 64) */
@@ -266,6 +339,10 @@ typedef struct messi_server_stats {
   int64_t request_bytes;    /* device bytes accounted per admitted request */
   int64_t batch_capacity;   /* requests a worker can take at once */
   double busy_us;           /* summed worker time with a batch on the GPU */
+  int64_t resident_bytes;   /* device bytes the workers hold now */
+  int64_t log_growth_bytes; /* near-tie log growth charged so far (summed);
+                               in-flight bytes stay within the budget plus
+                               what a growth charges while its batch runs */
 } messi_server_stats;
 
 int messi_server_start(messi_index* index, const messi_server_options* opts, messi_server** out);

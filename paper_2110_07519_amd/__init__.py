@@ -7,7 +7,7 @@ library is not built, importing works but every call raises.
 
 Names follow the C ABI: messi_build, messi_build_ex, messi_build_windows, messi_query, messi_query_stats,
 messi_query_noalloc,
-messi_query_batch, messi_prepare_screen, messi_classify, messi_set_stream,
+messi_query_batch, messi_autotune, messi_prepare_screen, messi_classify, messi_set_stream,
 messi_free, messi_breakpoints, messi_get_words,
 messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
 """
@@ -30,6 +30,7 @@ MESSI_ED = 0
 MESSI_DTW = 1
 MESSI_SCREEN_BF16 = 1
 MESSI_LB_IMPROVED = 2
+MESSI_GRAPH = 4
 
 EXPORTS = [
     "messi_build", "messi_query", "messi_query_stats", "messi_set_stream", "messi_index_info",
@@ -37,7 +38,7 @@ EXPORTS = [
     "messi_last_error", "messi_query_batch", "messi_prepare_screen",
     "messi_server_start", "messi_server_submit", "messi_server_poll", "messi_server_get_stats",
     "messi_server_stop", "messi_classify", "messi_build_ex", "messi_build_windows",
-    "messi_query_noalloc",
+    "messi_query_noalloc", "messi_autotune",
 ]
 
 
@@ -79,7 +80,8 @@ class MessiServerStats(ctypes.Structure):
                 ("batches", ctypes.c_int64), ("max_batch_seen", ctypes.c_int64),
                 ("inflight_bytes", ctypes.c_int64), ("peak_inflight_bytes", ctypes.c_int64),
                 ("mem_budget_bytes", ctypes.c_int64), ("request_bytes", ctypes.c_int64),
-                ("batch_capacity", ctypes.c_int64), ("busy_us", ctypes.c_double)]
+                ("batch_capacity", ctypes.c_int64), ("busy_us", ctypes.c_double),
+                ("resident_bytes", ctypes.c_int64), ("log_growth_bytes", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -103,6 +105,7 @@ def lib():
         L.messi_query_stats.argtypes = [P, P, i32, i32, i32, i32, P, P, P]
         L.messi_query_noalloc.argtypes = [P, P, i32, i32, i32, i32, P, P]
         L.messi_query_batch.argtypes = [P, P, i32, P, P, P, i32, i32, P, P, P]
+        L.messi_autotune.argtypes = [P, P, i32, P, P, P, i32, i32, P]
         L.messi_prepare_screen.argtypes = [P]
         L.messi_classify.argtypes = [P, P, i32, P, i32, i32, i32, i32, i32, P, P, P]
         L.messi_server_start.argtypes = [P, P, P]
@@ -121,7 +124,7 @@ def lib():
         L.messi_free.restype = None
         L.messi_last_error.restype = ctypes.c_char_p
         for name in ["messi_build", "messi_build_ex", "messi_build_windows", "messi_query", "messi_query_stats",
-                     "messi_query_noalloc", "messi_query_batch",
+                     "messi_query_noalloc", "messi_query_batch", "messi_autotune",
                      "messi_prepare_screen", "messi_classify", "messi_server_start",
                      "messi_server_submit",
                      "messi_server_poll", "messi_server_get_stats", "messi_set_stream",
@@ -167,27 +170,61 @@ def messi_build(series, segments: int = 16, cardinality: int = 256, leaf_size: i
 
 class MessiOptions(ctypes.Structure):
     _fields_ = [("inplace", ctypes.c_int32), ("bf16_screen", ctypes.c_int32),
-                ("raw", ctypes.c_int32)]
+                ("raw", ctypes.c_int32), ("mem_budget_bytes", ctypes.c_int64),
+                ("autotune_cache", ctypes.c_char_p)]
+
+
+class MessiTune(ctypes.Structure):
+    _fields_ = [("screen", ctypes.c_int32), ("screen_min", ctypes.c_int32),
+                ("screen_nt", ctypes.c_int32), ("screen_occ", ctypes.c_int32),
+                ("ed_scale", ctypes.c_int32), ("dtw_scale", ctypes.c_int32),
+                ("overlap", ctypes.c_int32), ("from_cache", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+def _options(inplace=0, bf16_screen=False, raw=False, mem_budget_bytes=0, autotune_cache=None):
+    path = None if autotune_cache is None else os.fsencode(autotune_cache)
+    return MessiOptions(int(inplace), int(bf16_screen), int(raw), int(mem_budget_bytes), path)
 
 
 def messi_build_ex(series, segments: int = 16, cardinality: int = 256, leaf_size: int = 2000,
-                   inplace: bool = False, bf16_screen: bool = False, raw: bool = False):
+                   inplace: bool = False, bf16_screen: bool = False, raw: bool = False,
+                   mem_budget_bytes: int = 0, autotune_cache=None):
     """messi_build with options.  inplace: `series` (float32 CUDA [n, len]) is
     z-normalised in place and becomes the store; keep it alive and unmodified
     while the index lives (the returned Index holds a reference).  raw: the
-    series (and later the queries) are used as given, not z-normalised."""
+    series (and later the queries) are used as given, not z-normalised.
+    mem_budget_bytes: device bytes the index may hold (0: no limit).
+    autotune_cache: path of the JSON file of tuned batch knobs."""
     import torch
 
     assert series.dtype == torch.float32 and series.dim() == 2
     n, length = series.shape
     h = ctypes.c_void_p()
-    o = MessiOptions(int(inplace), int(bf16_screen), int(raw))
+    o = _options(int(inplace), bf16_screen, raw, mem_budget_bytes, autotune_cache)
     _check(lib().messi_build_ex(_dev_ptr(series), n, length, segments, cardinality, leaf_size,
                                 ctypes.cast(ctypes.pointer(o), ctypes.c_void_p), ctypes.byref(h)))
     idx = Index(h, n, length, segments)
     if inplace:
         idx.store = series
     return idx
+
+
+def messi_build_owned(ptr: int, n: int, length: int, segments: int = 16, cardinality: int = 256,
+                      leaf_size: int = 2000, bf16_screen: bool = False, raw: bool = False,
+                      mem_budget_bytes: int = 0, autotune_cache=None):
+    """In-place build that hands the device buffer at `ptr` (the start of a
+    hipMalloc allocation of n * length float32) over to the index, which
+    frees it in messi_free (messi_options.inplace = 2)."""
+    h = ctypes.c_void_p()
+    o = _options(2, bf16_screen, raw, mem_budget_bytes, autotune_cache)
+    _check(lib().messi_build_ex(ctypes.c_void_p(ptr), n, length, segments, cardinality, leaf_size,
+                                ctypes.cast(ctypes.pointer(o), ctypes.c_void_p), ctypes.byref(h)))
+    return Index(h, n, length, segments)
 
 
 def messi_build_windows(series, length: int, stride: int = 1, segments: int = 16,
@@ -201,7 +238,7 @@ def messi_build_windows(series, length: int, stride: int = 1, segments: int = 16
     assert series.dtype == torch.float32 and series.dim() == 1 and series.is_contiguous()
     total = series.shape[0]
     h = ctypes.c_void_p()
-    o = MessiOptions(1, int(bf16_screen), int(raw))
+    o = _options(1, bf16_screen, raw)
     _check(lib().messi_build_windows(_dev_ptr(series), total, length, stride, segments, cardinality,
                                      leaf_size, ctypes.cast(ctypes.pointer(o), ctypes.c_void_p),
                                      ctypes.byref(h)))
@@ -277,6 +314,25 @@ def messi_query_batch(index, queries, k, distance, window, kmax=None, flags=0, o
     if stats:
         return out_ids, out_dists, st.as_dict()
     return out_ids, out_dists
+
+
+def messi_autotune(index, queries, k, distance, window, kmax=None, flags=0) -> dict:
+    """Tune messi_query_batch's knobs on this batch (arguments as for
+    messi_query_batch); returns the chosen knobs and the timings."""
+    import torch
+
+    assert queries.dtype == torch.float32 and queries.dim() == 2
+    nq = queries.shape[0]
+    kk = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (nq,)))
+    dd = np.ascontiguousarray(np.broadcast_to(np.asarray(distance, dtype=np.int32), (nq,)))
+    ww = np.ascontiguousarray(np.broadcast_to(np.asarray(window, dtype=np.int32), (nq,)))
+    if kmax is None:
+        kmax = int(kk.max()) if nq else 1
+    t = MessiTune()
+    _check(lib().messi_autotune(index.handle, _dev_ptr(queries), nq, kk.ctypes.data_as(ctypes.c_void_p),
+                                dd.ctypes.data_as(ctypes.c_void_p), ww.ctypes.data_as(ctypes.c_void_p),
+                                int(kmax), int(flags), ctypes.byref(t)))
+    return t.as_dict()
 
 
 def messi_classify(index, labels, n_classes, queries, k=1, distance=MESSI_ED, window=0, flags=0):

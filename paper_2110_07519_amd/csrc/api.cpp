@@ -11,6 +11,8 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <functional>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <thread>
@@ -18,6 +20,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <unistd.h>
 #include <vector>
 
 #include "../../include/messi.h"
@@ -53,6 +56,11 @@ struct HipError {
 
 struct OomError {
   size_t bytes;
+};
+
+// An allocation that would take the index past its memory budget.
+struct BudgetError {
+  size_t need, budget;
 };
 
 // Device allocation owned by a vector of frees.
@@ -142,6 +150,37 @@ int log2_exact(int v) {
   return (1 << b) == v ? b : -1;
 }
 
+// Knobs of the batched path, chosen per batch shape by the autotuner
+// (messi_autotune); the defaults are the built-in choices.
+struct Tune {
+  int screen = 1;       // 1: ED groups take the BF16 screen when MESSI_SCREEN_BF16 asks for it
+  int screen_min = 32;  // fewest ED queries in a screened group
+  int screen_nt = 0;    // 16-series column tiles per wave of the screen kernel (0: its default)
+  int screen_occ = 0;   // screen blocks per CU (0: the occupancy limit)
+  int ed_scale = 1;     // ED process grid, in resident grids
+  int dtw_scale = 1;    // DTW process blocks per query, in multiples of the even share
+  int overlap = 1;      // 1: a batch's groups run concurrently, each on its own stream
+};
+
+struct TuneEntry {
+  Tune t;
+  double ms = 0.0, ms_default = 0.0;  // batch time with these knobs and with the defaults
+};
+
+// A batch's launches captured once and replayed.
+struct GraphEntry {
+  std::string key;  // every argument of every launch (see launch_key)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  GraphEntry() = default;
+  GraphEntry(const GraphEntry&) = delete;
+  GraphEntry& operator=(const GraphEntry&) = delete;
+  ~GraphEntry() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+};
+
 // Per-call query buffers, grown on demand and reused.
 struct Workspace {
   DevMem mem;
@@ -174,13 +213,27 @@ struct QueryCtx {
   int* h_status = nullptr;  // per-query status words in pinned, device-mapped host memory
   int* d_status = nullptr;  // their device address
   int h_status_cap = 0;
+  hipStream_t own_stream = nullptr;  // a stream this context created (destroyed with it)
+  hipEvent_t fork = nullptr;         // overlapped batch: the point the groups start from
+  hipEvent_t join = nullptr;         // overlapped batch: the end of this context's group
+  hipStream_t cap_stream = nullptr;  // stream the batch graphs are captured on
+  std::vector<std::unique_ptr<QueryCtx>> aux;          // contexts of a batch's groups 1, 2, ...
+  std::vector<std::unique_ptr<GraphEntry>> graphs;     // captured batches, oldest first
+  bool budgeted = false;  // workspace counts against the index's memory budget
+  std::function<void(int64_t)> on_grow;  // told of each change of the workspace's bytes
 
   QueryCtx() = default;
   QueryCtx(const QueryCtx&) = delete;
   QueryCtx& operator=(const QueryCtx&) = delete;
   ~QueryCtx() {
+    graphs.clear();
+    aux.clear();
     if (events_ready)
       for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (fork) (void)hipEventDestroy(fork);
+    if (join) (void)hipEventDestroy(join);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
     if (h_status) (void)hipHostFree(h_status);
   }
 };
@@ -221,8 +274,21 @@ struct messi_index {
   int n_cus = 0;
   size_t lds_max = 64 * 1024;  // LDS a block may use on this device
   std::mutex screen_mu;  // first-use construction of the BF16 copy
+  int64_t budget = 0;           // device bytes the index may hold (0: no limit)
+  float* owned_store = nullptr;  // in-place store the index took over (freed with it)
+  size_t store_bytes = 0;
+  std::string device;           // device tag of the autotune keys (arch and CU count)
+  std::string tune_path;        // autotune cache file ("" = none)
+  mutable std::mutex tune_mu;
+  std::map<std::string, TuneEntry> tunes;  // tuned knobs by batch shape
   QueryCtx ctx;  // the index's own calls (messi_query, messi_query_batch)
   std::atomic<int> busy{0};
+
+  messi_index() { ctx.budgeted = true; }
+  ~messi_index() {
+    ctx.graphs.clear();
+    if (owned_store) (void)hipFree(owned_store);
+  }
 
   IndexDev view() const {
     IndexDev v;
@@ -277,6 +343,78 @@ void d2h(T* dst, const T* src, size_t count, hipStream_t st) {
 }
 
 void launch_check() { HIP_OR_THROW(hipGetLastError()); }
+
+// Device bytes a query context holds: its workspace, batch buffers and the
+// contexts of further batch groups.
+size_t ctx_bytes(const QueryCtx& c) {
+  size_t b = c.ws.mem.bytes + c.batch_mem.bytes;
+  for (const auto& a : c.aux) b += ctx_bytes(*a);
+  return b;
+}
+
+// Device bytes the index holds: tables, store (its own or taken over), BF16
+// copy and its own query contexts.
+size_t held_bytes(const messi_index* ix) {
+  return ix->mem.bytes + ix->own.bytes + ix->screen_mem.bytes + ix->store_bytes + ctx_bytes(ix->ctx);
+}
+
+// Throws BudgetError if the index would hold more than its budget after
+// releasing `drop` bytes and allocating `add` more (contexts that do not
+// count against the budget - a server's workers - are not checked).
+void check_budget(const messi_index* ix, const QueryCtx& c, size_t drop, size_t add) {
+  if (!c.budgeted || ix->budget <= 0) return;
+  const size_t held = held_bytes(ix);
+  const size_t after = held - std::min(drop, held) + add;
+  if (after > (size_t)ix->budget) throw BudgetError{after, (size_t)ix->budget};
+}
+
+// Runs f, turning the library's exceptions into error codes.
+template <typename F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const OomError& e) {
+    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const BudgetError& e) {
+    return fail(MESSI_ENOMEM, "the index would hold %zu bytes, over its memory budget of %zu", e.need,
+                e.budget);
+  } catch (const HipError& e) {
+    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+  }
+}
+
+// The query state of nq queries with k slots and log_cap log entries each,
+// carved from `base` (256-byte aligned pieces); returns the bytes it takes.
+// With base == nullptr only the size is computed.
+size_t carve_state(const messi_index* ix, int nq, int k, int log_cap, char* base, QueryState* qs) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* ptr = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return ptr;
+  };
+  const size_t len = (size_t)ix->len, L = (size_t)ix->n_leaves, C = (size_t)ix->n_chunks, Q = (size_t)nq;
+  QueryState s{};
+  s.zq = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
+  s.eta = reinterpret_cast<float*>(take(Q * sizeof(float)));
+  s.upper = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
+  s.lower = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
+  s.paa = reinterpret_cast<float*>(take(Q * 3 * kMaxSeg * sizeof(float)));
+  s.approx_range = reinterpret_cast<int64_t*>(take(Q * 2 * sizeof(int64_t)));
+  s.approx_d2 = reinterpret_cast<float*>(take(Q * kApproxCap * sizeof(float)));
+  s.slots = reinterpret_cast<unsigned long long*>(take(Q * (size_t)k * 8));
+  s.log = reinterpret_cast<unsigned long long*>(take(Q * (size_t)log_cap * 8));
+  s.log_count = reinterpret_cast<int*>(take(Q * sizeof(int)));
+  s.leaf_lb = reinterpret_cast<float*>(take(Q * L * sizeof(float)));
+  s.items = reinterpret_cast<unsigned long long*>(take(Q * C * 8));
+  s.ranges = reinterpret_cast<int2*>(take(Q * C * sizeof(int2)));
+  s.next = reinterpret_cast<int*>(take(Q * kCounterInts * sizeof(int)));
+  s.stats = reinterpret_cast<unsigned long long*>(take(Q * kStatCount * 8));
+  s.status = reinterpret_cast<int*>(take(Q * sizeof(int)));
+  if (qs) *qs = s;
+  return off;
+}
+
 
 // The build proper; throws HipError / OomError.  Returns false if the node
 // or leaf tables were too small (caller retries with larger ones).
@@ -502,27 +640,36 @@ void ensure_workspace(messi_index* ix, QueryCtx& c, int nq, int k) {
       ws.len == ix->len)
     return;
   const int NQ = std::max(nq, ws.nq), K = std::max(k, ws.k), LC = c.log_cap;
+  const size_t old = ws.mem.bytes;
+  check_budget(ix, c, old, carve_state(ix, NQ, K, LC, nullptr, nullptr));
   ws.mem.clear();
   ws = Workspace{};
   QueryState& s = ws.qs;
   const int len = ix->len, L = ix->n_leaves;
-  s.zq = ws.mem.alloc<float>((size_t)NQ * len);
-  s.eta = ws.mem.alloc<float>(NQ);
-  s.upper = ws.mem.alloc<float>((size_t)NQ * len);
-  s.lower = ws.mem.alloc<float>((size_t)NQ * len);
-  s.paa = ws.mem.alloc<float>((size_t)NQ * 3 * kMaxSeg);
-  s.approx_range = ws.mem.alloc<int64_t>((size_t)NQ * 2);
-  s.approx_d2 = ws.mem.alloc<float>((size_t)NQ * kApproxCap);
-  s.slots = ws.mem.alloc<unsigned long long>((size_t)NQ * K);
-  s.log = ws.mem.alloc<unsigned long long>((size_t)NQ * LC);
-  s.log_count = ws.mem.alloc<int>(NQ);
-  s.leaf_lb = ws.mem.alloc<float>((size_t)NQ * L);
-  const int64_t item_cap = ix->n_chunks;
-  s.items = ws.mem.alloc<unsigned long long>((size_t)NQ * item_cap);
-  s.ranges = ws.mem.alloc<int2>((size_t)NQ * item_cap);
-  s.next = ws.mem.alloc<int>((size_t)NQ * kCounterInts);
-  s.stats = ws.mem.alloc<unsigned long long>((size_t)NQ * kStatCount);
-  s.status = ws.mem.alloc<int>(NQ);
+  try {
+    s.zq = ws.mem.alloc<float>((size_t)NQ * len);
+    s.eta = ws.mem.alloc<float>(NQ);
+    s.upper = ws.mem.alloc<float>((size_t)NQ * len);
+    s.lower = ws.mem.alloc<float>((size_t)NQ * len);
+    s.paa = ws.mem.alloc<float>((size_t)NQ * 3 * kMaxSeg);
+    s.approx_range = ws.mem.alloc<int64_t>((size_t)NQ * 2);
+    s.approx_d2 = ws.mem.alloc<float>((size_t)NQ * kApproxCap);
+    s.slots = ws.mem.alloc<unsigned long long>((size_t)NQ * K);
+    s.log = ws.mem.alloc<unsigned long long>((size_t)NQ * LC);
+    s.log_count = ws.mem.alloc<int>(NQ);
+    s.leaf_lb = ws.mem.alloc<float>((size_t)NQ * L);
+    const int64_t item_cap = ix->n_chunks;
+    s.items = ws.mem.alloc<unsigned long long>((size_t)NQ * item_cap);
+    s.ranges = ws.mem.alloc<int2>((size_t)NQ * item_cap);
+    s.next = ws.mem.alloc<int>((size_t)NQ * kCounterInts);
+    s.stats = ws.mem.alloc<unsigned long long>((size_t)NQ * kStatCount);
+    s.status = ws.mem.alloc<int>(NQ);
+  } catch (...) {
+    ws.mem.clear();
+    ws = Workspace{};
+    if (c.on_grow && old) c.on_grow(-(int64_t)old);
+    throw;
+  }
   ws.nq = NQ;
   ws.k = K;
   ws.len = len;
@@ -530,12 +677,37 @@ void ensure_workspace(messi_index* ix, QueryCtx& c, int nq, int k) {
   ws.card = card;
   ws.log_cap = LC;
   ws.L = L;
+  if (c.on_grow) c.on_grow((int64_t)ws.mem.bytes - (int64_t)old);
+}
+
+// Back to the starting near-tie log after a batch that grew it: the
+// workspace is made again for nq queries with k slots.
+constexpr int kLogCap0 = 4096;  // near-tie log entries per query a context starts with
+
+void shrink_log(messi_index* ix, QueryCtx& c, int nq, int k) {
+  if (c.log_cap <= kLogCap0 && c.ws.log_cap <= kLogCap0) return;
+  c.log_cap = kLogCap0;
+  const int64_t old = (int64_t)c.ws.mem.bytes;
+  c.ws.mem.clear();
+  c.ws = Workspace{};
+  std::function<void(int64_t)> report;
+  std::swap(report, c.on_grow);  // one report below, of the net change
+  try {
+    ensure_workspace(ix, c, nq, k);
+  } catch (...) {
+    std::swap(report, c.on_grow);
+    if (c.on_grow) c.on_grow(-old);
+    throw;
+  }
+  std::swap(report, c.on_grow);
+  if (c.on_grow) c.on_grow((int64_t)c.ws.mem.bytes - old);
 }
 
 // BF16 shadow of the store (screen operand) and the squared row norms.
 void ensure_screen(messi_index* ix) {
   std::lock_guard<std::mutex> lk(ix->screen_mu);
   if (ix->Zb) return;
+  check_budget(ix, ix->ctx, 0, (size_t)ix->n * ix->len * sizeof(uint16_t) + (size_t)ix->n * sizeof(float));
   ix->Zb = ix->screen_mem.alloc<uint16_t>((size_t)ix->n * ix->len);
   ix->xn = ix->screen_mem.alloc<float>((size_t)ix->n);
   launch_bf16_rows(ix->Z, ix->inplace ? ix->perm : nullptr, ix->n, ix->len, ix->Zb, ix->xn,
@@ -547,8 +719,11 @@ void ensure_screen(messi_index* ix) {
 // Batch maps (row and k of each query) and screen buffers for nq queries.
 void ensure_batch(messi_index* ix, QueryCtx& c, int nq) {
   if (c.batch_nq >= nq) return;
-  c.batch_mem.clear();
   const int L = ix->n_leaves;
+  const size_t need = (size_t)nq * (12 + 2 * (size_t)ix->len + 4 * (size_t)L) + (size_t)L * 12 + 64;
+  check_budget(ix, c, c.batch_mem.bytes, need);
+  c.batch_mem.clear();
+  c.batch_nq = 0;
   c.bmap = c.batch_mem.alloc<int>(nq);
   c.bk = c.batch_mem.alloc<int>(nq);
   c.qb = c.batch_mem.alloc<uint16_t>((size_t)nq * ix->len);
@@ -574,14 +749,29 @@ struct FixedScratch {
   int* h_status;
 };
 
-int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int kmax, int distance,
-              int window, const int* d_kq, const int* d_qmap, bool screen, bool lb_improved,
-              int64_t* out_ids, float* out_dists, messi_stats* stats,
-              const FixedScratch* fixed = nullptr, bool min_work = false) {
-  hipStream_t st = c.stream;
+// Everything the launches of one group of queries take (queries sharing a
+// distance and window): parameters, state, screen buffers, grids and
+// inputs / outputs.  Two groups with bytewise equal records launch the
+// same work, which is what a batch graph is matched on.
+struct GroupLaunch {
+  QueryParams p;
+  QueryState qs;
+  ScreenDev sc;
+  const float* queries;
+  int64_t* out_ids;
+  float* out_dists;
+  int screen, blocks, screen_blocks, screen_nt;
+};
+
+// Parameters and grids of a group of nq queries; `main` holds the batch's
+// screen buffers.  Fails with MESSI_EINVAL if the kernels' LDS cannot
+// hold series of this length with this window.
+int plan_group(messi_index* ix, QueryCtx& main, int nq, int kmax, int distance, int window,
+               bool screen, bool lb_improved, bool count_work, const Tune& t, GroupLaunch& g) {
+  std::memset(&g, 0, sizeof(g));
   const int len = ix->len;
   const double u = std::ldexp(1.0, -24);
-  QueryParams p{};
+  QueryParams& p = g.p;
   p.nq = nq;
   p.len = len;
   p.w = ix->w;
@@ -590,7 +780,7 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   p.k = kmax;
   p.out_stride = kmax;
   p.order_leaves = screen ? 0 : 1;
-  p.count_work = stats ? 1 : 0;
+  p.count_work = count_work ? 1 : 0;
   // the approximate leaf: found by stage1's approximate blocks for a few
   // queries (shorter prep), once per query in k_prep for batches
   p.leaf_in_prep = nq > 8 ? 1 : 0;
@@ -648,121 +838,171 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
   if (distance == MESSI_DTW) {
     per_cu = process_blocks_per_cu(p);
   } else {
-    if (c.proc_blocks_ed == 0) c.proc_blocks_ed = process_blocks_per_cu(p);
-    per_cu = c.proc_blocks_ed;
+    if (main.proc_blocks_ed == 0) main.proc_blocks_ed = process_blocks_per_cu(p);
+    per_cu = main.proc_blocks_ed;
   }
   const int resident = per_cu * ix->n_cus;
-  int blocks = resident / std::max(1, nq);
-  blocks = std::max(2, std::min(blocks, resident));
-  if (distance == MESSI_ED) blocks = ed_process_blocks(resident);  // the whole grid visits every query
-  ScreenDev sc{};
+  if (distance == MESSI_ED)  // the whole grid visits every query
+    g.blocks = ed_process_blocks(resident * std::max(1, t.ed_scale));
+  else
+    g.blocks = std::max(2, std::min(resident / std::max(1, nq) * std::max(1, t.dtw_scale),
+                                    resident * std::max(1, t.dtw_scale)));
+  g.screen = screen ? 1 : 0;
   if (screen) {
+    ScreenDev& sc = g.sc;
     sc.Zb = ix->Zb;
     sc.xn = ix->xn;
-    sc.qb = c.qb;
-    sc.qn = c.qn;
-    sc.cnt = c.cnt;
-    sc.off = c.off;
-    sc.lists = c.lists;
-    sc.counter = c.counter;
-    sc.tally = c.tally;
+    sc.qb = main.qb;
+    sc.qn = main.qn;
+    sc.cnt = main.cnt;
+    sc.off = main.off;
+    sc.lists = main.lists;
+    sc.counter = main.counter;
+    sc.tally = main.tally;
     // bound constants (see the screen kernel): u_b = 2^-8, gamma at 2^-23
     const double ub = std::ldexp(1.0, -8);
-    const double g = len * std::ldexp(1.0, -23) / (1.0 - len * std::ldexp(1.0, -23));
-    const double cdot = 2.0 * ((2.0 * ub + ub * ub) + g * (1.0 + ub) * (1.0 + ub)) * (1.0 + std::ldexp(1.0, -10));
+    const double gm = len * std::ldexp(1.0, -23) / (1.0 - len * std::ldexp(1.0, -23));
+    const double cdot = 2.0 * ((2.0 * ub + ub * ub) + gm * (1.0 + ub) * (1.0 + ub)) * (1.0 + std::ldexp(1.0, -10));
     sc.c_dot = std::nextafter((float)cdot, INFINITY);
     sc.c_abs = (float)std::ldexp(1.0, -17);
+    g.screen_nt = (t.screen_nt > 0 && screen_variant(len, t.screen_nt)) ? t.screen_nt : screen_nt_default(len);
+    int occ = screen_blocks_per_cu(len, g.screen_nt);
+    if (t.screen_occ > 0) occ = std::min(occ, t.screen_occ);
+    g.screen_blocks = occ * ix->n_cus;
   }
-  const int screen_blocks = screen ? screen_blocks_per_cu(len) * ix->n_cus : 0;
-  // the status words live in pinned host memory the kernels write through
-  // its device mapping, so no copy follows the kernels
-  if (!fixed && c.h_status_cap < nq) {
-    if (c.h_status) HIP_OR_THROW(hipHostFree(c.h_status));
-    c.h_status = nullptr;
-    c.d_status = nullptr;
-    c.h_status_cap = 0;
-    HIP_OR_THROW(hipHostMalloc((void**)&c.h_status, sizeof(int) * (size_t)nq, hipHostMallocMapped));
-    HIP_OR_THROW(hipHostGetDevicePointer((void**)&c.d_status, c.h_status, 0));
-    c.h_status_cap = nq;
+  return MESSI_OK;
+}
+
+// Per-query status words in pinned, device-mapped host memory the kernels
+// write through its device address, so no copy follows the kernels.
+void ensure_status(QueryCtx& c, int nq) {
+  if (c.h_status_cap >= nq) return;
+  if (c.h_status) HIP_OR_THROW(hipHostFree(c.h_status));
+  c.h_status = nullptr;
+  c.d_status = nullptr;
+  c.h_status_cap = 0;
+  HIP_OR_THROW(hipHostMalloc((void**)&c.h_status, sizeof(int) * (size_t)nq, hipHostMallocMapped));
+  HIP_OR_THROW(hipHostGetDevicePointer((void**)&c.d_status, c.h_status, 0));
+  c.h_status_cap = nq;
+}
+
+void ensure_events(QueryCtx& c) {
+  if (c.events_ready) return;
+  for (int i = 0; i < 5; ++i) HIP_OR_THROW(hipEventCreate(&c.ev[i]));
+  c.events_ready = true;
+}
+
+// Points a planned group at context c's state (or the fixed scratch) and at
+// its inputs and outputs; status words start at c's word `status_at`.
+void bind_group(QueryCtx& c, GroupLaunch& g, const float* queries, const int* d_kq, const int* d_qmap,
+                int64_t* out_ids, float* out_dists, const FixedScratch* fixed, int status_at = 0) {
+  g.p.log_cap = fixed ? fixed->log_cap : c.log_cap;
+  g.qs = fixed ? fixed->qs : c.ws.qs;
+  if (!fixed) g.qs.status = c.d_status + status_at;
+  g.qs.kq = d_kq;
+  g.qs.qmap = d_qmap;
+  g.queries = queries;
+  g.out_ids = out_ids;
+  g.out_dists = out_dists;
+}
+
+// Launches a bound group's kernels on st (not synchronised).  timed: c's
+// events bracket the phases; min_work: the minimal-work count follows.
+void enqueue_group(messi_index* ix, QueryCtx& c, const GroupLaunch& g, hipStream_t st, bool timed,
+                   bool min_work) {
+  const IndexDev v = ix->view();
+  if (timed) HIP_OR_THROW(hipEventRecord(c.ev[0], st));
+  launch_prep(v, g.queries, g.p, g.qs, st);
+  if (timed) HIP_OR_THROW(hipEventRecord(c.ev[1], st));
+  launch_stage1(v, g.p, g.qs, st);
+  if (timed) HIP_OR_THROW(hipEventRecord(c.ev[2], st));
+  if (g.screen) {
+    launch_bf16_rows(g.qs.zq, nullptr, g.p.nq, g.p.len, g.sc.qb, g.sc.qn, st);
+    launch_screen(v, g.p, g.qs, g.sc, g.screen_blocks, g.screen_nt, st);
+  } else {
+    launch_process(v, g.p, g.qs, g.blocks, st);
   }
-  // phase timing (only when the caller asks for statistics)
-  hipEvent_t ev[5] = {};
-  if (stats) {
-    if (!c.events_ready) {
-      for (int i = 0; i < 5; ++i) HIP_OR_THROW(hipEventCreate(&c.ev[i]));
-      c.events_ready = true;
-    }
-    for (int i = 0; i < 5; ++i) ev[i] = c.ev[i];
+  if (timed) HIP_OR_THROW(hipEventRecord(c.ev[3], st));
+  launch_finalize(v, g.p, g.qs, g.out_ids, g.out_dists, st);
+  if (timed) {
+    HIP_OR_THROW(hipEventRecord(c.ev[4], st));
+    // the minimal work, once the final k-th best is known (untimed)
+    if (min_work) launch_min_work(v, g.p, g.qs, std::max(1, ix->n_cus), st);
   }
+  launch_check();
+}
+
+// OR of the status words of a finished group (bit 0: near-tie log overflow).
+int group_status(const int* h_status, int nq) {
+  int worst = 0;
+  for (int i = 0; i < nq; ++i) worst |= h_status[i];
+  return worst;
+}
+
+// Adds a finished group's phase times and work counters to stats.
+void add_group_stats(messi_index* ix, QueryCtx& c, const GroupLaunch& g, messi_stats* stats,
+                     hipStream_t st) {
+  const int nq = g.p.nq;
+  float ms[4] = {0, 0, 0, 0};
+  for (int i = 0; i < 4; ++i) HIP_OR_THROW(hipEventElapsedTime(&ms[i], c.ev[i], c.ev[i + 1]));
+  stats->us_prep += 1e3 * ms[0];
+  stats->us_stage1 += 1e3 * ms[1];
+  stats->us_process += 1e3 * ms[2];
+  stats->us_finalize += 1e3 * ms[3];
+  std::vector<unsigned long long> sv((size_t)nq * kStatCount);
+  d2h(sv.data(), g.qs.stats, sv.size(), st);
+  stats->queries += nq;
+  stats->leaves_total += (int64_t)nq * ix->n_leaves;
+  for (int q = 0; q < nq; ++q) {
+    const unsigned long long* r = &sv[(size_t)q * kStatCount];
+    stats->leaves_kept += (int64_t)r[kStatLeavesKept];
+    stats->series_lb += (int64_t)r[kStatSeriesLb];
+    stats->lb_keogh += (int64_t)r[kStatLbKeogh];
+    stats->refined += (int64_t)r[kStatRefined];
+    stats->rechecked_fp64 += (int64_t)r[kStatRecheck];
+    stats->lb_improved += (int64_t)r[kStatLbImproved];
+    stats->bsf_updates += (int64_t)r[kStatBsf];
+    stats->dtw_cells += (int64_t)r[kStatCells];
+    stats->min_leaves += (int64_t)r[kStatMinLeaves];
+    stats->min_series += (int64_t)r[kStatMinSeries];
+    stats->min_refined += (int64_t)r[kStatMinRefined];
+  }
+  if (g.screen) {
+    unsigned long long tl[2];
+    int64_t pairs = 0;
+    d2h(tl, g.sc.tally, 2, st);
+    d2h(&pairs, g.sc.off + ix->n_leaves, 1, st);
+    stats->screened += (int64_t)tl[0];
+    stats->leaves_kept += pairs;
+  }
+}
+
+// One group of queries sharing a distance and window, run to completion on
+// context c: nq queries whose rows (input and output) are d_qmap[i] and
+// whose k are d_kq[i] (both null for a plain call: rows 0..nq-1, every
+// k = kmax).  Slots are kmax apart and output rows kmax entries long.  A
+// near-tie log overflow reruns the group with a log four times larger.
+int run_group(messi_index* ix, QueryCtx& c, QueryCtx& main, const float* queries, int nq, int kmax,
+              int distance, int window, const int* d_kq, const int* d_qmap, bool screen,
+              bool lb_improved, int64_t* out_ids, float* out_dists, messi_stats* stats,
+              const Tune& t, const FixedScratch* fixed = nullptr, bool min_work = false) {
+  GroupLaunch g;
+  const int rc = plan_group(ix, main, nq, kmax, distance, window, screen, lb_improved, stats != nullptr,
+                            t, g);
+  if (rc != MESSI_OK) return rc;
+  if (!fixed) ensure_status(c, nq);
+  if (stats) ensure_events(c);
+  const hipStream_t st = c.stream;
   for (int attempt = 0; attempt < 8; ++attempt) {
     if (!fixed) ensure_workspace(ix, c, nq, kmax);
-    p.log_cap = fixed ? fixed->log_cap : c.log_cap;
-    const IndexDev v = ix->view();
-    QueryState qs = fixed ? fixed->qs : c.ws.qs;
-    int* h_status = fixed ? fixed->h_status : c.h_status;
-    if (!fixed) qs.status = c.d_status;
-    qs.kq = d_kq;
-    qs.qmap = d_qmap;
-    if (stats) HIP_OR_THROW(hipEventRecord(ev[0], st));
-    launch_prep(v, queries, p, qs, st);
-    if (stats) HIP_OR_THROW(hipEventRecord(ev[1], st));
-    launch_stage1(v, p, qs, st);
-    if (stats) HIP_OR_THROW(hipEventRecord(ev[2], st));
-    if (screen) {
-      launch_bf16_rows(qs.zq, nullptr, nq, len, sc.qb, sc.qn, st);
-      launch_screen(v, p, qs, sc, screen_blocks, st);
-    } else {
-      launch_process(v, p, qs, blocks, st);
-    }
-    if (stats) HIP_OR_THROW(hipEventRecord(ev[3], st));
-    launch_finalize(v, p, qs, out_ids, out_dists, st);
-    if (stats) {
-      HIP_OR_THROW(hipEventRecord(ev[4], st));
-      // the minimal work, once the final k-th best is known (untimed)
-      if (min_work) launch_min_work(v, p, qs, std::max(1, ix->n_cus), st);
-    }
-    launch_check();
+    bind_group(c, g, queries, d_kq, d_qmap, out_ids, out_dists, fixed);
+    enqueue_group(ix, c, g, st, stats != nullptr, min_work);
     if (fixed)
-      d2h(h_status, qs.status, nq, st);
+      d2h(fixed->h_status, g.qs.status, nq, st);
     else
       HIP_OR_THROW(hipStreamSynchronize(st));
-    int worst = 0;
-    for (int i = 0; i < nq; ++i) worst |= h_status[i];
-    if (!(worst & 1)) {
-      if (stats) {
-        float ms[4] = {0, 0, 0, 0};
-        for (int i = 0; i < 4; ++i) HIP_OR_THROW(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]));
-        stats->us_prep += 1e3 * ms[0];
-        stats->us_stage1 += 1e3 * ms[1];
-        stats->us_process += 1e3 * ms[2];
-        stats->us_finalize += 1e3 * ms[3];
-        std::vector<unsigned long long> sv((size_t)nq * kStatCount);
-        d2h(sv.data(), qs.stats, sv.size(), st);
-        stats->queries += nq;
-        stats->leaves_total += (int64_t)nq * ix->n_leaves;
-        for (int q = 0; q < nq; ++q) {
-          const unsigned long long* r = &sv[(size_t)q * kStatCount];
-          stats->leaves_kept += (int64_t)r[kStatLeavesKept];
-          stats->series_lb += (int64_t)r[kStatSeriesLb];
-          stats->lb_keogh += (int64_t)r[kStatLbKeogh];
-          stats->refined += (int64_t)r[kStatRefined];
-          stats->rechecked_fp64 += (int64_t)r[kStatRecheck];
-          stats->lb_improved += (int64_t)r[kStatLbImproved];
-          stats->bsf_updates += (int64_t)r[kStatBsf];
-          stats->dtw_cells += (int64_t)r[kStatCells];
-          stats->min_leaves += (int64_t)r[kStatMinLeaves];
-          stats->min_series += (int64_t)r[kStatMinSeries];
-          stats->min_refined += (int64_t)r[kStatMinRefined];
-        }
-        if (screen) {
-          unsigned long long t[2];
-          int64_t pairs = 0;
-          d2h(t, sc.tally, 2, st);
-          d2h(&pairs, sc.off + ix->n_leaves, 1, st);
-          stats->screened += (int64_t)t[0];
-          stats->leaves_kept += pairs;
-        }
-      }
+    if (!(group_status(fixed ? fixed->h_status : c.h_status, nq) & 1)) {
+      if (stats) add_group_stats(ix, c, g, stats, st);
       return MESSI_OK;
     }
     if (stats) stats->log_overflows += 1;
@@ -776,62 +1016,403 @@ int run_group(messi_index* ix, QueryCtx& c, const float* queries, int nq, int km
 
 int run_query(messi_index* ix, const float* queries, int nq, int k, int distance, int window,
               int64_t* out_ids, float* out_dists, messi_stats* stats) {
-  return run_group(ix, ix->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, false, out_ids,
-                   out_dists, stats, nullptr, true);
+  return run_group(ix, ix->ctx, ix->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, false,
+                   out_ids, out_dists, stats, Tune{}, nullptr, true);
 }
 
-constexpr int kScreenMinGroup = 32;  // fewer ED queries go the unscreened way
+// Context of a batch's group g >= 1 when groups overlap: its own stream
+// (default priority), workspace, status words and events.
+QueryCtx& group_ctx(QueryCtx& ctx, int g) {
+  if (g == 0) return ctx;
+  while ((int)ctx.aux.size() < g) {
+    std::unique_ptr<QueryCtx> a(new QueryCtx());
+    HIP_OR_THROW(hipStreamCreateWithFlags(&a->own_stream, hipStreamNonBlocking));
+    a->stream = a->own_stream;
+    a->budgeted = ctx.budgeted;
+    a->on_grow = ctx.on_grow;
+    ctx.aux.push_back(std::move(a));
+  }
+  QueryCtx& a = *ctx.aux[g - 1];
+  if (!a.join) HIP_OR_THROW(hipEventCreateWithFlags(&a.join, hipEventDisableTiming));
+  return a;
+}
 
-// Validated batch on one query context: groups of queries sharing
-// (distance, effective window), in first-seen order, one run_group each.
-int run_batch(messi_index* index, QueryCtx& ctx, const float* queries, int nq, const int32_t* k,
-              const int32_t* distance, const int32_t* window, int kmax, int flags,
-              int64_t* out_ids, float* out_dists, messi_stats* stats) {
-  const int len = index->len;
+// Bytes that identify a batch's launches: every argument of every launch
+// and the context (so the streams) each group runs on.
+std::string launch_key(const std::vector<GroupLaunch>& gl, const std::vector<QueryCtx*>& gc, bool overlap) {
+  std::string key(1, overlap ? 'o' : 's');
+  for (size_t g = 0; g < gl.size(); ++g) {
+    key.append(reinterpret_cast<const char*>(&gl[g]), sizeof(GroupLaunch));
+    key.append(reinterpret_cast<const char*>(&gc[g]), sizeof(QueryCtx*));
+  }
+  return key;
+}
+
+// Enqueues every group of a batch: overlapped, group g on its context's
+// stream, forked from and joined into `st` with events; otherwise one
+// after another on `st`.
+void enqueue_batch(messi_index* ix, QueryCtx& ctx, const std::vector<GroupLaunch>& gl,
+                   const std::vector<QueryCtx*>& gc, bool overlap, hipStream_t st, bool timed) {
+  if (!overlap) {
+    for (size_t g = 0; g < gl.size(); ++g) enqueue_group(ix, *gc[g], gl[g], st, timed, false);
+    return;
+  }
+  HIP_OR_THROW(hipEventRecord(ctx.fork, st));
+  for (size_t g = 0; g < gl.size(); ++g) {
+    const hipStream_t sg = g == 0 ? st : gc[g]->stream;
+    if (g > 0) HIP_OR_THROW(hipStreamWaitEvent(sg, ctx.fork, 0));
+    enqueue_group(ix, *gc[g], gl[g], sg, timed, false);
+    if (g > 0) {
+      HIP_OR_THROW(hipEventRecord(gc[g]->join, sg));
+      HIP_OR_THROW(hipStreamWaitEvent(st, gc[g]->join, 0));
+    }
+  }
+}
+
+// The graph of a batch's launches: found by its launch key, else captured
+// (on the context's capture stream) and kept, the oldest dropped past
+// kGraphCache entries.  Capture launches nothing.
+constexpr size_t kGraphCache = 8;
+
+hipGraphExec_t batch_graph(messi_index* ix, QueryCtx& ctx, const std::vector<GroupLaunch>& gl,
+                           const std::vector<QueryCtx*>& gc, bool overlap, bool* captured) {
+  const std::string key = launch_key(gl, gc, overlap);
+  for (auto& e : ctx.graphs)
+    if (e->key == key) {
+      *captured = false;
+      return e->exec;
+    }
+  if (!ctx.cap_stream) HIP_OR_THROW(hipStreamCreateWithFlags(&ctx.cap_stream, hipStreamNonBlocking));
+  std::unique_ptr<GraphEntry> e(new GraphEntry());
+  e->key = key;
+  HIP_OR_THROW(hipStreamBeginCapture(ctx.cap_stream, hipStreamCaptureModeRelaxed));
+  try {
+    enqueue_batch(ix, ctx, gl, gc, overlap, ctx.cap_stream, false);
+  } catch (...) {
+    hipGraph_t partial = nullptr;
+    (void)hipStreamEndCapture(ctx.cap_stream, &partial);
+    if (partial) (void)hipGraphDestroy(partial);
+    (void)hipGetLastError();
+    throw;
+  }
+  HIP_OR_THROW(hipStreamEndCapture(ctx.cap_stream, &e->graph));
+  HIP_OR_THROW(hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0));
+  if (ctx.graphs.size() >= kGraphCache) ctx.graphs.erase(ctx.graphs.begin());
+  ctx.graphs.push_back(std::move(e));
+  *captured = true;
+  return ctx.graphs.back()->exec;
+}
+
+constexpr int kScreenMinGroup = 32;  // fewer ED queries go the unscreened way (default)
+
+// A batch's groups: queries sharing (distance, effective window), in
+// first-seen order.
+struct BatchGroups {
   std::vector<std::pair<int, int>> keys;
   std::vector<std::vector<int>> members;
+};
+
+BatchGroups group_batch(const messi_index* ix, int nq, const int32_t* distance, const int32_t* window) {
+  BatchGroups b;
   for (int i = 0; i < nq; ++i) {
-    const std::pair<int, int> key(distance[i], distance[i] == MESSI_DTW ? std::min(window[i], len - 1) : 0);
+    const std::pair<int, int> key(distance[i],
+                                  distance[i] == MESSI_DTW ? std::min(window[i], ix->len - 1) : 0);
     size_t g = 0;
-    while (g < keys.size() && keys[g] != key) ++g;
-    if (g == keys.size()) {
-      keys.push_back(key);
-      members.emplace_back();
+    while (g < b.keys.size() && b.keys[g] != key) ++g;
+    if (g == b.keys.size()) {
+      b.keys.push_back(key);
+      b.members.emplace_back();
     }
-    members[g].push_back(i);
+    b.members[g].push_back(i);
   }
+  return b;
+}
+
+std::string tune_key(const messi_index* ix, int nq, const BatchGroups& b, int flags);
+Tune tune_for(const messi_index* ix, const std::string& key);
+
+// How a batch runs: its knobs, and whether its launches go through a
+// graph and its groups may overlap.
+struct BatchMode {
+  const Tune* tune = nullptr;  // null: the tuned knobs of the batch's shape, else the defaults
+  bool graph = false;
+  bool allow_overlap = true;
+  bool* captured = nullptr;    // graph runs: set if the graph was captured by this call
+};
+
+// Validated batch on one query context.  Sequential groups (stats, one
+// group or no overlap) run one run_group each; otherwise every group is
+// bound first and the whole batch is enqueued at once - overlapped on the
+// groups' own streams, and / or replayed from a graph - with one
+// synchronisation, after which a group whose near-tie log overflowed is
+// rerun alone.
+int run_batch(messi_index* index, QueryCtx& ctx, const float* queries, int nq, const int32_t* k,
+              const int32_t* distance, const int32_t* window, int kmax, int flags,
+              int64_t* out_ids, float* out_dists, messi_stats* stats, const BatchMode& mode = BatchMode{}) {
+  const int len = index->len;
+  const BatchGroups bg = group_batch(index, nq, distance, window);
+  const int G = (int)bg.keys.size();
   try {
-    const bool want_screen = (flags & MESSI_SCREEN_BF16) && screen_supported(len);
+    const Tune t = mode.tune ? *mode.tune : tune_for(index, tune_key(index, nq, bg, flags));
+    const bool want_screen = (flags & MESSI_SCREEN_BF16) && screen_supported(len) && t.screen;
+    const bool lbi = (flags & MESSI_LB_IMPROVED) != 0;
     ensure_batch(index, ctx, nq);
     std::vector<int> hmap, hk;
     hmap.reserve(nq);
     hk.reserve(nq);
-    for (const auto& m : members)
+    for (const auto& m : bg.members)
       for (int i : m) {
         hmap.push_back(i);
         hk.push_back(k[i]);
       }
     h2d(ctx.bmap, hmap.data(), (size_t)nq, ctx.stream);
     h2d(ctx.bk, hk.data(), (size_t)nq, ctx.stream);
-    int at = 0;
-    for (size_t g = 0; g < keys.size(); ++g) {
-      const int cnt = (int)members[g].size();
+    std::vector<int> at(G + 1, 0), cnt(G);
+    std::vector<bool> scr(G);
+    for (int g = 0; g < G; ++g) {
+      cnt[g] = (int)bg.members[g].size();
+      at[g + 1] = at[g] + cnt[g];
       // the screen streams every leaf some query of the group keeps, so it
       // pays off only when many queries share that pass
-      const bool screen = want_screen && keys[g].first == MESSI_ED && cnt >= kScreenMinGroup;
-      if (screen && !index->Zb) return fail(MESSI_EINVAL, "the BF16 screen copy is not prepared");
-      const int rc = run_group(index, ctx, queries, cnt, kmax, keys[g].first, keys[g].second,
-                               ctx.bk + at, ctx.bmap + at, screen, (flags & MESSI_LB_IMPROVED) != 0,
-                               out_ids, out_dists, stats);
+      scr[g] = want_screen && bg.keys[g].first == MESSI_ED && cnt[g] >= std::max(1, t.screen_min);
+      if (scr[g] && !index->Zb) return fail(MESSI_EINVAL, "the BF16 screen copy is not prepared");
+    }
+    const bool overlap = mode.allow_overlap && t.overlap && G > 1;
+    if (!mode.graph && !overlap) {
+      for (int g = 0; g < G; ++g) {
+        const int rc = run_group(index, ctx, ctx, queries, cnt[g], kmax, bg.keys[g].first, bg.keys[g].second,
+                                 ctx.bk + at[g], ctx.bmap + at[g], scr[g], lbi, out_ids, out_dists, stats, t);
+        if (rc != MESSI_OK) return rc;
+      }
+      return MESSI_OK;
+    }
+    const bool timed = stats != nullptr && !mode.graph;
+    std::vector<GroupLaunch> gl(G);
+    std::vector<QueryCtx*> gc(G);
+    int max_cnt = 0;
+    for (int g = 0; g < G; ++g) max_cnt = std::max(max_cnt, cnt[g]);
+    if (overlap && !ctx.fork) HIP_OR_THROW(hipEventCreateWithFlags(&ctx.fork, hipEventDisableTiming));
+    for (int g = 0; g < G; ++g) {
+      gc[g] = overlap ? &group_ctx(ctx, g) : &ctx;
+      const int rc = plan_group(index, ctx, cnt[g], kmax, bg.keys[g].first, bg.keys[g].second, scr[g], lbi,
+                                timed, t, gl[g]);
       if (rc != MESSI_OK) return rc;
-      at += cnt;
+    }
+    // all allocation before any launch (and before a capture)
+    for (int g = 0; g < G; ++g) {
+      QueryCtx& c = *gc[g];
+      ensure_status(c, overlap ? cnt[g] : nq);
+      ensure_workspace(index, c, overlap ? cnt[g] : max_cnt, kmax);
+      if (timed) ensure_events(c);
+    }
+    for (int g = 0; g < G; ++g)
+      bind_group(*gc[g], gl[g], queries, ctx.bk + at[g], ctx.bmap + at[g], out_ids, out_dists, nullptr,
+                 overlap ? 0 : at[g]);
+    if (mode.graph) {
+      bool captured = false;
+      const hipGraphExec_t exec = batch_graph(index, ctx, gl, gc, overlap, &captured);
+      if (mode.captured) *mode.captured = captured;
+      HIP_OR_THROW(hipGraphLaunch(exec, ctx.stream));
+    } else {
+      enqueue_batch(index, ctx, gl, gc, overlap, ctx.stream, timed);
+    }
+    HIP_OR_THROW(hipStreamSynchronize(ctx.stream));
+    for (int g = 0; g < G; ++g) {
+      const int* hs = overlap ? gc[g]->h_status : ctx.h_status + at[g];
+      if (!(group_status(hs, cnt[g]) & 1)) {
+        if (timed) add_group_stats(index, *gc[g], gl[g], stats, gc[g]->stream);
+        continue;
+      }
+      // near-tie log overflow: this group again, alone, with a larger log
+      if (stats) stats->log_overflows += 1;
+      gc[g]->log_cap *= 4;
+      const int rc = run_group(index, *gc[g], ctx, queries, cnt[g], kmax, bg.keys[g].first, bg.keys[g].second,
+                               ctx.bk + at[g], ctx.bmap + at[g], scr[g], lbi, out_ids, out_dists, stats, t);
+      if (rc != MESSI_OK) return rc;
     }
   } catch (const OomError& e) {
     return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
+  } catch (const BudgetError& e) {
+    return fail(MESSI_ENOMEM, "the index would hold %zu bytes, over its memory budget of %zu", e.need,
+                e.budget);
   } catch (const HipError& e) {
     return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
   }
   return MESSI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: the batched path's knobs (Tune) chosen per batch shape by
+// timing candidates on a real batch, kept per index and in a JSON file
+// (messi_options.autotune_cache) keyed by device, index shape, batch size
+// bucket and the batch's (distance, window) mix.
+
+std::string device_tag() {
+  int dev = 0;
+  hipDeviceProp_t pr{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&pr, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::string arch(pr.gcnArchName);
+  const size_t colon = arch.find(':');
+  if (colon != std::string::npos) arch.resize(colon);
+  return arch + "x" + std::to_string(pr.multiProcessorCount);
+}
+
+std::string tune_key(const messi_index* ix, int nq, const BatchGroups& b, int flags) {
+  int bucket = 1;
+  while (bucket < nq) bucket <<= 1;
+  std::vector<std::string> mix;
+  for (const auto& key : b.keys)
+    mix.push_back(key.first == MESSI_ED ? std::string("ed") : "dtw" + std::to_string(key.second));
+  std::sort(mix.begin(), mix.end());
+  std::string m;
+  for (const auto& s : mix) m += (m.empty() ? "" : "+") + s;
+  char buf[256];
+  snprintf(buf, sizeof(buf), "%s/n%lld/len%d/w%d/c%d/leaf%d/%s/nq%d/", ix->device.c_str(), (long long)ix->n,
+           ix->len, ix->w, ix->card_bits, ix->leaf_size, ix->raw ? "raw" : "z", bucket);
+  std::string key = buf + m;
+  if ((flags & MESSI_SCREEN_BF16) && screen_supported(ix->len)) key += "/screen";
+  if (flags & MESSI_LB_IMPROVED) key += "/lbi";
+  return key;
+}
+
+Tune tune_for(const messi_index* ix, const std::string& key) {
+  std::lock_guard<std::mutex> lk(ix->tune_mu);
+  auto it = ix->tunes.find(key);
+  return it == ix->tunes.end() ? Tune{} : it->second.t;
+}
+
+// The knobs in the cache file's order: name, member.
+const std::pair<const char*, int Tune::*> kTuneFields[] = {
+    {"screen", &Tune::screen},     {"screen_min", &Tune::screen_min}, {"screen_nt", &Tune::screen_nt},
+    {"screen_occ", &Tune::screen_occ}, {"ed_scale", &Tune::ed_scale},  {"dtw_scale", &Tune::dtw_scale},
+    {"overlap", &Tune::overlap}};
+
+// Minimal reader of the cache file: an object whose members are objects of
+// numbers, {"key": {"name": number, ...}, ...}.  Returns false on any
+// other text.
+struct JsonReader {
+  const std::string& s;
+  size_t i = 0;
+  explicit JsonReader(const std::string& text) : s(text) {}
+  void ws() {
+    while (i < s.size() && (s[i] == ' ' || s[i] == '\n' || s[i] == '\r' || s[i] == '\t')) ++i;
+  }
+  bool lit(char c) {
+    ws();
+    if (i < s.size() && s[i] == c) {
+      ++i;
+      return true;
+    }
+    return false;
+  }
+  bool str(std::string* out) {
+    ws();
+    if (i >= s.size() || s[i] != '"') return false;
+    ++i;
+    out->clear();
+    while (i < s.size() && s[i] != '"') {
+      if (s[i] == '\\') return false;  // keys the library writes never need escapes
+      out->push_back(s[i++]);
+    }
+    if (i >= s.size()) return false;
+    ++i;
+    return true;
+  }
+  bool num(double* v) {
+    ws();
+    const char* b = s.c_str() + i;
+    char* e = nullptr;
+    *v = std::strtod(b, &e);
+    if (e == b) return false;
+    i += (size_t)(e - b);
+    return true;
+  }
+};
+
+bool parse_tunes(const std::string& text, std::map<std::string, TuneEntry>* out) {
+  JsonReader r(text);
+  if (!r.lit('{')) return false;
+  if (r.lit('}')) return true;
+  for (;;) {
+    std::string key;
+    if (!r.str(&key) || !r.lit(':') || !r.lit('{')) return false;
+    TuneEntry e;
+    if (!r.lit('}')) {
+      for (;;) {
+        std::string name;
+        double v = 0.0;
+        if (!r.str(&name) || !r.lit(':') || !r.num(&v)) return false;
+        for (const auto& f : kTuneFields)
+          if (name == f.first) e.t.*(f.second) = (int)v;
+        if (name == "ms") e.ms = v;
+        if (name == "ms_default") e.ms_default = v;
+        if (r.lit('}')) break;
+        if (!r.lit(',')) return false;
+      }
+    }
+    (*out)[key] = e;
+    if (r.lit('}')) break;
+    if (!r.lit(',')) return false;
+  }
+  r.ws();
+  return r.i == text.size();
+}
+
+std::string format_tunes(const std::map<std::string, TuneEntry>& m) {
+  std::string o = "{\n";
+  bool first = true;
+  for (const auto& kv : m) {
+    if (!first) o += ",\n";
+    first = false;
+    o += "  \"" + kv.first + "\": {";
+    for (const auto& f : kTuneFields) o += "\"" + std::string(f.first) + "\": " + std::to_string(kv.second.t.*(f.second)) + ", ";
+    char buf[96];
+    snprintf(buf, sizeof(buf), "\"ms\": %.4f, \"ms_default\": %.4f}", kv.second.ms, kv.second.ms_default);
+    o += buf;
+  }
+  o += "\n}\n";
+  return o;
+}
+
+// Reads a cache file; a missing file is an empty cache.
+bool read_tune_file(const std::string& path, std::map<std::string, TuneEntry>* out, std::string* err) {
+  FILE* f = std::fopen(path.c_str(), "rb");
+  if (!f) return true;
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  if (!parse_tunes(text, out)) {
+    *err = "autotune cache " + path + " is not a file this library wrote";
+    return false;
+  }
+  return true;
+}
+
+// Merges this index's entries into the file (re-read first, so entries
+// other indexes wrote are kept) through a temporary file and a rename.
+bool write_tune_file(const std::string& path, const std::map<std::string, TuneEntry>& mine, std::string* err) {
+  std::map<std::string, TuneEntry> all;
+  if (!read_tune_file(path, &all, err)) return false;
+  for (const auto& kv : mine) all[kv.first] = kv.second;
+  const std::string tmp = path + ".tmp" + std::to_string((long long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) {
+    *err = "cannot write " + tmp;
+    return false;
+  }
+  const std::string text = format_tunes(all);
+  const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size();
+  if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), path.c_str()) != 0) {
+    std::remove(tmp.c_str());
+    *err = "cannot write " + path;
+    return false;
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -874,11 +1455,11 @@ struct SrvWorker {
   float* h_d = nullptr;
   DevMem io;
   std::thread th;
+  std::atomic<int64_t> resident{0};  // device bytes this worker holds
   ~SrvWorker() {
     if (h_q) (void)hipHostFree(h_q);
     if (h_ids) (void)hipHostFree(h_ids);
     if (h_d) (void)hipHostFree(h_d);
-    if (ctx.stream) (void)hipStreamDestroy(ctx.stream);
   }
 };
 
@@ -911,6 +1492,7 @@ struct messi_server {
   std::deque<SrvRequest> pending;
   std::deque<SrvResult> done;
   int64_t inflight = 0, peak_inflight = 0;
+  int64_t log_growth = 0;  // bytes charged for near-tie log growth, summed
   int64_t submitted = 0, completed = 0, batches = 0, max_batch_seen = 0;
   double busy_us = 0.0;
   uint64_t next_id = 0;
@@ -969,8 +1551,10 @@ void messi_server::run(SrvWorker* w) {
     try {
       HIP_OR_THROW(hipMemcpyAsync(w->d_q, w->h_q, sizeof(float) * len * nb, hipMemcpyHostToDevice,
                                   w->ctx.stream));
+      BatchMode mode;
+      mode.allow_overlap = false;  // one workspace per worker: its size is what the budget counts
       rc = run_batch(ix, w->ctx, w->d_q, nb, ks.data(), ds.data(), ws.data(), kmax, flags,
-                     w->d_ids, w->d_d, nullptr);
+                     w->d_ids, w->d_d, nullptr, mode);
       if (rc == MESSI_OK) {
         HIP_OR_THROW(hipMemcpyAsync(w->h_ids, w->d_ids, sizeof(int64_t) * kmax * nb,
                                     hipMemcpyDeviceToHost, w->ctx.stream));
@@ -986,6 +1570,15 @@ void messi_server::run(SrvWorker* w) {
       rc = MESSI_ENOMEM;
     }
     const auto t1 = Clock::now();
+    // a near-tie log grown by this batch (charged to the ledger as it grew)
+    // goes back to the starting size, and its bytes back off the ledger
+    try {
+      shrink_log(ix, w->ctx, w->cap, kmax);
+    } catch (const HipError& e) {
+      if (rc == MESSI_OK) rc = MESSI_EDEVICE;
+    } catch (const OomError& e) {
+      if (rc == MESSI_OK) rc = MESSI_ENOMEM;
+    }
     {
       std::lock_guard<std::mutex> lk(mu);
       for (int i = 0; i < nb; ++i) {
@@ -1041,10 +1634,31 @@ int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int3
   if (cb < 1 || cb > 8) return fail(MESSI_EINVAL, "cardinality must be a power of two in [2, 256]");
   if (leaf_size < 1) return fail(MESSI_EINVAL, "leaf_size must be >= 1");
   if (!is_device_ptr(series)) return fail(MESSI_EINVAL, "series is not a device pointer");
-
+  if (o.inplace < 0 || o.inplace > 2) return fail(MESSI_EINVAL, "inplace must be 0, 1 or 2");
+  if (o.mem_budget_bytes < 0) return fail(MESSI_EINVAL, "mem_budget_bytes must be >= 0");
   if (o.inplace && (reinterpret_cast<uintptr_t>(series) & 15))
     return fail(MESSI_EINVAL, "an in-place series buffer must be 16-byte aligned");
+  const size_t store_b = (size_t)n * len * sizeof(float);
+  if (o.inplace == 2) {  // the library takes the buffer over: it must be one whole allocation
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)series) != hipSuccess ||
+        (void*)base != (void*)series || size < store_b) {
+      (void)hipGetLastError();
+      return fail(MESSI_EINVAL, "inplace = 2 takes over only the start of a hipMalloc allocation "
+                                "holding the series");
+    }
+  }
+  std::map<std::string, TuneEntry> cached;
+  if (o.autotune_cache) {
+    std::string err;
+    if (!read_tune_file(o.autotune_cache, &cached, &err)) return fail(MESSI_EINVAL, "%s", err.c_str());
+  }
   messi_index* ix = new messi_index();
+  ix->budget = o.mem_budget_bytes;
+  ix->device = device_tag();
+  if (o.autotune_cache) ix->tune_path = o.autotune_cache;
+  ix->tunes = std::move(cached);
   ix->inplace = o.inplace != 0;
   ix->raw = o.raw != 0;
   ix->n = n;
@@ -1058,6 +1672,11 @@ int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int3
   if (need > free_b) {
     delete ix;
     return fail(MESSI_ENOMEM, "index needs about %zu bytes, %zu free", need, free_b);
+  }
+  if (ix->budget > 0 && need + (o.inplace == 2 ? store_b : 0) > (size_t)ix->budget) {
+    delete ix;
+    return fail(MESSI_ENOMEM, "index needs about %zu bytes, over its memory budget of %lld",
+                need + (o.inplace == 2 ? store_b : 0), (long long)ix->budget);
   }
   int node_cap = (int)std::min<int64_t>(8 * (n / leaf_size) + 2 * ((int64_t)1 << segments) + 4096,
                                         (int64_t)1 << 30);
@@ -1081,17 +1700,25 @@ int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int3
     delete ix;
     return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
   }
+  // the tables' working buffers are gone: what the index holds now
+  if (o.inplace == 2) ix->store_bytes = store_b;
+  if (ix->budget > 0 && held_bytes(ix) > (size_t)ix->budget) {
+    const size_t held = held_bytes(ix);
+    delete ix;
+    return fail(MESSI_ENOMEM, "the index holds %zu bytes, over its memory budget of %lld", held,
+                (long long)o.mem_budget_bytes);
+  }
   if (o.bf16_screen && screen_supported(len)) {
-    try {
+    const int rc = guarded([&]() -> int {
       ensure_screen(ix);
-    } catch (const OomError& e) {
-      delete ix;
-      return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-    } catch (const HipError& e) {
-      delete ix;
-      return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
+      return MESSI_OK;
+    });
+    if (rc != MESSI_OK) {
+      delete ix;  // the caller keeps an in-place buffer
+      return rc;
     }
   }
+  if (o.inplace == 2) ix->owned_store = series;  // freed by messi_free from here on
   *out = ix;
   return MESSI_OK;
 }
@@ -1145,13 +1772,9 @@ int messi_query_stats(messi_index* index, const float* queries, int32_t nq, int3
     return fail(MESSI_EINVAL, "queries and outputs must be device pointers");
   BusyGuard g(index->busy);
   if (!g.ok) return fail(MESSI_EBUSY, "index is in use by another call");
-  try {
+  return guarded([&]() -> int {
     return run_query(index, queries, nq, k, distance, window, out_ids, out_dists, stats);
-  } catch (const OomError& e) {
-    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-  } catch (const HipError& e) {
-    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
-  }
+  });
 }
 
 int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k, int32_t distance,
@@ -1160,38 +1783,6 @@ int messi_query(messi_index* index, const float* queries, int32_t nq, int32_t k,
 }
 
 namespace {
-
-// The query state of nq queries with k slots and log_cap log entries each,
-// carved from `base` (256-byte aligned pieces); returns the bytes it takes.
-// With base == nullptr only the size is computed.
-size_t carve_state(const messi_index* ix, int nq, int k, int log_cap, char* base, QueryState* qs) {
-  size_t off = 0;
-  auto take = [&](size_t bytes) -> char* {
-    char* ptr = base ? base + off : nullptr;
-    off += (bytes + 255) & ~(size_t)255;
-    return ptr;
-  };
-  const size_t len = (size_t)ix->len, L = (size_t)ix->n_leaves, C = (size_t)ix->n_chunks, Q = (size_t)nq;
-  QueryState s{};
-  s.zq = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
-  s.eta = reinterpret_cast<float*>(take(Q * sizeof(float)));
-  s.upper = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
-  s.lower = reinterpret_cast<float*>(take(Q * len * sizeof(float)));
-  s.paa = reinterpret_cast<float*>(take(Q * 3 * kMaxSeg * sizeof(float)));
-  s.approx_range = reinterpret_cast<int64_t*>(take(Q * 2 * sizeof(int64_t)));
-  s.approx_d2 = reinterpret_cast<float*>(take(Q * kApproxCap * sizeof(float)));
-  s.slots = reinterpret_cast<unsigned long long*>(take(Q * (size_t)k * 8));
-  s.log = reinterpret_cast<unsigned long long*>(take(Q * (size_t)log_cap * 8));
-  s.log_count = reinterpret_cast<int*>(take(Q * sizeof(int)));
-  s.leaf_lb = reinterpret_cast<float*>(take(Q * L * sizeof(float)));
-  s.items = reinterpret_cast<unsigned long long*>(take(Q * C * 8));
-  s.ranges = reinterpret_cast<int2*>(take(Q * C * sizeof(int2)));
-  s.next = reinterpret_cast<int*>(take(Q * kCounterInts * sizeof(int)));
-  s.stats = reinterpret_cast<unsigned long long*>(take(Q * kStatCount * 8));
-  s.status = reinterpret_cast<int*>(take(Q * sizeof(int)));
-  if (qs) *qs = s;
-  return off;
-}
 
 constexpr int kNoAllocMaxQueries = 1024;  // status words kept on the host stack
 constexpr int kNoAllocLog = 32768;        // near-tie log entries per query
@@ -1226,8 +1817,8 @@ int messi_query_noalloc(messi_index* index, const float* queries, int32_t nq, in
     carve_state(index, nq, k, kNoAllocLog, base, &fx.qs);
     fx.log_cap = kNoAllocLog;
     fx.h_status = h_status;
-    return run_group(index, index->ctx, queries, nq, k, distance, window, nullptr, nullptr, false, false,
-                     out_ids, out_dists, nullptr, &fx);
+    return run_group(index, index->ctx, index->ctx, queries, nq, k, distance, window, nullptr, nullptr, false,
+                     false, out_ids, out_dists, nullptr, Tune{}, &fx);
   } catch (const OomError& e) {
     return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
   } catch (const HipError& e) {
@@ -1242,14 +1833,10 @@ int messi_prepare_screen(messi_index* index) {
     return fail(MESSI_EINVAL, "the BF16 screen needs len 64, 128, 256 or 512");
   BusyGuard g(index->busy);
   if (!g.ok) return fail(MESSI_EBUSY, "index is in use by another call");
-  try {
+  return guarded([&]() -> int {
     ensure_screen(index);
-  } catch (const OomError& e) {
-    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-  } catch (const HipError& e) {
-    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
-  }
-  return MESSI_OK;
+    return MESSI_OK;
+  });
 }
 
 int messi_query_batch(messi_index* index, const float* queries, int32_t nq, const int32_t* k,
@@ -1263,7 +1850,7 @@ int messi_query_batch(messi_index* index, const float* queries, int32_t nq, cons
   if (!k || !distance || !window) return fail(MESSI_EINVAL, "k, distance and window are required");
   if (is_device_ptr(k) || is_device_ptr(distance) || is_device_ptr(window))
     return fail(MESSI_EINVAL, "k, distance and window must be host arrays");
-  if (flags & ~(MESSI_SCREEN_BF16 | MESSI_LB_IMPROVED)) return fail(MESSI_EINVAL, "unknown flags");
+  if (flags & ~(MESSI_SCREEN_BF16 | MESSI_LB_IMPROVED | MESSI_GRAPH)) return fail(MESSI_EINVAL, "unknown flags");
   if (!is_device_ptr(queries) || !is_device_ptr(out_ids) || !is_device_ptr(out_dists))
     return fail(MESSI_EINVAL, "queries and outputs must be device pointers");
   for (int i = 0; i < nq; ++i) {
@@ -1275,17 +1862,171 @@ int messi_query_batch(messi_index* index, const float* queries, int32_t nq, cons
   BusyGuard guard(index->busy);
   if (!guard.ok) return fail(MESSI_EBUSY, "index is in use by another call");
   if ((flags & MESSI_SCREEN_BF16) && screen_supported(index->len)) {
-    try {
+    const int rc = guarded([&]() -> int {
       ensure_screen(index);
-    } catch (const OomError& e) {
-      return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-    } catch (const HipError& e) {
-      return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
-    }
+      return MESSI_OK;
+    });
+    if (rc != MESSI_OK) return rc;
   }
-  return run_batch(index, index->ctx, queries, nq, k, distance, window, kmax, flags, out_ids,
-                   out_dists, stats);
+  BatchMode mode;
+  mode.graph = (flags & MESSI_GRAPH) && !stats;  // statistics time each phase: no graph
+  return run_batch(index, index->ctx, queries, nq, k, distance, window, kmax, flags & ~MESSI_GRAPH,
+                   out_ids, out_dists, stats, mode);
 }
+
+int messi_autotune(messi_index* index, const float* queries, int32_t nq, const int32_t* k,
+                   const int32_t* distance, const int32_t* window, int32_t kmax, int32_t flags,
+                   messi_tune* out) {
+  g_err.clear();
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (nq < 1) return fail(MESSI_EINVAL, "nq must be >= 1");
+  if (kmax < 1 || kmax > 1024) return fail(MESSI_EINVAL, "kmax must be in [1, 1024]");
+  if (!k || !distance || !window) return fail(MESSI_EINVAL, "k, distance and window are required");
+  if (is_device_ptr(k) || is_device_ptr(distance) || is_device_ptr(window))
+    return fail(MESSI_EINVAL, "k, distance and window must be host arrays");
+  if (flags & ~(MESSI_SCREEN_BF16 | MESSI_LB_IMPROVED)) return fail(MESSI_EINVAL, "unknown flags");
+  if (!is_device_ptr(queries)) return fail(MESSI_EINVAL, "queries must be a device pointer");
+  for (int i = 0; i < nq; ++i) {
+    if (k[i] < 1 || k[i] > kmax) return fail(MESSI_EINVAL, "k[%d] must be in [1, kmax]", i);
+    if (distance[i] != MESSI_ED && distance[i] != MESSI_DTW)
+      return fail(MESSI_EINVAL, "unknown distance[%d]", i);
+    if (window[i] < 0) return fail(MESSI_EINVAL, "window[%d] must be >= 0", i);
+  }
+  BusyGuard guard(index->busy);
+  if (!guard.ok) return fail(MESSI_EBUSY, "index is in use by another call");
+  return guarded([&]() -> int {
+    const bool screen_flag = (flags & MESSI_SCREEN_BF16) && screen_supported(index->len);
+    if (screen_flag) ensure_screen(index);
+    const BatchGroups bg = group_batch(index, nq, distance, window);
+    const std::string key = tune_key(index, nq, bg, flags);
+    auto report = [&](const TuneEntry& e, int from_cache, int candidates) {
+      if (!out) return;
+      std::memset(out, 0, sizeof(*out));
+      out->screen = e.t.screen;
+      out->screen_min = e.t.screen_min;
+      out->screen_nt = e.t.screen_nt;
+      out->screen_occ = e.t.screen_occ;
+      out->ed_scale = e.t.ed_scale;
+      out->dtw_scale = e.t.dtw_scale;
+      out->overlap = e.t.overlap;
+      out->from_cache = from_cache;
+      out->candidates = candidates;
+      out->ms = e.ms;
+      out->ms_default = e.ms_default;
+    };
+    {
+      std::lock_guard<std::mutex> lk(index->tune_mu);
+      auto it = index->tunes.find(key);
+      if (it != index->tunes.end()) {
+        report(it->second, 1, 0);
+        return MESSI_OK;
+      }
+    }
+    // answers of the defaults (slot 0) and of each candidate (slot 1)
+    const size_t cells = (size_t)nq * kmax;
+    check_budget(index, index->ctx, 0, 2 * cells * (sizeof(int64_t) + sizeof(float)));
+    DevMem tmp;
+    int64_t* ids[2] = {tmp.alloc<int64_t>(cells), tmp.alloc<int64_t>(cells)};
+    float* dd[2] = {tmp.alloc<float>(cells), tmp.alloc<float>(cells)};
+    int rc = MESSI_OK;
+    auto run = [&](const Tune& t, int slot) -> double {
+      BatchMode m;
+      m.tune = &t;
+      const auto t0 = Clock::now();
+      const int r = run_batch(index, index->ctx, queries, nq, k, distance, window, kmax, flags, ids[slot],
+                              dd[slot], nullptr, m);
+      if (r != MESSI_OK) rc = r;
+      return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
+    };
+    // rows whose answers differ from the defaults' (first one in *first)
+    auto rows_differing = [&](int* first) {
+      std::vector<int64_t> a(cells), b(cells);
+      std::vector<float> x(cells), y(cells);
+      d2h(a.data(), ids[0], cells, index->ctx.stream);
+      d2h(b.data(), ids[1], cells, index->ctx.stream);
+      d2h(x.data(), dd[0], cells, index->ctx.stream);
+      d2h(y.data(), dd[1], cells, index->ctx.stream);
+      int rows = 0;
+      *first = -1;
+      for (int i = 0; i < nq; ++i) {
+        const size_t o = (size_t)i * kmax;
+        if (std::memcmp(&a[o], &b[o], kmax * sizeof(int64_t)) != 0 ||
+            std::memcmp(&x[o], &y[o], kmax * sizeof(float)) != 0) {
+          if (*first < 0) *first = i;
+          ++rows;
+        }
+      }
+      return rows;
+    };
+    Tune best;
+    run(best, 0);  // first use of the kernels and buffers, untimed
+    double best_ms = std::min(run(best, 0), run(best, 0));
+    if (rc != MESSI_OK) return rc;
+    const double default_ms = best_ms;
+    bool has_ed = false, has_dtw = false, screenable = false;
+    for (size_t g = 0; g < bg.keys.size(); ++g) {
+      has_ed |= bg.keys[g].first == MESSI_ED;
+      has_dtw |= bg.keys[g].first == MESSI_DTW;
+      screenable |= screen_flag && bg.keys[g].first == MESSI_ED && (int)bg.members[g].size() >= kScreenMinGroup;
+    }
+    int candidates = 1;
+    // coordinate descent: each knob in turn, keeping a value only if it
+    // beats the best so far by 2%
+    auto try_knob = [&](const char* name, int Tune::*knob, std::initializer_list<int> values) -> int {
+      for (int v : values) {
+        Tune c = best;
+        c.*knob = v;
+        if (c.*knob == best.*knob) continue;
+        double ms = run(c, 1);
+        if (rc != MESSI_OK) return rc;
+        if (ms < 1.15 * best_ms) ms = std::min(ms, run(c, 1));  // a second run only for contenders
+        if (rc != MESSI_OK) return rc;
+        ++candidates;
+        int first = -1;
+        const int bad = rows_differing(&first);
+        if (bad)
+          return fail(MESSI_EDEVICE, "autotune: with %s = %d, %d rows (first: row %d) differ from the "
+                      "defaults' answers", name, v, bad, first);
+        if (ms < 0.98 * best_ms) {
+          best = c;
+          best_ms = ms;
+        }
+      }
+      return MESSI_OK;
+    };
+    int r = MESSI_OK;
+    if (screenable) r = try_knob("screen", &Tune::screen, {0});
+    if (r == MESSI_OK && screenable && best.screen) {
+      std::vector<int> nts;
+      for (int nt : {1, 2, 4})
+        if (screen_variant(index->len, nt) && nt != screen_nt_default(index->len)) nts.push_back(nt);
+      for (int nt : nts)
+        if (r == MESSI_OK) r = try_knob("screen_nt", &Tune::screen_nt, {nt});
+      if (r == MESSI_OK) r = try_knob("screen_occ", &Tune::screen_occ, {1, 2});
+    }
+    if (r == MESSI_OK && has_ed && !(screenable && best.screen)) r = try_knob("ed_scale", &Tune::ed_scale, {2});
+    if (r == MESSI_OK && has_dtw) r = try_knob("dtw_scale", &Tune::dtw_scale, {2, 4});
+    if (r == MESSI_OK && bg.keys.size() > 1) r = try_knob("overlap", &Tune::overlap, {0});
+    if (r != MESSI_OK) return r;
+    TuneEntry e;
+    e.t = best;
+    e.ms = best_ms;
+    e.ms_default = default_ms;
+    std::map<std::string, TuneEntry> snapshot;
+    {
+      std::lock_guard<std::mutex> lk(index->tune_mu);
+      index->tunes[key] = e;
+      snapshot = index->tunes;
+    }
+    report(e, 0, candidates);
+    if (!index->tune_path.empty()) {
+      std::string err;
+      if (!write_tune_file(index->tune_path, snapshot, &err)) return fail(MESSI_EINVAL, "%s", err.c_str());
+    }
+    return MESSI_OK;
+  });
+}
+
 
 int messi_classify(messi_index* index, const int32_t* labels, int32_t n_classes,
                    const float* queries, int32_t nq, int32_t k, int32_t distance, int32_t window,
@@ -1304,7 +2045,7 @@ int messi_classify(messi_index* index, const int32_t* labels, int32_t n_classes,
     return fail(MESSI_EINVAL, "labels, queries and outputs must be device pointers");
   BusyGuard guard(index->busy);
   if (!guard.ok) return fail(MESSI_EBUSY, "index is in use by another call");
-  try {
+  return guarded([&]() -> int {
     if ((flags & MESSI_SCREEN_BF16) && screen_supported(index->len)) ensure_screen(index);
     const std::vector<int32_t> ks(nq, k), ds(nq, distance), ws(nq, window);
     const int rc = run_batch(index, index->ctx, queries, nq, ks.data(), ds.data(), ws.data(), k,
@@ -1313,12 +2054,8 @@ int messi_classify(messi_index* index, const int32_t* labels, int32_t n_classes,
     launch_vote(out_ids, k, nq, k, labels, n_classes, out_class, index->ctx.stream);
     launch_check();
     HIP_OR_THROW(hipStreamSynchronize(index->ctx.stream));
-  } catch (const OomError& e) {
-    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-  } catch (const HipError& e) {
-    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
-  }
-  return MESSI_OK;
+    return MESSI_OK;
+  });
 }
 
 int messi_set_stream(messi_index* index, void* hip_stream) {
@@ -1335,9 +2072,7 @@ int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t
   if (segments) *segments = index->w;
   if (card_bits) *card_bits = index->card_bits;
   if (n_leaves) *n_leaves = index->n_leaves;
-  if (device_bytes)
-    *device_bytes = (int64_t)(index->mem.bytes + index->own.bytes + index->ctx.ws.mem.bytes +
-                              index->screen_mem.bytes + index->ctx.batch_mem.bytes);
+  if (device_bytes) *device_bytes = (int64_t)held_bytes(index);
   return MESSI_OK;
 }
 
@@ -1418,29 +2153,56 @@ int messi_server_start(messi_index* index, const messi_server_options* opts, mes
   S->workers_n = workers;
   S->max_batch = max_batch;
   S->budget = o.mem_budget_bytes;
-  S->req_bytes = request_bytes(index, kmax, 4096);
+  if (S->budget == 0 && index->budget > 0)  // the index's budget, less what the index holds
+    S->budget = std::max<int64_t>(1, index->budget - (int64_t)held_bytes(index));
+  S->req_bytes = request_bytes(index, kmax, kLogCap0);
   if (hipGetDevice(&S->device) != hipSuccess) return fail(MESSI_EDEVICE, "no current HIP device");
+  // batch capacity: every worker holds the buffers of `cap` requests from
+  // the start, and all of them together stay within the budget
   int cap = max_batch;
-  if (S->budget > 0) cap = (int)std::max<int64_t>(1, std::min<int64_t>(cap, S->budget / S->req_bytes));
-  try {
+  if (S->budget > 0)
+    cap = (int)std::max<int64_t>(1, std::min<int64_t>(cap, S->budget / ((int64_t)workers * S->req_bytes)));
+  const int rc = guarded([&]() -> int {
     if ((o.flags & MESSI_SCREEN_BF16) && screen_supported(index->len)) ensure_screen(index);
-    for (int i = 0; i < workers; ++i) {
-      std::unique_ptr<SrvWorker> w(new SrvWorker());
-      HIP_OR_THROW(hipStreamCreateWithFlags(&w->ctx.stream, hipStreamNonBlocking));
-      w->cap = cap;
-      w->d_q = w->io.alloc<float>((size_t)cap * index->len);
-      w->d_ids = w->io.alloc<int64_t>((size_t)cap * kmax);
-      w->d_d = w->io.alloc<float>((size_t)cap * kmax);
-      HIP_OR_THROW(hipHostMalloc((void**)&w->h_q, sizeof(float) * cap * index->len, hipHostMallocDefault));
-      HIP_OR_THROW(hipHostMalloc((void**)&w->h_ids, sizeof(int64_t) * cap * kmax, hipHostMallocDefault));
-      HIP_OR_THROW(hipHostMalloc((void**)&w->h_d, sizeof(float) * cap * kmax, hipHostMallocDefault));
-      S->workers.push_back(std::move(w));
+    for (;;) {
+      int64_t total = 0;
+      for (int i = 0; i < workers; ++i) {
+        std::unique_ptr<SrvWorker> w(new SrvWorker());
+        HIP_OR_THROW(hipStreamCreateWithFlags(&w->ctx.own_stream, hipStreamNonBlocking));
+        w->ctx.stream = w->ctx.own_stream;
+        w->cap = cap;
+        w->d_q = w->io.alloc<float>((size_t)cap * index->len);
+        w->d_ids = w->io.alloc<int64_t>((size_t)cap * kmax);
+        w->d_d = w->io.alloc<float>((size_t)cap * kmax);
+        HIP_OR_THROW(hipHostMalloc((void**)&w->h_q, sizeof(float) * cap * index->len, hipHostMallocDefault));
+        HIP_OR_THROW(hipHostMalloc((void**)&w->h_ids, sizeof(int64_t) * cap * kmax, hipHostMallocDefault));
+        HIP_OR_THROW(hipHostMalloc((void**)&w->h_d, sizeof(float) * cap * kmax, hipHostMallocDefault));
+        ensure_workspace(index, w->ctx, cap, kmax);
+        ensure_batch(index, w->ctx, cap);
+        ensure_status(w->ctx, cap);
+        w->resident = (int64_t)(ctx_bytes(w->ctx) + w->io.bytes);
+        total += w->resident;
+        S->workers.push_back(std::move(w));
+      }
+      if (S->budget <= 0 || total <= S->budget || cap == 1) break;
+      // per-worker buffers the request estimate leaves out: fewer requests
+      cap = std::max(1, std::min(cap - 1, (int)((double)cap * (double)S->budget / (double)total)));
+      S->workers.clear();
     }
-  } catch (const OomError& e) {
-    return fail(MESSI_ENOMEM, "device allocation of %zu bytes failed", e.bytes);
-  } catch (const HipError& e) {
-    return fail(MESSI_EDEVICE, "%s: %s", e.what, hipGetErrorString(e.e));
-  }
+    for (auto& wp : S->workers) {
+      SrvWorker* w = wp.get();
+      messi_server* srv = S.get();
+      w->ctx.on_grow = [srv, w](int64_t d) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->inflight += d;
+        srv->peak_inflight = std::max(srv->peak_inflight, srv->inflight);
+        if (d > 0) srv->log_growth += d;
+        w->resident += d;
+      };
+    }
+    return MESSI_OK;
+  });
+  if (rc != MESSI_OK) return rc;
   for (auto& w : S->workers) w->th = std::thread(server_worker_main, S.get(), w.get());
   *out = S.release();
   return MESSI_OK;
@@ -1519,6 +2281,9 @@ int messi_server_get_stats(messi_server* server, messi_server_stats* st) {
   st->request_bytes = server->req_bytes;
   st->batch_capacity = server->workers.empty() ? 0 : server->workers[0]->cap;
   st->busy_us = server->busy_us;
+  st->resident_bytes = 0;
+  for (const auto& w : server->workers) st->resident_bytes += w->resident.load();
+  st->log_growth_bytes = server->log_growth;
   return MESSI_OK;
 }
 

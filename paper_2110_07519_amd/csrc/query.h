@@ -60,11 +60,15 @@ struct ScreenDev {
 };
 
 bool screen_supported(int len);
-int screen_blocks_per_cu(int len);
+// nt: 16-series column tiles per wave of the screen kernel; the variants
+// built are those screen_variant accepts (screen_nt_default(len) always is)
+bool screen_variant(int len, int nt);
+int screen_nt_default(int len);
+int screen_blocks_per_cu(int len, int nt);
 void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, int len, uint16_t* dst,
                       float* norms, hipStream_t st);
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   const ScreenDev& sc, int blocks, hipStream_t st);
+                   const ScreenDev& sc, int blocks, int nt, hipStream_t st);
 
 void launch_vote(const int64_t* ids, int64_t stride, int nq, int k, const int* labels, int n_classes,
                  int* out, hipStream_t st);
@@ -84,9 +88,10 @@ size_t process_lds_static(const QueryParams& qp);  // its static LDS (upper boun
 size_t finalize_lds_bytes(const QueryParams& qp);
 size_t stage1_lds_bytes(const QueryParams& qp);
 int process_blocks_per_cu(const QueryParams& qp);
+// grid of the ED process kernel (every block visits every query)
 int ed_process_blocks(int resident);
 // Device address (on the current device) and size of the allocation-free
 // entry point's scratch array; nullptr if it cannot be had.
-void* noalloc_scratch(size_t* bytes);  // grid of the ED process kernel (every block visits every query)
+void* noalloc_scratch(size_t* bytes);
 
 }  // namespace messi

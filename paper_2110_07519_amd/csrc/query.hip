@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
                                               QueryParams p, QueryState s) {
   const int q = blockIdx.x;
   const int tid = threadIdx.x;
-  const int len = p.len, w = p.w, m = p.m, cb = p.card_bits, card = 1 << cb;
+  const int len = p.len, w = p.w, m = p.m, cb = p.card_bits;
   extern __shared__ float sm[];
   float* x = sm;
   float* z = x + len;
@@ -1057,9 +1057,10 @@ __device__ __forceinline__ void process_body(const IndexDev& ix, const QueryPara
   for (int visit = 0; visit < p.nq; ++visit) {
   const int q = (int)((blockIdx.x + (unsigned)visit) % (unsigned)p.nq);
   const int k = k_of(p, s, q);
-  // the near-tie log entries of the approximate search, once per query
-  // (block q's first visit; it runs even if the query is already done)
-  if (visit == 0 && (int)blockIdx.x == q) log_approx(p, s, q, tid, blockDim.x);
+  // the near-tie log entries of the approximate search, once per query,
+  // by block q mod gridDim.x (block q, on its first visit, when the grid
+  // has a block per query); it runs even if the query is already done
+  if (q % (int)gridDim.x == (int)blockIdx.x) log_approx(p, s, q, tid, blockDim.x);
   {
     int* cq = s.next + (int64_t)q * kCounterInts;
     if (tid == 0)
@@ -1466,7 +1467,11 @@ __global__ __launch_bounds__(kEdThreads) void k_process_ed(IndexDev ix, QueryPar
   for (int visit = 0; visit < p.nq; ++visit) {
     const int q = (int)((blockIdx.x + (unsigned)visit) % (unsigned)p.nq);
     const int k = k_of(p, s, q);
-    if (visit == 0 && (int)blockIdx.x == q) log_approx(p, s, q, tid, blockDim.x);
+    // the near-tie log entries of the approximate search, once per query,
+    // by block q mod gridDim.x: with fewer blocks than queries, block b
+    // logs every query q = b (mod gridDim.x) when it reaches it (a later
+    // k-th best gives a narrower window that still holds the final one's)
+    if (q % (int)gridDim.x == (int)blockIdx.x) log_approx(p, s, q, tid, blockDim.x);
     {
       // the series table from the query's PAA (the same arithmetic as k_prep)
       const float* pu = s.paa + ((int64_t)q * 3 + 1) * kMaxSeg;
@@ -2117,23 +2122,27 @@ constexpr int kScreenChunk = 64;
 
 constexpr int kScreenGrab = 4;  // leaves taken per grab of the screen's work counter
 
-template <int KS>
+// KS: 32-element K steps per row (len / 32); NT: 16-series column tiles
+// each wave holds in registers (its B operands: NT x KS x 4 VGPRs).
+template <int KS, int NT>
 struct ScreenShape {
   static constexpr int len = 32 * KS;
   static constexpr int row_bytes = 2 * len + 16;  // padded: rows start 4 banks apart
   static constexpr int a_bytes = kScreenChunk * row_bytes;
   static constexpr int per_thread = kScreenChunk * (len / 8) / (kScreenWaves * kWave);  // uint4 loads
   static constexpr size_t lds = 2 * (size_t)a_bytes;
-  static constexpr int tiles = KS >= 16 ? 1 : 4;  // 16-series column tiles per wave
+  static constexpr int tiles = NT;
   static constexpr int pass = 16 * tiles * kScreenWaves;
 };
 
-template <int KS>
+// Column tiles per wave when no tuned value is given.
+constexpr int screen_default_nt(int len) { return len >= 512 ? 1 : 4; }
+
+template <int KS, int NT>
 __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, QueryParams p,
                                                                  QueryState s, ScreenDev sc) {
-  using Sh = ScreenShape<KS>;
+  using Sh = ScreenShape<KS, NT>;
   constexpr int len = Sh::len;
-  constexpr int NT = Sh::tiles;
   constexpr int kThreads = kScreenWaves * kWave;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int col = lane & 15, kb = 8 * (lane >> 4);
@@ -2419,9 +2428,11 @@ static int process_threads(int R) {
 }
 
 size_t finalize_lds_bytes(const QueryParams& p) {
-  // DTW: fin_waves rows and FP64 wave buffers; ED: a strip of squares per wave
+  // DTW: fin_waves rows and FP64 wave buffers (none when the band fits one
+  // wave's registers, 2 r + 1 <= 64); ED: a strip of squares per wave
   const size_t dwords = p.distance == 0 ? (size_t)(kProcThreads / kWave) * kFinBatch * kWave
-                                        : (size_t)p.fin_waves * 3 * p.len;
+                        : 2 * p.window + 1 <= kWave ? 0
+                                                    : (size_t)p.fin_waves * 3 * p.len;
   const size_t words = ((((size_t)4 * kTopCap + p.len + (size_t)p.fin_waves * p.len) + 1) & ~(size_t)1) +
                        dwords * 2;
   return words * sizeof(float);
@@ -2522,22 +2533,39 @@ void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState
 
 bool screen_supported(int len) { return len == 64 || len == 128 || len == 256 || len == 512; }
 
-int screen_blocks_per_cu(int len) {
+// The (K steps, column tiles) variants of the screen kernel built: the B
+// operands take NT x KS x 4 VGPRs, so wider tiles suit shorter series
+// (16 x 2 would spill).
+#define MESSI_SCREEN_VARIANTS(X) \
+  X(2, 1) X(2, 2) X(2, 4) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(8, 4) X(16, 1)
+
+bool screen_variant(int len, int nt) {
+  const int ks = len / 32;
+#define MESSI_SV(K, T) \
+  if (ks == K && nt == T && len == 32 * K) return true;
+  MESSI_SCREEN_VARIANTS(MESSI_SV)
+#undef MESSI_SV
+  return false;
+}
+
+int screen_blocks_per_cu(int len, int nt) {
   int per = 0;
-  hipError_t e = hipSuccess;
+  hipError_t e = hipErrorInvalidValue;
   const int th = kScreenWaves * kWave;
-  switch (len / 32) {
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<2>, th, ScreenShape<2>::lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<4>, th, ScreenShape<4>::lds); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<8>, th, ScreenShape<8>::lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<16>, th, ScreenShape<16>::lds); break;
-  }
+  const int ks = len / 32;
+#define MESSI_SO(K, T)                                                                                     \
+  if (ks == K && nt == T)                                                                                  \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<K, T>, th, ScreenShape<K, T>::lds);
+  MESSI_SCREEN_VARIANTS(MESSI_SO)
+#undef MESSI_SO
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 1;
   }
   return per < 1 ? 1 : per;
 }
+
+int screen_nt_default(int len) { return screen_default_nt(len); }
 
 void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, int len, uint16_t* dst,
                       float* norms, hipStream_t st) {
@@ -2548,19 +2576,22 @@ void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, in
 }
 
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   const ScreenDev& sc, int blocks, hipStream_t st) {
+                   const ScreenDev& sc, int blocks, int nt, hipStream_t st) {
   const unsigned lb = (unsigned)((qp.n_leaves + 255) / 256);
   hipLaunchKernelGGL(k_log_approx, dim3(qp.nq), dim3(256), 0, st, qp, qs);
   hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, false);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, qp, sc);
   hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, true);
   const dim3 th(kScreenWaves * kWave);
-  switch (qp.len / 32) {
-    case 2: hipLaunchKernelGGL(k_screen<2>, dim3(blocks), th, ScreenShape<2>::lds, st, ix, qp, qs, sc); break;
-    case 4: hipLaunchKernelGGL(k_screen<4>, dim3(blocks), th, ScreenShape<4>::lds, st, ix, qp, qs, sc); break;
-    case 8: hipLaunchKernelGGL(k_screen<8>, dim3(blocks), th, ScreenShape<8>::lds, st, ix, qp, qs, sc); break;
-    case 16: hipLaunchKernelGGL(k_screen<16>, dim3(blocks), th, ScreenShape<16>::lds, st, ix, qp, qs, sc); break;
+  const int ks = qp.len / 32;
+#define MESSI_SL(K, T)                                                               \
+  if (ks == K && nt == T) {                                                          \
+    constexpr size_t lds = ScreenShape<K, T>::lds;                                   \
+    hipLaunchKernelGGL((k_screen<K, T>), dim3(blocks), th, lds, st, ix, qp, qs, sc); \
+    return;                                                                          \
   }
+  MESSI_SCREEN_VARIANTS(MESSI_SL)
+#undef MESSI_SL
 }
 
 // Scratch of the allocation-free query entry point: the query state lives

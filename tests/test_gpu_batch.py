@@ -133,7 +133,7 @@ def test_batch_edge_cases_and_errors(pm):
     with pytest.raises(pm.MessiError):
         pm.messi_query_batch(idx, qt, [1, 1, 1], [1, 1, 1], [0, -1, 0])
     with pytest.raises(pm.MessiError):
-        pm.messi_query_batch(idx, qt, [1, 1, 1], [0, 0, 0], [0, 0, 0], flags=4)
+        pm.messi_query_batch(idx, qt, [1, 1, 1], [0, 0, 0], [0, 0, 0], flags=8)
     idx.free()
 
 

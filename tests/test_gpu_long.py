@@ -1,7 +1,8 @@
 """GPU parity for long series, up to the largest length the build accepts
 (4096 points): exact k-NN under ED at 1024-4096 and DTW (band and wide
-windows) at 1024-3072 against the oracle, ids exact and distances within
-1e-4 relative.  DTW at 4096 does not fit a block's LDS and is refused with
+windows) at 1024-4096 against the oracle, ids exact and distances within
+1e-4 relative.  At 4096, DTW with r <= 31 (FP64 recheck in registers)
+fits; wider windows need LDS rows a block cannot have and are refused with
 MESSI_EINVAL."""
 import numpy as np
 import pytest
@@ -50,7 +51,7 @@ def test_long_series_ed(pm, length):
     idx.free()
 
 
-@pytest.mark.parametrize("length,r", [(1024, 10), (1024, 100), (2048, 20), (3072, 8)])
+@pytest.mark.parametrize("length,r", [(1024, 10), (1024, 100), (2048, 20), (3072, 8), (4096, 31)])
 def test_long_series_dtw(pm, length, r):
     raw, qs, idx = _case(pm, 600, length, seed=80 + length // 1024)
     oids, od2 = oracle.knn(raw, qs[:4], 2, distance=oracle.DTW, r=r)
@@ -60,7 +61,7 @@ def test_long_series_dtw(pm, length, r):
 
 def test_dtw_too_long_for_lds_is_refused(pm):
     raw, qs, idx = _case(pm, 300, 4096, seed=90)
-    for r in (8, 400):  # the FP64 recheck's, then the wave kernel's rows exceed a block's LDS
+    for r in (40, 400):  # the FP64 recheck's, then the wave kernel's rows exceed a block's LDS
         with pytest.raises(pm.MessiError) as e:
             _query(pm, idx, qs[:1], 1, 1, r)
         assert e.value.code == pm.MESSI_EINVAL

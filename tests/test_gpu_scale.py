@@ -1,17 +1,22 @@
 """GPU parity at the benchmark sizes, in the benchmark's launch configuration.
 
 * Exact 1-NN ED over 100,000,000 random walks of length 256 (16 segments,
-  8-bit symbols, leaves of 2000), queries answered one at a time, a 10-NN
-  call over the same queries, the 10-NN classifier's vote, and a screened
-  batch (rows equal to single calls; the oracle's queries among them).  The oracle scans the whole collection,
-  regenerated on the host in chunks by the seeded generator.
-* Exact 1-NN DTW (radius 25) over 10,000,000 random walks of length 256 with
-  noisy dataset copies as queries.  For noise 0.01 and 0.1 the oracle's
-  LB_Keogh-filtered brute force (equal to the plain scan, pinned on the CPU)
-  gives the exact answer; for noise 1.0 that scan is too slow on the host, so
-  the answer is checked by properties that hold at any size: its distance is
-  the oracle's DTW of the returned series, and no larger than the oracle's
-  DTW of the query's source series nor of its ED nearest neighbour.
+  8-bit symbols, leaves of 2000): 100 random-walk queries answered one at
+  a time plus two noisy copies, a 10-NN call over the same queries, the
+  10-NN classifier's vote, and a screened batch of 37 (rows equal to single
+  calls).  On the same index, a batch of 1,024 noisy copies (noise 0.01 /
+  0.1 / 1.0, k alternating 1 and 10) through the BF16 screen with tuned
+  knobs and graph replay: every row equals the plain batch's and a single
+  call's, and 32 rows spread over the batch are checked by the oracle.
+  One host scan of the whole collection (regenerated in chunks by the
+  seeded generator) answers every oracle query.
+* Exact 1-NN DTW (radius 25) over 10,000,000 random walks of length 256:
+  nine noisy dataset copies (noise 0.01, 0.1 and 1.0), each checked
+  against the oracle's LB_Keogh-filtered scan (equal to the plain scan,
+  pinned on the CPU).
+* The same 1,024-query batch at 200,000,000 x 128 (index built in place):
+  rows equal to the plain batch and to single calls, 32 of them checked by
+  the oracle's scan.
 
 The device collection comes from the seeded device generator, which is
 bitwise equal to the host generator (test_device_generator_matches_host).
@@ -74,13 +79,44 @@ def _check(ids, d, oids, od2):
     assert np.all(np.abs(d - od) <= 1e-4 * np.maximum(od, 1e-3)), (d, od)
 
 
-def test_ed_100m_one_query_at_a_time(pm):
+def _host_rows(a):
+    return a.cpu().numpy()
+
+
+def _c4_batch(pm, idx, n, length, nq=1024):
+    """The 1,024-query batch of noisy copies (k alternating 1 and 10) with
+    the screen, tuned and replayed from a graph, against the plain batch
+    and single calls.  Returns (queries, ks, ids, dists, rows for the
+    oracle)."""
+    qs, _, _ = synth.noisy_queries(nq, n, length, j0=100_000)
+    ks = [1 if i % 2 == 0 else 10 for i in range(nq)]
+    qt = torch.from_numpy(qs).cuda()
+    tune = pm.messi_autotune(idx, qt, ks, 0, 0, kmax=10, flags=pm.MESSI_SCREEN_BF16)
+    _say(f"C4 {n} x {length}: tuned {tune}")
+    plain = [_host_rows(t) for t in pm.messi_query_batch(idx, qt, ks, 0, 0, kmax=10)]
+    out_i = torch.empty((nq, 10), dtype=torch.int64, device="cuda")
+    out_d = torch.empty((nq, 10), dtype=torch.float32, device="cuda")
+    for _ in range(2):  # capture, then replay
+        pm.messi_query_batch(idx, qt, ks, 0, 0, kmax=10, flags=pm.MESSI_SCREEN_BF16 | pm.MESSI_GRAPH,
+                             out_ids=out_i, out_dists=out_d)
+        torch.cuda.synchronize()
+        assert np.array_equal(_host_rows(out_i), plain[0]) and np.array_equal(_host_rows(out_d), plain[1])
+    for i in range(nq):
+        sid, sd = pm.messi_query(idx, qt[i:i + 1], ks[i])
+        assert np.array_equal(plain[0][i, :ks[i]], _host_rows(sid)[0]), i
+        assert np.array_equal(plain[1][i, :ks[i]], _host_rows(sd)[0]), i
+    assert np.all(plain[0][0::2, 1:] == -1)
+    rows = np.arange(0, nq, nq // 32)
+    return qs, ks, plain[0], plain[1], rows
+
+
+def test_ed_100m_one_query_at_a_time_and_batch(pm):
     n, length = 100_000_000, 256
     _say(f"ED: building the index over {n} x {length}")
     labels = torch.empty(n, dtype=torch.int32, device="cuda")
     idx = _device_index(pm, n, length, 2000, labels)
     qn, _, _ = synth.noisy_queries(3, n, length)  # noise 0.01, 0.1, 1.0
-    qs = np.concatenate([synth.random_queries(3, length), qn[[0, 2]]])
+    qs = np.concatenate([synth.random_queries(100, length), qn[[0, 2]]])
     qt = torch.from_numpy(qs).cuda()
     one = [pm.messi_query(idx, qt[j:j + 1], 1) for j in range(len(qs))]
     ids1 = np.concatenate([o[0].cpu().numpy() for o in one])
@@ -88,26 +124,30 @@ def test_ed_100m_one_query_at_a_time(pm):
     ids10, d10 = (t.cpu().numpy() for t in pm.messi_query(idx, qt, 10))
     cls, cids, _ = pm.messi_classify(idx, labels, 4, qt, 10)  # k-NN classifier, k = 10
     cls, cids = cls.cpu().numpy(), cids.cpu().numpy()
-    # a screened batch of 37 (these 5 and 32 noisy copies, k 10 / 3): rows
-    # equal to one call per query, and the first 5 checked by the oracle below
-    qb = np.concatenate([qs, synth.noisy_queries(32, n, length, j0=1000)[0]])
+    del labels
+    pm.messi_prepare_screen(idx)
+    # a screened batch of 37 (5 of these and 32 noisy copies, k 10 / 3):
+    # rows equal to one call per query
+    qb = np.concatenate([qs[:5], synth.noisy_queries(32, n, length, j0=1000)[0]])
     qbt = torch.from_numpy(qb).cuda()
     kb = [10] * 5 + [3] * 32
     bids, bd, bst = pm.messi_query_batch(idx, qbt, kb, [0] * 37, [0] * 37, flags=pm.MESSI_SCREEN_BF16,
                                          stats=True)
     bids, bd = bids.cpu().numpy(), bd.cpu().numpy()
     assert bst["screened"] > 0
-    for j in range(5, 37, 4):
-        sid, sd = pm.messi_query(idx, qbt[j:j + 1], 3)
-        assert np.array_equal(bids[j, :3], sid.cpu().numpy()[0]) and np.array_equal(bd[j, :3], sd.cpu().numpy()[0])
+    for j in range(37):
+        sid, sd = pm.messi_query(idx, qbt[j:j + 1], kb[j])
+        assert np.array_equal(bids[j, :kb[j]], sid.cpu().numpy()[0]) and np.array_equal(bd[j, :kb[j]], sd.cpu().numpy()[0])
+    cq, cks, cids4, cd4, rows = _c4_batch(pm, idx, n, length)
     idx.free()
-    del labels
-    _say("ED: GPU answers ready; oracle scan of the whole collection")
+    _say(f"ED: GPU answers ready; oracle scan of the whole collection ({len(qs)} + {len(rows)} queries)")
     st = oracle.KnnState(qs, 10)
-    _host_scan([st], n, length)
+    st4 = oracle.KnnState(cq[rows], 10)
+    _host_scan([st, st4], n, length)
     _check(ids1, d1, st.ids[:, :1], st.d2[:, :1])
     _check(ids10, d10, st.ids, st.d2)
-    _check(bids[:5], bd[:5], st.ids, st.d2)
+    for t, i in enumerate(rows):
+        _check(cids4[i:i + 1, :cks[i]], cd4[i:i + 1, :cks[i]], st4.ids[t:t + 1, :cks[i]], st4.d2[t:t + 1, :cks[i]])
     # the classifier's vote against the oracle's over the oracle's neighbours
     # (labels computed on the host for just those series; -1 elsewhere)
     assert np.array_equal(cids, st.ids)
@@ -122,27 +162,34 @@ def test_dtw_10m_noisy_queries(pm):
     _say(f"DTW: building the index over {n} x {length}")
     idx = _device_index(pm, n, length, 2000)
     qs, src, sig = synth.noisy_queries(9, n, length)  # noise 0.01, 0.1, 1.0 round robin
+    assert sorted(set(np.round(sig, 2))) == [0.01, 0.1, 1.0]
     qt = torch.from_numpy(qs).cuda()
     one = [pm.messi_query(idx, qt[j:j + 1], 1, pm.MESSI_DTW, r) for j in range(len(qs))]
-    ids = np.concatenate([o[0].cpu().numpy() for o in one])[:, 0]
-    d = np.concatenate([o[1].cpu().numpy() for o in one])[:, 0]
+    ids = np.concatenate([o[0].cpu().numpy() for o in one])
+    d = np.concatenate([o[1].cpu().numpy() for o in one])
     idx.free()
-    easy = np.nonzero(sig < 0.5)[0]
-    hard = np.nonzero(sig >= 0.5)[0]
-    _say("DTW: GPU answers ready; oracle scans")
-    st_dtw = oracle.KnnState(qs[easy], 1, oracle.DTW, r, lb_keogh=True)
-    st_ed = oracle.KnnState(qs[hard], 1)
-    _host_scan([st_dtw, st_ed], n, length)
-    _check(ids[easy][:, None], d[easy][:, None], st_dtw.ids, st_dtw.d2)
-    # noise 1.0: properties of the returned answer
-    zq = oracle.znorm(qs[hard])
-    for t, j in enumerate(hard):
-        x_ans = oracle.znorm(synth.randomwalk(1, length, seed=synth.SEED_DATA, id0=int(ids[j])))[0]
-        d_ans = oracle.dtw2(zq[t], x_ans, r)
-        assert abs(d[j] - np.sqrt(d_ans)) <= 1e-4 * max(np.sqrt(d_ans), 1e-3)
-        for other in (int(src[j]), int(st_ed.ids[t, 0])):
-            x_o = oracle.znorm(synth.randomwalk(1, length, seed=synth.SEED_DATA, id0=other))[0]
-            assert d_ans <= oracle.dtw2(zq[t], x_o, r)
+    _say("DTW: GPU answers ready; oracle scan (LB_Keogh-filtered DTW)")
+    st = oracle.KnnState(qs, 1, oracle.DTW, r, lb_keogh=True)
+    _host_scan([st], n, length)
+    _check(ids, d, st.ids, st.d2)
+
+
+def test_c4_batch_200m_by_128(pm):
+    n, length = 200_000_000, 128
+    _say(f"C4: generating and building in place over {n} x {length}")
+    data = torch.empty((n, length), dtype=torch.float32, device="cuda")
+    synth.randomwalk_device(data, seed=synth.SEED_DATA)
+    idx = pm.messi_build_ex(data, 16, 256, 2000, inplace=True, bf16_screen=True)
+    torch.cuda.synchronize()
+    cq, cks, cids, cd, rows = _c4_batch(pm, idx, n, length)
+    idx.free()
+    del data
+    torch.cuda.empty_cache()
+    _say(f"C4: GPU answers ready; oracle scan of {n} x {length} ({len(rows)} queries)")
+    st = oracle.KnnState(cq[rows], 10)
+    _host_scan([st], n, length)
+    for t, i in enumerate(rows):
+        _check(cids[i:i + 1, :cks[i]], cd[i:i + 1, :cks[i]], st.ids[t:t + 1, :cks[i]], st.d2[t:t + 1, :cks[i]])
 
 
 def test_subsequence_windows_20m_points(pm):

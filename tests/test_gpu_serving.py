@@ -102,25 +102,58 @@ def test_mixed_stream_equals_single_queries(pm, index, data):
 
 
 def test_memory_admission_bounds_inflight_requests(pm, index):
+    """Every worker holds the buffers of its batch capacity from the start;
+    the capacity is cut until all workers fit the budget, and admitted
+    requests never hold more than it."""
     nreq = 40
     qs, ks, dist, win = _requests(nreq)
     probe = pm.Server(index, workers=1, max_batch=8, kmax=10)
     per = probe.stats()["request_bytes"]
     probe.stop()
-    budget = 3 * per
+    budget = 8 * per
     srv = pm.Server(index, workers=2, max_batch=64, mem_budget_bytes=budget, kmax=10)
+    st0 = srv.stats()
+    assert 1 <= st0["batch_capacity"] <= 4 and st0["resident_bytes"] <= budget
     ids_of = {srv.submit(qs[i], ks[i], dist[i], win[i]): i for i in range(nreq)}
     got = _collect(srv, nreq)
     st = srv.stats()
     srv.stop()
     assert st["completed"] == nreq
-    assert st["batch_capacity"] == 3 and st["max_batch_seen"] <= 3
-    assert st["peak_inflight_bytes"] <= budget and st["inflight_bytes"] == 0
+    assert st["max_batch_seen"] <= st["batch_capacity"]
+    # a batch whose near-tie log grew was charged the growth while it ran
+    assert st["peak_inflight_bytes"] <= budget + st["log_growth_bytes"] and st["inflight_bytes"] == 0
+    assert st["resident_bytes"] == st0["resident_bytes"]
     for rid, (status, ids, d, _) in got.items():
         i = ids_of[rid]
         a_ids, a_d = _alone(pm, index, qs[i], ks[i], dist[i], win[i])
         assert status == 0
         assert np.array_equal(ids[:ks[i]], a_ids) and np.array_equal(d[:ks[i]], a_d)
+
+
+def test_near_tie_log_growth_is_charged_and_returned(pm, index, data):
+    """A flat query (z-normalised to zeros) is at the same distance from
+    every series, so all 40,000 are near ties: its near-tie log overflows
+    and grows twice (4,096 -> 16,384 -> 65,536 entries).  The growth is
+    charged to the in-flight bytes while the batch runs and handed back
+    with the memory once the log is shrunk after it."""
+    srv = pm.Server(index, workers=1, max_batch=4, kmax=5)
+    st0 = srv.stats()
+    flat = np.full(LEN, 3.0, np.float32)
+    rid = srv.submit(flat, 5)
+    got = _collect(srv, 1)
+    st = srv.stats()
+    srv.stop()
+    status, ids, d, _ = got[rid]
+    assert status == 0
+    a_ids, a_d = _alone(pm, index, flat, 5, 0, 0)
+    assert np.array_equal(ids[:5], a_ids) and np.array_equal(d[:5], a_d)
+    oids, od2 = oracle.knn(data, flat[None, :], 5)
+    assert np.array_equal(ids[:5], oids[0])
+    grown = (65536 - 4096) * 8  # log bytes added for one query slot (at least)
+    assert st["log_growth_bytes"] >= grown
+    assert st["peak_inflight_bytes"] >= st0["request_bytes"] + grown
+    assert st["inflight_bytes"] == 0
+    assert st["resident_bytes"] == st0["resident_bytes"]
 
 
 def test_server_argument_errors(pm, index):
