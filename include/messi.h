@@ -11,9 +11,12 @@
  * unless the index was built with messi_options.raw.
  *
  * Conventions for every call:
- *   - Returns MESSI_OK (0) or a negative MESSI_E* code; on error the output
- *     buffers' contents are unspecified and messi_last_error() describes
- *     the cause.
+ *   - Returns MESSI_OK (0) or a negative MESSI_E* code, and
+ *     messi_last_error() describes the cause.  On error the output
+ *     buffers' contents are unspecified: a call may fail after its kernels
+ *     have written part of them (a rerun that cannot get the memory it
+ *     needs, a device error).  Argument errors (MESSI_EINVAL found before
+ *     any device work) leave them untouched.
  *   - "device pointer" = memory on the current HIP device (hipMalloc'd or a
  *     torch CUDA tensor); "host pointer" = ordinary process memory.
  *     Passing a host pointer where a device pointer is required is rejected
@@ -145,8 +148,13 @@ typedef struct messi_options {
                           messi_query_batch for the batch shapes they name. */
 } messi_options;
 
-/* messi_build with options (NULL = defaults).  With inplace, `series` is
- * overwritten with its z-normalised rows; otherwise it is only read. */
+/* messi_build with options (NULL = defaults): the same index construction
+ * (Section 3.2; Algorithms 1-4).  With inplace, `series` is overwritten
+ * with its z-normalised rows and becomes the store, which lets a
+ * collection of most of the device's memory be indexed (the paper's
+ * in-memory setting, Section 5.1); otherwise it is only read.  Errors as
+ * for messi_build, plus MESSI_ENOMEM over mem_budget_bytes and
+ * MESSI_EINVAL for an autotune_cache file it cannot read. */
 int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int32_t cardinality,
                    int32_t leaf_size, const messi_options* opts, messi_index** out);
 
@@ -362,7 +370,10 @@ int messi_server_get_stats(messi_server* server, messi_server_stats* stats);
 void messi_server_stop(messi_server* server);
 
 /* Order the index's work after / before the caller's on this HIP stream
- * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream. */
+ * (e.g. torch.cuda.current_stream().cuda_stream).  NULL = null stream.
+ * Library plumbing (no passage of the paper): a batch's further groups
+ * and graph captures use streams of the library's own, joined back into
+ * this one; the stream must stay valid while the index uses it. */
 int messi_set_stream(messi_index* index, void* hip_stream);
 
 /* Shape of a built index (any pointer may be NULL). */
@@ -382,9 +393,13 @@ int messi_get_leaves(const messi_index* index, messi_leaf* leaves, int64_t cap, 
  * for k = 1 .. 2^b - 1, as FP32, into a HOST buffer. */
 int messi_breakpoints(int32_t card_bits, float* beta);
 
+/* Library plumbing (no passage of the paper): releases every device and
+ * pinned host buffer of the index, and an inplace = 2 store; NULL is a
+ * no-op.  No call on the index may be running. */
 void messi_free(messi_index* index);
 
-/* Description of the last error on this thread; valid until the next call. */
+/* Description of the last error on this thread; valid until the next call
+ * (library plumbing, no passage of the paper). */
 const char* messi_last_error(void);
 
 #ifdef __cplusplus

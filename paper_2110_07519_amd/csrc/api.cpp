@@ -1177,6 +1177,14 @@ int run_batch(messi_index* index, QueryCtx& ctx, const float* queries, int nq, c
       scr[g] = want_screen && bg.keys[g].first == MESSI_ED && cnt[g] >= std::max(1, t.screen_min);
       if (scr[g] && !index->Zb) return fail(MESSI_EINVAL, "the BF16 screen copy is not prepared");
     }
+    // every group's kernels must fit this length and window before any
+    // group runs (argument errors leave the outputs untouched)
+    for (int g = 0; g < G; ++g) {
+      GroupLaunch probe;
+      const int rc = plan_group(index, ctx, cnt[g], kmax, bg.keys[g].first, bg.keys[g].second, scr[g], lbi,
+                                false, t, probe);
+      if (rc != MESSI_OK) return rc;
+    }
     const bool overlap = mode.allow_overlap && t.overlap && G > 1;
     if (!mode.graph && !overlap) {
       for (int g = 0; g < G; ++g) {
