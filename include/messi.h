@@ -274,7 +274,8 @@ typedef struct messi_tune {
   int32_t overlap;     /* 1: groups run concurrently (1) */
   int32_t from_cache;  /* 1: found in the cache, nothing measured */
   int32_t candidates;  /* knob settings timed */
-  int32_t reserved;
+  int32_t screen_waves; /* waves per screen block (0: 4, two blocks to a
+                          CU; 8: one) */
   double ms;           /* batch time with these knobs (best of up to 2 runs) */
   double ms_default;   /* batch time with the defaults */
 } messi_tune;
@@ -282,8 +283,8 @@ typedef struct messi_tune {
 /* Autotuner of messi_query_batch (not part of the paper's method): times
  * the batch (arguments as for messi_query_batch) with the default knobs
  * and then one knob at a time - screen on / off, the screen kernel's
- * column tiles and blocks per CU, the ED grid, DTW blocks per query,
- * concurrent groups - keeping a setting only if it is at least 2% faster,
+ * column tiles, waves per block and blocks per CU, the ED grid, DTW
+ * blocks per query, concurrent groups - keeping a setting only if it is at least 2% faster,
  * and checks that every setting's answers equal the defaults' bit for bit
  * (MESSI_EDEVICE if not).  The choice is kept in the index for batches of
  * the same shape (device, index shape, nq rounded up to a power of two,

@@ -179,11 +179,11 @@ class MessiTune(ctypes.Structure):
                 ("screen_nt", ctypes.c_int32), ("screen_occ", ctypes.c_int32),
                 ("ed_scale", ctypes.c_int32), ("dtw_scale", ctypes.c_int32),
                 ("overlap", ctypes.c_int32), ("from_cache", ctypes.c_int32),
-                ("candidates", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("candidates", ctypes.c_int32), ("screen_waves", ctypes.c_int32),
                 ("ms", ctypes.c_double), ("ms_default", ctypes.c_double)]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def _options(inplace=0, bf16_screen=False, raw=False, mem_budget_bytes=0, autotune_cache=None):

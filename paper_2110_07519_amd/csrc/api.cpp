@@ -157,6 +157,7 @@ struct Tune {
   int screen_min = 32;  // fewest ED queries in a screened group
   int screen_nt = 0;    // 16-series column tiles per wave of the screen kernel (0: its default)
   int screen_occ = 0;   // screen blocks per CU (0: the occupancy limit)
+  int screen_waves = 0; // waves per screen block (0: its default, 4)
   int ed_scale = 1;     // ED process grid, in resident grids
   int dtw_scale = 1;    // DTW process blocks per query, in multiples of the even share
   int overlap = 1;      // 1: a batch's groups run concurrently, each on its own stream
@@ -760,7 +761,7 @@ struct GroupLaunch {
   const float* queries;
   int64_t* out_ids;
   float* out_dists;
-  int screen, blocks, screen_blocks, screen_nt;
+  int screen, blocks, screen_blocks, screen_nt, screen_waves;
 };
 
 // Parameters and grids of a group of nq queries; `main` holds the batch's
@@ -865,8 +866,13 @@ int plan_group(messi_index* ix, QueryCtx& main, int nq, int kmax, int distance, 
     const double cdot = 2.0 * ((2.0 * ub + ub * ub) + gm * (1.0 + ub) * (1.0 + ub)) * (1.0 + std::ldexp(1.0, -10));
     sc.c_dot = std::nextafter((float)cdot, INFINITY);
     sc.c_abs = (float)std::ldexp(1.0, -17);
-    g.screen_nt = (t.screen_nt > 0 && screen_variant(len, t.screen_nt)) ? t.screen_nt : screen_nt_default(len);
-    int occ = screen_blocks_per_cu(len, g.screen_nt);
+    g.screen_nt = t.screen_nt > 0 ? t.screen_nt : screen_nt_default(len);
+    g.screen_waves = t.screen_waves > 0 ? t.screen_waves : screen_waves_default();
+    if (!screen_variant(len, g.screen_nt, g.screen_waves)) {  // a shape not built: the defaults
+      g.screen_nt = screen_nt_default(len);
+      g.screen_waves = screen_waves_default();
+    }
+    int occ = screen_blocks_per_cu(len, g.screen_nt, g.screen_waves);
     if (t.screen_occ > 0) occ = std::min(occ, t.screen_occ);
     g.screen_blocks = occ * ix->n_cus;
   }
@@ -918,7 +924,7 @@ void enqueue_group(messi_index* ix, QueryCtx& c, const GroupLaunch& g, hipStream
   if (timed) HIP_OR_THROW(hipEventRecord(c.ev[2], st));
   if (g.screen) {
     launch_bf16_rows(g.qs.zq, nullptr, g.p.nq, g.p.len, g.sc.qb, g.sc.qn, st);
-    launch_screen(v, g.p, g.qs, g.sc, g.screen_blocks, g.screen_nt, st);
+    launch_screen(v, g.p, g.qs, g.sc, g.screen_blocks, g.screen_nt, g.screen_waves, st);
   } else {
     launch_process(v, g.p, g.qs, g.blocks, st);
   }
@@ -1295,8 +1301,8 @@ Tune tune_for(const messi_index* ix, const std::string& key) {
 // The knobs in the cache file's order: name, member.
 const std::pair<const char*, int Tune::*> kTuneFields[] = {
     {"screen", &Tune::screen},     {"screen_min", &Tune::screen_min}, {"screen_nt", &Tune::screen_nt},
-    {"screen_occ", &Tune::screen_occ}, {"ed_scale", &Tune::ed_scale},  {"dtw_scale", &Tune::dtw_scale},
-    {"overlap", &Tune::overlap}};
+    {"screen_occ", &Tune::screen_occ}, {"screen_waves", &Tune::screen_waves}, {"ed_scale", &Tune::ed_scale},
+    {"dtw_scale", &Tune::dtw_scale}, {"overlap", &Tune::overlap}};
 
 // Minimal reader of the cache file: an object whose members are objects of
 // numbers, {"key": {"name": number, ...}, ...}.  Returns false on any
@@ -1914,6 +1920,7 @@ int messi_autotune(messi_index* index, const float* queries, int32_t nq, const i
       out->screen_min = e.t.screen_min;
       out->screen_nt = e.t.screen_nt;
       out->screen_occ = e.t.screen_occ;
+      out->screen_waves = e.t.screen_waves;
       out->ed_scale = e.t.ed_scale;
       out->dtw_scale = e.t.dtw_scale;
       out->overlap = e.t.overlap;
@@ -1978,38 +1985,55 @@ int messi_autotune(messi_index* index, const float* queries, int32_t nq, const i
       screenable |= screen_flag && bg.keys[g].first == MESSI_ED && (int)bg.members[g].size() >= kScreenMinGroup;
     }
     int candidates = 1;
-    // coordinate descent: each knob in turn, keeping a value only if it
+    // coordinate descent: each knob in turn, keeping a setting only if it
     // beats the best so far by 2%
+    auto try_setting = [&](const char* name, const Tune& c) -> int {
+      double ms = run(c, 1);
+      if (rc != MESSI_OK) return rc;
+      if (ms < 1.15 * best_ms) ms = std::min(ms, run(c, 1));  // a second run only for contenders
+      if (rc != MESSI_OK) return rc;
+      ++candidates;
+      int first = -1;
+      const int bad = rows_differing(&first);
+      if (bad)
+        return fail(MESSI_EDEVICE, "autotune: with %s, %d rows (first: row %d) differ from the defaults' "
+                    "answers", name, bad, first);
+      if (ms < 0.98 * best_ms) {
+        best = c;
+        best_ms = ms;
+      }
+      return MESSI_OK;
+    };
     auto try_knob = [&](const char* name, int Tune::*knob, std::initializer_list<int> values) -> int {
       for (int v : values) {
         Tune c = best;
         c.*knob = v;
         if (c.*knob == best.*knob) continue;
-        double ms = run(c, 1);
-        if (rc != MESSI_OK) return rc;
-        if (ms < 1.15 * best_ms) ms = std::min(ms, run(c, 1));  // a second run only for contenders
-        if (rc != MESSI_OK) return rc;
-        ++candidates;
-        int first = -1;
-        const int bad = rows_differing(&first);
-        if (bad)
-          return fail(MESSI_EDEVICE, "autotune: with %s = %d, %d rows (first: row %d) differ from the "
-                      "defaults' answers", name, v, bad, first);
-        if (ms < 0.98 * best_ms) {
-          best = c;
-          best_ms = ms;
-        }
+        char what[64];
+        snprintf(what, sizeof(what), "%s = %d", name, v);
+        const int r2 = try_setting(what, c);
+        if (r2 != MESSI_OK) return r2;
       }
       return MESSI_OK;
     };
     int r = MESSI_OK;
     if (screenable) r = try_knob("screen", &Tune::screen, {0});
     if (r == MESSI_OK && screenable && best.screen) {
-      std::vector<int> nts;
+      const int len = index->len, w0 = screen_waves_default();
       for (int nt : {1, 2, 4})
-        if (screen_variant(index->len, nt) && nt != screen_nt_default(index->len)) nts.push_back(nt);
-      for (int nt : nts)
-        if (r == MESSI_OK) r = try_knob("screen_nt", &Tune::screen_nt, {nt});
+        if (r == MESSI_OK && nt != screen_nt_default(len) && screen_variant(len, nt, w0))
+          r = try_knob("screen_nt", &Tune::screen_nt, {nt});
+      // the other block size, with each column tile count it is built for
+      const int w1 = w0 == 4 ? 8 : 4;
+      for (int nt : {1, 2, 4}) {
+        if (r != MESSI_OK || !screen_variant(len, nt, w1)) continue;
+        Tune c = best;
+        c.screen_nt = nt;
+        c.screen_waves = w1;
+        char what[64];
+        snprintf(what, sizeof(what), "screen_nt = %d, screen_waves = %d", nt, w1);
+        r = try_setting(what, c);
+      }
       if (r == MESSI_OK) r = try_knob("screen_occ", &Tune::screen_occ, {1, 2});
     }
     if (r == MESSI_OK && has_ed && !(screenable && best.screen)) r = try_knob("ed_scale", &Tune::ed_scale, {2});

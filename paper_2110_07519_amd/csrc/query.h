@@ -60,15 +60,17 @@ struct ScreenDev {
 };
 
 bool screen_supported(int len);
-// nt: 16-series column tiles per wave of the screen kernel; the variants
-// built are those screen_variant accepts (screen_nt_default(len) always is)
-bool screen_variant(int len, int nt);
+// nt: 16-series column tiles per wave of the screen kernel, waves: waves
+// per block; the variants built are those screen_variant accepts (the
+// defaults, screen_nt_default(len) with screen_waves_default(), always are)
+bool screen_variant(int len, int nt, int waves);
 int screen_nt_default(int len);
-int screen_blocks_per_cu(int len, int nt);
+int screen_waves_default();
+int screen_blocks_per_cu(int len, int nt, int waves);
 void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, int len, uint16_t* dst,
                       float* norms, hipStream_t st);
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   const ScreenDev& sc, int blocks, int nt, hipStream_t st);
+                   const ScreenDev& sc, int blocks, int nt, int waves, hipStream_t st);
 
 void launch_vote(const int64_t* ids, int64_t stride, int nq, int k, const int* labels, int n_classes,
                  int* out, hipStream_t st);

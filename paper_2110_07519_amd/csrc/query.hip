@@ -557,7 +557,7 @@ __global__ __launch_bounds__(256) void k_prep(IndexDev ix, const float* __restri
                                               QueryParams p, QueryState s) {
   const int q = blockIdx.x;
   const int tid = threadIdx.x;
-  const int len = p.len, w = p.w, m = p.m, cb = p.card_bits;
+  const int len = p.len, w = p.w, m = p.m;
   extern __shared__ float sm[];
   float* x = sm;
   float* z = x + len;
@@ -1999,14 +1999,28 @@ __global__ __launch_bounds__(kProcThreads) void k_finalize(IndexDev ix, QueryPar
 // rounding of both operands, 2 (2 u_b + u_b^2), u_b = 2^-8, and the FP32
 // accumulation of len products, 2 gamma_len (1 + u_b)^2 with gamma taken
 // at unit 2^-23; c_abs covers the FP32 norms and the FP32 evaluation of
-// d~^2.  A pair is dropped only if d~^2 - E exceeds the k-th best times the
-// near-tie window, so every pair that could be logged or accepted is
-// refined in FP32 as in the unscreened path.  The series the approximate
-// search already refined are skipped (their keys are in the k best; they
-// are logged from the approximate distances).
+// d~^2.  A pair is dropped only if d~^2 - E, a lower bound of its exact
+// squared distance, exceeds the k-th best times the near-tie window.  So
+// every pair whose exact squared distance is within that window survives
+// and is refined in FP32, among them every true k nearest (an exact
+// distance of at most the final k-th best over 1 - rho is inside the
+// window).  A pair just outside the window by exact distance may be
+// dropped where the unscreened path, whose FP32 distance can round into
+// the window, would log it; the answers are the same, as the log only has
+// to hold the true k best.  The series the approximate search already
+// refined are skipped (their keys are in the k best; they are logged from
+// the approximate distances).
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));  // 16 bytes kept in registers
+// Global-memory views of generic pointers: loads through them are global
+// loads, which the hardware counts in order with the other vector loads
+// (a load through a generic pointer also counts as an LDS access, and
+// waiting for one waits for every load issued before it).
+typedef __attribute__((address_space(1))) const int g_int;
+typedef __attribute__((address_space(1))) const float g_float;
+typedef __attribute__((address_space(1))) const u32x4 g_u32x4;
 
 __device__ __forceinline__ uint32_t bf16_bits(float f) {  // finite f, round to nearest even
   const uint32_t u = __float_as_uint(f);
@@ -2100,10 +2114,12 @@ __global__ __launch_bounds__(1024) void k_list_scan(QueryParams p, ScreenDev sc)
 }
 
 // Screen and refinement, leaf-major, as a tiled BF16 GEMM per leaf: the
-// block's eight waves hold 64 series each (16 at len 512) of a column pass
-// in registers (MFMA B operand); the leaf's query list streams through LDS
-// in chunks of 64 queries (A operand), double buffered.  Lane l holds
-// output rows 4 (l / 16) .. + 3 of column l % 16 of each 16 x 16 tile.
+// block's W waves hold 16 NT series each of a column pass in registers
+// (MFMA B operand); the leaf's query list streams through LDS in chunks of
+// 8 W queries (A operand), double buffered.  Lane l holds output rows
+// 4 (l / 16) .. + 3 of column l % 16 of each 16 x 16 tile.  With W = 4 two
+// blocks share a CU, and one block's loads of a new pass's B operands
+// overlap the other's MFMA work (a block waits at its own barriers only).
 //
 // The test of a pair is folded into per-row and per-column terms.  With
 // |s~| <= (|q|^2 + |x|^2) / 2 the bound is at most
@@ -2117,39 +2133,46 @@ __global__ __launch_bounds__(1024) void k_list_scan(QueryParams p, ScreenDev sc)
 // kept are refined by the whole wave in FP32 and offered to their query's
 // k best, except the query's own approximate-search range (already in its
 // k best and logged).
-constexpr int kScreenWaves = 8;
-constexpr int kScreenChunk = 64;
-
 constexpr int kScreenGrab = 4;  // leaves taken per grab of the screen's work counter
+constexpr int kScreenListCap = 2048;  // query-list entries of a leaf staged in LDS
 
 // KS: 32-element K steps per row (len / 32); NT: 16-series column tiles
-// each wave holds in registers (its B operands: NT x KS x 4 VGPRs).
-template <int KS, int NT>
+// each wave holds in registers (its B operands: NT x KS x 4 VGPRs); W:
+// waves per block, with query chunks of 8 W rows (so a thread stages KS / 2
+// 16-byte pieces of A per chunk whatever W is).
+template <int KS, int NT, int W>
 struct ScreenShape {
   static constexpr int len = 32 * KS;
+  static constexpr int waves = W;
+  static constexpr int threads = W * kWave;
+  static constexpr int chunk = 8 * W;             // query rows per A chunk
   static constexpr int row_bytes = 2 * len + 16;  // padded: rows start 4 banks apart
-  static constexpr int a_bytes = kScreenChunk * row_bytes;
-  static constexpr int per_thread = kScreenChunk * (len / 8) / (kScreenWaves * kWave);  // uint4 loads
+  static constexpr int a_bytes = chunk * row_bytes;
+  static constexpr int per_thread = chunk * (len / 8) / threads;  // uint4 loads
   static constexpr size_t lds = 2 * (size_t)a_bytes;
   static constexpr int tiles = NT;
-  static constexpr int pass = 16 * tiles * kScreenWaves;
+  static constexpr int pass = 16 * tiles * W;
 };
 
 // Column tiles per wave when no tuned value is given.
 constexpr int screen_default_nt(int len) { return len >= 512 ? 1 : 4; }
 
-template <int KS, int NT>
-__global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, QueryParams p,
-                                                                 QueryState s, ScreenDev sc) {
-  using Sh = ScreenShape<KS, NT>;
+template <int KS, int NT, int W>
+__global__ __launch_bounds__(W * kWave) __attribute__((amdgpu_waves_per_eu(2)))
+void k_screen(IndexDev ix, QueryParams p, QueryState s, ScreenDev sc) {
+  using Sh = ScreenShape<KS, NT, W>;
   constexpr int len = Sh::len;
-  constexpr int kThreads = kScreenWaves * kWave;
+  constexpr int kThreads = Sh::threads;
+  constexpr int kScreenChunk = Sh::chunk;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int col = lane & 15, kb = 8 * (lane >> 4);
   extern __shared__ uint4 smem_v[];
   char* abuf = reinterpret_cast<char*>(smem_v);
   __shared__ float s_R[2][kScreenChunk], s_a[2][kScreenChunk];
   __shared__ int s_q[2][kScreenChunk];
+  // the leaf's query list when it fits: each entry's query, its k and |q|^2
+  __shared__ int s_list[kScreenListCap], s_lk[kScreenListCap];
+  __shared__ float s_ln[kScreenListCap];
   __shared__ int s_leaf;
   const float one_m = 1.0f - sc.c_abs;
   unsigned long long screened = 0, passed = 0;
@@ -2169,73 +2192,118 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
     const int nlist = (int)(l1 - l0);
     const int nch = (nlist + kScreenChunk - 1) / kScreenChunk;
     const int64_t b = ix.leaf_begin[leaf], e = ix.leaf_end[leaf];
-    // chunk c of the list into registers: A rows and the row terms
-    uint4 pa[Sh::per_thread];
+    // the list's entries, with each query's k and |q|^2, into LDS (when
+    // they fit), so that fetching a chunk is one round trip to memory (its
+    // rows and k-th best distances), which the chunk before it covers
+    const bool in_lds = nlist <= kScreenListCap;
+    g_int* glist = (g_int*)(sc.lists + l0);
+    if (in_lds)
+      for (int i = tid; i < nlist; i += kThreads) {
+        const int q = glist[i];
+        s_list[i] = q;
+        s_lk[i] = ((g_int*)s.kq)[q];
+        s_ln[i] = ((g_float*)sc.qn)[q];
+      }
+    __syncthreads();
+    // chunk c of the list into registers: A rows and the row terms.  Every
+    // load is unconditional (rows past the list read the list's last query
+    // and are masked by R = +inf), so they are all in flight together
+    u32x4 pa[Sh::per_thread];
     int pq = -1;
-    float pR = INFINITY, pA = 0.0f;
-    auto fetch = [&](int c) {
+    float pqn = 0.0f;   // the row's |q|^2
+    float pkth = 0.0f;  // its query's k-th best squared distance when fetched
+    auto fetch = [&](int c) __attribute__((always_inline)) {
+      int qi[Sh::per_thread];
+      const int li = c * kScreenChunk + tid;
+      const int l1c = min(li, nlist - 1);
+      int q0 = 0, kq = 0;
+      float qn = 0.0f;
+      if (in_lds) {
+#pragma unroll
+        for (int u = 0; u < Sh::per_thread; ++u)
+          qi[u] = s_list[min(c * kScreenChunk + (tid + u * kThreads) / (len / 8), nlist - 1)];
+        q0 = s_list[l1c];
+        kq = s_lk[l1c];
+        qn = s_ln[l1c];
+      } else {  // a long list: from memory (the screen runs for batches, which give every k)
+#pragma unroll
+        for (int u = 0; u < Sh::per_thread; ++u)
+          qi[u] = glist[min(c * kScreenChunk + (tid + u * kThreads) / (len / 8), nlist - 1)];
+        q0 = glist[l1c];
+        kq = ((g_int*)s.kq)[q0];
+        qn = ((g_float*)sc.qn)[q0];
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int u = 0; u < Sh::per_thread; ++u) {
-        const int v = tid + u * kThreads;  // uint4 index in the chunk
-        const int row = v / (len / 8), c16 = v % (len / 8);
-        const int li = c * kScreenChunk + row;
-        pa[u] = make_uint4(0, 0, 0, 0);
-        if (li < nlist) {
-          const int q = sc.lists[l0 + li];
-          pa[u] = reinterpret_cast<const uint4*>(sc.qb + (int64_t)q * len)[c16];
-        }
+        const int c16 = (tid + u * kThreads) % (len / 8);
+        pa[u] = ((g_u32x4*)(sc.qb + (int64_t)qi[u] * len))[c16];
       }
-      if (tid < kScreenChunk) {
-        const int li = c * kScreenChunk + tid;
-        pq = -1;
-        pR = INFINITY;
-        pA = 0.0f;
-        if (li < nlist) {
-          pq = sc.lists[l0 + li];
-          const float qn = sc.qn[pq];
-          const float thr = kth_dist(s.slots + (int64_t)pq * p.k, k_of(p, s, pq)) * p.win;
-          pR = qn * one_m - thr;
-          pA = sc.c_dot * sqrtf(qn);
-        }
-      }
+      __builtin_amdgcn_sched_barrier(0);
+      // the row terms are formed when the chunk is stashed, so that nothing
+      // here waits for these loads.  A plain load of the upper half (the
+      // distance) of the k-th best key: a stale value is larger (slots only
+      // decrease), so only looser
+      pkth = ((g_float*)s.slots)[2 * ((int64_t)q0 * p.k + kq - 1) + 1];
+      pqn = qn;
+      pq = li < nlist ? q0 : -1;
     };
-    auto stash = [&](int buf) {
+    auto stash = [&](int buf) __attribute__((always_inline)) {
       char* dst = abuf + buf * Sh::a_bytes;
 #pragma unroll
       for (int u = 0; u < Sh::per_thread; ++u) {
         const int v = tid + u * kThreads;
         const int row = v / (len / 8), c16 = v % (len / 8);
-        *reinterpret_cast<uint4*>(dst + row * Sh::row_bytes + 16 * c16) = pa[u];
+        *reinterpret_cast<u32x4*>(dst + row * Sh::row_bytes + 16 * c16) = pa[u];
       }
       if (tid < kScreenChunk) {
+        const bool ok = pq >= 0;
         s_q[buf][tid] = pq;
-        s_R[buf][tid] = pR;
-        s_a[buf][tid] = pA;
+        s_R[buf][tid] = ok ? pqn * one_m - pkth * p.win : INFINITY;
+        s_a[buf][tid] = ok ? sc.c_dot * sqrtf(pqn) : 0.0f;
       }
     };
+    // Column passes over the leaf.  The query list is the same for every
+    // pass: chunk c of a pass sits in LDS buffer cur ^ (c & 1), and the last
+    // chunk's step stages chunk 0 again for the next pass (a one-chunk list
+    // simply stays in buffer cur), so only the leaf's first pass waits for
+    // its chunk 0.  Its row terms keep the k-th best of that first fetch,
+    // which only makes them looser.  Every fetch is unconditional (a step
+    // with nothing to stage fetches its own chunk again and discards it),
+    // so no loaded value has to be merged at a branch's end, which would
+    // wait for it there.
+    int cur = 0;
+    fetch(0);
+    stash(0);
+    __syncthreads();
     for (int64_t base = b; base < e; base += Sh::pass) {
       const int64_t wbase = base + 16 * NT * wv;
-      float cx[NT], sx[NT];
+      float cx[NT], sx[NT], xnv[NT];
       bf16x8 B[NT][KS];
+      // B operands, all loads unconditional (columns past the leaf read its
+      // last row; their column term C_x = +inf masks them)
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const int64_t j = wbase + 16 * t + col;
-        const bool v = j < e;
-        const float xn = v ? sc.xn[j] : 0.0f;
-        cx[t] = v ? xn * one_m : INFINITY;
-        sx[t] = sqrtf(xn);
-        const uint4* src = reinterpret_cast<const uint4*>(sc.Zb + j * len + kb);
+        const int64_t jc = j < e ? j : e - 1;
+        xnv[t] = sc.xn[jc];
+        const u32x4* src = reinterpret_cast<const u32x4*>(sc.Zb + jc * len + kb);
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-          B[t][ks] = __builtin_bit_cast(bf16x8, v ? src[4 * ks] : make_uint4(0, 0, 0, 0));
+        for (int ks = 0; ks < KS; ++ks) B[t][ks] = __builtin_bit_cast(bf16x8, src[4 * ks]);
+      }
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const bool v = wbase + 16 * t + col < e;
+        cx[t] = v ? xnv[t] * one_m : INFINITY;
+        sx[t] = sqrtf(xnv[t]);
       }
       const int ncols = (int)((e - wbase) < 16 * NT ? ((e - wbase) > 0 ? (e - wbase) : 0) : 16 * NT);
-      fetch(0);
-      stash(0);
-      __syncthreads();
+      const bool more = base + Sh::pass < e;
       for (int c = 0; c < nch; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nch) fetch(c + 1);
+        const int buf = cur ^ (c & 1);
+        // the next chunk of this pass, or chunk 0 again for the next pass
+        const int nxt = c + 1 < nch ? c + 1 : (more && nch > 1 ? 0 : -1);
+        fetch(nxt >= 0 ? nxt : c);
         const char* A = abuf + buf * Sh::a_bytes;
         const int rows_valid = min(kScreenChunk, nlist - c * kScreenChunk);
 #pragma unroll 1
@@ -2293,9 +2361,10 @@ __global__ __launch_bounds__(kScreenWaves * kWave) void k_screen(IndexDev ix, Qu
             }
           }
         }
-        if (c + 1 < nch) stash(buf ^ 1);
+        if (nxt >= 0) stash(buf ^ 1);
         __syncthreads();
       }
+      if (nch > 1) cur ^= nch & 1;  // where the next pass's chunk 0 was staged
     }
   }
   // lanes of a wave counted the same tiles: one add per wave
@@ -2533,29 +2602,32 @@ void launch_finalize(const IndexDev& ix, const QueryParams& qp, const QueryState
 
 bool screen_supported(int len) { return len == 64 || len == 128 || len == 256 || len == 512; }
 
-// The (K steps, column tiles) variants of the screen kernel built: the B
-// operands take NT x KS x 4 VGPRs, so wider tiles suit shorter series
-// (16 x 2 would spill).
-#define MESSI_SCREEN_VARIANTS(X) \
-  X(2, 1) X(2, 2) X(2, 4) X(4, 1) X(4, 2) X(4, 4) X(8, 1) X(8, 2) X(8, 4) X(16, 1)
+// The (K steps, column tiles, waves) variants of the screen kernel built:
+// the B operands take NT x KS x 4 VGPRs, so wider tiles suit shorter
+// series (16 x 2 would spill).  Every variant keeps to 256 registers, two
+// waves per SIMD, so 4-wave blocks run two to a CU.
+#define MESSI_SCREEN_VARIANTS(X)                                                                        \
+  X(2, 1, 8) X(2, 2, 8) X(2, 4, 8) X(4, 1, 8) X(4, 2, 8) X(4, 4, 8) X(8, 1, 8) X(8, 2, 8) X(8, 4, 8)   \
+  X(16, 1, 8) X(2, 4, 4) X(4, 4, 4) X(8, 2, 4) X(8, 4, 4) X(16, 1, 4)
 
-bool screen_variant(int len, int nt) {
+bool screen_variant(int len, int nt, int waves) {
   const int ks = len / 32;
-#define MESSI_SV(K, T) \
-  if (ks == K && nt == T && len == 32 * K) return true;
+#define MESSI_SV(K, T, WV) \
+  if (ks == K && nt == T && waves == WV && len == 32 * K) return true;
   MESSI_SCREEN_VARIANTS(MESSI_SV)
 #undef MESSI_SV
   return false;
 }
 
-int screen_blocks_per_cu(int len, int nt) {
+int screen_blocks_per_cu(int len, int nt, int waves) {
   int per = 0;
   hipError_t e = hipErrorInvalidValue;
-  const int th = kScreenWaves * kWave;
   const int ks = len / 32;
-#define MESSI_SO(K, T)                                                                                     \
-  if (ks == K && nt == T)                                                                                  \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<K, T>, th, ScreenShape<K, T>::lds);
+#define MESSI_SO(K, T, WV)                                                                 \
+  if (ks == K && nt == T && waves == WV) {                                                 \
+    constexpr size_t lds = ScreenShape<K, T, WV>::lds;                                     \
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_screen<K, T, WV>, WV * kWave, lds); \
+  }
   MESSI_SCREEN_VARIANTS(MESSI_SO)
 #undef MESSI_SO
   if (e != hipSuccess) {
@@ -2566,6 +2638,7 @@ int screen_blocks_per_cu(int len, int nt) {
 }
 
 int screen_nt_default(int len) { return screen_default_nt(len); }
+int screen_waves_default() { return 4; }  // two blocks per CU: one's loads overlap the other's MFMA
 
 void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, int len, uint16_t* dst,
                       float* norms, hipStream_t st) {
@@ -2576,19 +2649,18 @@ void launch_bf16_rows(const float* src, const int32_t* src_row, int64_t rows, in
 }
 
 void launch_screen(const IndexDev& ix, const QueryParams& qp, const QueryState& qs,
-                   const ScreenDev& sc, int blocks, int nt, hipStream_t st) {
+                   const ScreenDev& sc, int blocks, int nt, int waves, hipStream_t st) {
   const unsigned lb = (unsigned)((qp.n_leaves + 255) / 256);
   hipLaunchKernelGGL(k_log_approx, dim3(qp.nq), dim3(256), 0, st, qp, qs);
   hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, false);
   hipLaunchKernelGGL(k_list_scan, dim3(1), dim3(1024), 0, st, qp, sc);
   hipLaunchKernelGGL(k_leaf_lists, dim3(lb), dim3(256), 0, st, qp, qs, sc, true);
-  const dim3 th(kScreenWaves * kWave);
   const int ks = qp.len / 32;
-#define MESSI_SL(K, T)                                                               \
-  if (ks == K && nt == T) {                                                          \
-    constexpr size_t lds = ScreenShape<K, T>::lds;                                   \
-    hipLaunchKernelGGL((k_screen<K, T>), dim3(blocks), th, lds, st, ix, qp, qs, sc); \
-    return;                                                                          \
+#define MESSI_SL(K, T, WV)                                                                              \
+  if (ks == K && nt == T && waves == WV) {                                                              \
+    constexpr size_t lds = ScreenShape<K, T, WV>::lds;                                                  \
+    hipLaunchKernelGGL((k_screen<K, T, WV>), dim3(blocks), dim3(WV * kWave), lds, st, ix, qp, qs, sc); \
+    return;                                                                                             \
   }
   MESSI_SCREEN_VARIANTS(MESSI_SL)
 #undef MESSI_SL

@@ -245,3 +245,26 @@ def test_ed_batch_larger_than_the_process_grid(pm, index, data):
     oids, od2 = oracle.knn(data, qs, 5)
     for i in range(nq):
         _check(ids[i:i + 1, :ks[i]], d[i:i + 1, :ks[i]], oids[i:i + 1, :ks[i]], np.sqrt(od2[i:i + 1, :ks[i]]))
+
+
+def test_screen_lists_longer_than_the_lds_copy(pm):
+    """A screened batch of 2,300 queries over 4,000 series in leaves of up
+    to 400: most leaves are kept by more queries than the screen stages in
+    LDS (2,048), so their lists are read from memory.  Rows equal the
+    unscreened batch's and the oracle's."""
+    raw = synth.randomwalk(4000, LEN, seed=53)
+    idx = pm.messi_build(torch.from_numpy(raw).cuda(), 16, 256, 400)
+    nq = 2300
+    qs = np.concatenate([synth.noisy_queries(nq // 2, 4000, LEN, data_seed=53)[0],
+                         synth.random_queries(nq - nq // 2, LEN, seed=54)])
+    ks = [1 if i % 3 else 4 for i in range(nq)]
+    qt = torch.from_numpy(qs).cuda()
+    plain = [_host(t) for t in pm.messi_query_batch(idx, qt, ks, 0, 0, kmax=4)]
+    ids, d, st = pm.messi_query_batch(idx, qt, ks, 0, 0, kmax=4, flags=pm.MESSI_SCREEN_BF16, stats=True)
+    assert st["screened"] > 0
+    assert np.array_equal(_host(ids), plain[0]) and np.array_equal(_host(d), plain[1])
+    oids, od2 = oracle.knn(raw, qs, 4)
+    for i in range(0, nq, 7):
+        _check(plain[0][i:i + 1, :ks[i]], plain[1][i:i + 1, :ks[i]], oids[i:i + 1, :ks[i]],
+               np.sqrt(od2[i:i + 1, :ks[i]]))
+    idx.free()
