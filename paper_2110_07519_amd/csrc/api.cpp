@@ -454,7 +454,10 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
     norm2 = tmp.alloc<unsigned int>(1);
     HIP_OR_THROW(hipMemsetAsync(norm2, 0, sizeof(unsigned int), st));
   }
-  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, hist, norm2, st, ix->n_cus);
+  uint16_t* keys = tmp.alloc<uint16_t>(n);
+  launch_summarize(series, n, len, w, cb, spw, ix->bp, words_id, musd, keys, norm2, st, ix->n_cus);
+  launch_check();
+  launch_key_hist(keys, n, nkeys, hist, ix->n_cus, st);
   launch_check();
   {
     // z-normalised rows have |z|^2 = len up to a relative len u; a raw
@@ -478,7 +481,7 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   d.W1 = tmp.alloc<uint4>(n);
   d.I0 = tmp.alloc<int32_t>(n);
   d.I1 = tmp.alloc<int32_t>(n);
-  launch_root_scatter(words_id, n, w, cb, key_cursor, d.W0, d.I0, st);
+  launch_root_scatter(words_id, keys, n, nkeys, key_cursor, d.W0, d.I0, ix->n_cus, st);
   launch_check();
 
   // node and leaf tables

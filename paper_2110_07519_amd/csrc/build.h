@@ -52,13 +52,17 @@ struct BuildDev {
   int32_t* I1;
 };
 
+// keys: [n] root key of each series (its w symbols' top bits)
 void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
-                      const float* bp, uint4* words, float2* musd, unsigned int* hist,
+                      const float* bp, uint4* words, float2* musd, uint16_t* keys,
                       unsigned int* norm2_max, hipStream_t st, int n_cus);
+// hist must be zero on entry
+void launch_key_hist(const uint16_t* keys, int64_t n, int nkeys, unsigned int* hist, int n_cus,
+                     hipStream_t st);
 void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
                       unsigned long long* cursor, hipStream_t st);
-void launch_root_scatter(const uint4* words, int64_t n, int w, int card_bits,
-                         unsigned long long* cursor, uint4* W0, int32_t* I0, hipStream_t st);
+void launch_root_scatter(const uint4* words, const uint16_t* keys, int64_t n, int nkeys,
+                         unsigned long long* cursor, uint4* W0, int32_t* I0, int n_cus, hipStream_t st);
 void launch_roots(const int64_t* begin, int nkeys, int w, int leaf_size, const BuildDev& d,
                   hipStream_t st);
 void launch_round_count(const Chunk* chunks, int n_chunks, const BuildDev& d, int w,

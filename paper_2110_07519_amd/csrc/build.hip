@@ -29,7 +29,7 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
                                                       const float* __restrict__ bp_g,
                                                       uint4* __restrict__ words,
                                                       float2* __restrict__ musd,
-                                                      unsigned int* __restrict__ hist,
+                                                      uint16_t* __restrict__ keys,
                                                       unsigned int* __restrict__ norm2_max) {
   extern __shared__ float smem[];
   float* bp = smem;               // card + 1 entries (bp[0] = -inf, bp[card] = +inf)
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
   const int64_t id = first + lane;
   words[id] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
   musd[id] = make_float2(mu, flat ? 0.0f : sd);
-  atomicAdd(&hist[key], 1u);
+  keys[id] = (uint16_t)key;
 }
 
 // Summaries for 16 segments and len a multiple of 64 up to 256 (the usual
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
                                                      int card_bits, const float* __restrict__ bp_g,
                                                      uint8_t* __restrict__ words,
                                                      float2* __restrict__ musd,
-                                                     unsigned int* __restrict__ hist,
+                                                     uint16_t* __restrict__ keys,
                                                      unsigned int* __restrict__ norm2_max) {
   __shared__ float bp[257];
   const int card = 1 << card_bits;
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
         const uint32_t bits16 = (uint32_t)(msb >> (lane & 48)) & 0xffffu;  // bit g = segment g
         const uint32_t key = __brev(bits16) >> 16;                         // segment 0 -> bit 15
         musd[id] = make_float2(mu, flat ? 0.0f : sd);
-        atomicAdd(&hist[key], 1u);
+        keys[id] = (uint16_t)key;
       }
     }
   }
@@ -227,9 +227,37 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
 }
 
 // ---------------------------------------------------------------------------
-// (2) Root grouping: exclusive scan of the key histogram (one block), then a
-// scatter of (word, id) into the key's range.  Order inside a range is the
-// atomics' order; leaves are re-sorted by id at the end.
+// (2) Root grouping: a histogram of the root keys, its exclusive scan (one
+// block), then a scatter of (word, id) into each key's range.
+//
+// Root keys are far from uniform (z-normalised random walks share a few
+// sign patterns of their segment means), so one device atomic per series
+// on its key's counter would queue thousands of waves at the few memory
+// channels holding the hot keys.  Both passes count in LDS instead: block
+// (x, r) covers the keys of range r (kKeyRange of them) over the x-th part
+// of the series, and adds each nonzero count to memory once.  The scatter
+// reserves a block's run of positions per key with that one atomic and
+// places its series inside the run with LDS atomics; order inside a key's
+// range is the atomics' order (leaves are sorted by id at the end).
+
+constexpr int kKeyRange = 16384;  // keys per block's LDS counters (64 KB)
+
+__global__ __launch_bounds__(1024) void k_key_hist(const uint16_t* __restrict__ keys, int64_t n,
+                                                   int nkeys, unsigned int* __restrict__ hist) {
+  __shared__ unsigned int cnt[kKeyRange];
+  const int r0 = blockIdx.y * kKeyRange;
+  const int rn = min(kKeyRange, nkeys - r0);
+  for (int j = threadIdx.x; j < rn; j += blockDim.x) cnt[j] = 0;
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const unsigned k = (unsigned)keys[i] - (unsigned)r0;
+    if (k < (unsigned)rn) atomicAdd(&cnt[k], 1u);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < rn; j += blockDim.x)
+    if (cnt[j]) atomicAdd(&hist[r0 + j], cnt[j]);
+}
 
 __global__ __launch_bounds__(1024) void k_scan_hist(const unsigned int* __restrict__ hist, int nkeys,
                                                      int64_t* __restrict__ begin,
@@ -257,21 +285,41 @@ __global__ __launch_bounds__(1024) void k_scan_hist(const unsigned int* __restri
   if (threadIdx.x == 1023) begin[nkeys] = part[1023];
 }
 
-__global__ void k_root_scatter(const uint4* __restrict__ words, int64_t n, int w, int card_bits,
-                               unsigned long long* __restrict__ cursor, uint4* __restrict__ W0,
-                               int32_t* __restrict__ I0) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const uint4 wd = words[i];
-  const uint32_t part[4] = {wd.x, wd.y, wd.z, wd.w};
-  uint32_t key = 0;
-  for (int s = 0; s < w; ++s) {
-    const uint32_t sym = (part[s >> 2] >> (8 * (s & 3))) & 0xffu;
-    key = (key << 1) | (sym >> (card_bits - 1));
+// Block (x, r): the series of part x with a key in range r.  First their
+// counts per key in LDS; then one device atomic per nonzero key reserves
+// the block's run in that key's range; then each series takes its place in
+// the run with an LDS atomic.  Positions fit 32 bits (n < 2^31).
+__global__ __launch_bounds__(1024) void k_root_scatter(const uint4* __restrict__ words,
+                                                       const uint16_t* __restrict__ keys, int64_t n,
+                                                       int nkeys, unsigned long long* __restrict__ cursor,
+                                                       uint4* __restrict__ W0, int32_t* __restrict__ I0) {
+  __shared__ unsigned int cnt[kKeyRange], base[kKeyRange];
+  const int r0 = blockIdx.y * kKeyRange;
+  const int rn = min(kKeyRange, nkeys - r0);
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x * per;
+  const int64_t c1 = min(n, c0 + per);
+  for (int j = threadIdx.x; j < rn; j += blockDim.x) cnt[j] = 0;
+  __syncthreads();
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    const unsigned k = (unsigned)keys[i] - (unsigned)r0;
+    if (k < (unsigned)rn) atomicAdd(&cnt[k], 1u);
   }
-  const unsigned long long pos = atomicAdd(&cursor[key], 1ull);
-  W0[pos] = wd;
-  I0[pos] = (int32_t)i;
+  __syncthreads();
+  for (int j = threadIdx.x; j < rn; j += blockDim.x) {
+    const unsigned c = cnt[j];
+    if (c) base[j] = (unsigned)atomicAdd(&cursor[r0 + j], (unsigned long long)c);
+    cnt[j] = 0;
+  }
+  __syncthreads();
+  for (int64_t i = c0 + threadIdx.x; i < c1; i += blockDim.x) {
+    const unsigned k = (unsigned)keys[i] - (unsigned)r0;
+    if (k < (unsigned)rn) {
+      const unsigned pos = base[k] + atomicAdd(&cnt[k], 1u);
+      W0[pos] = words[i];
+      I0[pos] = (int32_t)i;
+    }
+  }
 }
 
 __device__ __forceinline__ int append(int* counter, int cap, int* overflow) {
@@ -693,7 +741,7 @@ __global__ void k_make_tree(const NodeDev* __restrict__ nodes, int n_nodes, int 
 // Host-side launchers.
 
 void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits, int spw,
-                      const float* bp, uint4* words, float2* musd, unsigned int* hist,
+                      const float* bp, uint4* words, float2* musd, uint16_t* keys,
                       unsigned int* norm2_max, hipStream_t st, int n_cus) {
   // the register path reads float4s: the rows must start 16-byte aligned
   if (w == 16 && len % 64 == 0 && len <= 256 && (reinterpret_cast<uintptr_t>(raw) & 15) == 0) {
@@ -702,17 +750,23 @@ void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits
     const unsigned blocks = (unsigned)std::min<int64_t>(want, (int64_t)n_cus * 32);
     uint8_t* wb = reinterpret_cast<uint8_t*>(words);
     switch (len / 16) {
-      case 4: hipLaunchKernelGGL(k_summarize16<4>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
-      case 8: hipLaunchKernelGGL(k_summarize16<8>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
-      case 12: hipLaunchKernelGGL(k_summarize16<12>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
-      default: hipLaunchKernelGGL(k_summarize16<16>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, hist, norm2_max); break;
+      case 4: hipLaunchKernelGGL(k_summarize16<4>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, keys, norm2_max); break;
+      case 8: hipLaunchKernelGGL(k_summarize16<8>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, keys, norm2_max); break;
+      case 12: hipLaunchKernelGGL(k_summarize16<12>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, keys, norm2_max); break;
+      default: hipLaunchKernelGGL(k_summarize16<16>, dim3(blocks), dim3(256), 0, st, raw, n, card_bits, bp, wb, musd, keys, norm2_max); break;
     }
     return;
   }
   const int64_t blocks = (n + spw - 1) / spw;
   const size_t lds = (257 + (size_t)spw * len) * sizeof(float);
   hipLaunchKernelGGL(k_summarize, dim3((unsigned)blocks), dim3(kWave), lds, st, raw, n, len, w,
-                     card_bits, spw, bp, words, musd, hist, norm2_max);
+                     card_bits, spw, bp, words, musd, keys, norm2_max);
+}
+
+void launch_key_hist(const uint16_t* keys, int64_t n, int nkeys, unsigned int* hist, int n_cus,
+                     hipStream_t st) {
+  const dim3 g((unsigned)std::max(1, n_cus), (unsigned)((nkeys + kKeyRange - 1) / kKeyRange));
+  hipLaunchKernelGGL(k_key_hist, g, dim3(1024), 0, st, keys, n, nkeys, hist);
 }
 
 void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
@@ -720,10 +774,10 @@ void launch_scan_hist(const unsigned int* hist, int nkeys, int64_t* begin,
   hipLaunchKernelGGL(k_scan_hist, dim3(1), dim3(1024), 0, st, hist, nkeys, begin, cursor);
 }
 
-void launch_root_scatter(const uint4* words, int64_t n, int w, int card_bits,
-                         unsigned long long* cursor, uint4* W0, int32_t* I0, hipStream_t st) {
-  hipLaunchKernelGGL(k_root_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, words, n,
-                     w, card_bits, cursor, W0, I0);
+void launch_root_scatter(const uint4* words, const uint16_t* keys, int64_t n, int nkeys,
+                         unsigned long long* cursor, uint4* W0, int32_t* I0, int n_cus, hipStream_t st) {
+  const dim3 g((unsigned)std::max(1, n_cus), (unsigned)((nkeys + kKeyRange - 1) / kKeyRange));
+  hipLaunchKernelGGL(k_root_scatter, g, dim3(1024), 0, st, words, keys, n, nkeys, cursor, W0, I0);
 }
 
 void launch_roots(const int64_t* begin, int nkeys, int w, int leaf_size, const BuildDev& d,
