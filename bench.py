@@ -9,9 +9,12 @@ Euclidean distance).  A step is one query through the whole hot path
 (preparation, approximate search, leaf bounds, leaf processing with series
 bounds and refinement, FP64 near-tie recheck).  Also reported: index build
 time, per-phase device times, the roofline of the dominant kernel, the CPU
-oracle timed on a sample, and exact 1-NN DTW (radius 25 = 10% of 256) over
-the first 10,000,000 series with noisy dataset copies as queries (noise
-0.01, 0.1, 1.0 times the series' standard deviation, round robin).
+oracle timed on a sample, exact 1-NN DTW (radius 25 = 10% of 256) over the
+first 10,000,000 series and over the whole collection with noisy dataset
+copies as queries (noise 0.01, 0.1, 1.0 times the series' standard
+deviation, round robin), and batches of 1,024 noisy copies through the
+plain path, the BF16 screen and graph replay at 100M x 256 and, built in
+place, at 200M x 128.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -511,6 +514,8 @@ def main():
     ap.add_argument("--dtw-n", type=int, default=10_000_000)
     ap.add_argument("--dtw-queries", type=int, default=100)
     ap.add_argument("--window", type=int, default=25)
+    ap.add_argument("--dtw-full-queries", type=int, default=30,
+                    help="DTW queries on the full collection (noisy copies, one at a time)")
     ap.add_argument("--batch", type=int, default=1024,
                     help="queries of the batched run (noisy copies, k alternating 1 and 10)")
     ap.add_argument("--batch-reps", type=int, default=2)
@@ -639,6 +644,26 @@ def main():
         dtw["filters"] = dtw_filters(pm, didx, dt[3:3 + dk], args.window)
         didx.free()
 
+    dtw_full = None
+    if args.dtw_full_queries > 0:
+        fq, _, _ = synth.noisy_queries(args.dtw_full_queries + 2, n, length, j0=200_000)
+        ft = torch.from_numpy(fq).cuda()
+        run_queries(pm, idx, ft[:2], 1, pm.MESSI_DTW, args.window)
+        log(f"timing {args.dtw_full_queries} DTW queries (r={args.window}) over all {n} series")
+        fwall, flat = run_queries(pm, idx, ft[2:], 1, pm.MESSI_DTW, args.window, budget_s=60)
+        fk = len(flat)
+        fst = query_stats(pm, idx, ft[2:2 + fk], 1, pm.MESSI_DTW, args.window)
+        dtw_full = {"metric": "exact 1-NN DTW queries/s (one query at a time)", "value": fk / fwall,
+                    "unit": "queries/s", "queries": fk, "window": args.window,
+                    "workload": f"all {n} random walks, noisy dataset copies (noise 0.01/0.1/1.0 x "
+                                "series sd, round robin)",
+                    "p50_ms": float(np.percentile(flat, 50) * 1e3),
+                    "p99_ms": float(np.percentile(flat, 99) * 1e3),
+                    "phases_us": {p: fst[f"us_{p}"] / fk for p in PHASES},
+                    "refined_per_query": fst["refined"] / fk, "lb_keogh_per_query": fst["lb_keogh"] / fk}
+        log(f"DTW at {n}: {dtw_full['value']:.2f} q/s, p50 {dtw_full['p50_ms']:.2f} ms, "
+            f"p99 {dtw_full['p99_ms']:.2f} ms")
+
     batched = None
     if args.batch > 0:
         batched = {f"{n // 1_000_000}Mx{length}": run_c4(pm, idx, n, length, args.batch, args.batch_reps)}
@@ -714,6 +739,7 @@ def main():
                              "the search needs once the answer is known); the kernel did "
                              "bytes_per_launch_running_kth with its running k-th best"},
         "dtw": dtw,
+        "dtw_full": dtw_full,
         "batched": batched,
         "classification": classification,
         "serving": serving,

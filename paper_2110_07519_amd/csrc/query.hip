@@ -2307,7 +2307,10 @@ void k_screen(IndexDev ix, QueryParams p, QueryState s, ScreenDev sc) {
         const char* A = abuf + buf * Sh::a_bytes;
         const int rows_valid = min(kScreenChunk, nlist - c * kScreenChunk);
 #pragma unroll 1
-        for (int qt = 0; qt < kScreenChunk / 16 && 16 * qt < rows_valid; ++qt) {
+        // (a wave whose columns all lie past the leaf, in a leaf's last
+        // pass, has nothing to screen: the other block on the CU gets its
+        // share of the matrix cores meanwhile)
+        for (int qt = 0; ncols > 0 && qt < kScreenChunk / 16 && 16 * qt < rows_valid; ++qt) {
           f32x4 acc[NT];
 #pragma unroll
           for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};

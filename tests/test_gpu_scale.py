@@ -8,8 +8,10 @@
   0.1 / 1.0, k alternating 1 and 10) through the BF16 screen with tuned
   knobs and graph replay: every row equals the plain batch's and a single
   call's, and 32 rows spread over the batch are checked by the oracle.
-  One host scan of the whole collection (regenerated in chunks by the
-  seeded generator) answers every oracle query.
+  Two noisy copies (noise 0.01 and 0.1) answered under DTW (r = 25) over
+  the whole collection.  One host scan of the whole collection
+  (regenerated in chunks by the seeded generator) answers every oracle
+  query (DTW through the LB_Keogh-filtered scan).
 * Exact 1-NN DTW (radius 25) over 10,000,000 random walks of length 256:
   nine noisy dataset copies (noise 0.01, 0.1 and 1.0), each checked
   against the oracle's LB_Keogh-filtered scan (equal to the plain scan,
@@ -139,11 +141,19 @@ def test_ed_100m_one_query_at_a_time_and_batch(pm):
         sid, sd = pm.messi_query(idx, qbt[j:j + 1], kb[j])
         assert np.array_equal(bids[j, :kb[j]], sid.cpu().numpy()[0]) and np.array_equal(bd[j, :kb[j]], sd.cpu().numpy()[0])
     cq, cks, cids4, cd4, rows = _c4_batch(pm, idx, n, length)
+    # DTW (r = 25) over the whole collection: the noise 0.01 and 0.1 copies
+    dq = synth.noisy_queries(2, n, length, j0=200_000)[0]
+    dqt = torch.from_numpy(dq).cuda()
+    dres = [pm.messi_query(idx, dqt[j:j + 1], 1, pm.MESSI_DTW, 25) for j in range(2)]
+    dids = np.concatenate([o[0].cpu().numpy() for o in dres])
+    dd = np.concatenate([o[1].cpu().numpy() for o in dres])
     idx.free()
     _say(f"ED: GPU answers ready; oracle scan of the whole collection ({len(qs)} + {len(rows)} queries)")
     st = oracle.KnnState(qs, 10)
     st4 = oracle.KnnState(cq[rows], 10)
-    _host_scan([st, st4], n, length)
+    std = oracle.KnnState(dq, 1, oracle.DTW, 25, lb_keogh=True)
+    _host_scan([st, st4, std], n, length)
+    _check(dids, dd, std.ids, std.d2)
     _check(ids1, d1, st.ids[:, :1], st.d2[:, :1])
     _check(ids10, d10, st.ids, st.d2)
     for t, i in enumerate(rows):
