@@ -124,26 +124,30 @@ __global__ __launch_bounds__(kWave) void k_summarize(const float* __restrict__ r
 }
 
 // Summaries for 16 segments and len a multiple of 64 up to 256 (the usual
-// shapes): 16 lanes per series, lane g holding the len/16 points of segment
-// g in registers, four series per wave, no LDS staging.  The two sequential
-// sums of the z-normalisation keep their index order by passing the running
-// sum from lane g to lane g+1 (a DPP row shift) after lane g has added its
-// points; the point-wise work (squares, z, segment sums) runs on all lanes.
+// shapes): 4 lanes per series, lane j of a quad holding points
+// j len/4 .. (j+1) len/4 - 1 (segments 4j .. 4j+3) in registers, sixteen
+// series per wave, no LDS staging.  The two sequential sums of the
+// z-normalisation keep their index order by passing the running sum from
+// lane j to lane j+1 of the quad (a DPP quad permutation) after lane j has
+// added its points: each sum takes len wave-instructions for sixteen
+// series.  The point-wise work (squares, z, segment sums) runs on all lanes.
 
-template <int C>
-__device__ __forceinline__ float chain_sum16(const float (&v)[C], int g) {
+template <int Q>
+__device__ __forceinline__ float chain_sum4(const float (&v)[Q], int j) {
   float acc = 0.0f;
 #pragma unroll
-  for (int stage = 0; stage < 16; ++stage) {
-    if (g == stage) {
+  for (int stage = 0; stage < 4; ++stage) {
+    if (j == stage) {
 #pragma unroll
-      for (int i = 0; i < C; ++i) acc = acc + v[i];
+      for (int i = 0; i < Q; ++i) acc = acc + v[i];
     }
-    if (stage < 15)  // row_shr:1 - lane g receives lane g-1's sum
-      acc = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(acc), __float_as_int(acc),
-                                                       0x111, 0xf, 0xf, false));
+    if (stage < 3)  // quad_perm [0, 0, 1, 2]: lane j receives lane j-1's sum
+      acc = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(acc), __float_as_int(acc), 0x90,
+                                                       0xf, 0xf, false));
   }
-  return __shfl(acc, (int)(threadIdx.x & 48) | 15);  // lane 15 of the row holds the total
+  // quad_perm [3, 3, 3, 3]: every lane of the quad takes the total
+  return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(acc), __float_as_int(acc), 0xff, 0xf,
+                                                    0xf, false));
 }
 
 template <int C>
@@ -157,64 +161,70 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
   const int card = 1 << card_bits;
   for (int j = threadIdx.x; j <= card; j += blockDim.x) bp[j] = bp_g[j];
   __syncthreads();
-  constexpr int len = 16 * C;
+  constexpr int len = 16 * C;  // C points per segment
+  constexpr int Q = 4 * C;     // points per lane: four segments
   const int lane = threadIdx.x & 63;
-  const int g = lane & 15;
+  const int j = lane & 3;      // quarter of the row
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   const float flen = (float)len;
   const float fm = (float)C;
   const bool as_given = norm2_max != nullptr;  // mu = 0, sd = 1: z = x exactly
   float n2 = 0.0f;  // largest squared row norm seen (as-given rows)
-  for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); grp * 4 < n;
+  for (int64_t grp = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); grp * 16 < n;
        grp += waves) {
-    const int64_t id = grp * 4 + (lane >> 4);
+    const int64_t id = grp * 16 + (lane >> 2);
     const bool valid = id < n;
-    float v[C];
-    if (valid) {
-      const float4* src = reinterpret_cast<const float4*>(raw + id * len + g * C);
+    float v[Q];
+    {
+      const float4* src = reinterpret_cast<const float4*>(raw + (valid ? id : 0) * len + j * Q);
 #pragma unroll
-      for (int i = 0; i < C / 4; ++i) {
+      for (int i = 0; i < Q / 4; ++i) {
         const float4 t = src[i];
         v[4 * i] = t.x;
         v[4 * i + 1] = t.y;
         v[4 * i + 2] = t.z;
         v[4 * i + 3] = t.w;
       }
-    } else {
-#pragma unroll
-      for (int i = 0; i < C; ++i) v[i] = 0.0f;
     }
-    const float mu = as_given ? 0.0f : __fdiv_rn(chain_sum16<C>(v, g), flen);
-    float sq[C];
+    const float mu = as_given ? 0.0f : __fdiv_rn(chain_sum4<Q>(v, j), flen);
+    float sq[Q];
 #pragma unroll
-    for (int i = 0; i < C; ++i) {
+    for (int i = 0; i < Q; ++i) {
       const float d = v[i] - mu;
       sq[i] = d * d;
     }
-    const float ss = chain_sum16<C>(sq, g);
+    const float ss = chain_sum4<Q>(sq, j);
     if (valid) n2 = fmaxf(n2, ss);
     const float sd = as_given ? 1.0f : sqrtf(__fdiv_rn(ss, flen));
     const bool flat = !(sd > 0.0f);
-    float a = 0.0f;
-    if (!flat) {
+    uint32_t part = 0, nib = 0;
 #pragma unroll
-      for (int i = 0; i < C; ++i) a = a + __fdiv_rn(v[i] - mu, sd);
+    for (int sg = 0; sg < 4; ++sg) {
+      float a = 0.0f;
+      if (!flat) {
+#pragma unroll
+        for (int i = 0; i < C; ++i) a = a + __fdiv_rn(v[sg * C + i] - mu, sd);
+      }
+      const float pv = __fdiv_rn(a, fm);
+      int lo = 0, hi = card - 1;
+      for (int step = 0; step < card_bits; ++step) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (bp[mid] <= pv)
+          lo = mid;
+        else
+          hi = mid - 1;
+      }
+      part |= (uint32_t)lo << (8 * sg);
+      nib = (nib << 1) | ((uint32_t)lo >> (card_bits - 1));  // segment 4j + sg, most significant first
     }
-    const float p = __fdiv_rn(a, fm);
-    int lo = 0, hi = card - 1;
-    for (int step = 0; step < card_bits; ++step) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (bp[mid] <= p)
-        lo = mid;
-      else
-        hi = mid - 1;
-    }
-    const unsigned long long msb = __ballot((lo >> (card_bits - 1)) & 1);
+    // root key: segment 0 is the most significant bit, so quarter j's four
+    // bits sit at 12 - 4j; the quad's nibbles combined in every lane
+    uint32_t key = nib << (12 - 4 * j);
+    key |= (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, 0xb1, 0xf, 0xf, false);  // [1,0,3,2]
+    key |= (uint32_t)__builtin_amdgcn_update_dpp((int)key, (int)key, 0x4e, 0xf, 0xf, false);  // [2,3,0,1]
     if (valid) {
-      words[id * 16 + g] = (uint8_t)lo;
-      if (g == 0) {
-        const uint32_t bits16 = (uint32_t)(msb >> (lane & 48)) & 0xffffu;  // bit g = segment g
-        const uint32_t key = __brev(bits16) >> 16;                         // segment 0 -> bit 15
+      reinterpret_cast<uint32_t*>(words + id * 16)[j] = part;
+      if (j == 0) {
         musd[id] = make_float2(mu, flat ? 0.0f : sd);
         keys[id] = (uint16_t)key;
       }
@@ -656,6 +666,12 @@ __global__ __launch_bounds__(1024) void k_leaf_sort_global(int64_t b, int cnt, i
 // (5) Leaf-ordered store: z = (x - mu) / sd per point (the same rounding as
 // in the summary pass), one wave per row, float4 per lane.
 
+// Leaf-ordered store: position p takes row perm[p], z-normalised.  A wave
+// moves kGatherRows rows per step, every load of the step issued before
+// any is used (the ids, then their (mu, sd), then the rows), so four rows'
+// chains are in flight per wave instead of one.
+constexpr int kGatherRows = 4;
+
 __global__ __launch_bounds__(256) void k_gather_store(const float* __restrict__ raw, int64_t n, int len,
                                                        const int32_t* __restrict__ perm,
                                                        const float2* __restrict__ musd,
@@ -665,26 +681,43 @@ __global__ __launch_bounds__(256) void k_gather_store(const float* __restrict__ 
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t p = wave; p < n; p += nwaves) {
-    const int32_t id = perm[p];
-    const float2 ms = musd[id];
-    const float* __restrict__ x = raw + (int64_t)id * len;
-    float* __restrict__ z = Z + p * (int64_t)len;
-    const bool flat = !(ms.y > 0.0f);
+  for (int64_t p0 = wave * kGatherRows; p0 < n; p0 += nwaves * kGatherRows) {
+    int32_t id[kGatherRows];
+    float2 ms[kGatherRows];
+#pragma unroll
+    for (int r = 0; r < kGatherRows; ++r) id[r] = perm[p0 + r < n ? p0 + r : p0];  // past n: a valid row, not stored
+#pragma unroll
+    for (int r = 0; r < kGatherRows; ++r) ms[r] = musd[id[r]];
     if ((len & 3) == 0) {
       for (int t = 4 * lane; t < len; t += 4 * kWave) {
-        const float4 v = *reinterpret_cast<const float4*>(x + t);
-        float4 o;
-        o.x = flat ? 0.0f : __fdiv_rn(v.x - ms.x, ms.y);
-        o.y = flat ? 0.0f : __fdiv_rn(v.y - ms.x, ms.y);
-        o.z = flat ? 0.0f : __fdiv_rn(v.z - ms.x, ms.y);
-        o.w = flat ? 0.0f : __fdiv_rn(v.w - ms.x, ms.y);
-        *reinterpret_cast<float4*>(z + t) = o;
+        float4 v[kGatherRows];
+#pragma unroll
+        for (int r = 0; r < kGatherRows; ++r) v[r] = *reinterpret_cast<const float4*>(raw + (int64_t)id[r] * len + t);
+#pragma unroll
+        for (int r = 0; r < kGatherRows; ++r) {
+          if (p0 + r >= n) continue;
+          const bool flat = !(ms[r].y > 0.0f);
+          float4 o;
+          o.x = flat ? 0.0f : __fdiv_rn(v[r].x - ms[r].x, ms[r].y);
+          o.y = flat ? 0.0f : __fdiv_rn(v[r].y - ms[r].x, ms[r].y);
+          o.z = flat ? 0.0f : __fdiv_rn(v[r].z - ms[r].x, ms[r].y);
+          o.w = flat ? 0.0f : __fdiv_rn(v[r].w - ms[r].x, ms[r].y);
+          *reinterpret_cast<float4*>(Z + (p0 + r) * (int64_t)len + t) = o;
+        }
       }
     } else {
-      for (int t = lane; t < len; t += kWave) z[t] = flat ? 0.0f : __fdiv_rn(x[t] - ms.x, ms.y);
+      for (int r = 0; r < kGatherRows; ++r) {
+        if (p0 + r >= n) continue;
+        const bool flat = !(ms[r].y > 0.0f);
+        const float* __restrict__ x = raw + (int64_t)id[r] * len;
+        float* __restrict__ z = Z + (p0 + r) * (int64_t)len;
+        for (int t = lane; t < len; t += kWave) z[t] = flat ? 0.0f : __fdiv_rn(x[t] - ms[r].x, ms[r].y);
+      }
     }
-    if (lane == 0) words_sorted[p] = words[id];
+    int32_t mine = id[0];  // lane r < kGatherRows moves row r's word
+#pragma unroll
+    for (int r = 1; r < kGatherRows; ++r) mine = lane == r ? id[r] : mine;
+    if (lane < kGatherRows && p0 + lane < n) words_sorted[p0 + lane] = words[mine];
   }
 }
 
@@ -745,7 +778,7 @@ void launch_summarize(const float* raw, int64_t n, int len, int w, int card_bits
                       unsigned int* norm2_max, hipStream_t st, int n_cus) {
   // the register path reads float4s: the rows must start 16-byte aligned
   if (w == 16 && len % 64 == 0 && len <= 256 && (reinterpret_cast<uintptr_t>(raw) & 15) == 0) {
-    const int64_t groups = (n + 3) / 4;  // 4 series per wave, 4 waves per block
+    const int64_t groups = (n + 15) / 16;  // 16 series per wave, 4 waves per block
     const int64_t want = (groups + 3) / 4;
     const unsigned blocks = (unsigned)std::min<int64_t>(want, (int64_t)n_cus * 32);
     uint8_t* wb = reinterpret_cast<uint8_t*>(words);
@@ -835,7 +868,7 @@ void launch_make_tree(const NodeDev* nodes, int n_nodes, int card_bits, int4* tr
 void launch_gather_store(const float* raw, int64_t n, int len, const int32_t* perm,
                          const float2* musd, const uint4* words, float* Z, uint4* words_sorted,
                          hipStream_t st) {
-  int64_t blocks = (n + 3) / 4;
+  int64_t blocks = (n + 4 * kGatherRows - 1) / (4 * kGatherRows);
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_gather_store, dim3((unsigned)blocks), dim3(256), 0, st, raw, n, len, perm,
                      musd, words, Z, words_sorted);
