@@ -95,6 +95,33 @@ struct DevMem {
   ~DevMem() { clear(); }
 };
 
+// Temporaries carved from one allocation: one hipMalloc and one hipFree for
+// all of them.  A request past the reserved end gets an allocation of its
+// own.
+struct Slab {
+  DevMem mem;
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+  template <typename T>
+  static size_t bytes_for(size_t count) {
+    return (std::max<size_t>(count, 1) * sizeof(T) + 255) & ~(size_t)255;
+  }
+  void reserve(size_t b) {
+    base = mem.alloc<char>(b);
+    cap = b;
+  }
+  template <typename T>
+  T* alloc(size_t count) {
+    const size_t b = bytes_for<T>(count);
+    if (base && used + b <= cap) {
+      T* p = reinterpret_cast<T*>(base + used);
+      used += b;
+      return p;
+    }
+    return mem.alloc<T>(count);
+  }
+};
+
 bool is_device_ptr(const void* p) {
   if (!p) return false;
   hipPointerAttribute_t a;
@@ -424,7 +451,22 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   const int len = ix->len, w = ix->w, cb = ix->card_bits, card = 1 << cb;
   const int nkeys = 1 << w;
   hipStream_t st = ix->ctx.stream;
-  DevMem tmp;
+  const int round_cap = (int)std::min<int64_t>(n / (ix->leaf_size + 1) + 1, (int64_t)node_cap);
+  const int chunk_cap = (int)std::min<int64_t>(n / kChunk + round_cap + 1, (int64_t)1 << 30);
+  Slab tmp;
+  {
+    size_t b = 0;
+    b += 3 * Slab::bytes_for<uint4>(n);  // words_id, W0, W1
+    b += Slab::bytes_for<float2>(n) + Slab::bytes_for<uint16_t>(n) + 2 * Slab::bytes_for<int32_t>(n);
+    b += Slab::bytes_for<unsigned int>(nkeys) + Slab::bytes_for<unsigned int>(1);
+    b += Slab::bytes_for<int64_t>(nkeys + 1) + Slab::bytes_for<unsigned long long>(nkeys);
+    b += 2 * Slab::bytes_for<int>(leaf_cap) + 3 * Slab::bytes_for<int>(round_cap);
+    b += Slab::bytes_for<int>(8) + Slab::bytes_for<int>(4);
+    b += Slab::bytes_for<int>((size_t)round_cap * kMaxSeg);
+    b += Slab::bytes_for<unsigned long long>((size_t)round_cap * 2);
+    b += Slab::bytes_for<Chunk>(chunk_cap);
+    tmp.reserve(b);
+  }
 
   // breakpoints with open ends
   std::vector<float> bph(card + 1);
@@ -490,49 +532,53 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   d.leaves = tmp.alloc<int>(leaf_cap);
   d.leaf_cap = leaf_cap;
   d.root_node = ix->mem.alloc<int>(nkeys);
-  const int round_cap = (int)std::min<int64_t>(n / (ix->leaf_size + 1) + 1, (int64_t)node_cap);
   d.cur_list = tmp.alloc<int>(round_cap);
   d.next_list = tmp.alloc<int>(round_cap);
   d.round_cap = round_cap;
-  int* counters = tmp.alloc<int>(8);  // node_count, leaf_count, next_count, overflow, chunk_count
+  // node_count, leaf_count, round list counts (two, swapped each round),
+  // overflow, chunk_count, chunk table overflow
+  int* counters = tmp.alloc<int>(8);
   HIP_OR_THROW(hipMemsetAsync(counters, 0, sizeof(int) * 8, st));
   d.node_count = counters + 0;
   d.leaf_count = counters + 1;
-  d.next_count = counters + 2;
+  int* list_count[2] = {counters + 2, counters + 5};
+  d.next_count = list_count[0];
+  d.cur_count = list_count[1];
   d.overflow = counters + 3;
   int* chunk_count = counters + 4;
+  int* chunk_overflow = counters + 6;
   d.c1 = tmp.alloc<int>((size_t)round_cap * kMaxSeg);
+  HIP_OR_THROW(hipMemsetAsync(d.c1, 0, sizeof(int) * (size_t)round_cap * kMaxSeg, st));
   d.split_seg = tmp.alloc<int>(round_cap);
   d.cursor = tmp.alloc<unsigned long long>((size_t)round_cap * 2);
-  const int chunk_cap = (int)std::min<int64_t>(n / kChunk + round_cap + 1, (int64_t)1 << 30);
   Chunk* chunks = tmp.alloc<Chunk>(chunk_cap);
 
   // the next_list of launch_roots becomes the first round's list
   launch_roots(key_begin, nkeys, w, ix->leaf_size, d, st);
   launch_check();
 
+  // (3) split rounds, queued kRoundsPerSync at a time: each round takes its
+  // sizes from the device, so the host only looks at the counters between
+  // groups (a round after the last one with nodes, or after an overflow of
+  // the roots, does nothing)
+  constexpr int kRoundsPerSync = 4;
+  const int round_blocks = std::max(1, ix->n_cus) * 8;
   int hc[8];
-  d2h(hc, counters, 8, st);
-  if (hc[3]) return false;
-  int n_cur = hc[2];
-  // (3) split rounds
-  for (int round = 0; n_cur > 0; ++round) {
-    if (round > 16 * 8 + 8) throw HipError{hipErrorUnknown, "split rounds did not converge"};
-    std::swap(d.cur_list, d.next_list);
-    HIP_OR_THROW(hipMemsetAsync(d.next_count, 0, sizeof(int), st));
-    HIP_OR_THROW(hipMemsetAsync(d.c1, 0, sizeof(int) * (size_t)n_cur * kMaxSeg, st));
-    launch_make_chunks(d, n_cur, kChunk, chunks, chunk_cap, chunk_count, st);
-    launch_check();
-    int n_chunks = 0;
-    d2h(&n_chunks, chunk_count, 1, st);
-    if (n_chunks > chunk_cap) throw HipError{hipErrorUnknown, "chunk table overflow"};
-    launch_round_count(chunks, n_chunks, d, w, cb, st);
-    launch_round_decide(n_cur, w, cb, ix->leaf_size, d, st);
-    launch_round_scatter(chunks, n_chunks, d, cb, st);
-    launch_check();
+  for (int round = 0, n_cur = 1; n_cur > 0;) {
+    for (int j = 0; j < kRoundsPerSync; ++j, ++round) {
+      if (round > 16 * 8 + 8) throw HipError{hipErrorUnknown, "split rounds did not converge"};
+      std::swap(d.cur_list, d.next_list);
+      std::swap(d.cur_count, d.next_count);
+      launch_make_chunks(d, kChunk, chunks, chunk_cap, chunk_count, chunk_overflow, st);
+      launch_round_count(chunks, chunk_count, chunk_cap, d, w, cb, round_blocks, st);
+      launch_round_decide(w, cb, ix->leaf_size, d, st);
+      launch_round_scatter(chunks, chunk_count, chunk_cap, d, cb, round_blocks, st);
+      launch_check();
+    }
     d2h(hc, counters, 8, st);
     if (hc[3]) return false;
-    n_cur = hc[2];
+    if (hc[6]) throw HipError{hipErrorUnknown, "chunk table overflow"};
+    n_cur = d.next_count == list_count[0] ? hc[2] : hc[5];
   }
   const int n_leaves = hc[1];
   ix->n_nodes = hc[0];
@@ -549,34 +595,45 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   ix->perm = ix->mem.alloc<int32_t>(n);
   launch_leaf_sort(n_leaves, ix->leaf_begin, ix->leaf_end, leaf_buf, d.I0, d.I1, ix->perm, st);
   launch_check();
-  std::vector<int64_t> hb(n_leaves), he(n_leaves);
-  std::vector<int> hbuf(n_leaves);
-  d2h(hb.data(), ix->leaf_begin, n_leaves, st);
-  d2h(he.data(), ix->leaf_end, n_leaves, st);
-  d2h(hbuf.data(), leaf_buf, n_leaves, st);
-  int64_t maxl = 0;
-  int32_t* sort_scratch = nullptr;
-  for (int l = 0; l < n_leaves; ++l) {
-    const int64_t c = he[l] - hb[l];
-    maxl = std::max(maxl, c);
-    if (c > kLeafSortMax) {
-      int p2 = 1;
-      while (p2 < c) p2 <<= 1;
-      if (!sort_scratch) {
-        int64_t big = 1;
-        for (int j = 0; j < n_leaves; ++j) big = std::max<int64_t>(big, he[j] - hb[j]);
-        int64_t pb = 1;
-        while (pb < big) pb <<= 1;
-        sort_scratch = tmp.alloc<int32_t>(pb);
+  // the query's shard-major leaf table, and the leaf sizes the host needs:
+  // one readback for the largest leaf, the over-full leaves and the work
+  // chunks
+  int* small = tmp.alloc<int>(4);  // largest leaf, leaves over kLeafSortMax, chunks
+  HIP_OR_THROW(hipMemsetAsync(small, 0, sizeof(int) * 4, st));
+  launch_leaf_stats(ix->leaf_begin, ix->leaf_end, n_leaves, small, st);
+  ix->shard_off = ix->mem.alloc<int>(kShards + 1);
+  ix->leaf_sh_off = ix->mem.alloc<int>(kShards + 1);
+  ix->sh_sym = ix->mem.alloc<uint4>(n_leaves);
+  ix->sh_bits = ix->mem.alloc<uint4>(n_leaves);
+  ix->sh_rng = ix->mem.alloc<int2>(n_leaves);
+  launch_shard_layout(ix->leaf_begin, ix->leaf_end, ix->leaf_sym, ix->leaf_bits, n_leaves,
+                      ix->shard_off, ix->leaf_sh_off, small + 2, ix->sh_sym, ix->sh_bits, ix->sh_rng,
+                      st);
+  launch_check();
+  int hs[4];
+  d2h(hs, small, 4, st);
+  const int64_t maxl = hs[0];
+  ix->n_chunks = hs[2];
+  if (hs[1] > 0) {  // leaves over kLeafSortMax: sorted one at a time through global memory
+    std::vector<int64_t> hb(n_leaves), he(n_leaves);
+    std::vector<int> hbuf(n_leaves);
+    d2h(hb.data(), ix->leaf_begin, n_leaves, st);
+    d2h(he.data(), ix->leaf_end, n_leaves, st);
+    d2h(hbuf.data(), leaf_buf, n_leaves, st);
+    int64_t pb = 1;
+    while (pb < maxl) pb <<= 1;
+    int32_t* sort_scratch = tmp.alloc<int32_t>(pb);
+    for (int l = 0; l < n_leaves; ++l) {
+      const int64_t c = he[l] - hb[l];
+      if (c > kLeafSortMax) {
+        int p2 = 1;
+        while (p2 < c) p2 <<= 1;
+        launch_leaf_sort_global(hb[l], (int)c, p2, hbuf[l] ? d.I1 : d.I0, sort_scratch, ix->perm, st);
+        launch_check();
       }
-      launch_leaf_sort_global(hb[l], (int)c, p2, hbuf[l] ? d.I1 : d.I0, sort_scratch, ix->perm, st);
-      launch_check();
     }
   }
   ix->max_leaf = maxl;
-  // keep only what queries need
-  tmp.release(d.W0);
-  tmp.release(d.W1);
 
   // (5) leaf-ordered words and z-normalised store (a leaf-ordered copy, or
   // the caller's rows normalised in place)
@@ -595,44 +652,7 @@ bool build_index(messi_index* ix, const float* series, int node_cap, int leaf_ca
   ix->tree = ix->mem.alloc<int4>(ix->n_nodes);
   launch_make_tree(d.nodes, ix->n_nodes, cb, ix->tree, st);
   launch_check();
-  // chunk layout of the query's leaf order: leaf l in shard l % kShards,
-  // each shard's chunks contiguous
-  {
-    const int L = ix->n_leaves;
-    std::vector<int64_t> lb(L), le(L);
-    d2h(lb.data(), ix->leaf_begin, L, st);
-    d2h(le.data(), ix->leaf_end, L, st);
-    std::vector<int> off(kShards + 1, 0);
-    for (int l = 0; l < L; ++l)
-      off[l % kShards + 1] += (int)((le[l] - lb[l] + kChunkSeries - 1) / kChunkSeries);
-    for (int sh = 0; sh < kShards; ++sh) off[sh + 1] += off[sh];
-    ix->n_chunks = off[kShards];
-    ix->shard_off = ix->mem.alloc<int>(kShards + 1);
-    h2d(ix->shard_off, off.data(), kShards + 1, st);
-    // the leaf table again in shard-major order (shard s: leaves s, s + 64,
-    // ...), read contiguously by the per-shard bound blocks
-    std::vector<uint4> sy(L), bi(L), shs(L), shb(L);
-    std::vector<int2> shr(L);
-    std::vector<int> loff(kShards + 1, 0);
-    d2h(sy.data(), ix->leaf_sym, L, st);
-    d2h(bi.data(), ix->leaf_bits, L, st);
-    for (int sh = 0; sh < kShards; ++sh) loff[sh + 1] = loff[sh] + (sh < L ? (L - sh + kShards - 1) / kShards : 0);
-    for (int l = 0; l < L; ++l) {
-      const int j = loff[l % kShards] + l / kShards;
-      shs[j] = sy[l];
-      shb[j] = bi[l];
-      shr[j] = make_int2((int)lb[l], (int)le[l]);
-    }
-    ix->sh_sym = ix->mem.alloc<uint4>(L);
-    ix->sh_bits = ix->mem.alloc<uint4>(L);
-    ix->sh_rng = ix->mem.alloc<int2>(L);
-    ix->leaf_sh_off = ix->mem.alloc<int>(kShards + 1);
-    h2d(ix->sh_sym, shs.data(), L, st);
-    h2d(ix->sh_bits, shb.data(), L, st);
-    h2d(ix->sh_rng, shr.data(), L, st);
-    h2d(ix->leaf_sh_off, loff.data(), kShards + 1, st);
-    HIP_OR_THROW(hipStreamSynchronize(st));  // the host vectors are pageable memory
-  }
+  HIP_OR_THROW(hipStreamSynchronize(st));  // the index is complete when the build returns
   return true;
 }
 

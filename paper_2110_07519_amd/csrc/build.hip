@@ -150,6 +150,46 @@ __device__ __forceinline__ float chain_sum4(const float (&v)[Q], int j) {
                                                     0xf, false));
 }
 
+// Correctly rounded num / den for many numerators over one divisor.  The
+// hardware's IEEE division runs in three parts: a scaling step that moves
+// operands near the exponent limits, a reciprocal of den refined by one
+// Newton step followed by two FMA residual corrections of the quotient, and
+// a fix-up step for zeros, infinities and NaNs.  Away from the limits the
+// scaling and the fix-up leave the corrected quotient unchanged, and the
+// reciprocal part depends on den alone, so it is computed once per series
+// (refined_rcp) and each numerator costs a multiply and four FMAs (div_by).
+// quick_divisor states when that holds for every numerator x - mu of a
+// series: with |mu| >= 2^-60 a nonzero x - mu is at least 2^-84 in
+// magnitude (within a factor of two of mu it is a multiple of the smaller
+// ulp, else at least |mu| / 2), and |x - mu| <= sd sqrt(len) <= 64 sd, so
+// for 2^-40 <= sd <= 2^40 every quotient is normal and no operand is near
+// a limit.  A zero numerator gives a zero of either sign, which leaves the
+// segment sums (started at +0) unchanged.
+__device__ __forceinline__ bool quick_divisor(float mu, float sd) {
+  return sd >= 0x1p-40f && sd <= 0x1p40f && fabsf(mu) >= 0x1p-60f;
+}
+
+__device__ __forceinline__ float refined_rcp(float den) {
+  const float r0 = __builtin_amdgcn_rcpf(den);
+  const float e0 = __builtin_fmaf(-den, r0, 1.0f);
+  return __builtin_fmaf(e0, r0, r0);
+}
+
+__device__ __forceinline__ float div_by(float num, float den, float r) {
+  const float m = num * r;
+  const float e1 = __builtin_fmaf(-den, m, num);
+  const float q1 = __builtin_fmaf(e1, r, m);
+  const float e2 = __builtin_fmaf(-den, q1, num);
+  return __builtin_fmaf(e2, r, q1);
+}
+
+// div_by with the sign of a zero quotient as IEEE division gives it (that
+// of the numerator, the divisor being positive): the stored rows equal the
+// plain division bit for bit.
+__device__ __forceinline__ float div_by_signed(float num, float den, float r) {
+  return copysignf(div_by(num, den, r), num);
+}
+
 template <int C>
 __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ raw, int64_t n,
                                                      int card_bits, const float* __restrict__ bp_g,
@@ -190,22 +230,36 @@ __global__ __launch_bounds__(256) void k_summarize16(const float* __restrict__ r
     float sq[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const float d = v[i] - mu;
-      sq[i] = d * d;
+      v[i] = v[i] - mu;  // v holds x - mu from here on
+      sq[i] = v[i] * v[i];
     }
     const float ss = chain_sum4<Q>(sq, j);
     if (valid) n2 = fmaxf(n2, ss);
     const float sd = as_given ? 1.0f : sqrtf(__fdiv_rn(ss, flen));
     const bool flat = !(sd > 0.0f);
+    // segment sums of z = (v - mu) / sd, each z correctly rounded
+    float a4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (as_given) {  // mu = 0, sd = 1: z = x
+#pragma unroll
+      for (int sg = 0; sg < 4; ++sg)
+#pragma unroll
+        for (int i = 0; i < C; ++i) a4[sg] = a4[sg] + v[sg * C + i];
+    } else if (!flat && quick_divisor(mu, sd)) {
+      const float r = refined_rcp(sd);
+#pragma unroll
+      for (int sg = 0; sg < 4; ++sg)
+#pragma unroll
+        for (int i = 0; i < C; ++i) a4[sg] = a4[sg] + div_by(v[sg * C + i], sd, r);
+    } else if (!flat) {
+#pragma unroll
+      for (int sg = 0; sg < 4; ++sg)
+#pragma unroll
+        for (int i = 0; i < C; ++i) a4[sg] = a4[sg] + __fdiv_rn(v[sg * C + i], sd);
+    }
     uint32_t part = 0, nib = 0;
 #pragma unroll
     for (int sg = 0; sg < 4; ++sg) {
-      float a = 0.0f;
-      if (!flat) {
-#pragma unroll
-        for (int i = 0; i < C; ++i) a = a + __fdiv_rn(v[sg * C + i] - mu, sd);
-      }
-      const float pv = __fdiv_rn(a, fm);
+      const float pv = __fdiv_rn(a4[sg], fm);
       int lo = 0, hi = card - 1;
       for (int step = 0; step < card_bits; ++step) {
         const int mid = (lo + hi + 1) >> 1;
@@ -390,48 +444,66 @@ __device__ __forceinline__ uint32_t word_byte(const uint4& wd, int s) {
   return (v >> (8 * (s & 3))) & 0xffu;
 }
 
-__global__ __launch_bounds__(256) void k_round_count(const Chunk* __restrict__ chunks, BuildDev d,
-                                                      int w, int card_bits) {
-  const Chunk ch = chunks[blockIdx.x];
-  const int id = d.cur_list[ch.slot];
-  const NodeDev& nd = d.nodes[id];
-  const uint4* __restrict__ W = nd.buf ? d.W1 : d.W0;
-  int bits[kMaxSeg];
-  for (int s = 0; s < kMaxSeg; ++s) bits[s] = nd.bits[s];
-  int c[kMaxSeg];
-  for (int s = 0; s < kMaxSeg; ++s) c[s] = 0;
-  for (int64_t e = ch.begin + threadIdx.x; e < ch.end; e += 256) {
-    const uint4 wd = W[e];
-    for (int s = 0; s < kMaxSeg; ++s) {
-      if (s < w && bits[s] < card_bits) c[s] += (int)((word_byte(wd, s) >> (card_bits - 1 - bits[s])) & 1u);
-    }
-  }
+__global__ __launch_bounds__(256) void k_round_count(const Chunk* __restrict__ chunks,
+                                                      const int* __restrict__ n_chunks, int cap,
+                                                      BuildDev d, int w, int card_bits) {
+  const int nch = min(*n_chunks, cap);
   __shared__ int acc[kMaxSeg];
-  if (threadIdx.x < kMaxSeg) acc[threadIdx.x] = 0;
-  __syncthreads();
-  for (int s = 0; s < kMaxSeg; ++s) {
-    int v = c[s];
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&acc[s], v);
+  for (int ci = blockIdx.x; ci < nch; ci += gridDim.x) {
+    const Chunk ch = chunks[ci];
+    const int id = d.cur_list[ch.slot];
+    const NodeDev& nd = d.nodes[id];
+    const uint4* __restrict__ W = nd.buf ? d.W1 : d.W0;
+    int bits[kMaxSeg];
+    for (int s = 0; s < kMaxSeg; ++s) bits[s] = nd.bits[s];
+    int c[kMaxSeg];
+    for (int s = 0; s < kMaxSeg; ++s) c[s] = 0;
+    for (int64_t e = ch.begin + threadIdx.x; e < ch.end; e += 256) {
+      const uint4 wd = W[e];
+      for (int s = 0; s < kMaxSeg; ++s) {
+        if (s < w && bits[s] < card_bits) c[s] += (int)((word_byte(wd, s) >> (card_bits - 1 - bits[s])) & 1u);
+      }
+    }
+    if (threadIdx.x < kMaxSeg) acc[threadIdx.x] = 0;
+    __syncthreads();
+    for (int s = 0; s < kMaxSeg; ++s) {
+      int v = c[s];
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+      if ((threadIdx.x & (kWave - 1)) == 0 && v) atomicAdd(&acc[s], v);
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxSeg && acc[threadIdx.x])
+      atomicAdd(&d.c1[(int64_t)ch.slot * kMaxSeg + threadIdx.x], acc[threadIdx.x]);
+    __syncthreads();  // acc is cleared for the next chunk
   }
-  __syncthreads();
-  if (threadIdx.x < kMaxSeg && acc[threadIdx.x])
-    atomicAdd(&d.c1[(int64_t)ch.slot * kMaxSeg + threadIdx.x], acc[threadIdx.x]);
 }
 
 // Most balanced split: the segment minimising |2 c1 - count| among those
 // with a bit left, lowest segment on ties (Section 2.2).
-__global__ void k_round_decide(int n_cur, int w, int card_bits, int leaf_size, BuildDev d) {
+// It clears the slot's counts after reading them, so c1 is zero for the
+// next round.
+__global__ void k_round_decide(int w, int card_bits, int leaf_size, BuildDev d) {
+  const int n_cur = *d.cur_count;  // clamped by k_make_chunks
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   if (slot >= n_cur) return;
   const int id = d.cur_list[slot];
   NodeDev nd = d.nodes[id];
   const int64_t count = nd.end - nd.begin;
+  int ones[kMaxSeg];
+  int4* c1v = reinterpret_cast<int4*>(d.c1 + (int64_t)slot * kMaxSeg);
+  for (int j = 0; j < kMaxSeg / 4; ++j) {
+    const int4 v = c1v[j];
+    ones[4 * j + 0] = v.x;
+    ones[4 * j + 1] = v.y;
+    ones[4 * j + 2] = v.z;
+    ones[4 * j + 3] = v.w;
+    c1v[j] = make_int4(0, 0, 0, 0);
+  }
   int best = -1;
   int64_t gap = 0;
   for (int s = 0; s < w; ++s) {
     if (nd.bits[s] >= card_bits) continue;
-    const int64_t c1 = d.c1[(int64_t)slot * kMaxSeg + s];
+    const int64_t c1 = ones[s];
     int64_t g = 2 * c1 - count;
     g = g < 0 ? -g : g;
     if (best < 0 || g < gap) {
@@ -448,7 +520,8 @@ __global__ void k_round_decide(int n_cur, int w, int card_bits, int leaf_size, B
     }
     return;
   }
-  const int64_t n1 = d.c1[(int64_t)slot * kMaxSeg + best];
+  int64_t n1 = 0;
+  for (int s = 0; s < kMaxSeg; ++s) n1 = s == best ? ones[s] : n1;
   const int64_t n0 = count - n1;
   d.cursor[2 * slot + 0] = (unsigned long long)nd.begin;
   d.cursor[2 * slot + 1] = (unsigned long long)(nd.begin + n0);
@@ -477,11 +550,15 @@ __global__ void k_round_decide(int n_cur, int w, int card_bits, int leaf_size, B
   d.nodes[id].child[1] = kids[1];
 }
 
-// Two-way scatter into the other buffer; ranks inside a 256-entry tile by
-// ballot + prefix over the block's waves, tile bases by one atomic per side.
-__global__ __launch_bounds__(256) void k_round_scatter(const Chunk* __restrict__ chunks, BuildDev d,
-                                                        int card_bits) {
-  const Chunk ch = chunks[blockIdx.x];
+// Two-way scatter of one chunk into the other buffer.  The block (256
+// threads) holds the chunk in registers, entry begin + 256 i + t in thread
+// t's slot i, ranks each entry inside its side by ballots and one scan over
+// the chunk's (slot, wave) cells, and reserves the chunk's run on each side
+// with one atomic per side.  Inside a side the chunk keeps entry order.
+constexpr int kScatterPer = kChunk / 256;  // entries per thread
+static_assert(kScatterPer * 4 == kWave, "one wave scans the (slot, wave) cells");
+
+__device__ void scatter_chunk(const Chunk ch, const BuildDev& d, int card_bits) {
   const int seg = d.split_seg[ch.slot];
   if (seg < 0) return;
   const int id = d.cur_list[ch.slot];
@@ -491,61 +568,87 @@ __global__ __launch_bounds__(256) void k_round_scatter(const Chunk* __restrict__
   uint4* __restrict__ Wout = nd.buf ? d.W0 : d.W1;
   int32_t* __restrict__ Iout = nd.buf ? d.I0 : d.I1;
   const int shift = card_bits - 1 - nd.bits[seg];
-  __shared__ int wave_ones[4];
-  __shared__ int wave_vals[4];
+  __shared__ int s_ones[kScatterPer * 4];  // per (slot, wave): ones, then their exclusive scan
+  __shared__ int s_zeros[kScatterPer * 4];
   __shared__ unsigned long long base[2];
   const int lane = threadIdx.x & (kWave - 1);
   const int wv = threadIdx.x >> 6;
-  for (int64_t t0 = ch.begin; t0 < ch.end; t0 += 256) {
-    const int64_t e = t0 + threadIdx.x;
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint4 wd[kScatterPer];
+  int32_t idv[kScatterPer];
+  int rank[kScatterPer];  // rank inside the wave's side; -1: past the chunk
+  bool one[kScatterPer];
+#pragma unroll
+  for (int i = 0; i < kScatterPer; ++i) {
+    const int64_t e = ch.begin + (int64_t)i * 256 + threadIdx.x;
     const bool valid = e < ch.end;
-    uint4 wd = make_uint4(0, 0, 0, 0);
-    int32_t idv = 0;
-    int bit = 0;
-    if (valid) {
-      wd = Win[e];
-      idv = Iin[e];
-      bit = (int)((word_byte(wd, seg) >> shift) & 1u);
-    }
-    const unsigned long long ones = __ballot(valid && bit);
-    const unsigned long long vals = __ballot(valid);
-    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    const int ones_before = __popcll(ones & below);
-    const int zeros_before = __popcll(vals & ~ones & below);
-    if (lane == 0) {
-      wave_ones[wv] = __popcll(ones);
-      wave_vals[wv] = __popcll(vals);
-    }
-    __syncthreads();
-    int o_off = 0, z_off = 0, o_tot = 0, z_tot = 0;
-    for (int j = 0; j < 4; ++j) {
-      const int oj = wave_ones[j], zj = wave_vals[j] - wave_ones[j];
-      if (j < wv) {
-        o_off += oj;
-        z_off += zj;
-      }
-      o_tot += oj;
-      z_tot += zj;
-    }
-    if (threadIdx.x == 0) {
-      base[0] = z_tot ? atomicAdd(&d.cursor[2 * ch.slot + 0], (unsigned long long)z_tot) : 0ull;
-      base[1] = o_tot ? atomicAdd(&d.cursor[2 * ch.slot + 1], (unsigned long long)o_tot) : 0ull;
-    }
-    __syncthreads();
-    if (valid) {
-      const int64_t dst = bit ? (int64_t)base[1] + o_off + ones_before : (int64_t)base[0] + z_off + zeros_before;
-      Wout[dst] = wd;
-      Iout[dst] = idv;
-    }
-    __syncthreads();
+    wd[i] = valid ? Win[e] : make_uint4(0, 0, 0, 0);
+    idv[i] = valid ? Iin[e] : 0;
   }
+#pragma unroll
+  for (int i = 0; i < kScatterPer; ++i) {
+    const bool valid = ch.begin + (int64_t)i * 256 + threadIdx.x < ch.end;
+    one[i] = valid && ((word_byte(wd[i], seg) >> shift) & 1u);
+    const unsigned long long ones = __ballot(one[i]);
+    const unsigned long long vals = __ballot(valid);
+    rank[i] = !valid ? -1 : (one[i] ? __popcll(ones & below) : __popcll(vals & ~ones & below));
+    if (lane == 0) {
+      s_ones[i * 4 + wv] = __popcll(ones);
+      s_zeros[i * 4 + wv] = __popcll(vals & ~ones);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {  // one wave scans the 64 cells in entry order
+    const int o = s_ones[threadIdx.x], z = s_zeros[threadIdx.x];
+    int so = o, sz = z;
+    for (int k = 1; k < kWave; k <<= 1) {
+      const int po = __shfl_up(so, k, kWave), pz = __shfl_up(sz, k, kWave);
+      if (lane >= k) {
+        so += po;
+        sz += pz;
+      }
+    }
+    s_ones[threadIdx.x] = so - o;
+    s_zeros[threadIdx.x] = sz - z;
+    if (lane == kWave - 1) {
+      base[0] = sz ? atomicAdd(&d.cursor[2 * ch.slot + 0], (unsigned long long)sz) : 0ull;
+      base[1] = so ? atomicAdd(&d.cursor[2 * ch.slot + 1], (unsigned long long)so) : 0ull;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kScatterPer; ++i) {
+    if (rank[i] < 0) continue;
+    const int64_t dst = one[i] ? (int64_t)base[1] + s_ones[i * 4 + wv] + rank[i]
+                               : (int64_t)base[0] + s_zeros[i * 4 + wv] + rank[i];
+    Wout[dst] = wd[i];
+    Iout[dst] = idv[i];
+  }
+  __syncthreads();  // the cells are rewritten by the block's next chunk
 }
 
-// Chunk list of the next round (one block): exclusive scan of chunk counts.
-__global__ __launch_bounds__(1024) void k_make_chunks(BuildDev d, int n_cur, int chunk,
+__global__ __launch_bounds__(256) void k_round_scatter(const Chunk* __restrict__ chunks,
+                                                        const int* __restrict__ n_chunks, int cap,
+                                                        BuildDev d, int card_bits) {
+  const int nch = min(*n_chunks, cap);
+  for (int ci = blockIdx.x; ci < nch; ci += gridDim.x) scatter_chunk(chunks[ci], d, card_bits);
+}
+
+// Chunk list of the round (one block): exclusive scan of chunk counts.  It
+// opens the round: the node count becomes 0 after an overflow (so nothing
+// runs until the host sees it) and at most round_cap, and the next round's
+// list starts empty.
+__global__ __launch_bounds__(1024) void k_make_chunks(BuildDev d, int chunk,
                                                        Chunk* __restrict__ out, int cap,
-                                                       int* __restrict__ out_count) {
+                                                       int* __restrict__ out_count,
+                                                       int* __restrict__ out_overflow) {
   __shared__ int part[1024];
+  const int n_cur = *d.overflow ? 0 : min(*d.cur_count, d.round_cap);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *d.cur_count = n_cur;
+    *d.next_count = 0;
+  }
   const int per = (n_cur + 1023) / 1024;
   const int a = threadIdx.x * per;
   const int b = min(a + per, n_cur);
@@ -577,7 +680,10 @@ __global__ __launch_bounds__(1024) void k_make_chunks(BuildDev d, int n_cur, int
       ++run;
     }
   }
-  if (threadIdx.x == 1023) *out_count = part[1023];
+  if (threadIdx.x == 1023) {
+    *out_count = part[1023];
+    if (part[1023] > cap) *out_overflow = 1;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -662,6 +768,84 @@ __global__ __launch_bounds__(1024) void k_leaf_sort_global(int64_t b, int cnt, i
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) perm[b + i] = scratch[i];
 }
 
+// Leaf sizes: out[0] = the largest, out[1] = how many exceed kLeafSortMax
+// (those are sorted by k_leaf_sort_global).  out must be zero on entry.
+__global__ __launch_bounds__(1024) void k_leaf_stats(const int64_t* __restrict__ begin,
+                                                     const int64_t* __restrict__ end, int L,
+                                                     int* __restrict__ out) {
+  __shared__ int s_max, s_big;
+  if (threadIdx.x == 0) {
+    s_max = 0;
+    s_big = 0;
+  }
+  __syncthreads();
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = l < L ? (int)(end[l] - begin[l]) : 0;
+  int m = c;
+  for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+  const int big = __popcll(__ballot(c > kLeafSortMax));
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    atomicMax(&s_max, m);
+    atomicAdd(&s_big, big);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicMax(&out[0], s_max);
+    if (s_big) atomicAdd(&out[1], s_big);
+  }
+}
+
+// The leaf table in the query's shard-major order.  Leaf l belongs to shard
+// l % kShards; shard s holds leaves s, s + kShards, ... contiguously,
+// starting at s q + min(s, r) for L = kShards q + r.
+__device__ __forceinline__ int shard_leaf_start(int s, int L) {
+  const int q = L / kShards, r = L % kShards;
+  return s * q + min(s, r);
+}
+
+// One block: per shard, its work chunks (kChunkSeries series each, per leaf)
+// and their exclusive scan (shard_off, n_chunks = shard_off[kShards]); the
+// shard-major leaf offsets (leaf_sh_off).
+__global__ __launch_bounds__(1024) void k_shard_offsets(const int64_t* __restrict__ begin,
+                                                        const int64_t* __restrict__ end, int L,
+                                                        int* __restrict__ shard_off,
+                                                        int* __restrict__ leaf_sh_off,
+                                                        int* __restrict__ n_chunks) {
+  __shared__ int cnt[kShards];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int nw = blockDim.x >> 6;
+  for (int sh = threadIdx.x >> 6; sh < kShards; sh += nw) {
+    int c = 0;
+    for (int l = sh + kShards * lane; l < L; l += kShards * kWave)
+      c += (int)((end[l] - begin[l] + kChunkSeries - 1) / kChunkSeries);
+    for (int o = 32; o >= 1; o >>= 1) c += __shfl_xor(c, o, kWave);
+    if (lane == 0) cnt[sh] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int sh = 0; sh < kShards; ++sh) {
+      shard_off[sh] = run;
+      run += cnt[sh];
+    }
+    shard_off[kShards] = run;
+    *n_chunks = run;
+  }
+  if (threadIdx.x <= kShards) leaf_sh_off[threadIdx.x] = shard_leaf_start(threadIdx.x, L);
+}
+
+__global__ void k_shard_tables(const int64_t* __restrict__ begin, const int64_t* __restrict__ end,
+                               const uint4* __restrict__ sym, const uint4* __restrict__ bits,
+                               int L, uint4* __restrict__ sh_sym, uint4* __restrict__ sh_bits,
+                               int2* __restrict__ sh_rng) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  const int j = shard_leaf_start(l % kShards, L) + l / kShards;
+  sh_sym[j] = sym[l];
+  sh_bits[j] = bits[l];
+  sh_rng[j] = make_int2((int)begin[l], (int)end[l]);
+}
+
 // ---------------------------------------------------------------------------
 // (5) Leaf-ordered store: z = (x - mu) / sd per point (the same rounding as
 // in the summary pass), one wave per row, float4 per lane.
@@ -671,6 +855,42 @@ __global__ __launch_bounds__(1024) void k_leaf_sort_global(int64_t b, int cnt, i
 // any is used (the ids, then their (mu, sd), then the rows), so four rows'
 // chains are in flight per wave instead of one.
 constexpr int kGatherRows = 4;
+
+// The build reads each raw row once here and writes each stored row once:
+// non-temporal accesses keep them from displacing cached lines.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float4 load_nt(const float* p) {
+  const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
+  return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void store_nt(float* p, const float4 o) {
+  const f32x4 v = {o.x, o.y, o.z, o.w};
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
+}
+
+// Four points of a row z-normalised with its (mu, sd): zero for a flat row,
+// else each (x - mu) / sd correctly rounded (div_by_signed where
+// quick_divisor allows it, the plain division otherwise).
+__device__ __forceinline__ float4 znorm4(const float4 v, const float2 ms) {
+  const float mu = ms.x, sd = ms.y;
+  float4 o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (!(sd > 0.0f)) return o;
+  if (quick_divisor(mu, sd)) {
+    const float r = refined_rcp(sd);
+    o.x = div_by_signed(v.x - mu, sd, r);
+    o.y = div_by_signed(v.y - mu, sd, r);
+    o.z = div_by_signed(v.z - mu, sd, r);
+    o.w = div_by_signed(v.w - mu, sd, r);
+  } else {
+    o.x = __fdiv_rn(v.x - mu, sd);
+    o.y = __fdiv_rn(v.y - mu, sd);
+    o.z = __fdiv_rn(v.z - mu, sd);
+    o.w = __fdiv_rn(v.w - mu, sd);
+  }
+  return o;
+}
 
 __global__ __launch_bounds__(256) void k_gather_store(const float* __restrict__ raw, int64_t n, int len,
                                                        const int32_t* __restrict__ perm,
@@ -692,17 +912,11 @@ __global__ __launch_bounds__(256) void k_gather_store(const float* __restrict__ 
       for (int t = 4 * lane; t < len; t += 4 * kWave) {
         float4 v[kGatherRows];
 #pragma unroll
-        for (int r = 0; r < kGatherRows; ++r) v[r] = *reinterpret_cast<const float4*>(raw + (int64_t)id[r] * len + t);
+        for (int r = 0; r < kGatherRows; ++r) v[r] = load_nt(raw + (int64_t)id[r] * len + t);
 #pragma unroll
         for (int r = 0; r < kGatherRows; ++r) {
           if (p0 + r >= n) continue;
-          const bool flat = !(ms[r].y > 0.0f);
-          float4 o;
-          o.x = flat ? 0.0f : __fdiv_rn(v[r].x - ms[r].x, ms[r].y);
-          o.y = flat ? 0.0f : __fdiv_rn(v[r].y - ms[r].x, ms[r].y);
-          o.z = flat ? 0.0f : __fdiv_rn(v[r].z - ms[r].x, ms[r].y);
-          o.w = flat ? 0.0f : __fdiv_rn(v[r].w - ms[r].x, ms[r].y);
-          *reinterpret_cast<float4*>(Z + (p0 + r) * (int64_t)len + t) = o;
+          store_nt(Z + (p0 + r) * (int64_t)len + t, znorm4(v[r], ms[r]));
         }
       }
     } else {
@@ -742,12 +956,7 @@ __global__ __launch_bounds__(256) void k_store_inplace(float* __restrict__ raw, 
     if ((len & 3) == 0) {
       for (int t = 4 * lane; t < len; t += 4 * kWave) {
         const float4 v = *reinterpret_cast<const float4*>(x + t);
-        float4 o;
-        o.x = flat ? 0.0f : __fdiv_rn(v.x - ms.x, ms.y);
-        o.y = flat ? 0.0f : __fdiv_rn(v.y - ms.x, ms.y);
-        o.z = flat ? 0.0f : __fdiv_rn(v.z - ms.x, ms.y);
-        o.w = flat ? 0.0f : __fdiv_rn(v.w - ms.x, ms.y);
-        *reinterpret_cast<float4*>(x + t) = o;
+        *reinterpret_cast<float4*>(x + t) = znorm4(v, ms);
       }
     } else {
       for (int t = lane; t < len; t += kWave) x[t] = flat ? 0.0f : __fdiv_rn(x[t] - ms.x, ms.y);
@@ -819,26 +1028,27 @@ void launch_roots(const int64_t* begin, int nkeys, int w, int leaf_size, const B
                      leaf_size, d);
 }
 
-void launch_round_count(const Chunk* chunks, int n_chunks, const BuildDev& d, int w,
-                        int card_bits, hipStream_t st) {
-  hipLaunchKernelGGL(k_round_count, dim3(n_chunks), dim3(256), 0, st, chunks, d, w, card_bits);
+void launch_make_chunks(const BuildDev& d, int chunk, Chunk* out, int cap, int* out_count,
+                        int* out_overflow, hipStream_t st) {
+  hipLaunchKernelGGL(k_make_chunks, dim3(1), dim3(1024), 0, st, d, chunk, out, cap, out_count,
+                     out_overflow);
 }
 
-void launch_round_decide(int n_cur, int w, int card_bits, int leaf_size, const BuildDev& d,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(k_round_decide, dim3((n_cur + 255) / 256), dim3(256), 0, st, n_cur, w,
+void launch_round_count(const Chunk* chunks, const int* n_chunks, int cap, const BuildDev& d,
+                        int w, int card_bits, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_round_count, dim3(blocks), dim3(256), 0, st, chunks, n_chunks, cap, d, w,
+                     card_bits);
+}
+
+void launch_round_decide(int w, int card_bits, int leaf_size, const BuildDev& d, hipStream_t st) {
+  hipLaunchKernelGGL(k_round_decide, dim3((d.round_cap + 255) / 256), dim3(256), 0, st, w,
                      card_bits, leaf_size, d);
 }
 
-void launch_round_scatter(const Chunk* chunks, int n_chunks, const BuildDev& d, int card_bits,
-                          hipStream_t st) {
-  hipLaunchKernelGGL(k_round_scatter, dim3(n_chunks), dim3(256), 0, st, chunks, d, card_bits);
-}
-
-void launch_make_chunks(const BuildDev& d, int n_cur, int chunk, Chunk* out, int cap,
-                        int* out_count, hipStream_t st) {
-  hipLaunchKernelGGL(k_make_chunks, dim3(1), dim3(1024), 0, st, d, n_cur, chunk, out, cap,
-                     out_count);
+void launch_round_scatter(const Chunk* chunks, const int* n_chunks, int cap, const BuildDev& d,
+                          int card_bits, int blocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_round_scatter, dim3(blocks), dim3(256), 0, st, chunks, n_chunks, cap, d,
+                     card_bits);
 }
 
 void launch_leaf_records(const BuildDev& d, int n_leaves, int64_t* leaf_begin, int64_t* leaf_end,
@@ -857,6 +1067,21 @@ void launch_leaf_sort(int n_leaves, const int64_t* leaf_begin, const int64_t* le
 void launch_leaf_sort_global(int64_t b, int cnt, int p2, const int32_t* I, int32_t* scratch,
                              int32_t* perm, hipStream_t st) {
   hipLaunchKernelGGL(k_leaf_sort_global, dim3(1), dim3(1024), 0, st, b, cnt, p2, I, scratch, perm);
+}
+
+void launch_leaf_stats(const int64_t* leaf_begin, const int64_t* leaf_end, int n_leaves, int* out,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_leaf_stats, dim3((unsigned)((n_leaves + 1023) / 1024)), dim3(1024), 0, st,
+                     leaf_begin, leaf_end, n_leaves, out);
+}
+
+void launch_shard_layout(const int64_t* leaf_begin, const int64_t* leaf_end, const uint4* leaf_sym,
+                         const uint4* leaf_bits, int n_leaves, int* shard_off, int* leaf_sh_off,
+                         int* n_chunks, uint4* sh_sym, uint4* sh_bits, int2* sh_rng, hipStream_t st) {
+  hipLaunchKernelGGL(k_shard_offsets, dim3(1), dim3(1024), 0, st, leaf_begin, leaf_end, n_leaves,
+                     shard_off, leaf_sh_off, n_chunks);
+  hipLaunchKernelGGL(k_shard_tables, dim3((unsigned)((n_leaves + 255) / 256)), dim3(256), 0, st,
+                     leaf_begin, leaf_end, leaf_sym, leaf_bits, n_leaves, sh_sym, sh_bits, sh_rng);
 }
 
 void launch_make_tree(const NodeDev* nodes, int n_nodes, int card_bits, int4* tree,
