@@ -381,6 +381,12 @@ int messi_set_stream(messi_index* index, void* hip_stream);
 int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t* segments,
                      int32_t* card_bits, int64_t* n_leaves, int64_t* device_bytes);
 
+/* Host wall time of the build call that made the index, in ms, and the part
+ * of it spent in device allocation (hipMalloc), which depends on the device's
+ * state: a driver may clear reused memory before handing it out.  Library
+ * plumbing (no passage of the paper).  Either pointer may be NULL. */
+int messi_build_times(const messi_index* index, double* build_ms, double* alloc_ms);
+
 /* Copies out of a built index into HOST buffers, for inspection and tests:
  *   words   uint8 [n][segments], series in id order (Section 2.2 symbols);
  *   perm    int32 [n], the id at each leaf-order position;

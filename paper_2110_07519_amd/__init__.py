@@ -9,7 +9,7 @@ Names follow the C ABI: messi_build, messi_build_ex, messi_build_windows, messi_
 messi_query_noalloc,
 messi_query_batch, messi_autotune, messi_prepare_screen, messi_classify, messi_set_stream,
 messi_free, messi_breakpoints, messi_get_words,
-messi_get_perm, messi_get_leaves, messi_index_info, messi_last_error.
+messi_get_perm, messi_get_leaves, messi_index_info, messi_build_times, messi_last_error.
 """
 from __future__ import annotations
 
@@ -34,8 +34,8 @@ MESSI_GRAPH = 4
 
 EXPORTS = [
     "messi_build", "messi_query", "messi_query_stats", "messi_set_stream", "messi_index_info",
-    "messi_get_words", "messi_get_perm", "messi_get_leaves", "messi_breakpoints", "messi_free",
-    "messi_last_error", "messi_query_batch", "messi_prepare_screen",
+    "messi_build_times", "messi_get_words", "messi_get_perm", "messi_get_leaves",
+    "messi_breakpoints", "messi_free", "messi_last_error", "messi_query_batch", "messi_prepare_screen",
     "messi_server_start", "messi_server_submit", "messi_server_poll", "messi_server_get_stats",
     "messi_server_stop", "messi_classify", "messi_build_ex", "messi_build_windows",
     "messi_query_noalloc", "messi_autotune",
@@ -116,6 +116,7 @@ def lib():
         L.messi_server_stop.restype = None
         L.messi_set_stream.argtypes = [P, P]
         L.messi_index_info.argtypes = [P, P, P, P, P, P, P]
+        L.messi_build_times.argtypes = [P, P, P]
         L.messi_get_words.argtypes = [P, P]
         L.messi_get_perm.argtypes = [P, P]
         L.messi_get_leaves.argtypes = [P, P, i64, P]
@@ -128,8 +129,8 @@ def lib():
                      "messi_prepare_screen", "messi_classify", "messi_server_start",
                      "messi_server_submit",
                      "messi_server_poll", "messi_server_get_stats", "messi_set_stream",
-                     "messi_index_info", "messi_get_words", "messi_get_perm", "messi_get_leaves",
-                     "messi_breakpoints"]:
+                     "messi_index_info", "messi_build_times", "messi_get_words", "messi_get_perm",
+                     "messi_get_leaves", "messi_breakpoints"]:
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -373,6 +374,13 @@ def messi_index_info(index) -> dict:
                                   ctypes.byref(cb), ctypes.byref(nl), ctypes.byref(db)))
     return {"n": n.value, "len": ln.value, "segments": w.value, "card_bits": cb.value,
             "n_leaves": nl.value, "device_bytes": db.value}
+
+
+def messi_build_times(index) -> dict:
+    """Host wall time of the build call, and its part in device allocation (ms)."""
+    t, a = ctypes.c_double(), ctypes.c_double()
+    _check(lib().messi_build_times(index.handle, ctypes.byref(t), ctypes.byref(a)))
+    return {"build_ms": t.value, "alloc_ms": a.value}
 
 
 def messi_get_words(index) -> np.ndarray:

@@ -63,6 +63,9 @@ struct BudgetError {
   size_t need, budget;
 };
 
+// Host time this thread has spent in hipMalloc (the build reports its part).
+thread_local double g_alloc_ms = 0.0;
+
 // Device allocation owned by a vector of frees.
 struct DevMem {
   std::vector<void*> ptrs;
@@ -71,7 +74,9 @@ struct DevMem {
   T* alloc(size_t count) {
     void* p = nullptr;
     const size_t b = std::max<size_t>(count, 1) * sizeof(T);
+    const auto t0 = std::chrono::steady_clock::now();
     hipError_t e = hipMalloc(&p, b);
+    g_alloc_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (e != hipSuccess) {
       (void)hipGetLastError();
       throw OomError{b};
@@ -273,6 +278,7 @@ struct messi_index {
   int len = 0, w = 0, card_bits = 0, leaf_size = 0;
   int n_leaves = 0, n_nodes = 0;
   int64_t max_leaf = 0;
+  double build_ms = 0.0, build_alloc_ms = 0.0;  // host time of the build call, and in hipMalloc
   DevMem mem;
   float* Z = nullptr;
   uint4* words = nullptr;
@@ -1660,6 +1666,8 @@ int messi_build(const float* series, int64_t n, int32_t len, int32_t segments,
 int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int32_t cardinality,
                    int32_t leaf_size, const messi_options* opts, messi_index** out) {
   g_err.clear();
+  const auto t_start = std::chrono::steady_clock::now();
+  const double alloc0 = g_alloc_ms;
   messi_options o{};
   if (opts) o = *opts;
   if (!out) return fail(MESSI_EINVAL, "out is NULL");
@@ -1756,6 +1764,8 @@ int messi_build_ex(float* series, int64_t n, int32_t len, int32_t segments, int3
     }
   }
   if (o.inplace == 2) ix->owned_store = series;  // freed by messi_free from here on
+  ix->build_alloc_ms = g_alloc_ms - alloc0;
+  ix->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
   *out = ix;
   return MESSI_OK;
 }
@@ -2128,6 +2138,13 @@ int messi_index_info(const messi_index* index, int64_t* n, int32_t* len, int32_t
   if (card_bits) *card_bits = index->card_bits;
   if (n_leaves) *n_leaves = index->n_leaves;
   if (device_bytes) *device_bytes = (int64_t)held_bytes(index);
+  return MESSI_OK;
+}
+
+int messi_build_times(const messi_index* index, double* build_ms, double* alloc_ms) {
+  if (!index) return fail(MESSI_EINVAL, "index is NULL");
+  if (build_ms) *build_ms = index->build_ms;
+  if (alloc_ms) *alloc_ms = index->build_alloc_ms;
   return MESSI_OK;
 }
 

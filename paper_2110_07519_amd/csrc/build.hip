@@ -707,7 +707,35 @@ __global__ void k_leaf_records(BuildDev d, int n_leaves, int64_t* __restrict__ l
   leaf_buf[l] = nd.buf;
 }
 
-// Bitonic sort of one leaf's ids in LDS (size up to kLeafSortMax).
+// Bitonic sort of one leaf's ids (size up to kLeafSortMax, padded to a
+// power of two of at least 128 with INT_MAX).  A wave owns 128-element
+// windows (lane l holds positions l and l + 64): the network's steps with
+// stride 64 or less stay inside a window and run in registers (stride 64
+// inside the lane, smaller ones by lane exchanges), so only the steps with
+// stride 128 or more go through LDS between block barriers.
+
+// One compare-exchange of the pair (p, p ^ s), s < 64, from the lane
+// holding p: the lower position keeps the minimum when the run ascends.
+__device__ __forceinline__ int32_t bitonic_lanes(int32_t x, int s, bool lower, bool up) {
+  const int32_t y = __shfl_xor(x, s, kWave);
+  return (lower == up) ? min(x, y) : max(x, y);
+}
+
+// The steps of stage `size` with stride 64 and less on the window at base.
+__device__ __forceinline__ void bitonic_window(int32_t& a, int32_t& b, int base, int lane, int size) {
+  const bool upa = ((base + lane) & size) == 0, upb = ((base + lane + 64) & size) == 0;
+  if (size >= 128) {  // stride 64: a and b are the pair (same run direction)
+    const int32_t lo = min(a, b), hi = max(a, b);
+    a = upa ? lo : hi;
+    b = upa ? hi : lo;
+  }
+  for (int s = min(size >> 1, 32); s >= 1; s >>= 1) {
+    const bool lower = (lane & s) == 0;
+    a = bitonic_lanes(a, s, lower, upa);
+    b = bitonic_lanes(b, s, lower, upb);
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_leaf_sort(const int64_t* __restrict__ leaf_begin,
                                                      const int64_t* __restrict__ leaf_end,
                                                      const int* __restrict__ leaf_buf,
@@ -720,12 +748,21 @@ __global__ __launch_bounds__(1024) void k_leaf_sort(const int64_t* __restrict__ 
   const int cnt = (int)(e - b);
   if (cnt > kLeafSortMax) return;  // sorted by k_leaf_sort_global
   const int32_t* __restrict__ I = leaf_buf[l] ? I1 : I0;
-  int p2 = 1;
+  int p2 = 128;
   while (p2 < cnt) p2 <<= 1;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int i = threadIdx.x; i < p2; i += blockDim.x) v[i] = i < cnt ? I[b + i] : 0x7fffffff;
   __syncthreads();
-  for (int size = 2; size <= p2; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+  for (int base = wv * 128; base < p2; base += nw * 128) {  // stages 2 .. 128
+    int32_t x = v[base + lane], y = v[base + lane + 64];
+    for (int size = 2; size <= 128; size <<= 1) bitonic_window(x, y, base, lane, size);
+    v[base + lane] = x;
+    v[base + lane + 64] = y;
+  }
+  __syncthreads();
+  for (int size = 256; size <= p2; size <<= 1) {
+    for (int stride = size >> 1; stride >= 128; stride >>= 1) {
       for (int i = threadIdx.x; i < (p2 >> 1); i += blockDim.x) {
         const int lo = 2 * i - (i & (stride - 1));
         const int hi = lo + stride;
@@ -738,6 +775,13 @@ __global__ __launch_bounds__(1024) void k_leaf_sort(const int64_t* __restrict__ 
       }
       __syncthreads();
     }
+    for (int base = wv * 128; base < p2; base += nw * 128) {
+      int32_t x = v[base + lane], y = v[base + lane + 64];
+      bitonic_window(x, y, base, lane, size);
+      v[base + lane] = x;
+      v[base + lane + 64] = y;
+    }
+    __syncthreads();
   }
   for (int i = threadIdx.x; i < cnt; i += blockDim.x) perm[b + i] = v[i];
 }
