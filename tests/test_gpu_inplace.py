@@ -57,3 +57,35 @@ def test_inplace_build_and_queries(pm, length, leaf):
     assert torch.equal(b1[0], b2[0]) and torch.equal(b1[1], b2[1])
     ip_idx.free()
     copy_idx.free()
+
+
+@pytest.mark.parametrize("length", [256, 100])
+def test_store_and_words_at_extreme_scales(pm, length):
+    """Rows whose (mu, sd) fall outside the range where the build divides
+    by a hoisted reciprocal (sd below 2^-40 or above 2^40, mu exactly zero)
+    take the plain division; both kinds mixed within each wave give the
+    oracle's store and words bit for bit."""
+    n = 4096
+    raw = synth.randomwalk(n, length, seed=29)
+    rows = np.arange(n)
+    raw[rows % 7 == 1] *= np.float32(1e-14)             # sd about 1e-14
+    raw[rows % 7 == 2] *= np.float32(1e14)              # sd about 1e14
+    sym = rows[rows % 7 == 3]                           # mean exactly zero: +a, -a pairs
+    half = raw[sym, : length // 2]
+    raw[sym, 0::2] = half
+    raw[sym, 1::2] = -half
+    raw[rows % 7 == 4] += np.float32(1e6)               # large offset, ordinary sd
+    raw[5] = -3.0                                       # flat
+    w = 16 if length % 16 == 0 else 4
+    buf = torch.from_numpy(raw.copy()).cuda()
+    idx = pm.messi_build_ex(buf, w, 256, 64, inplace=True)
+    got, want = buf.cpu().numpy(), oracle.znorm(raw)
+    bad = np.argwhere(got.view(np.uint32) != want.view(np.uint32))
+    assert len(bad) == 0, (len(bad), bad[:5], np.unique(bad[:, 0] % 7))
+    Wo = oracle.words(raw, w, 8)
+    assert np.array_equal(pm.messi_get_words(idx), Wo)
+    perm, _ = oracle.leaf_partition(Wo, 64, 8)
+    assert np.array_equal(pm.messi_get_perm(idx), perm)
+    bt = pm.messi_build_times(idx)
+    assert 0.0 <= bt["alloc_ms"] <= bt["build_ms"]
+    idx.free()
