@@ -2129,6 +2129,9 @@ __global__ __launch_bounds__(1024) void k_list_scan(QueryParams p, ScreenDev sc)
 //   R_q + C_x - a_q s_x - 2 s~ > 0,
 //   R_q = |q|^2 (1 - c_abs) - thr_q,  C_x = |x|^2 (1 - c_abs),
 //   a_q = c_dot |q|,  s_x = |x|.
+// The terms are kept halved (exact scalings by 1/2), so T = fl(fl(R_q / 2 +
+// C_x / 2) - a_q s_x / 2) is half the folded FP32 value, and the test is one
+// exact comparison, s~ < T.
 // Rows past the list and columns past the leaf get R_q / C_x = +inf.  Pairs
 // kept are refined by the whole wave in FP32 and offered to their query's
 // k best, except the query's own approximate-search range (already in its
@@ -2259,8 +2262,8 @@ void k_screen(IndexDev ix, QueryParams p, QueryState s, ScreenDev sc) {
       if (tid < kScreenChunk) {
         const bool ok = pq >= 0;
         s_q[buf][tid] = pq;
-        s_R[buf][tid] = ok ? pqn * one_m - pkth * p.win : INFINITY;
-        s_a[buf][tid] = ok ? sc.c_dot * sqrtf(pqn) : 0.0f;
+        s_R[buf][tid] = ok ? 0.5f * (pqn * one_m - pkth * p.win) : INFINITY;
+        s_a[buf][tid] = ok ? 0.5f * (sc.c_dot * sqrtf(pqn)) : 0.0f;
       }
     };
     // Column passes over the leaf.  The query list is the same for every
@@ -2294,7 +2297,7 @@ void k_screen(IndexDev ix, QueryParams p, QueryState s, ScreenDev sc) {
 #pragma unroll
       for (int t = 0; t < NT; ++t) {
         const bool v = wbase + 16 * t + col < e;
-        cx[t] = v ? xnv[t] * one_m : INFINITY;
+        cx[t] = v ? 0.5f * (xnv[t] * one_m) : INFINITY;
         sx[t] = sqrtf(xnv[t]);
       }
       const int ncols = (int)((e - wbase) < 16 * NT ? ((e - wbase) > 0 ? (e - wbase) : 0) : 16 * NT);
@@ -2315,26 +2318,38 @@ void k_screen(IndexDev ix, QueryParams p, QueryState s, ScreenDev sc) {
 #pragma unroll
           for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
           const char* arow = A + (16 * qt + col) * Sh::row_bytes + 2 * kb;
+          // the tile's A operands all in flight before the first product
+          bf16x8 av[KS];
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks)
+            av[ks] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(arow + 64 * ks));
 #pragma unroll
           for (int ks = 0; ks < KS; ++ks) {
-            const bf16x8 a = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(arow + 64 * ks));
 #pragma unroll
             for (int t = 0; t < NT; ++t)
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, B[t][ks], acc[t], 0, 0, 0);
+              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ks], B[t][ks], acc[t], 0, 0, 0);
           }
           screened += (unsigned long long)(min(16, rows_valid - 16 * qt) * ncols);
-          uint32_t keep = 0;
+          float Rh[4], ah[4];
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = 16 * qt + 4 * (lane >> 4) + r;
-            const float R = s_R[buf][row], a = s_a[buf][row];
-#pragma unroll
-            for (int t = 0; t < NT; ++t) {
-              const float x = __builtin_fmaf(-2.0f, acc[t][r], __builtin_fmaf(-a, sx[t], R + cx[t]));
-              keep |= (x > 0.0f ? 0u : 1u) << (r * NT + t);
-            }
+            Rh[r] = s_R[buf][row];
+            ah[r] = s_a[buf][row];
           }
-          if (__ballot(keep != 0)) {  // rare: refine the kept pairs one at a time
+          // kept: s~ >= T (or NaN); which pairs, only when some lane has one
+          bool any = false;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int t = 0; t < NT; ++t) any |= !(acc[t][r] < __builtin_fmaf(-ah[r], sx[t], Rh[r] + cx[t]));
+          if (__ballot(any)) {  // rare: refine the kept pairs one at a time
+            uint32_t keep = 0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+              for (int t = 0; t < NT; ++t)
+                keep |= (acc[t][r] < __builtin_fmaf(-ah[r], sx[t], Rh[r] + cx[t]) ? 0u : 1u) << (r * NT + t);
             unsigned long long m = __ballot(keep != 0);
             while (m) {
               const int src_lane = __ffsll((long long)m) - 1;
