@@ -2191,198 +2191,204 @@ void k_screen(IndexDev ix, QueryParams p, QueryState s, ScreenDev sc) {
     }
     if (leaf >= p.n_leaves) break;
     const int64_t l0 = sc.off[leaf], l1 = sc.off[leaf + 1];
-    if (l0 == l1) continue;
-    const int nlist = (int)(l1 - l0);
-    const int nch = (nlist + kScreenChunk - 1) / kScreenChunk;
     const int64_t b = ix.leaf_begin[leaf], e = ix.leaf_end[leaf];
-    // the list's entries, with each query's k and |q|^2, into LDS (when
-    // they fit), so that fetching a chunk is one round trip to memory (its
-    // rows and k-th best distances), which the chunk before it covers
-    const bool in_lds = nlist <= kScreenListCap;
-    g_int* glist = (g_int*)(sc.lists + l0);
-    if (in_lds)
+    // the list in segments of at most kScreenListCap queries (one, unless
+    // the batch is larger), each screened against the whole leaf
+    for (int64_t s0 = l0; s0 < l1; s0 += kScreenListCap) {
+      const int nlist = (int)min<int64_t>(l1 - s0, kScreenListCap);
+      const int nch = (nlist + kScreenChunk - 1) / kScreenChunk;
+      // the segment's entries, with each query's k and |q|^2, into LDS, so
+      // that fetching a chunk is one round trip to memory (its rows and k-th
+      // best distances), which the chunk before it covers
+      // (the previous segment's or leaf's last chunk step ended at a barrier)
+      g_int* glist = (g_int*)(sc.lists + s0);
       for (int i = tid; i < nlist; i += kThreads) {
         const int q = glist[i];
         s_list[i] = q;
         s_lk[i] = ((g_int*)s.kq)[q];
         s_ln[i] = ((g_float*)sc.qn)[q];
       }
-    __syncthreads();
-    // chunk c of the list into registers: A rows and the row terms.  Every
-    // load is unconditional (rows past the list read the list's last query
-    // and are masked by R = +inf), so they are all in flight together
-    u32x4 pa[Sh::per_thread];
-    int pq = -1;
-    float pqn = 0.0f;   // the row's |q|^2
-    float pkth = 0.0f;  // its query's k-th best squared distance when fetched
-    auto fetch = [&](int c) __attribute__((always_inline)) {
-      int qi[Sh::per_thread];
-      const int li = c * kScreenChunk + tid;
-      const int l1c = min(li, nlist - 1);
-      int q0 = 0, kq = 0;
-      float qn = 0.0f;
-      if (in_lds) {
+      __syncthreads();
+      // chunk c of the list into registers: A rows and the row terms.  Every
+      // load is unconditional (rows past the list read the list's last query
+      // and are masked by R = +inf), so they are all in flight together
+      u32x4 pa[Sh::per_thread];
+      int pq = -1;
+      float pqn = 0.0f;   // the row's |q|^2
+      float pkth = 0.0f;  // its query's k-th best squared distance when fetched
+      auto fetch = [&](int c) __attribute__((always_inline)) {
+        int qi[Sh::per_thread];
+        const int li = c * kScreenChunk + tid;
+        const int l1c = min(li, nlist - 1);
 #pragma unroll
         for (int u = 0; u < Sh::per_thread; ++u)
           qi[u] = s_list[min(c * kScreenChunk + (tid + u * kThreads) / (len / 8), nlist - 1)];
-        q0 = s_list[l1c];
-        kq = s_lk[l1c];
-        qn = s_ln[l1c];
-      } else {  // a long list: from memory (the screen runs for batches, which give every k)
+        const int q0 = s_list[l1c], kq = s_lk[l1c];
+        const float qn = s_ln[l1c];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < Sh::per_thread; ++u)
-          qi[u] = glist[min(c * kScreenChunk + (tid + u * kThreads) / (len / 8), nlist - 1)];
-        q0 = glist[l1c];
-        kq = ((g_int*)s.kq)[q0];
-        qn = ((g_float*)sc.qn)[q0];
-      }
-      __builtin_amdgcn_sched_barrier(0);
+        for (int u = 0; u < Sh::per_thread; ++u) {
+          const int c16 = (tid + u * kThreads) % (len / 8);
+          pa[u] = ((g_u32x4*)(sc.qb + (int64_t)qi[u] * len))[c16];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // the row terms are formed when the chunk is stashed, so that nothing
+        // here waits for these loads.  A plain load of the upper half (the
+        // distance) of the k-th best key: a stale value is larger (slots only
+        // decrease), so only looser
+        pkth = ((g_float*)s.slots)[2 * ((int64_t)q0 * p.k + kq - 1) + 1];
+        pqn = qn;
+        pq = li < nlist ? q0 : -1;
+      };
+      auto stash = [&](int buf) __attribute__((always_inline)) {
+        char* dst = abuf + buf * Sh::a_bytes;
 #pragma unroll
-      for (int u = 0; u < Sh::per_thread; ++u) {
-        const int c16 = (tid + u * kThreads) % (len / 8);
-        pa[u] = ((g_u32x4*)(sc.qb + (int64_t)qi[u] * len))[c16];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-      // the row terms are formed when the chunk is stashed, so that nothing
-      // here waits for these loads.  A plain load of the upper half (the
-      // distance) of the k-th best key: a stale value is larger (slots only
-      // decrease), so only looser
-      pkth = ((g_float*)s.slots)[2 * ((int64_t)q0 * p.k + kq - 1) + 1];
-      pqn = qn;
-      pq = li < nlist ? q0 : -1;
-    };
-    auto stash = [&](int buf) __attribute__((always_inline)) {
-      char* dst = abuf + buf * Sh::a_bytes;
+        for (int u = 0; u < Sh::per_thread; ++u) {
+          const int v = tid + u * kThreads;
+          const int row = v / (len / 8), c16 = v % (len / 8);
+          *reinterpret_cast<u32x4*>(dst + row * Sh::row_bytes + 16 * c16) = pa[u];
+        }
+        if (tid < kScreenChunk) {
+          const bool ok = pq >= 0;
+          s_q[buf][tid] = pq;
+          s_R[buf][tid] = ok ? 0.5f * (pqn * one_m - pkth * p.win) : INFINITY;
+          s_a[buf][tid] = ok ? 0.5f * (sc.c_dot * sqrtf(pqn)) : 0.0f;
+        }
+      };
+      // Column passes over the leaf.  The query list is the same for every
+      // pass: chunk c of a pass sits in LDS buffer cur ^ (c & 1), and the last
+      // chunk's step stages chunk 0 again for the next pass (a one-chunk list
+      // simply stays in buffer cur), so only the leaf's first pass waits for
+      // its chunk 0.  Its row terms keep the k-th best of that first fetch,
+      // which only makes them looser.  Every fetch is unconditional (a step
+      // with nothing to stage fetches its own chunk again and discards it),
+      // so no loaded value has to be merged at a branch's end, which would
+      // wait for it there.
+      int cur = 0;
+      fetch(0);
+      stash(0);
+      __syncthreads();
+      for (int64_t base = b; base < e; base += Sh::pass) {
+        const int64_t wbase = base + 16 * NT * wv;
+        float cx[NT], sx[NT], xnv[NT];
+        bf16x8 B[NT][KS];
+        // the column norms, then the B operands, all loads unconditional
+        // (columns past the leaf read its last row; their column term C_x =
+        // +inf masks them).  Loads complete in issue order: the column terms
+        // formed next wait for the norms only, and the B operands are issued
+        // in the order the products use them, so the pass's first products
+        // wait for the first K step only
+        const u32x4* src[NT];
 #pragma unroll
-      for (int u = 0; u < Sh::per_thread; ++u) {
-        const int v = tid + u * kThreads;
-        const int row = v / (len / 8), c16 = v % (len / 8);
-        *reinterpret_cast<u32x4*>(dst + row * Sh::row_bytes + 16 * c16) = pa[u];
-      }
-      if (tid < kScreenChunk) {
-        const bool ok = pq >= 0;
-        s_q[buf][tid] = pq;
-        s_R[buf][tid] = ok ? 0.5f * (pqn * one_m - pkth * p.win) : INFINITY;
-        s_a[buf][tid] = ok ? 0.5f * (sc.c_dot * sqrtf(pqn)) : 0.0f;
-      }
-    };
-    // Column passes over the leaf.  The query list is the same for every
-    // pass: chunk c of a pass sits in LDS buffer cur ^ (c & 1), and the last
-    // chunk's step stages chunk 0 again for the next pass (a one-chunk list
-    // simply stays in buffer cur), so only the leaf's first pass waits for
-    // its chunk 0.  Its row terms keep the k-th best of that first fetch,
-    // which only makes them looser.  Every fetch is unconditional (a step
-    // with nothing to stage fetches its own chunk again and discards it),
-    // so no loaded value has to be merged at a branch's end, which would
-    // wait for it there.
-    int cur = 0;
-    fetch(0);
-    stash(0);
-    __syncthreads();
-    for (int64_t base = b; base < e; base += Sh::pass) {
-      const int64_t wbase = base + 16 * NT * wv;
-      float cx[NT], sx[NT], xnv[NT];
-      bf16x8 B[NT][KS];
-      // B operands, all loads unconditional (columns past the leaf read its
-      // last row; their column term C_x = +inf masks them)
+        for (int t = 0; t < NT; ++t) {
+          const int64_t j = wbase + 16 * t + col;
+          const int64_t jc = j < e ? j : e - 1;
+          xnv[t] = sc.xn[jc];
+          src[t] = reinterpret_cast<const u32x4*>(sc.Zb + jc * len + kb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const int64_t j = wbase + 16 * t + col;
-        const int64_t jc = j < e ? j : e - 1;
-        xnv[t] = sc.xn[jc];
-        const u32x4* src = reinterpret_cast<const u32x4*>(sc.Zb + jc * len + kb);
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) B[t][ks] = __builtin_bit_cast(bf16x8, src[4 * ks]);
-      }
+          for (int t = 0; t < NT; ++t) B[t][ks] = __builtin_bit_cast(bf16x8, src[t][4 * ks]);
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int t = 0; t < NT; ++t) {
-        const bool v = wbase + 16 * t + col < e;
-        cx[t] = v ? 0.5f * (xnv[t] * one_m) : INFINITY;
-        sx[t] = sqrtf(xnv[t]);
-      }
-      const int ncols = (int)((e - wbase) < 16 * NT ? ((e - wbase) > 0 ? (e - wbase) : 0) : 16 * NT);
-      const bool more = base + Sh::pass < e;
-      for (int c = 0; c < nch; ++c) {
-        const int buf = cur ^ (c & 1);
-        // the next chunk of this pass, or chunk 0 again for the next pass
-        const int nxt = c + 1 < nch ? c + 1 : (more && nch > 1 ? 0 : -1);
-        fetch(nxt >= 0 ? nxt : c);
-        const char* A = abuf + buf * Sh::a_bytes;
-        const int rows_valid = min(kScreenChunk, nlist - c * kScreenChunk);
+        for (int t = 0; t < NT; ++t) {
+          const bool v = wbase + 16 * t + col < e;
+          cx[t] = v ? 0.5f * (xnv[t] * one_m) : INFINITY;
+          sx[t] = sqrtf(xnv[t]);
+        }
+        const int ncols = (int)((e - wbase) < 16 * NT ? ((e - wbase) > 0 ? (e - wbase) : 0) : 16 * NT);
+        const bool more = base + Sh::pass < e;
+        for (int c = 0; c < nch; ++c) {
+          const int buf = cur ^ (c & 1);
+          // the next chunk of this pass, or chunk 0 again for the next pass
+          const int nxt = c + 1 < nch ? c + 1 : (more && nch > 1 ? 0 : -1);
+          fetch(nxt >= 0 ? nxt : c);
+          const char* A = abuf + buf * Sh::a_bytes;
+          const int rows_valid = min(kScreenChunk, nlist - c * kScreenChunk);
 #pragma unroll 1
-        // (a wave whose columns all lie past the leaf, in a leaf's last
-        // pass, has nothing to screen: the other block on the CU gets its
-        // share of the matrix cores meanwhile)
-        for (int qt = 0; ncols > 0 && qt < kScreenChunk / 16 && 16 * qt < rows_valid; ++qt) {
-          f32x4 acc[NT];
+          // (a wave whose columns all lie past the leaf, in a leaf's last
+          // pass, has nothing to screen: the other block on the CU gets its
+          // share of the matrix cores meanwhile)
+          for (int qt = 0; ncols > 0 && qt < kScreenChunk / 16 && 16 * qt < rows_valid; ++qt) {
+            f32x4 acc[NT];
 #pragma unroll
-          for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-          const char* arow = A + (16 * qt + col) * Sh::row_bytes + 2 * kb;
-          // the tile's A operands all in flight before the first product
-          bf16x8 av[KS];
+            for (int t = 0; t < NT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            const char* arow = A + (16 * qt + col) * Sh::row_bytes + 2 * kb;
+            // the tile's A operands all in flight before the first product
+            bf16x8 av[KS];
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks)
-            av[ks] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(arow + 64 * ks));
+            for (int ks = 0; ks < KS; ++ks)
+              av[ks] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(arow + 64 * ks));
 #pragma unroll
-          for (int ks = 0; ks < KS; ++ks) {
+            for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-              acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ks], B[t][ks], acc[t], 0, 0, 0);
-          }
-          screened += (unsigned long long)(min(16, rows_valid - 16 * qt) * ncols);
-          float Rh[4], ah[4];
+              for (int t = 0; t < NT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ks], B[t][ks], acc[t], 0, 0, 0);
+            }
+            screened += (unsigned long long)(min(16, rows_valid - 16 * qt) * ncols);
+            float Rh[4], ah[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int row = 16 * qt + 4 * (lane >> 4) + r;
-            Rh[r] = s_R[buf][row];
-            ah[r] = s_a[buf][row];
-          }
-          // kept: s~ >= T (or NaN); which pairs, only when some lane has one
-          bool any = false;
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-#pragma unroll
-            for (int t = 0; t < NT; ++t) any |= !(acc[t][r] < __builtin_fmaf(-ah[r], sx[t], Rh[r] + cx[t]));
-          if (__ballot(any)) {  // rare: refine the kept pairs one at a time
-            uint32_t keep = 0;
+            for (int r = 0; r < 4; ++r) {
+              const int row = 16 * qt + 4 * (lane >> 4) + r;
+              Rh[r] = s_R[buf][row];
+              ah[r] = s_a[buf][row];
+            }
+            // kept: s~ >= T (or NaN); which pairs, only when some lane has one
+            bool any = false;
 #pragma unroll
             for (int r = 0; r < 4; ++r)
 #pragma unroll
-              for (int t = 0; t < NT; ++t)
-                keep |= (acc[t][r] < __builtin_fmaf(-ah[r], sx[t], Rh[r] + cx[t]) ? 0u : 1u) << (r * NT + t);
-            unsigned long long m = __ballot(keep != 0);
-            while (m) {
-              const int src_lane = __ffsll((long long)m) - 1;
-              m &= m - 1;
-              uint32_t bits = __shfl(keep, src_lane, kWave);
-              while (bits) {
-                const int bit = __ffs(bits) - 1;
-                bits &= bits - 1;
-                const int r = bit / NT, t = bit % NT;
-                const int row = 16 * qt + 4 * (src_lane >> 4) + r;
-                const int qsel = s_q[buf][row];
-                const int64_t jsel = wbase + 16 * t + (src_lane & 15);
-                if (qsel < 0 || jsel >= e) continue;
-                if (jsel >= s.approx_range[2 * qsel] && jsel < s.approx_range[2 * qsel + 1]) continue;
-                const float d2 = ed_wave(s.zq + (int64_t)qsel * len, zrow_ptr(ix, jsel), len, lane);
-                if (lane == 0) {
-                  const int kk = k_of(p, s, qsel);
-                  const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
-                  const bool in = offer(ix, p, s, qsel, d2, jsel, ck, true);
-                  if (p.count_work) {
-                    if (in) atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatBsf], 1ull);
-                    atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
+              for (int t = 0; t < NT; ++t) any |= !(acc[t][r] < __builtin_fmaf(-ah[r], sx[t], Rh[r] + cx[t]));
+            if (__ballot(any)) {  // rare: refine the kept pairs one at a time
+              uint32_t keep = 0;
+#pragma unroll
+              for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int t = 0; t < NT; ++t)
+                  keep |= (acc[t][r] < __builtin_fmaf(-ah[r], sx[t], Rh[r] + cx[t]) ? 0u : 1u) << (r * NT + t);
+              unsigned long long m = __ballot(keep != 0);
+              while (m) {
+                const int src_lane = __ffsll((long long)m) - 1;
+                m &= m - 1;
+                uint32_t bits = __shfl(keep, src_lane, kWave);
+                while (bits) {
+                  const int bit = __ffs(bits) - 1;
+                  bits &= bits - 1;
+                  const int r = bit / NT, t = bit % NT;
+                  const int row = 16 * qt + 4 * (src_lane >> 4) + r;
+                  const int qsel = s_q[buf][row];
+                  const int64_t jsel = wbase + 16 * t + (src_lane & 15);
+                  if (qsel < 0 || jsel >= e) continue;
+                  if (jsel >= s.approx_range[2 * qsel] && jsel < s.approx_range[2 * qsel + 1]) continue;
+                  const float d2 = ed_wave(s.zq + (int64_t)qsel * len, zrow_ptr(ix, jsel), len, lane);
+                  if (lane == 0) {
+                    const int kk = k_of(p, s, qsel);
+                    const unsigned long long ck = load_key(s.slots + (int64_t)qsel * p.k + kk - 1);
+                    const bool in = offer(ix, p, s, qsel, d2, jsel, ck, true);
+                    if (p.count_work) {
+                      if (in) atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatBsf], 1ull);
+                      atomicAdd(&s.stats[(int64_t)qsel * kStatCount + kStatRefined], 1ull);
+                    }
                   }
+                  ++passed;
                 }
-                ++passed;
               }
             }
           }
+          if (nxt >= 0) {
+            stash(buf ^ 1);
+          } else {  // the discarded fetch's loads are waited for here, where they have
+                    // long arrived, so that no later step waits on them
+#pragma unroll
+            for (int u = 0; u < Sh::per_thread; ++u) asm volatile("" ::"v"(pa[u]));
+            asm volatile("" ::"v"(pkth));
+          }
+          __syncthreads();
         }
-        if (nxt >= 0) stash(buf ^ 1);
-        __syncthreads();
+        if (nch > 1) cur ^= nch & 1;  // where the next pass's chunk 0 was staged
       }
-      if (nch > 1) cur ^= nch & 1;  // where the next pass's chunk 0 was staged
     }
   }
   // lanes of a wave counted the same tiles: one add per wave
