@@ -28,6 +28,8 @@
 // the FP32 error window of the running k-th best is logged, and the final
 // order is decided on FP64 distances of the logged candidates.
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <algorithm>
 #include <mutex>
 #include <stdint.h>
@@ -2720,13 +2722,19 @@ void* noalloc_scratch(size_t* bytes) {
 size_t process_lds_static(const QueryParams& p) {
   bool mask;
   if (band_of(p, &mask) != -1) return 4096;  // a few shared scalars
+  // the kernels' static LDS, asked once per instance (it is fixed at build)
+  static std::atomic<long long> cached[2] = {{-1}, {-1}};
+  const int which = p.card_bits == 8 ? 1 : 0;
+  const long long c = cached[which].load(std::memory_order_relaxed);
+  if (c >= 0) return (size_t)c;
   hipFuncAttributes a{};
-  const hipError_t e = p.card_bits == 8 ? hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_process_ed<8>))
-                                        : hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_process_ed<0>));
+  const hipError_t e = which ? hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_process_ed<8>))
+                             : hipFuncGetAttributes(&a, reinterpret_cast<const void*>(k_process_ed<0>));
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 48 * 1024;  // above the kernel's own (a refusal rather than a failed launch)
   }
+  cached[which].store((long long)a.sharedSizeBytes, std::memory_order_relaxed);
   return a.sharedSizeBytes;
 }
 
