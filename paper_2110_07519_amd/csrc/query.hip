@@ -981,6 +981,56 @@ __global__ __launch_bounds__(256) void k_stage1(IndexDev ix, QueryParams p, Quer
   }
 }
 
+// Leaf bounds of a batch when only the bounds are needed (the screen's leaf
+// lists): block (x, y) takes 256 leaves and kBoundQueries queries, so each
+// leaf's box ends are looked up once and serve every query of the tile.
+// The box of a b-bit prefix y of segment s is the union of the symbols
+// y 2^(cb-b) .. (y+1) 2^(cb-b) - 1, so its ends are bp[y << (cb-b)] and
+// bp[(y+1) << (cb-b)], and its gap equals the smallest gap of its symbols'
+// boxes (the one at its first or last symbol, or zero), which is the value
+// the bound blocks' min-tree holds: the same arithmetic gives the same bits.
+constexpr int kBoundQueries = 32;
+
+__global__ __launch_bounds__(256) void k_leaf_bounds(IndexDev ix, QueryParams p, QueryState s) {
+  __shared__ float s_bp[257];
+  __shared__ float s_pu[kBoundQueries][kMaxSeg], s_pl[kBoundQueries][kMaxSeg];
+  const int tid = threadIdx.x, cb = p.card_bits, card = 1 << cb, w = p.w;
+  const int q0 = blockIdx.y * kBoundQueries;
+  const int nqt = min(kBoundQueries, p.nq - q0);
+  for (int j = tid; j <= card; j += blockDim.x) s_bp[j] = ix.bp[j];
+  for (int i = tid; i < nqt * kMaxSeg; i += blockDim.x) {
+    const int qi = i / kMaxSeg, sg = i % kMaxSeg;
+    s_pu[qi][sg] = s.paa[((int64_t)(q0 + qi) * 3 + 1) * kMaxSeg + sg];
+    s_pl[qi][sg] = s.paa[((int64_t)(q0 + qi) * 3 + 2) * kMaxSeg + sg];
+  }
+  __syncthreads();
+  const int l = blockIdx.x * blockDim.x + tid;
+  if (l >= p.n_leaves) return;
+  const uint4 sy = ix.leaf_sym[l], bi = ix.leaf_bits[l];
+  float lo[kMaxSeg], hi[kMaxSeg];
+#pragma unroll
+  for (int sg = 0; sg < kMaxSeg; ++sg) {
+    const int b = (int)byte_of(bi, sg), y = (int)byte_of(sy, sg);
+    lo[sg] = s_bp[y << (cb - b)];
+    hi[sg] = s_bp[(y + 1) << (cb - b)];
+  }
+  const float fm = (float)p.m;
+  float* out = s.leaf_lb + (int64_t)q0 * p.n_leaves + l;
+  for (int qi = 0; qi < nqt; ++qi) {
+    float t[kMaxSeg];
+#pragma unroll
+    for (int sg = 0; sg < kMaxSeg; ++sg) {
+      const float g = fmaxf(lo[sg] - s_pu[qi][sg], 0.0f) + fmaxf(s_pl[qi][sg] - hi[sg], 0.0f);
+      t[sg] = sg < w ? fm * (g * g) : 0.0f;
+    }
+#pragma unroll
+    for (int h = kMaxSeg / 2; h >= 1; h >>= 1)
+#pragma unroll
+      for (int sg = 0; sg < h; ++sg) t[sg] = t[sg] + t[sg + h];
+    out[(int64_t)qi * p.n_leaves] = t[0];
+  }
+}
+
 // Near-tie log entries of the approximate search: its distances within the
 // window of the first k-th best (the k-th best only decreases afterwards,
 // so this covers the window of the final one).
@@ -2557,9 +2607,14 @@ void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& 
   bool mask;
   const int R = band_of(qp, &mask);
   const int approx_blocks = R == -1 ? (qp.leaf_in_prep ? 32 : 64) : (R == -2 ? 64 : (kApproxCap + 255) / 256);
-  // one bound block per shard when the chunk order is written, else eight
-  const dim3 g(approx_blocks + (qp.order_leaves ? kShards : 8), qp.nq);
+  // one bound block per shard when the chunk order is written; otherwise
+  // the bounds alone come from k_leaf_bounds, query tiles sharing each leaf
+  const dim3 g(approx_blocks + (qp.order_leaves ? kShards : 0), qp.nq);
   const size_t lds = stage1_lds_bytes(qp, R);
+  if (!qp.order_leaves) {
+    const dim3 gb((unsigned)((qp.n_leaves + 255) / 256), (unsigned)((qp.nq + kBoundQueries - 1) / kBoundQueries));
+    hipLaunchKernelGGL(k_leaf_bounds, gb, dim3(256), 0, st, ix, qp, qs);
+  }
   if (R == -1) {
     hipLaunchKernelGGL((k_stage1<-1, false>), g, dim3(256), lds, st, ix, qp, qs, approx_blocks);
     return;
