@@ -2120,11 +2120,20 @@ __global__ __launch_bounds__(256) void k_leaf_lists(QueryParams p, QueryState s,
     __syncthreads();
     const int nn = min(256, p.nq - q0);
     if (l < p.n_leaves) {
-      for (int j = 0; j < nn; ++j) {
-        if (s.leaf_lb[(int64_t)(q0 + j) * p.n_leaves + l] <= thr[j]) {
-          if (fill) sc.lists[at++] = q0 + j;
-          ++c;
-        }
+      // sixteen queries' bounds of this leaf in flight at a time (the index
+      // is clamped, the comparison masked past the chunk)
+      const float* __restrict__ col = s.leaf_lb + (int64_t)q0 * p.n_leaves + l;
+      int* __restrict__ lists = sc.lists;
+      for (int j0 = 0; j0 < nn; j0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = col[(int64_t)min(j0 + u, nn - 1) * p.n_leaves];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (j0 + u < nn && v[u] <= thr[j0 + u]) {
+            if (fill) lists[at++] = q0 + j0 + u;
+            ++c;
+          }
       }
     }
   }
