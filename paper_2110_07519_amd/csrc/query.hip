@@ -2144,30 +2144,51 @@ __global__ __launch_bounds__(256) void k_log_approx(QueryParams p, QueryState s)
   log_approx(p, s, blockIdx.x, threadIdx.x, blockDim.x);
 }
 
-// Exclusive scan of the list lengths (one block); also resets the work
-// counter and the tallies.
+// Exclusive scan of the list lengths (one block, tiles of 4,096 lengths:
+// four consecutive per thread, a wave scan, a scan of the wave sums, and
+// the running total carried between tiles); also resets the work counter
+// and the tallies.
 __global__ __launch_bounds__(1024) void k_list_scan(QueryParams p, ScreenDev sc) {
-  __shared__ int64_t part[1024];
+  __shared__ int64_t wsum[16];
+  __shared__ int64_t s_carry;
   const int L = p.n_leaves;
-  const int per = (L + 1023) / 1024;
-  const int a = threadIdx.x * per, b = min(a + per, L);
-  int64_t sum = 0;
-  for (int i = a; i < b; ++i) sum += sc.cnt[i];
-  part[threadIdx.x] = sum;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+  if (tid == 0) s_carry = 0;
   __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int64_t v = threadIdx.x >= (unsigned)o ? part[threadIdx.x - o] : 0;
+  for (int base = 0; base < L; base += 4096) {
+    const int i0 = base + 4 * tid;
+    int c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = i0 + u < L ? sc.cnt[i0 + u] : 0;
+    const int64_t t = (int64_t)c[0] + c[1] + c[2] + c[3];
+    int64_t x = t;  // inclusive scan over the wave
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int64_t y = __shfl_up(x, o, kWave);
+      if (lane >= o) x += y;
+    }
+    if (lane == kWave - 1) wsum[wv] = x;
     __syncthreads();
-    part[threadIdx.x] += v;
+    if (wv == 0) {  // inclusive scan of the 16 wave sums
+      int64_t w = lane < 16 ? wsum[lane] : 0;
+      for (int o = 1; o < 16; o <<= 1) {
+        const int64_t y = __shfl_up(w, o, kWave);
+        if (lane >= o) w += y;
+      }
+      if (lane < 16) wsum[lane] = w;
+    }
+    __syncthreads();
+    int64_t run = s_carry + (wv ? wsum[wv - 1] : 0) + (x - t);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (i0 + u < L) sc.off[i0 + u] = run;
+      run += c[u];
+    }
+    __syncthreads();  // every thread has read s_carry and wsum
+    if (tid == 0) s_carry += wsum[15];
     __syncthreads();
   }
-  int64_t run = part[threadIdx.x] - sum;
-  for (int i = a; i < b; ++i) {
-    sc.off[i] = run;
-    run += sc.cnt[i];
-  }
-  if (threadIdx.x == 1023) sc.off[L] = part[1023];
-  if (threadIdx.x == 0) {
+  if (tid == 0) {
+    sc.off[L] = s_carry;
     *sc.counter = 0;
     sc.tally[0] = 0;
     sc.tally[1] = 0;
