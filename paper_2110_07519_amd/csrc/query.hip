@@ -2636,9 +2636,9 @@ void launch_stage1(const IndexDev& ix, const QueryParams& qp, const QueryState& 
                    hipStream_t st) {
   bool mask;
   const int R = band_of(qp, &mask);
-  // ED: a leaf of at most 2,000 rows is eight-row groups for 32 waves (a
+  // ED: a leaf of at most 2,000 rows is eight-row groups for 16 waves (a
   // batch: the grid has many queries) or, for a few queries, 256 waves
-  const int approx_blocks = R == -1 ? (qp.leaf_in_prep ? 8 : 64) : (R == -2 ? 64 : (kApproxCap + 255) / 256);
+  const int approx_blocks = R == -1 ? (qp.leaf_in_prep ? 4 : 64) : (R == -2 ? 64 : (kApproxCap + 255) / 256);
   // one bound block per shard when the chunk order is written; otherwise
   // the bounds alone come from k_leaf_bounds, query tiles sharing each leaf
   const dim3 g(approx_blocks + (qp.order_leaves ? kShards : 0), qp.nq);
