@@ -309,7 +309,11 @@ __device__ __forceinline__ float dtw_band_body(const float* __restrict__ qpad_an
   float D[2 * R + 1];
 #pragma unroll
   for (int b = 0; b <= 2 * R; ++b) D[b] = (b == R) ? 0.0f : INFINITY;
-  if (R < 24 && (len & 3) == 0) {
+  // four rows per step share their query values (r = 25: 205 VGPRs, two
+  // waves per SIMD, faster than one row per step at 142); two rows from
+  // radius 32, whose four-row form would need more than 256 VGPRs; one
+  // row for the widest bands
+  if (R < 32 && (len & 3) == 0) {
     float4 xn = as_float4(*(const glb_f4v*)x);
 #pragma unroll 1
     for (int j = 0; j < len; j += 4) {
@@ -326,10 +330,29 @@ __device__ __forceinline__ float dtw_band_body(const float* __restrict__ qpad_an
         if (mn > cutoff) return -(float)(j + 4);
       }
     }
+  } else if (R < 48 && (len & 1) == 0) {
+    // two rows per step: the second row's query values are the first's
+    // shifted by one, read once; abandonment checked after the same rows as
+    // one row per step
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) f2v glb_f2v;
+    f2v xn = *(const glb_f2v*)x;
+#pragma unroll 1
+    for (int j = 0; j < len; j += 2) {
+      const f2v xa = xn;
+      if (j + 2 < len) xn = *(const glb_f2v*)(x + j + 2);
+      dtw_row<R, MASK>(D, qpad, j + 0, xa.x, r);
+      dtw_row<R, MASK>(D, qpad, j + 1, xa.y, r);
+      if ((j & 7) == 6) {
+        float mn = D[0];
+#pragma unroll
+        for (int b = 1; b <= 2 * R; ++b) mn = fminf(mn, D[b]);
+        if (mn > cutoff) return -(float)(j + 2);
+      }
+    }
   } else {
-    // one row per step from radius 24 (four rows at once keep their shared
-    // query values live beside the band: r = 25 needs 198 VGPRs that way,
-    // 128 this way), the next point loading while the current row runs
+    // one row per step (wide bands), the next point loading while the
+    // current row runs
     float xn = x[0];
 #pragma unroll 1
     for (int j = 0; j < len; ++j) {
